@@ -1,0 +1,191 @@
+"""One time step of the look-ahead DPF (Section 2.2, Fig. 4), FP64.
+
+TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
+
+State after step t-1 of one filter: outer particles x_{t-1}^{(i)} (N, dx),
+inner clouds z_{t-1}^{(i,j)} (N, M, dz) and the normalised inner
+log-weights lam^{(i,j)} = log qbar_{t-1}^{(i,j)} (N, M) of eq:qbar.  The
+outer particles are equally weighted (each step ends with outer resampling).
+
+Step t, given y_t, in the order of Fig. 4:
+
+1. Look-ahead particles.  For every outer i and every inner j, one
+   candidate xla^{(i,j)} ~ p(x_t | x_{t-1}^{(i)}, z_{t-1}^{(i,j)}) and its
+   companion zla^{(i,j)} ~ p(z_t | x_{t-1}^{(i)}, xla^{(i,j)}, z_{t-1}^{(i,j)}).
+   Drawing x from every inner component once, weighted by qbar, is the
+   mixture eq:approx1; each candidate carries one companion z
+   (N_x' = M candidates with N_z' = 1 companion each, the O(N M) cost stated
+   after eq:weightsMC).
+2. Weights (eq:weightsMC): ell^{(i,j)} = lam^{(i,j)} + log p(y_t | xla, zla)
+   and log w^{(i)} = logsumexp_j ell^{(i,j)}, an estimate of the predictive
+   likelihood p(y_t | y_{0:t-1}, x_{0:t-1}^{(i)}) that eq:weightsopt makes the
+   optimal-proposal weight.
+3. Outer resampling at t-1 with those weights (systematic, U53 OUTER_U).
+4. New particles.  For new particle k with parent p = A_k:
+   x_t^{(k)} is drawn from the MC optimal proposal eq:approx3 by
+   sampling-importance-resampling over the parent's M candidates with
+   probabilities proportional to exp(ell^{(p,j)}) (U53 CAND_U);
+   the parent's cloud is conditioned on x_t^{(k)} as in eq:qnobar,
+   kappa^{(j)} = lam^{(p,j)} + log p(x_t^{(k)} | x_{t-1}^{(p)}, z_{t-1}^{(p,j)}),
+   resampled systematically (U53 INNER_U), and propagated with the prior
+   inner proposal (the inner predictive of Section 2, importance weight 1):
+   z_t^{(k,j)} ~ p(z_t | x_{t-1}^{(p)}, x_t^{(k)}, z_{t-1}^{(p,b_j)}) (NEW_Z);
+   finally the inner measurement update eq:qbar gives
+   lam_t^{(k,j)} = log p(y_t | x_t^{(k)}, z_t^{(k,j)}) - logsumexp_j(.).
+
+Estimates: xhat = mean_k x_t^{(k)}, zhat = mean_k sum_j qbar_t z_t,
+ESS of the look-ahead weights, dlogZ = logsumexp_i log w - log N, and the
+Rao-Blackwellised xhat_rb = sum_i Wbar_i sum_j pi_ij xla^{(i,j)} (the exact
+conditional expectation of the new x given the look-ahead draws).
+"""
+import math
+
+import numpy as np
+
+from . import philox as P
+from .resample import (FLAG_DEGENERATE_INNER, FLAG_DEGENERATE_OUTER, FLAG_NONFINITE,
+                       logsumexp, normalise_log, systematic_log, weights_from_log)
+
+
+def init_state(model, N, M, seed, fid):
+    """Prior draws [x_0; z_0] ~ N(0, I) and lam_0 = -log M."""
+    i = np.arange(N)
+    j = np.arange(M)
+    x0 = P.normals(seed, fid, 0, i, 0, P.INIT_X, model.dx)
+    z0 = P.normals(seed, fid, 0, i[:, None], j[None, :], P.INIT_Z, model.dz)
+    lam0 = np.full((N, M), -math.log(M))
+    return {"x": x0, "z": z0, "lam": lam0, "t": 0}
+
+
+def cloud_moments(z, lam):
+    """qbar-weighted mean and variance of each inner cloud, (N, dz) each."""
+    q = np.exp(lam)
+    m = np.einsum("nm,nmd->nd", q, z)
+    v = np.einsum("nm,nmd->nd", q, (z - m[:, None, :]) ** 2)
+    return m, v
+
+
+def lookahead(model, state, y, seed, fid):
+    """Fig. 4 steps 1-2 for all outer particles; returns (xla, zla, ell, logw)."""
+    x, z, lam = state["x"], state["z"], state["lam"]
+    t = state["t"] + 1
+    N, M = lam.shape
+    i = np.arange(N)[:, None]
+    j = np.arange(M)[None, :]
+    nu_x = P.normals(seed, fid, t, i, j, P.LA_X, model.dx)
+    nu_z = P.normals(seed, fid, t, i, j, P.LA_Z, model.dz)
+    xp = x[:, None, :]
+    xla = model.fx(xp, z, nu_x)
+    zla = model.fz(xp, xla, z, nu_z)
+    ell = lam + model.logpy(y, xla, zla)
+    logw = logsumexp(ell)
+    return xla, zla, ell, logw
+
+
+def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None):
+    """One look-ahead DPF step consuming y_t.  Returns (new_state, info).
+
+    The ``u_*`` arguments replace the Philox offsets (test hooks for
+    enumerating resampling outcomes); by default they come from the
+    random-number contract.
+    """
+    x, z, lam = state["x"], state["z"], state["lam"]
+    t = state["t"] + 1
+    N, M = lam.shape
+    flags = 0
+
+    xla, zla, ell, logw = lookahead(model, state, y, seed, fid)
+
+    # Step 3: outer resampling with the look-ahead weights.
+    if u_outer is None:
+        u_outer = float(P.uniform53(seed, fid, t, 0, P.OUTER_U))
+    A, deg, nonf = systematic_log(logw, N, u_outer)
+    if deg:
+        flags |= FLAG_DEGENERATE_OUTER
+    if nonf:
+        flags |= FLAG_NONFINITE
+    Wn, _, _ = weights_from_log(logw)
+    Wbar = Wn / np.sum(Wn)
+    ess = 1.0 / np.sum(Wbar ** 2)
+    lse_all = logsumexp(logw)
+    dlogz = lse_all - math.log(N)
+
+    # Rao-Blackwellised estimate of the new x.
+    pi = np.stack([weights_from_log(ell[i])[0] for i in range(N)])
+    pi = pi / pi.sum(axis=1, keepdims=True)
+    xhat_rb = np.einsum("n,nm,nmd->d", Wbar, pi, xla)
+
+    # Step 4: new particles.
+    if u_cand is None:
+        u_cand = P.uniform53(seed, fid, t, np.arange(N), P.CAND_U)
+    if u_inner is None:
+        u_inner = P.uniform53(seed, fid, t, np.arange(N), P.INNER_U)
+    xnew = np.empty_like(x)
+    znew = np.empty_like(z)
+    lamnew = np.empty_like(lam)
+    cand = np.empty(N, dtype=np.int64)
+    binner = np.empty((N, M), dtype=np.int64)
+    j = np.arange(M)
+    for k in range(N):
+        p = A[k]
+        c, deg_c, _ = systematic_log(ell[p], 1, float(u_cand[k]))
+        cand[k] = c[0]
+        xnew[k] = xla[p, cand[k]]
+        kappa = lam[p] + model.logpx(xnew[k], x[p], z[p])
+        b, deg_i, nonf_i = systematic_log(kappa, M, float(u_inner[k]))
+        if deg_i:
+            flags |= FLAG_DEGENERATE_INNER
+        if nonf_i:
+            flags |= FLAG_NONFINITE
+        binner[k] = b
+        nu = P.normals(seed, fid, t, k, j, P.NEW_Z, model.dz)
+        znew[k] = model.fz(x[p], xnew[k], z[p, b], nu)
+        lamnew[k], deg_l = normalise_log(model.logpy(y, xnew[k], znew[k]))
+        if deg_l:
+            flags |= FLAG_DEGENERATE_INNER
+
+    xhat = xnew.mean(axis=0)
+    zhat = np.einsum("nm,nmd->d", np.exp(lamnew), znew) / N
+    new_state = {"x": xnew, "z": znew, "lam": lamnew, "t": t}
+    info = {
+        "xla": xla, "zla": zla, "ell": ell, "logw": logw, "A": A, "cand": cand,
+        "binner": binner, "u_outer": u_outer, "u_cand": np.asarray(u_cand),
+        "u_inner": np.asarray(u_inner),
+        "xhat": xhat, "zhat": zhat, "ess": ess, "dlogz": dlogz, "xhat_rb": xhat_rb,
+        "flags": flags,
+    }
+    return new_state, info
+
+
+def training_pairs(state, y, info):
+    """(features of the parent, SIR-selected x_t) for every new particle.
+
+    Features: [x_{t-1}^{(p)}, y_t, qbar-weighted mean and variance of the
+    parent's cloud] -- the inputs the learned proposal conditions on.
+    """
+    m, v = cloud_moments(state["z"], state["lam"])
+    A = info["A"]
+    N = len(A)
+    yy = np.broadcast_to(np.asarray(y, dtype=np.float64), (N, len(y)))
+    feats = np.concatenate([state["x"][A], yy, m[A], v[A]], axis=1)
+    return feats, state_x_new(info)
+
+
+def state_x_new(info):
+    A, cand, xla = info["A"], info["cand"], info["xla"]
+    return xla[A, cand]
+
+
+def run(model, N, M, ys, seed, fid):
+    """Run the look-ahead DPF over observations y_1..y_T; returns per-step estimates."""
+    state = init_state(model, N, M, seed, fid)
+    out = {"xhat": [], "zhat": [], "ess": [], "dlogz": [], "xhat_rb": [], "flags": 0}
+    for y in ys:
+        state, info = step(model, state, y, seed, fid)
+        for key in ("xhat", "zhat", "ess", "dlogz", "xhat_rb"):
+            out[key].append(info[key])
+        out["flags"] |= info["flags"]
+    for key in ("xhat", "zhat", "ess", "dlogz", "xhat_rb"):
+        out[key] = np.asarray(out[key])
+    out["state"] = state
+    return out

@@ -1,0 +1,188 @@
+"""Nested state-space models of Eq. (1), oracle side (FP64).
+
+TEST INFRASTRUCTURE ONLY -- see ``oracle/__init__.py``.
+
+Section 2, Eq. (1) writes the model as x_{t+1} = f^x(x_t, z_t, v^x),
+z_{t+1} = f^z(x_{t:t+1}, z_t, v^z), y_t = h(x_t, z_t, e_t), equivalently as
+p(x_0), p(z_0|x_0), p(x_{t+1}|x_t,z_t), p(z_{t+1}|x_{t:t+1},z_t) and
+p(y_t|x_t,z_t), with all parameters known.  Each model below provides
+
+    fx(x, z, nu)        sample of x_{t+1} given standard normals nu (dx)
+    fz(x, xn, z, nu)    sample of z_{t+1} given x_t, x_{t+1}, z_t, normals (dz)
+    logpx(xn, x, z)     log p(x_{t+1} | x_t, z_t)
+    logpy(y, x, z)      log p(y_t | x_t, z_t)
+
+on arrays whose last axis is the state dimension (leading axes broadcast).
+The prior is [x_0; z_0] ~ N(0, I) for every model (as in Table 1).
+
+Parameters arrive as the flat float64 blob of the library interface; the
+layouts are parsed here, independently of the HIP side:
+
+LINGAUSS (linear-Gaussian; the coupled variant has Cxz != 0):
+    Ax[dx*dx] Cxz[dx*dz] qx Az[dz*dz] Bzx[dz*dx] qz Hx[dy*dx] Hz[dy*dz] r
+    x' = Ax x + Cxz z + sqrt(qx) v,  z' = Az z + Bzx x' + sqrt(qz) w,
+    y  = Hx x + Hz z + sqrt(r) e.
+NONLIN (dy = dz):
+    a b qx W[dz*dx] rho qz c r bmode
+    x'_d = a x_d + b x_d/(1+x_d^2) + sqrt(qx) v_d,
+    z'   = tanh(W x') + rho z + sqrt(qz) w,
+    y_k  = z_k + c g_k(x) + sqrt(r) e_k,  g_k = x_{k mod dx}^2 (bmode 0)
+                                          or |x|^2 (bmode 1).
+HIGHDIM:
+    a b qx Alo[dz-1] Adiag[dz] Aup[dz-1] B[dz*dx] qz C[dy*dz] r eps nu gonly
+    x' as NONLIN's x (dx components),  z' = A z + B sin(x') + sqrt(qz) w with
+    A tridiagonal,  y = C z + e where each e_k has density
+    (1-eps) N(0, r) + eps * t_nu(e/sqrt(r))/sqrt(r)  (gonly=1: pure N(0, r)).
+"""
+import math
+
+import numpy as np
+
+LINGAUSS, NONLIN, HIGHDIM = 1, 2, 3
+
+LOG2PI = math.log(2.0 * math.pi)
+
+
+def _take(blob, pos, n):
+    return np.asarray(blob[pos:pos + n], dtype=np.float64), pos + n
+
+
+def _matvec(Mat, v):
+    """Mat (r, c) times v (..., c) -> (..., r)."""
+    return np.einsum("rc,...c->...r", Mat, v)
+
+
+def _gauss_iso_logpdf(resid, var):
+    """log N(resid; 0, var I) summed over the last axis."""
+    d = resid.shape[-1]
+    return -0.5 * np.sum(resid * resid, axis=-1) / var - 0.5 * d * (LOG2PI + math.log(var))
+
+
+class LinGauss:
+    kind = LINGAUSS
+
+    def __init__(self, dx, dz, dy, blob):
+        self.dx, self.dz, self.dy = dx, dz, dy
+        p = 0
+        a, p = _take(blob, p, dx * dx); self.Ax = a.reshape(dx, dx)
+        a, p = _take(blob, p, dx * dz); self.Cxz = a.reshape(dx, dz)
+        self.qx = float(blob[p]); p += 1
+        a, p = _take(blob, p, dz * dz); self.Az = a.reshape(dz, dz)
+        a, p = _take(blob, p, dz * dx); self.Bzx = a.reshape(dz, dx)
+        self.qz = float(blob[p]); p += 1
+        a, p = _take(blob, p, dy * dx); self.Hx = a.reshape(dy, dx)
+        a, p = _take(blob, p, dy * dz); self.Hz = a.reshape(dy, dz)
+        self.r = float(blob[p]); p += 1
+        if p != len(blob):
+            raise ValueError("LINGAUSS blob has %d values, expected %d" % (len(blob), p))
+
+    def mean_x(self, x, z):
+        return _matvec(self.Ax, x) + _matvec(self.Cxz, z)
+
+    def fx(self, x, z, nu):
+        return self.mean_x(x, z) + math.sqrt(self.qx) * nu
+
+    def fz(self, x, xn, z, nu):
+        return _matvec(self.Az, z) + _matvec(self.Bzx, xn) + math.sqrt(self.qz) * nu
+
+    def logpx(self, xn, x, z):
+        return _gauss_iso_logpdf(xn - self.mean_x(x, z), self.qx)
+
+    def logpy(self, y, x, z):
+        return _gauss_iso_logpdf(y - _matvec(self.Hx, x) - _matvec(self.Hz, z), self.r)
+
+
+def _growth(a, b, x):
+    return a * x + b * x / (1.0 + x * x)
+
+
+class NonLin:
+    kind = NONLIN
+
+    def __init__(self, dx, dz, dy, blob):
+        if dy != dz:
+            raise ValueError("NONLIN needs dy == dz")
+        self.dx, self.dz, self.dy = dx, dz, dy
+        self.a, self.b, self.qx = (float(v) for v in blob[0:3])
+        p = 3
+        a, p = _take(blob, p, dz * dx); self.W = a.reshape(dz, dx)
+        self.rho, self.qz, self.c, self.r, bmode = (float(v) for v in blob[p:p + 5])
+        p += 5
+        self.bmode = int(bmode)
+        if p != len(blob):
+            raise ValueError("NONLIN blob has %d values, expected %d" % (len(blob), p))
+
+    def fx(self, x, z, nu):
+        return _growth(self.a, self.b, x) + math.sqrt(self.qx) * nu
+
+    def fz(self, x, xn, z, nu):
+        return np.tanh(_matvec(self.W, xn)) + self.rho * z + math.sqrt(self.qz) * nu
+
+    def logpx(self, xn, x, z):
+        return _gauss_iso_logpdf(xn - _growth(self.a, self.b, x), self.qx)
+
+    def obs_offset(self, x):
+        """c * g(x) broadcast to the dy outputs."""
+        if self.bmode == 0:
+            idx = np.arange(self.dy) % self.dx
+            return self.c * (x[..., idx] ** 2)
+        return self.c * np.sum(x * x, axis=-1, keepdims=True) * np.ones(self.dy)
+
+    def logpy(self, y, x, z):
+        return _gauss_iso_logpdf(y - z - self.obs_offset(x), self.r)
+
+
+class HighDim:
+    kind = HIGHDIM
+
+    def __init__(self, dx, dz, dy, blob):
+        self.dx, self.dz, self.dy = dx, dz, dy
+        self.a, self.b, self.qx = (float(v) for v in blob[0:3])
+        p = 3
+        lo, p = _take(blob, p, dz - 1)
+        dg, p = _take(blob, p, dz)
+        up, p = _take(blob, p, dz - 1)
+        self.A = np.diag(dg) + np.diag(lo, -1) + np.diag(up, 1)
+        a, p = _take(blob, p, dz * dx); self.B = a.reshape(dz, dx)
+        self.qz = float(blob[p]); p += 1
+        a, p = _take(blob, p, dy * dz); self.C = a.reshape(dy, dz)
+        self.r, self.eps, self.nu, gonly = (float(v) for v in blob[p:p + 4])
+        p += 4
+        self.gaussian_only = bool(gonly)
+        if p != len(blob):
+            raise ValueError("HIGHDIM blob has %d values, expected %d" % (len(blob), p))
+
+    def fx(self, x, z, nu):
+        return _growth(self.a, self.b, x) + math.sqrt(self.qx) * nu
+
+    def fz(self, x, xn, z, nu):
+        return _matvec(self.A, z) + _matvec(self.B, np.sin(xn)) + math.sqrt(self.qz) * nu
+
+    def logpx(self, xn, x, z):
+        return _gauss_iso_logpdf(xn - _growth(self.a, self.b, x), self.qx)
+
+    def logpy(self, y, x, z):
+        e = y - _matvec(self.C, z)
+        if self.gaussian_only:
+            return _gauss_iso_logpdf(e, self.r)
+        sd = math.sqrt(self.r)
+        log_g = -0.5 * e * e / self.r - 0.5 * (LOG2PI + math.log(self.r))
+        nu = self.nu
+        # Student-t density with nu degrees of freedom, scaled by sd.
+        log_t_norm = (math.lgamma(0.5 * (nu + 1.0)) - math.lgamma(0.5 * nu)
+                      - 0.5 * math.log(nu * math.pi))
+        s = e / sd
+        log_t = log_t_norm - 0.5 * (nu + 1.0) * np.log1p(s * s / nu) - math.log(sd)
+        comp = np.logaddexp(math.log1p(-self.eps) + log_g, math.log(self.eps) + log_t)
+        return np.sum(comp, axis=-1)
+
+
+def make_model(kind, dx, dz, dy, blob):
+    blob = np.asarray(blob, dtype=np.float64)
+    if kind == LINGAUSS:
+        return LinGauss(dx, dz, dy, blob)
+    if kind == NONLIN:
+        return NonLin(dx, dz, dy, blob)
+    if kind == HIGHDIM:
+        return HighDim(dx, dz, dy, blob)
+    raise ValueError("unknown model kind %r" % (kind,))
