@@ -1,0 +1,231 @@
+/*
+ * dpf.h -- C interface of the MI355X (gfx950) look-ahead decentralized
+ * particle filter library (libdpf.so).
+ *
+ * Method: Ahmed, Bibalan, de Freitas, Fauvel, "Decentralized, Adaptive,
+ * Look-Ahead Particle Filtering", arXiv:1203.2394.
+ *
+ * Problem statement (Section 2, Eq. (1)): a state split into an outer block
+ * x (dimension dx) and an inner block z (dz) with observations y (dy),
+ *     x_{t+1} = f^x(x_t, z_t, v^x),  z_{t+1} = f^z(x_{t:t+1}, z_t, v^z),
+ *     y_t = h(x_t, z_t, e_t),
+ * with known parameters.  Following the factorisation Eq. (2), a filter
+ * keeps N outer particles x^{(i)}, each carrying a conditional particle
+ * filter of M inner particles z^{(i,j)} with normalised log-weights
+ * log qbar^{(i,j)} (eq:qbar).  One call advances every filter of a handle by
+ * one time step.
+ *
+ * Conventions for every function below:
+ *  - "d_" pointers are device memory of the GPU current when the handle was
+ *    created; "h_" or unprefixed pointers in dpf_config are host memory.
+ *  - The caller owns all device memory (workspace, inputs, outputs); the
+ *    library never allocates device memory.  Buffers must stay valid until
+ *    the work queued on the handle's stream has finished.
+ *  - All calls are asynchronous on the handle's HIP stream and return after
+ *    queueing.  Argument and launch errors return synchronously with a
+ *    non-zero dpf_status and a message from dpf_last_error(); conditions
+ *    that depend on the data never fail a call -- they set per-filter flag
+ *    bits (DPF_FLAG_*), readable with dpf_estimate.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - Floating point: particle state in FP32; normalisations, scans,
+ *    evidence and estimates accumulated in FP64.
+ *  - Random numbers: Philox4x32-10 keyed by (seed, filter index) with
+ *    counters (t, outer index, inner index, purpose); results are a pure
+ *    function of (config, observations) and reproducible bit for bit.
+ */
+#ifndef DPF_H
+#define DPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPF_ABI_VERSION 1u
+
+typedef struct dpf_handle dpf_handle; /* opaque; host memory; freed by dpf_destroy */
+
+typedef enum {
+  DPF_OK = 0,
+  DPF_EINVAL = 1,       /* bad argument (null pointer, size, mismatch)        */
+  DPF_ENOMEM = 2,       /* workspace too small                                */
+  DPF_EDEVICE = 3,      /* a HIP call failed (message names it)               */
+  DPF_ESTATE = 4,       /* call not valid for this handle (e.g. wrong algo)   */
+  DPF_EUNSUPPORTED = 5  /* model / dimensions / sizes not built into library  */
+} dpf_status;
+
+/* Models (parameter blob layouts; all values double, copied at create):
+ *
+ * DPF_MODEL_LINGAUSS -- linear-Gaussian, built for (dx,dz,dy) = (1,2,1):
+ *   Ax[dx*dx] Cxz[dx*dz] qx Az[dz*dz] Bzx[dz*dx] qz Hx[dy*dx] Hz[dy*dz] r
+ *   x' = Ax x + Cxz z + sqrt(qx) v ; z' = Az z + Bzx x' + sqrt(qz) w ;
+ *   y = Hx x + Hz z + sqrt(r) e.                      (row-major matrices)
+ * DPF_MODEL_NONLIN -- built for (dx,dz,dy) = (2,8,8):
+ *   a b qx W[dz*dx] rho qz c r bmode
+ *   x'_d = a x_d + b x_d/(1+x_d^2) + sqrt(qx) v_d ;
+ *   z' = tanh(W x') + rho z + sqrt(qz) w ;
+ *   y_k = z_k + c g_k(x) + sqrt(r) e_k, g_k = x_{k mod dx}^2 (bmode 0) or
+ *   |x|^2 (bmode 1).
+ * DPF_MODEL_HIGHDIM -- built for (dx,dz,dy) = (4,64,32):
+ *   a b qx Alo[dz-1] Adiag[dz] Aup[dz-1] B[dz*dx] qz C[dy*dz] r eps nu gonly
+ *   x' as NONLIN ; z' = A z + B sin(x') + sqrt(qz) w, A tridiagonal ;
+ *   y = C z + e, each e_k with density (1-eps) N(0,r) + eps t_nu(e/sqrt r)/sqrt r
+ *   (gonly != 0: plain N(0, r)).
+ * Every model has the prior [x_0; z_0] ~ N(0, I).
+ */
+typedef enum {
+  DPF_MODEL_LINGAUSS = 1,
+  DPF_MODEL_NONLIN = 2,
+  DPF_MODEL_HIGHDIM = 3
+} dpf_model;
+
+/* Which filter a handle runs. */
+typedef enum {
+  DPF_ALGO_LOOKAHEAD = 0, /* look-ahead DPF (Fig. 4); also the learned step */
+  DPF_ALGO_PLAIN = 1      /* DPF with prior proposals (Fig. 2)              */
+} dpf_algo;
+
+/* Per-filter flag bits (latched until dpf_reset / dpf_create). */
+#define DPF_FLAG_DEGENERATE_OUTER 1u /* no finite outer weight: uniform resampling used */
+#define DPF_FLAG_DEGENERATE_INNER 2u /* an inner cloud had no finite weight: uniform    */
+#define DPF_FLAG_NONFINITE 4u        /* NaN / +inf weight or non-finite observation     */
+#define DPF_FLAG_FALLBACK 8u         /* learned step fell back to the look-ahead step   */
+
+typedef struct {
+  uint32_t abi_version;  /* DPF_ABI_VERSION                                  */
+  int32_t model;         /* dpf_model                                        */
+  int32_t algo;          /* dpf_algo                                         */
+  int32_t dx, dz, dy;    /* must match a built (model, dims) combination     */
+  const double* params;  /* host, n_params values in the model's blob layout */
+  size_t n_params;
+  int32_t n_filters;     /* F >= 1 independent filters                       */
+  const int32_t* N;      /* host [F]: outer particles per filter, 1..65536   */
+  const int32_t* M;      /* host [F]: inner particles per filter, 1..4096    */
+  uint64_t seed;         /* Philox key; filter f uses key (seed, f)          */
+  uint32_t reserved;     /* must be 0                                        */
+} dpf_config;
+
+/* Bytes of device workspace a handle with this config needs (0 on error). */
+size_t dpf_workspace_bytes(const dpf_config* cfg);
+
+/* Validate cfg, carve d_workspace (>= dpf_workspace_bytes, 256-byte
+ * aligned), upload parameters and queue the initialisation (prior draws at
+ * t = 0, Fig. 2 / Fig. 4 "Initialize"; the plain DPF also proposes t = 1
+ * from the prior since no y_0 is observed).  hip_stream: hipStream_t or
+ * NULL for the default stream.  On success *out owns host state only. */
+dpf_status dpf_create(const dpf_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+                      dpf_handle** out);
+
+/* Queue the initialisation again (t = 0, flags and evidence cleared). */
+dpf_status dpf_reset(dpf_handle* h);
+
+/* Release host state (does not synchronise or free the workspace). */
+dpf_status dpf_destroy(dpf_handle* h);
+
+/* One look-ahead DPF step (Section 2.2, Fig. 4, steps 1-4) for every active
+ * filter, consuming y_t for its next t: look-ahead weights eq:weightsMC over
+ * each outer particle's inner cloud, systematic outer resampling at t-1,
+ * new x from the Monte Carlo optimal proposal eq:approx3 (SIR over the
+ * look-ahead candidates), x-conditioned local inner resampling eq:qnobar,
+ * inner propagation and the inner measurement update eq:qbar.
+ * d_y: [F][dy] float.  d_active: [F] bytes (0 = skip this filter) or NULL.
+ * Requires algo DPF_ALGO_LOOKAHEAD. */
+dpf_status dpf_lookahead_step(dpf_handle* h, const float* d_y, const uint8_t* d_active);
+
+/* One plain DPF step (Section 2, Fig. 2, steps 1-7, prior proposals of
+ * Section 2.1) consuming y_t: weights (eq:approx2), estimates, systematic
+ * outer resampling, x proposal from eq:approx1, eq:qnobar inner
+ * resampling and inner proposal.  Same arguments as dpf_lookahead_step.
+ * Requires algo DPF_ALGO_PLAIN. */
+dpf_status dpf_step(dpf_handle* h, const float* d_y, const uint8_t* d_active);
+
+/* Copy the estimates of each filter's last step (any pointer may be NULL):
+ * d_xmean [F][dx], d_zmean [F][dz] float (posterior means), d_ess [F] float
+ * (effective sample size of the outer weights used for resampling),
+ * d_loglik [F] double (cumulative log evidence, sum over steps of
+ * logsumexp_i log w_i - log N), d_flags [F] uint32 (DPF_FLAG_* bits). */
+dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean, float* d_ess,
+                        double* d_loglik, uint32_t* d_flags);
+
+/* Run up to T steps of the handle's algorithm over device-resident
+ * observations, each filter f stepping while its time is below
+ * min(T_f, T).  d_Y: [T][F][dy] float, row t-1 holding y_t of every filter
+ * (absolute time).  d_Tf: [F] int32 or NULL (all T).  d_xtrace [T][F][dx]
+ * and d_ztrace [T][F][dz] (or NULL) receive the per-step estimates at row
+ * t-1.  use_graph != 0 captures one step into a HIP graph once and replays
+ * it T times (the step's launches read every per-filter time and buffer
+ * choice from device memory, so replays need no host work). */
+dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_Tf,
+                   float* d_xtrace, float* d_ztrace, int32_t use_graph);
+
+/* State import / export (checkpoint, and step-level comparisons).  Layout,
+ * all little-endian: int32 t[F] padded to a multiple of 16 bytes, then
+ * float x[dx][sum N], float z[sum_f N_f*dz*M_f] (filter blocks in order,
+ * each [N][dz][M]), float lam[sum_f N_f*M_f] (log qbar, [N][M] per filter).
+ * For DPF_ALGO_PLAIN, x and z are the proposals for the next step and lam
+ * is unused.  Import resets the flags and the cumulative evidence. */
+size_t dpf_state_bytes(const dpf_handle* h);
+dpf_status dpf_export_state(dpf_handle* h, void* d_dst, size_t bytes);
+dpf_status dpf_import_state(dpf_handle* h, const void* d_src, size_t bytes);
+
+/* Internal buffers of the last step, copied out for inspection:
+ * DPF_BUF_ELL  float [sum N*M]: look-ahead (or measurement) log-weights ell
+ * DPF_BUF_LOGW float [sum N]:   outer log-weights log w_i
+ * DPF_BUF_ANC  int32 [sum N]:   outer ancestors A_k
+ * DPF_BUF_SEL  int32 [sum N]:   selected candidate (look-ahead) or
+ *                               inner ancestor a_k (plain) per new particle
+ * DPF_BUF_MOM  float [sum N][2 dz]: qbar-weighted mean and variance of each
+ *                               new inner cloud (look-ahead steps) */
+typedef enum {
+  DPF_BUF_ELL = 0,
+  DPF_BUF_LOGW = 1,
+  DPF_BUF_ANC = 2,
+  DPF_BUF_SEL = 3,
+  DPF_BUF_MOM = 4
+} dpf_buffer;
+dpf_status dpf_copy_buffer(dpf_handle* h, int32_t which, void* d_dst, size_t bytes);
+
+/* Phase timing.  hip_events: n_events hipEvent_t handles created by the
+ * caller (n_events a multiple of 5), or NULL / 0 to stop.  Each following
+ * step call (dpf_step, dpf_lookahead_step, and every step of dpf_run without
+ * a graph) records the next 5 events on the handle's stream: before the
+ * weight kernels, after them, after the outer resampling, after the
+ * new-cloud kernels and after the estimates, until the array is used up.
+ * Elapsed times between consecutive events give each phase's duration. */
+dpf_status dpf_set_phase_events(dpf_handle* h, void* const* hip_events, int32_t n_events);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* dpf_last_error(void);
+
+/* ---- kernel-level primitives (same device code as the step kernels) ---- */
+
+/* Philox4x32-10 words: d_ctr [n][4] uint32 counters -> d_out [n][4] words
+ * under key (seed_lo32, seed_hi32 ^ filter_id). */
+dpf_status dpf_philox_words(uint64_t seed, uint32_t filter_id, const uint32_t* d_ctr, size_t n,
+                            uint32_t* d_out, void* hip_stream);
+
+/* FP32 standard normals of the random-number contract: d_out [n_a][n_b][D]
+ * = normal d of counter (t, a, b, purpose) for a < n_a, b < n_b. */
+dpf_status dpf_normals(uint64_t seed, uint32_t filter_id, uint32_t t, uint32_t purpose, int32_t n_a,
+                       int32_t n_b, int32_t D, float* d_out, void* hip_stream);
+
+/* Systematic resampling of one weight vector by the outer-resampling code:
+ * d_w [n] non-negative doubles (not all zero), points ((k + u) C) / n_out,
+ * d_out[k] = first i with C_i > point (C = inclusive FP64 cumulative sum).
+ * d_scratch: n doubles of device memory (receives C). */
+dpf_status dpf_systematic(const double* d_w, int32_t n, int32_t n_out, double u, double* d_scratch,
+                          int32_t* d_out, void* hip_stream);
+
+/* The same rule per segment by the inner-resampling code: d_w [S][n]
+ * doubles, d_u [S], n_out = n (local resampling) or 1 (single draw);
+ * d_out [S][n_out].  n <= 4096. */
+dpf_status dpf_segmented_systematic(const double* d_w, int32_t S, int32_t n, int32_t n_out,
+                                    const double* d_u, int32_t* d_out, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPF_H */

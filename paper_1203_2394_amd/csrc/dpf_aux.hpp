@@ -1,0 +1,151 @@
+// Small service kernels: per-filter reset, activity mask for multi-step
+// runs, state export / import, and the kernel-level primitives exposed for
+// testing (raw Philox words, normals, systematic resampling) -- the latter
+// call the same device functions as the step kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dpf_kernels.hpp"
+
+namespace dpf {
+
+// t = 0, state in copy `start_copy`, flags and evidence cleared.
+__global__ void k_reset(int* tcur, unsigned char* cur, uint32_t* flags, double* loglik, int F,
+                        int start_copy) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  tcur[f] = 0;
+  cur[f] = (unsigned char)start_copy;
+  flags[f] = 0u;
+  loglik[f] = 0.0;
+}
+
+// Filter f steps while its time is below min(T_f, T).
+__global__ void k_active_mask(const int* tcur, const int* Tf, int T, unsigned char* active, int F) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  const int lim = Tf ? min(Tf[f], T) : T;
+  active[f] = (unsigned char)(tcur[f] < lim ? 1 : 0);
+}
+
+// Element e of an array of per-filter segments: find the filter by binary
+// search over the offsets (the arrays are sized by the host).
+__device__ __forceinline__ int filter_of(const long long* off, int F, long long e) {
+  int lo = 0, hi = F - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Export (dir = 0) or import (dir = 1) one per-particle array whose filter
+// blocks start at `off[f] * width` (width = elements per unit of off).
+__global__ void k_state_copy(float* ext, float* buf0, float* buf1, const unsigned char* cur,
+                             const long long* off, int F, long long n_units, int width, int dir) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_units * width) return;
+  const int f = filter_of(off, F, e / width);
+  float* buf = cur[f] ? buf1 : buf0;
+  if (dir == 0)
+    ext[e] = buf[e];
+  else
+    buf0[e] = ext[e];
+}
+
+// x is [DX][NT]: element e = d * NT + g, filter by g.
+__global__ void k_state_copy_x(float* ext, float* buf0, float* buf1, const unsigned char* cur,
+                               const long long* ooff64, int F, int NT, int DX, int dir) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)NT * DX) return;
+  const int f = filter_of(ooff64, F, e % NT);
+  float* buf = cur[f] ? buf1 : buf0;
+  if (dir == 0)
+    ext[e] = buf[e];
+  else
+    buf0[e] = ext[e];
+}
+
+// Export of the time header: t[f] for f < F, zeros in the padding up to n_words.
+__global__ void k_export_time(const int* tcur, int* ext_t, int F, int n_words) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_words) return;
+  ext_t[q] = q < F ? tcur[q] : 0;
+}
+
+__global__ void k_import_time(const int* ext_t, int* tcur, unsigned char* cur, uint32_t* flags,
+                              double* loglik, int F) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= F) return;
+  tcur[f] = ext_t[f];
+  cur[f] = 0;
+  flags[f] = 0u;
+  loglik[f] = 0.0;
+}
+
+// ---------------------------------------------------------------- primitives
+__global__ void k_philox_words(Key key, const uint32_t* ctr, long long n, uint32_t* out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const Words w = philox(key, ctr[4 * e], ctr[4 * e + 1], ctr[4 * e + 2], ctr[4 * e + 3]);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[4 * e + q] = w.w[q];
+}
+
+template <int D>
+__global__ void k_normals_grid(Key key, uint32_t t, uint32_t purpose, int na, int nb, float* out) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)na * nb) return;
+  const int a = (int)(e / nb), b = (int)(e % nb);
+  float v[D];
+  normals<D>(key, t, (uint32_t)a, (uint32_t)b, purpose, v);
+#pragma unroll
+  for (int d = 0; d < D; ++d) out[e * D + d] = v[d];
+}
+
+__global__ __launch_bounds__(kResBlock) void k_systematic_prim(const double* w, int n, int n_out,
+                                                                double u, double* C, int* out) {
+  __shared__ ResScratch sh;
+  for (int i = threadIdx.x; i < n; i += kResBlock) C[i] = w[i];
+  __syncthreads();
+  block_scan_inplace(C, n, sh);
+  block_systematic(C, n, n_out, u, out);
+}
+
+// One segment per (S index); the cdf build and search are those of k_newcloud.
+template <int SEG, int JPT>
+__global__ __launch_bounds__(kBlock) void k_seg_systematic_prim(const double* w, int S, int n,
+                                                                 int n_out, const double* u,
+                                                                 int* out) {
+  constexpr int NSEG = kBlock / SEG;
+  __shared__ SegScratch sh;
+  __shared__ double cdf[NSEG][SEG * JPT];
+  const int s = threadIdx.x / SEG;
+  const int ls = threadIdx.x % SEG;
+  const int g = blockIdx.x * NSEG + s;
+  const bool vg = g < S;
+  double carry = 0.0;
+#pragma unroll
+  for (int r = 0; r < JPT; ++r) {
+    const int j = ls + r * SEG;
+    const double wj = (vg && j < n) ? w[(long long)g * n + j] : 0.0;
+    double tot;
+    const double c = seg_scan_incl<SEG>(wj, sh, tot);
+    cdf[s][r * SEG + ls] = carry + c;
+    carry += tot;
+  }
+  __syncthreads();
+  if (!vg) return;
+  const double uu = u[g];
+  const double total = cdf[s][n - 1];
+  for (int r = 0; r < JPT; ++r) {
+    const int k = ls + r * SEG;
+    if (k < n_out) out[(long long)g * n_out + k] = cdf_search(cdf[s], n, sys_point(k, uu, total, n_out));
+  }
+}
+
+}  // namespace dpf

@@ -1,0 +1,757 @@
+// Host side of libdpf.so: the C interface of include/dpf.h.
+//
+// A handle owns host state only.  dpf_create validates the config, carves
+// the caller's device workspace into the buffers of the step kernels,
+// uploads the parameters (converted to FP32 plus derived constants computed
+// in FP64), builds the tile lists and queues the initialisation.  Each step
+// call queues a fixed sequence of launches on the handle's stream; nothing
+// synchronises with the host.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dpf.h"
+#include "dpf_aux.hpp"
+#include "dpf_kernels.hpp"
+
+using namespace dpf;
+
+static thread_local std::string g_err;
+
+static dpf_status fail(dpf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(DPF_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_CHECK(what)                                                                 \
+  do {                                                                                     \
+    hipError_t e_ = hipGetLastError();                                                     \
+    if (e_ != hipSuccess) return fail(DPF_EDEVICE, "launch of %s failed: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" const char* dpf_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------ tile classes
+struct ClassShape {
+  int seg, jpt;
+};
+static const ClassShape kClasses[] = {{32, 1}, {64, 1}, {128, 1}, {256, 1}, {256, 4}, {256, 16}};
+constexpr int kNumClasses = 6;
+
+static int class_of(int M) {
+  for (int c = 0; c < kNumClasses; ++c)
+    if (M <= kClasses[c].seg * kClasses[c].jpt) return c;
+  return -1;
+}
+
+struct TileClass {
+  int cls;
+  int n_tiles;
+  int2* d_tiles;
+};
+
+// ------------------------------------------------------------ model engines
+struct Engine {
+  int dx, dz, dy;
+  size_t n_raw;
+  size_t n_total;
+  void (*derive)(const double* raw, std::vector<float>& out);
+  dpf_status (*launch)(int op, const StepArgs& a, const TileClass& tc, hipStream_t s);
+};
+
+enum Op { OP_INIT_LA, OP_INIT_PLAIN, OP_LA_WEIGHTS, OP_DPF_WEIGHTS, OP_NEWCLOUD_LA, OP_NEWCLOUD_PLAIN };
+
+template <class Mdl, int SEG, int JPT>
+static void launch_op(int op, const StepArgs& a, int n, hipStream_t s) {
+  switch (op) {
+    case OP_INIT_LA:
+      hipLaunchKernelGGL((k_init<Mdl, SEG, JPT, false>), dim3(n), dim3(kBlock), 0, s, a);
+      break;
+    case OP_INIT_PLAIN:
+      hipLaunchKernelGGL((k_init<Mdl, SEG, JPT, true>), dim3(n), dim3(kBlock), 0, s, a);
+      break;
+    case OP_LA_WEIGHTS:
+      hipLaunchKernelGGL((k_la_weights<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
+      break;
+    case OP_DPF_WEIGHTS:
+      hipLaunchKernelGGL((k_dpf_weights<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
+      break;
+    case OP_NEWCLOUD_LA:
+      hipLaunchKernelGGL((k_newcloud<Mdl, SEG, JPT, false>), dim3(n), dim3(kBlock), 0, s, a);
+      break;
+    case OP_NEWCLOUD_PLAIN:
+      hipLaunchKernelGGL((k_newcloud<Mdl, SEG, JPT, true>), dim3(n), dim3(kBlock), 0, s, a);
+      break;
+  }
+}
+
+template <class Mdl>
+static dpf_status engine_launch(int op, const StepArgs& a, const TileClass& tc, hipStream_t s) {
+  const int n = tc.n_tiles;
+  switch (tc.cls) {
+    case 0: launch_op<Mdl, 32, 1>(op, a, n, s); break;
+    case 1: launch_op<Mdl, 64, 1>(op, a, n, s); break;
+    case 2: launch_op<Mdl, 128, 1>(op, a, n, s); break;
+    case 3: launch_op<Mdl, 256, 1>(op, a, n, s); break;
+    case 4: launch_op<Mdl, 256, 4>(op, a, n, s); break;
+    case 5: launch_op<Mdl, 256, 16>(op, a, n, s); break;
+    default: return fail(DPF_EUNSUPPORTED, "no kernel class %d", tc.cls);
+  }
+  LAUNCH_CHECK("step kernel");
+  return DPF_OK;
+}
+
+// Derived constants (computed in double, stored as float after the raw values).
+static void derive_lingauss(int dx, int dz, int dy, const double* p, std::vector<float>& o) {
+  const size_t iqx = dx * dx + dx * dz, iqz = iqx + 1 + dz * dz + dz * dx,
+               ir = iqz + 1 + dy * dx + dy * dz;
+  const double qx = p[iqx], qz = p[iqz], r = p[ir];
+  o.push_back((float)sqrt(qx));
+  o.push_back((float)sqrt(qz));
+  o.push_back((float)(1.0 / qx));
+  o.push_back((float)(1.0 / r));
+  o.push_back((float)(-0.5 * dx * log(2.0 * M_PI * qx)));
+  o.push_back((float)(-0.5 * dy * log(2.0 * M_PI * r)));
+}
+
+static void derive_nonlin(int dx, int dz, const double* p, std::vector<float>& o) {
+  const double qx = p[2];
+  const size_t irho = 3 + (size_t)dz * dx;
+  const double qz = p[irho + 1], r = p[irho + 3];
+  o.push_back((float)sqrt(qx));
+  o.push_back((float)sqrt(qz));
+  o.push_back((float)(1.0 / qx));
+  o.push_back((float)(1.0 / r));
+  o.push_back((float)(-0.5 * dx * log(2.0 * M_PI * qx)));
+  o.push_back((float)(-0.5 * dz * log(2.0 * M_PI * r)));
+}
+
+static void derive_highdim(int dx, int dz, int dy, const double* p, std::vector<float>& o) {
+  const double qx = p[2];
+  const size_t iqz = 3 + (size_t)(dz - 1) + dz + (dz - 1) + (size_t)dz * dx;
+  const double qz = p[iqz];
+  const size_t ir = iqz + 1 + (size_t)dy * dz;
+  const double r = p[ir], eps = p[ir + 1], nu = p[ir + 2];
+  o.push_back((float)sqrt(qx));                                  // sx
+  o.push_back((float)sqrt(qz));                                  // sz
+  o.push_back((float)(1.0 / qx));                                // inv_qx
+  o.push_back((float)(-0.5 * dx * log(2.0 * M_PI * qx)));        // cx
+  o.push_back((float)(1.0 / r));                                 // inv_r
+  o.push_back((float)(-0.5 * dy * log(2.0 * M_PI * r)));         // cy
+  o.push_back((float)(log1p(-eps) - 0.5 * log(2.0 * M_PI * r))); // lg0
+  o.push_back((float)(log(eps) + lgamma(0.5 * (nu + 1.0)) - lgamma(0.5 * nu) -
+                      0.5 * log(nu * M_PI * r)));                // lt0
+  o.push_back((float)(0.5 * (nu + 1.0)));                        // tnu
+  o.push_back((float)(1.0 / (nu * r)));                          // inv_nur
+}
+
+using MLG = LinGauss<1, 2, 1>;
+using MNL = NonLin<2, 8>;
+using MHD = HighDim<4, 64, 32>;
+
+static const Engine kEngines[] = {
+    {1, 2, 1, (size_t)MLG::L::n_raw, (size_t)MLG::L::n_total,
+     [](const double* p, std::vector<float>& o) { derive_lingauss(1, 2, 1, p, o); },
+     engine_launch<MLG>},
+    {2, 8, 8, (size_t)MNL::L::n_raw, (size_t)MNL::L::n_total,
+     [](const double* p, std::vector<float>& o) { derive_nonlin(2, 8, p, o); }, engine_launch<MNL>},
+    {4, 64, 32, (size_t)MHD::L::n_raw, (size_t)MHD::L::n_total,
+     [](const double* p, std::vector<float>& o) { derive_highdim(4, 64, 32, p, o); },
+     engine_launch<MHD>},
+};
+
+static const Engine* find_engine(int model, int dx, int dz, int dy) {
+  int idx = -1;
+  if (model == DPF_MODEL_LINGAUSS) idx = 0;
+  if (model == DPF_MODEL_NONLIN) idx = 1;
+  if (model == DPF_MODEL_HIGHDIM) idx = 2;
+  if (idx < 0) return nullptr;
+  const Engine* e = &kEngines[idx];
+  if (e->dx != dx || e->dz != dz || e->dy != dy) return nullptr;
+  return e;
+}
+
+// ---------------------------------------------------------------- layout
+struct Layout {
+  size_t total = 0;
+  size_t prm, fN, fM, ooff, ooff64, ioff, tcur, cur, active, tiles, x0, x1, z0, z1, l0, l1, ell,
+      logw, anc, sel, kpart, mom, cdf, fstat, ess, dlogz, loglik, flags, est_x, est_z;
+  std::vector<size_t> tile_off;  // per class (in int2 units from `tiles`)
+  std::vector<int> tile_n;
+  int NT = 0;
+  long long NMT = 0;
+};
+
+static size_t carve(size_t& cursor, size_t bytes) {
+  const size_t off = cursor;
+  cursor += (bytes + 255) & ~(size_t)255;
+  return off;
+}
+
+static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
+  if (!c) return fail(DPF_EINVAL, "config is NULL");
+  if (c->abi_version != DPF_ABI_VERSION)
+    return fail(DPF_EINVAL, "abi_version %u, library is %u", c->abi_version, DPF_ABI_VERSION);
+  if (c->reserved != 0) return fail(DPF_EINVAL, "reserved field must be 0");
+  if (c->algo != DPF_ALGO_LOOKAHEAD && c->algo != DPF_ALGO_PLAIN)
+    return fail(DPF_EINVAL, "unknown algo %d", c->algo);
+  eng = find_engine(c->model, c->dx, c->dz, c->dy);
+  if (!eng)
+    return fail(DPF_EUNSUPPORTED, "model %d with dims (%d,%d,%d) is not built", c->model, c->dx, c->dz,
+                c->dy);
+  if (!c->params || c->n_params != eng->n_raw)
+    return fail(DPF_EINVAL, "model %d needs %zu parameters, got %zu", c->model, eng->n_raw, c->n_params);
+  if (c->n_filters < 1 || !c->N || !c->M) return fail(DPF_EINVAL, "need n_filters >= 1 and N, M arrays");
+  const int F = c->n_filters;
+  L.NT = 0;
+  L.NMT = 0;
+  L.tile_n.assign(kNumClasses, 0);
+  for (int f = 0; f < F; ++f) {
+    if (c->N[f] < 1 || c->N[f] > 65536) return fail(DPF_EUNSUPPORTED, "N[%d] = %d outside 1..65536", f, c->N[f]);
+    const int cls = class_of(c->M[f]);
+    if (c->M[f] < 1 || cls < 0) return fail(DPF_EUNSUPPORTED, "M[%d] = %d outside 1..4096", f, c->M[f]);
+    if ((long long)L.NT + c->N[f] > 0x7fffffffLL) return fail(DPF_EUNSUPPORTED, "total N too large");
+    L.NT += c->N[f];
+    L.NMT += (long long)c->N[f] * c->M[f];
+    const int segs = kBlock / kClasses[cls].seg;
+    L.tile_n[cls] += (c->N[f] + segs - 1) / segs;
+  }
+  const int dx = c->dx, dz = c->dz;
+  const size_t NT = L.NT, NMT = (size_t)L.NMT;
+  size_t cur = 0;
+  L.prm = carve(cur, eng->n_total * 4);
+  L.fN = carve(cur, F * 4);
+  L.fM = carve(cur, F * 4);
+  L.ooff = carve(cur, (F + 1) * 4);
+  L.ooff64 = carve(cur, (F + 1) * 8);
+  L.ioff = carve(cur, (F + 1) * 8);
+  L.tcur = carve(cur, F * 4);
+  L.cur = carve(cur, F);
+  L.active = carve(cur, F);
+  size_t ntiles = 0;
+  L.tile_off.assign(kNumClasses, 0);
+  for (int k = 0; k < kNumClasses; ++k) {
+    L.tile_off[k] = ntiles;
+    ntiles += L.tile_n[k];
+  }
+  L.tiles = carve(cur, ntiles * sizeof(int2));
+  L.x0 = carve(cur, NT * dx * 4);
+  L.x1 = carve(cur, NT * dx * 4);
+  L.z0 = carve(cur, NMT * dz * 4);
+  L.z1 = carve(cur, NMT * dz * 4);
+  L.l0 = carve(cur, NMT * 4);
+  L.l1 = carve(cur, NMT * 4);
+  L.ell = carve(cur, NMT * 4);
+  L.logw = carve(cur, NT * 4);
+  L.anc = carve(cur, NT * 4);
+  L.sel = carve(cur, NT * 4);
+  L.kpart = carve(cur, NT * dz * 4);
+  L.mom = carve(cur, NT * 2 * dz * 4);
+  L.cdf = carve(cur, NT * 8);
+  L.fstat = carve(cur, F * 4 * 8);
+  L.ess = carve(cur, F * 4);
+  L.dlogz = carve(cur, F * 8);
+  L.loglik = carve(cur, F * 8);
+  L.flags = carve(cur, F * 4);
+  L.est_x = carve(cur, F * dx * 4);
+  L.est_z = carve(cur, F * dz * 4);
+  L.total = cur;
+  return DPF_OK;
+}
+
+// ---------------------------------------------------------------- handle
+struct dpf_handle {
+  const Engine* eng;
+  int model, algo, dx, dz, dy, F;
+  uint64_t seed;
+  hipStream_t stream;
+  Layout L;
+  char* ws;
+  std::vector<int> N, M, ooff;
+  std::vector<long long> ioff, ooff64;
+  std::vector<int2> tiles_h;
+  std::vector<float> prm_h;
+  std::vector<TileClass> classes;
+  // multi-step graph cache
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void* g_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int g_T = -1;
+  // phase timing: caller-owned events consumed kPhaseEvents per step
+  std::vector<hipEvent_t> prof_events;
+  size_t prof_next = 0;
+};
+
+constexpr int kPhaseEvents = 5;
+
+static void phase_mark(dpf_handle* h, int phase) {
+  if (h->prof_next + (size_t)(kPhaseEvents - phase) > h->prof_events.size()) return;
+  (void)hipEventRecord(h->prof_events[h->prof_next], h->stream);
+  h->prof_next++;
+}
+
+template <class T>
+static T* at(dpf_handle* h, size_t off) {
+  return reinterpret_cast<T*>(h->ws + off);
+}
+
+static StepArgs make_args(dpf_handle* h) {
+  StepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.prm = at<float>(h, h->L.prm);
+  a.tiles = nullptr;
+  a.fN = at<int>(h, h->L.fN);
+  a.fM = at<int>(h, h->L.fM);
+  a.ooff = at<int>(h, h->L.ooff);
+  a.ioff = at<long long>(h, h->L.ioff);
+  a.NT = h->L.NT;
+  a.t_offset = 1;
+  a.seed = h->seed;
+  a.tcur = at<int>(h, h->L.tcur);
+  a.cur = at<unsigned char>(h, h->L.cur);
+  a.active = nullptr;
+  a.x[0] = at<float>(h, h->L.x0);
+  a.x[1] = at<float>(h, h->L.x1);
+  a.z[0] = at<float>(h, h->L.z0);
+  a.z[1] = at<float>(h, h->L.z1);
+  a.lam[0] = at<float>(h, h->L.l0);
+  a.lam[1] = at<float>(h, h->L.l1);
+  a.ell = at<float>(h, h->L.ell);
+  a.logw = at<float>(h, h->L.logw);
+  a.anc = at<int>(h, h->L.anc);
+  a.sel = at<int>(h, h->L.sel);
+  a.kpart = at<float>(h, h->L.kpart);
+  a.mom = at<float>(h, h->L.mom);
+  a.cdf = at<double>(h, h->L.cdf);
+  a.fstat = at<double>(h, h->L.fstat);
+  a.ess = at<float>(h, h->L.ess);
+  a.dlogz = at<double>(h, h->L.dlogz);
+  a.loglik = at<double>(h, h->L.loglik);
+  a.flags = at<uint32_t>(h, h->L.flags);
+  a.est_x = at<float>(h, h->L.est_x);
+  a.est_z = at<float>(h, h->L.est_z);
+  a.n_filters = h->F;
+  a.dy = h->dy;
+  return a;
+}
+
+static dpf_status launch_classes(dpf_handle* h, int op, StepArgs a) {
+  for (const TileClass& tc : h->classes) {
+    a.tiles = tc.d_tiles;
+    dpf_status s = h->eng->launch(op, a, tc, h->stream);
+    if (s != DPF_OK) return s;
+  }
+  return DPF_OK;
+}
+
+static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a, bool plain, int advance) {
+  const int F = h->F;
+#define FIN(DX, DZ)                                                                                  \
+  if (h->dx == DX && h->dz == DZ) {                                                                  \
+    if (plain)                                                                                       \
+      hipLaunchKernelGGL((k_finalize<DX, DZ, true>), dim3(F), dim3(kBlock), 0, h->stream, a, advance); \
+    else                                                                                             \
+      hipLaunchKernelGGL((k_finalize<DX, DZ, false>), dim3(F), dim3(kBlock), 0, h->stream, a, advance); \
+    LAUNCH_CHECK("k_finalize");                                                                      \
+    return DPF_OK;                                                                                   \
+  }
+  FIN(1, 2)
+  FIN(2, 8)
+  FIN(4, 64)
+#undef FIN
+  return fail(DPF_EUNSUPPORTED, "no finalize kernel for dims (%d,%d)", h->dx, h->dz);
+}
+
+static dpf_status queue_init(dpf_handle* h) {
+  const bool plain = h->algo == DPF_ALGO_PLAIN;
+  hipLaunchKernelGGL(k_reset, dim3((h->F + 255) / 256), dim3(256), 0, h->stream, at<int>(h, h->L.tcur),
+                     at<unsigned char>(h, h->L.cur), at<uint32_t>(h, h->L.flags),
+                     at<double>(h, h->L.loglik), h->F, plain ? 1 : 0);
+  LAUNCH_CHECK("k_reset");
+  StepArgs a = make_args(h);
+  a.t_offset = 0;
+  dpf_status s = launch_classes(h, plain ? OP_INIT_PLAIN : OP_INIT_LA, a);
+  if (s != DPF_OK) return s;
+  if (plain) {
+    s = launch_classes(h, OP_NEWCLOUD_PLAIN, a);
+    if (s != DPF_OK) return s;
+    s = launch_finalize(h, a, true, 0);
+    if (s != DPF_OK) return s;
+  }
+  return DPF_OK;
+}
+
+extern "C" size_t dpf_workspace_bytes(const dpf_config* cfg) {
+  const Engine* eng;
+  Layout L;
+  if (plan(cfg, eng, L) != DPF_OK) return 0;
+  return L.total;
+}
+
+extern "C" dpf_status dpf_create(const dpf_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+                                 dpf_handle** out) {
+  if (!out) return fail(DPF_EINVAL, "out is NULL");
+  *out = nullptr;
+  const Engine* eng;
+  Layout L;
+  dpf_status st = plan(cfg, eng, L);
+  if (st != DPF_OK) return st;
+  if (!d_workspace) return fail(DPF_EINVAL, "workspace is NULL");
+  if (((uintptr_t)d_workspace & 255) != 0) return fail(DPF_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < L.total) return fail(DPF_ENOMEM, "workspace has %zu bytes, needs %zu", bytes, L.total);
+
+  dpf_handle* h = new dpf_handle();
+  h->eng = eng;
+  h->model = cfg->model;
+  h->algo = cfg->algo;
+  h->dx = cfg->dx;
+  h->dz = cfg->dz;
+  h->dy = cfg->dy;
+  h->F = cfg->n_filters;
+  h->seed = cfg->seed;
+  h->stream = (hipStream_t)hip_stream;
+  h->L = L;
+  h->ws = (char*)d_workspace;
+  const int F = h->F;
+  h->N.assign(cfg->N, cfg->N + F);
+  h->M.assign(cfg->M, cfg->M + F);
+  h->ooff.assign(F + 1, 0);
+  h->ooff64.assign(F + 1, 0);
+  h->ioff.assign(F + 1, 0);
+  for (int f = 0; f < F; ++f) {
+    h->ooff[f + 1] = h->ooff[f] + h->N[f];
+    h->ooff64[f + 1] = h->ooff[f + 1];
+    h->ioff[f + 1] = h->ioff[f] + (long long)h->N[f] * h->M[f];
+  }
+  // parameters: raw values as float, then derived constants
+  h->prm_h.reserve(eng->n_total);
+  for (size_t q = 0; q < cfg->n_params; ++q) h->prm_h.push_back((float)cfg->params[q]);
+  eng->derive(cfg->params, h->prm_h);
+  if (h->prm_h.size() != eng->n_total) {
+    delete h;
+    return fail(DPF_EINVAL, "internal: parameter layout mismatch");
+  }
+  // tiles grouped by class
+  size_t ntiles = 0;
+  for (int k = 0; k < kNumClasses; ++k) ntiles += L.tile_n[k];
+  h->tiles_h.assign(ntiles, make_int2(0, 0));
+  std::vector<size_t> fill(L.tile_off);
+  for (int f = 0; f < F; ++f) {
+    const int cls = class_of(h->M[f]);
+    const int segs = kBlock / kClasses[cls].seg;
+    for (int i0 = 0; i0 < h->N[f]; i0 += segs) h->tiles_h[fill[cls]++] = make_int2(f, i0);
+  }
+  for (int k = 0; k < kNumClasses; ++k) {
+    if (L.tile_n[k] == 0) continue;
+    TileClass tc;
+    tc.cls = k;
+    tc.n_tiles = L.tile_n[k];
+    tc.d_tiles = at<int2>(h, L.tiles) + L.tile_off[k];
+    h->classes.push_back(tc);
+  }
+  hipError_t e = hipSuccess;
+#define UP(off, vec)                                                                                   \
+  if (e == hipSuccess && !(vec).empty())                                                               \
+    e = hipMemcpyAsync(h->ws + (off), (vec).data(), (vec).size() * sizeof((vec)[0]), hipMemcpyHostToDevice, \
+                       h->stream);
+  UP(L.prm, h->prm_h)
+  UP(L.fN, h->N)
+  UP(L.fM, h->M)
+  UP(L.ooff, h->ooff)
+  UP(L.ooff64, h->ooff64)
+  UP(L.ioff, h->ioff)
+  UP(L.tiles, h->tiles_h)
+#undef UP
+  if (e != hipSuccess) {
+    delete h;
+    return fail(DPF_EDEVICE, "parameter upload failed: %s", hipGetErrorString(e));
+  }
+  st = queue_init(h);
+  if (st != DPF_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_reset(dpf_handle* h) {
+  if (!h) return fail(DPF_EINVAL, "handle is NULL");
+  return queue_init(h);
+}
+
+extern "C" dpf_status dpf_destroy(dpf_handle* h) {
+  if (!h) return DPF_OK;
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  delete h;
+  return DPF_OK;
+}
+
+static dpf_status queue_step(dpf_handle* h, const float* Y, long long y_tstride, const unsigned char* active,
+                             float* trace_x, float* trace_z) {
+  StepArgs a = make_args(h);
+  a.Y = Y;
+  a.y_tstride = y_tstride;
+  a.active = active;
+  a.trace_x = trace_x;
+  a.trace_z = trace_z;
+  a.t_offset = 1;
+  const bool plain = h->algo == DPF_ALGO_PLAIN;
+  phase_mark(h, 0);
+  dpf_status s = launch_classes(h, plain ? OP_DPF_WEIGHTS : OP_LA_WEIGHTS, a);
+  if (s != DPF_OK) return s;
+  phase_mark(h, 1);
+  hipLaunchKernelGGL(k_outer_resample, dim3(h->F), dim3(kResBlock), 0, h->stream, a);
+  LAUNCH_CHECK("k_outer_resample");
+  phase_mark(h, 2);
+  s = launch_classes(h, plain ? OP_NEWCLOUD_PLAIN : OP_NEWCLOUD_LA, a);
+  if (s != DPF_OK) return s;
+  phase_mark(h, 3);
+  s = launch_finalize(h, a, plain, 1);
+  phase_mark(h, 4);
+  return s;
+}
+
+extern "C" dpf_status dpf_set_phase_events(dpf_handle* h, void* const* hip_events, int32_t n_events) {
+  if (!h) return fail(DPF_EINVAL, "handle is NULL");
+  if (n_events < 0 || (n_events > 0 && !hip_events)) return fail(DPF_EINVAL, "bad event array");
+  if (n_events % kPhaseEvents) return fail(DPF_EINVAL, "n_events must be a multiple of %d", kPhaseEvents);
+  h->prof_events.assign((hipEvent_t*)hip_events, (hipEvent_t*)hip_events + n_events);
+  h->prof_next = 0;
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_lookahead_step(dpf_handle* h, const float* d_y, const uint8_t* d_active) {
+  if (!h || !d_y) return fail(DPF_EINVAL, "handle and d_y are required");
+  if (h->algo != DPF_ALGO_LOOKAHEAD) return fail(DPF_ESTATE, "handle was created for the plain DPF");
+  return queue_step(h, d_y, 0, d_active, nullptr, nullptr);
+}
+
+extern "C" dpf_status dpf_step(dpf_handle* h, const float* d_y, const uint8_t* d_active) {
+  if (!h || !d_y) return fail(DPF_EINVAL, "handle and d_y are required");
+  if (h->algo != DPF_ALGO_PLAIN) return fail(DPF_ESTATE, "handle was created for the look-ahead DPF");
+  return queue_step(h, d_y, 0, d_active, nullptr, nullptr);
+}
+
+extern "C" dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean, float* d_ess,
+                                   double* d_loglik, uint32_t* d_flags) {
+  if (!h) return fail(DPF_EINVAL, "handle is NULL");
+  const int F = h->F;
+  if (d_xmean)
+    HIP_TRY(hipMemcpyAsync(d_xmean, h->ws + h->L.est_x, (size_t)F * h->dx * 4, hipMemcpyDeviceToDevice, h->stream));
+  if (d_zmean)
+    HIP_TRY(hipMemcpyAsync(d_zmean, h->ws + h->L.est_z, (size_t)F * h->dz * 4, hipMemcpyDeviceToDevice, h->stream));
+  if (d_ess) HIP_TRY(hipMemcpyAsync(d_ess, h->ws + h->L.ess, (size_t)F * 4, hipMemcpyDeviceToDevice, h->stream));
+  if (d_loglik)
+    HIP_TRY(hipMemcpyAsync(d_loglik, h->ws + h->L.loglik, (size_t)F * 8, hipMemcpyDeviceToDevice, h->stream));
+  if (d_flags)
+    HIP_TRY(hipMemcpyAsync(d_flags, h->ws + h->L.flags, (size_t)F * 4, hipMemcpyDeviceToDevice, h->stream));
+  return DPF_OK;
+}
+
+static dpf_status queue_run_step(dpf_handle* h, const float* d_Y, int T, const int32_t* d_Tf, float* xt,
+                                 float* zt) {
+  unsigned char* act = at<unsigned char>(h, h->L.active);
+  hipLaunchKernelGGL(k_active_mask, dim3((h->F + 255) / 256), dim3(256), 0, h->stream, at<int>(h, h->L.tcur),
+                     (const int*)d_Tf, T, act, h->F);
+  LAUNCH_CHECK("k_active_mask");
+  return queue_step(h, d_Y, (long long)h->F * h->dy, act, xt, zt);
+}
+
+extern "C" dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_Tf, float* d_xtrace,
+                              float* d_ztrace, int32_t use_graph) {
+  if (!h || !d_Y) return fail(DPF_EINVAL, "handle and d_Y are required");
+  if (T < 0) return fail(DPF_EINVAL, "T = %d", T);
+  if (T == 0) return DPF_OK;
+  if (!use_graph) {
+    for (int s = 0; s < T; ++s) {
+      dpf_status st = queue_run_step(h, d_Y, T, d_Tf, d_xtrace, d_ztrace);
+      if (st != DPF_OK) return st;
+    }
+    return DPF_OK;
+  }
+  const void* key[5] = {d_Y, d_Tf, d_xtrace, d_ztrace, (const void*)h->stream};
+  const bool cached = h->gexec && h->g_T == T && memcmp(key, h->g_key, sizeof(key)) == 0;
+  if (!cached) {
+    if (h->gexec) {
+      (void)hipGraphExecDestroy(h->gexec);
+      h->gexec = nullptr;
+    }
+    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    hipStream_t user = h->stream;
+    h->stream = h->cap_stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    dpf_status st = DPF_OK;
+    if (e == hipSuccess) st = queue_run_step(h, d_Y, T, d_Tf, d_xtrace, d_ztrace);
+    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+    h->stream = user;
+    if (e != hipSuccess) return fail(DPF_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    if (st != DPF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e2 != hipSuccess) return fail(DPF_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      h->gexec = nullptr;
+      return fail(DPF_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    memcpy(h->g_key, key, sizeof(key));
+    h->g_T = T;
+  }
+  for (int s = 0; s < T; ++s) HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
+  return DPF_OK;
+}
+
+// ---------------------------------------------------------------- state I/O
+static size_t state_time_bytes(int F) { return ((size_t)F * 4 + 15) & ~(size_t)15; }
+
+extern "C" size_t dpf_state_bytes(const dpf_handle* h) {
+  if (!h) return 0;
+  return state_time_bytes(h->F) + (size_t)h->L.NT * h->dx * 4 + (size_t)h->L.NMT * h->dz * 4 +
+         (size_t)h->L.NMT * 4;
+}
+
+static dpf_status state_io(dpf_handle* h, char* ext, int dir) {
+  const int F = h->F;
+  const size_t tb = state_time_bytes(F);
+  float* ex = (float*)(ext + tb);
+  float* ez = ex + (size_t)h->L.NT * h->dx;
+  float* el = ez + (size_t)h->L.NMT * h->dz;
+  const unsigned char* cur = at<unsigned char>(h, h->L.cur);
+  const long long* ioff = at<long long>(h, h->L.ioff);
+  const long long* oo64 = at<long long>(h, h->L.ooff64);
+  const int B = 256;
+  const long long nx = (long long)h->L.NT * h->dx, nz = h->L.NMT * h->dz, nl = h->L.NMT;
+  if (dir == 0) {
+    const int words = (int)(tb / 4);
+    hipLaunchKernelGGL(k_export_time, dim3((words + 255) / 256), dim3(256), 0, h->stream, at<int>(h, h->L.tcur),
+                       (int*)ext, F, words);
+    LAUNCH_CHECK("k_export_time");
+  }
+  hipLaunchKernelGGL(k_state_copy_x, dim3((unsigned)((nx + B - 1) / B)), dim3(B), 0, h->stream, ex,
+                     at<float>(h, h->L.x0), at<float>(h, h->L.x1), cur, oo64, F, h->L.NT, h->dx, dir);
+  hipLaunchKernelGGL(k_state_copy, dim3((unsigned)((nz + B - 1) / B)), dim3(B), 0, h->stream, ez,
+                     at<float>(h, h->L.z0), at<float>(h, h->L.z1), cur, ioff, F, h->L.NMT, h->dz, dir);
+  hipLaunchKernelGGL(k_state_copy, dim3((unsigned)((nl + B - 1) / B)), dim3(B), 0, h->stream, el,
+                     at<float>(h, h->L.l0), at<float>(h, h->L.l1), cur, ioff, F, h->L.NMT, 1, dir);
+  LAUNCH_CHECK("state copy");
+  if (dir == 1) {
+    hipLaunchKernelGGL(k_import_time, dim3((F + 255) / 256), dim3(256), 0, h->stream, (const int*)ext,
+                       at<int>(h, h->L.tcur), at<unsigned char>(h, h->L.cur), at<uint32_t>(h, h->L.flags),
+                       at<double>(h, h->L.loglik), F);
+    LAUNCH_CHECK("k_import_time");
+  }
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_export_state(dpf_handle* h, void* d_dst, size_t bytes) {
+  if (!h || !d_dst) return fail(DPF_EINVAL, "handle and destination are required");
+  if (bytes < dpf_state_bytes(h)) return fail(DPF_EINVAL, "state needs %zu bytes", dpf_state_bytes(h));
+  return state_io(h, (char*)d_dst, 0);
+}
+
+extern "C" dpf_status dpf_import_state(dpf_handle* h, const void* d_src, size_t bytes) {
+  if (!h || !d_src) return fail(DPF_EINVAL, "handle and source are required");
+  if (bytes < dpf_state_bytes(h)) return fail(DPF_EINVAL, "state needs %zu bytes", dpf_state_bytes(h));
+  return state_io(h, (char*)d_src, 1);
+}
+
+extern "C" dpf_status dpf_copy_buffer(dpf_handle* h, int32_t which, void* d_dst, size_t bytes) {
+  if (!h || !d_dst) return fail(DPF_EINVAL, "handle and destination are required");
+  size_t off = 0, need = 0;
+  switch (which) {
+    case DPF_BUF_ELL: off = h->L.ell; need = (size_t)h->L.NMT * 4; break;
+    case DPF_BUF_LOGW: off = h->L.logw; need = (size_t)h->L.NT * 4; break;
+    case DPF_BUF_ANC: off = h->L.anc; need = (size_t)h->L.NT * 4; break;
+    case DPF_BUF_SEL: off = h->L.sel; need = (size_t)h->L.NT * 4; break;
+    case DPF_BUF_MOM: off = h->L.mom; need = (size_t)h->L.NT * 2 * h->dz * 4; break;
+    default: return fail(DPF_EINVAL, "unknown buffer %d", which);
+  }
+  if (bytes < need) return fail(DPF_EINVAL, "buffer %d needs %zu bytes", which, need);
+  HIP_TRY(hipMemcpyAsync(d_dst, h->ws + off, need, hipMemcpyDeviceToDevice, h->stream));
+  return DPF_OK;
+}
+
+// ---------------------------------------------------------------- primitives
+extern "C" dpf_status dpf_philox_words(uint64_t seed, uint32_t filter_id, const uint32_t* d_ctr, size_t n,
+                                       uint32_t* d_out, void* hip_stream) {
+  if ((!d_ctr || !d_out) && n) return fail(DPF_EINVAL, "null buffer");
+  if (n == 0) return DPF_OK;
+  hipLaunchKernelGGL(k_philox_words, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)hip_stream,
+                     make_key(seed, filter_id), d_ctr, (long long)n, d_out);
+  LAUNCH_CHECK("k_philox_words");
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_normals(uint64_t seed, uint32_t filter_id, uint32_t t, uint32_t purpose, int32_t n_a,
+                                  int32_t n_b, int32_t D, float* d_out, void* hip_stream) {
+  if (!d_out || n_a < 0 || n_b < 0) return fail(DPF_EINVAL, "bad arguments");
+  const long long n = (long long)n_a * n_b;
+  if (n == 0) return DPF_OK;
+  const dim3 g((unsigned)((n + 255) / 256));
+  const Key key = make_key(seed, filter_id);
+  hipStream_t s = (hipStream_t)hip_stream;
+  switch (D) {
+    case 1: hipLaunchKernelGGL(k_normals_grid<1>, g, dim3(256), 0, s, key, t, purpose, n_a, n_b, d_out); break;
+    case 2: hipLaunchKernelGGL(k_normals_grid<2>, g, dim3(256), 0, s, key, t, purpose, n_a, n_b, d_out); break;
+    case 4: hipLaunchKernelGGL(k_normals_grid<4>, g, dim3(256), 0, s, key, t, purpose, n_a, n_b, d_out); break;
+    case 8: hipLaunchKernelGGL(k_normals_grid<8>, g, dim3(256), 0, s, key, t, purpose, n_a, n_b, d_out); break;
+    case 64: hipLaunchKernelGGL(k_normals_grid<64>, g, dim3(256), 0, s, key, t, purpose, n_a, n_b, d_out); break;
+    default: return fail(DPF_EUNSUPPORTED, "D = %d (built: 1, 2, 4, 8, 64)", D);
+  }
+  LAUNCH_CHECK("k_normals_grid");
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_systematic(const double* d_w, int32_t n, int32_t n_out, double u, double* d_scratch,
+                                     int32_t* d_out, void* hip_stream) {
+  if (!d_w || !d_scratch || !d_out || n < 1 || n_out < 1) return fail(DPF_EINVAL, "bad arguments");
+  if (!(u >= 0.0 && u < 1.0)) return fail(DPF_EINVAL, "u must be in [0, 1)");
+  hipLaunchKernelGGL(k_systematic_prim, dim3(1), dim3(kResBlock), 0, (hipStream_t)hip_stream, d_w, n, n_out, u,
+                     d_scratch, (int*)d_out);
+  LAUNCH_CHECK("k_systematic_prim");
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_segmented_systematic(const double* d_w, int32_t S, int32_t n, int32_t n_out,
+                                               const double* d_u, int32_t* d_out, void* hip_stream) {
+  if (!d_w || !d_u || !d_out || S < 0 || n < 1) return fail(DPF_EINVAL, "bad arguments");
+  if (n_out != n && n_out != 1) return fail(DPF_EINVAL, "n_out must be n or 1");
+  if (S == 0) return DPF_OK;
+  const int cls = class_of(n);
+  if (cls < 0) return fail(DPF_EUNSUPPORTED, "n = %d > 4096", n);
+  const int segs = kBlock / kClasses[cls].seg;
+  const dim3 g((S + segs - 1) / segs);
+  hipStream_t s = (hipStream_t)hip_stream;
+  switch (cls) {
+    case 0: hipLaunchKernelGGL((k_seg_systematic_prim<32, 1>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
+    case 1: hipLaunchKernelGGL((k_seg_systematic_prim<64, 1>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
+    case 2: hipLaunchKernelGGL((k_seg_systematic_prim<128, 1>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
+    case 3: hipLaunchKernelGGL((k_seg_systematic_prim<256, 1>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
+    case 4: hipLaunchKernelGGL((k_seg_systematic_prim<256, 4>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
+    case 5: hipLaunchKernelGGL((k_seg_systematic_prim<256, 16>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
+  }
+  LAUNCH_CHECK("k_seg_systematic_prim");
+  return DPF_OK;
+}

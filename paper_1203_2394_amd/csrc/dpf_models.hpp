@@ -1,0 +1,286 @@
+// Device models of the nested state space of Section 2, Eq. (1).
+//
+// Each model is a struct of static device functions over small register
+// arrays, split so that the work that depends only on the outer state is
+// done once per segment when it is uniform there:
+//
+//   fx(P, x, z, nu, xn)           x_{t+1} = f^x(x_t, z_t, v^x)    (nu: DX normals)
+//   fz_pre(P, x, xn, pre)         the part of f^z that depends only on x_{t:t+1}
+//   fz_post(P, pre, z, nu, zn)    z_{t+1} = f^z(x_{t:t+1}, z_t, v^z) (nu: DZ normals)
+//   obs_pre(P, y, x, r0)          the part of y - h(x, z) that depends only on x
+//   logpy_post(P, r0, z)          log p(y_t | x_t, z_t)
+//   logpx(P, xn, x, z)            log p(x_{t+1} | x_t, z_t)
+//
+// kXdepZ says whether p(x_{t+1} | x_t, z_t) depends on z_t; when it does
+// not, the x-conditioning factor of eq:qnobar is constant over the inner
+// cloud and the kernels skip it.
+//
+// Parameters live in one float array in device memory: the raw parameter
+// values in the interface's blob order, followed by constants the host
+// derives from them in double precision (square roots, reciprocals, log
+// normalisers) at fixed offsets given by each model's `Layout`.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace dpf {
+
+constexpr float kLn2Pi = 1.8378770664093453f;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kInv2Pi = 0.15915494309189535f;
+
+__device__ __forceinline__ float fast_exp(float v) { return __builtin_amdgcn_exp2f(v * kLog2e); }
+__device__ __forceinline__ float fast_log(float v) { return __builtin_amdgcn_logf(v) * 0.6931471805599453f; }
+
+// tanh(a) = sign(a) (1 - 2 / (exp(2|a|) + 1)); absolute error ~1e-7.
+__device__ __forceinline__ float tanh_f(float a) {
+  const float e = fast_exp(2.0f * fabsf(a));
+  const float r = 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+  return copysignf(r, a);
+}
+
+// ---------------------------------------------------------------- LINGAUSS
+// x' = Ax x + Cxz z + sqrt(qx) v ; z' = Az z + Bzx x' + sqrt(qz) w ;
+// y = Hx x + Hz z + sqrt(r) e.
+template <int DX_, int DZ_, int DY_>
+struct LinGauss {
+  static constexpr int DX = DX_, DZ = DZ_, DY = DY_;
+  static constexpr bool kXdepZ = true;
+  struct Layout {
+    static constexpr int Ax = 0, Cxz = Ax + DX * DX, qx = Cxz + DX * DZ, Az = qx + 1,
+                         Bzx = Az + DZ * DZ, qz = Bzx + DZ * DX, Hx = qz + 1, Hz = Hx + DY * DX,
+                         r = Hz + DY * DZ, n_raw = r + 1;
+    // derived
+    static constexpr int sx = n_raw, sz = sx + 1, inv_qx = sz + 1, inv_r = inv_qx + 1,
+                         cx = inv_r + 1, cy = cx + 1, n_total = cy + 1;
+  };
+  using L = Layout;
+
+  __device__ static void fx(const float* P, const float* x, const float* z, const float* nu,
+                            float* xn) {
+#pragma unroll
+    for (int a = 0; a < DX; ++a) {
+      float s = 0.f;
+#pragma unroll
+      for (int b = 0; b < DX; ++b) s += P[L::Ax + a * DX + b] * x[b];
+#pragma unroll
+      for (int b = 0; b < DZ; ++b) s += P[L::Cxz + a * DZ + b] * z[b];
+      xn[a] = s + P[L::sx] * nu[a];
+    }
+  }
+  __device__ static void fz_pre(const float* P, const float* x, const float* xn, float* pre) {
+#pragma unroll
+    for (int a = 0; a < DZ; ++a) {
+      float s = 0.f;
+#pragma unroll
+      for (int b = 0; b < DX; ++b) s += P[L::Bzx + a * DX + b] * xn[b];
+      pre[a] = s;
+    }
+  }
+  __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu,
+                                 float* zn) {
+#pragma unroll
+    for (int a = 0; a < DZ; ++a) {
+      float s = pre[a];
+#pragma unroll
+      for (int b = 0; b < DZ; ++b) s += P[L::Az + a * DZ + b] * z[b];
+      zn[a] = s + P[L::sz] * nu[a];
+    }
+  }
+  __device__ static void obs_pre(const float* P, const float* y, const float* x, float* r0) {
+#pragma unroll
+    for (int a = 0; a < DY; ++a) {
+      float s = y[a];
+#pragma unroll
+      for (int b = 0; b < DX; ++b) s -= P[L::Hx + a * DX + b] * x[b];
+      r0[a] = s;
+    }
+  }
+  __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
+    float q = 0.f;
+#pragma unroll
+    for (int a = 0; a < DY; ++a) {
+      float e = r0[a];
+#pragma unroll
+      for (int b = 0; b < DZ; ++b) e -= P[L::Hz + a * DZ + b] * z[b];
+      q += e * e;
+    }
+    return P[L::cy] - 0.5f * P[L::inv_r] * q;
+  }
+  __device__ static float logpx(const float* P, const float* xn, const float* x, const float* z) {
+    float q = 0.f;
+#pragma unroll
+    for (int a = 0; a < DX; ++a) {
+      float s = xn[a];
+#pragma unroll
+      for (int b = 0; b < DX; ++b) s -= P[L::Ax + a * DX + b] * x[b];
+#pragma unroll
+      for (int b = 0; b < DZ; ++b) s -= P[L::Cxz + a * DZ + b] * z[b];
+      q += s * s;
+    }
+    return P[L::cx] - 0.5f * P[L::inv_qx] * q;
+  }
+};
+
+// Growth model of the outer block shared by NONLIN and HIGHDIM:
+// x'_d = a x_d + b x_d / (1 + x_d^2) + sqrt(qx) v_d.
+__device__ __forceinline__ float growth(float a, float b, float x) {
+  return a * x + b * x * __builtin_amdgcn_rcpf(1.0f + x * x);
+}
+
+// ------------------------------------------------------------------ NONLIN
+// z' = tanh(W x') + rho z + sqrt(qz) w ; y_k = z_k + c g_k(x) + sqrt(r) e_k
+// with g_k = x_{k mod DX}^2 (bmode 0) or |x|^2 (bmode 1).
+template <int DX_, int DZ_>
+struct NonLin {
+  static constexpr int DX = DX_, DZ = DZ_, DY = DZ_;
+  static constexpr bool kXdepZ = false;
+  struct Layout {
+    static constexpr int a = 0, b = 1, qx = 2, W = 3, rho = W + DZ * DX, qz = rho + 1, c = qz + 1,
+                         r = c + 1, bmode = r + 1, n_raw = bmode + 1;
+    static constexpr int sx = n_raw, sz = sx + 1, inv_qx = sz + 1, inv_r = inv_qx + 1,
+                         cx = inv_r + 1, cy = cx + 1, n_total = cy + 1;
+  };
+  using L = Layout;
+
+  __device__ static void fx(const float* P, const float* x, const float*, const float* nu,
+                            float* xn) {
+    const float a = P[L::a], b = P[L::b], s = P[L::sx];
+#pragma unroll
+    for (int d = 0; d < DX; ++d) xn[d] = growth(a, b, x[d]) + s * nu[d];
+  }
+  __device__ static void fz_pre(const float* P, const float*, const float* xn, float* pre) {
+#pragma unroll
+    for (int k = 0; k < DZ; ++k) {
+      float s = 0.f;
+#pragma unroll
+      for (int d = 0; d < DX; ++d) s += P[L::W + k * DX + d] * xn[d];
+      pre[k] = tanh_f(s);
+    }
+  }
+  __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu,
+                                 float* zn) {
+    const float rho = P[L::rho], s = P[L::sz];
+#pragma unroll
+    for (int k = 0; k < DZ; ++k) zn[k] = pre[k] + rho * z[k] + s * nu[k];
+  }
+  __device__ static void obs_pre(const float* P, const float* y, const float* x, float* r0) {
+    const float c = P[L::c];
+    if (P[L::bmode] == 0.0f) {
+#pragma unroll
+      for (int k = 0; k < DY; ++k) r0[k] = y[k] - c * x[k % DX] * x[k % DX];
+    } else {
+      float q = 0.f;
+#pragma unroll
+      for (int d = 0; d < DX; ++d) q += x[d] * x[d];
+#pragma unroll
+      for (int k = 0; k < DY; ++k) r0[k] = y[k] - c * q;
+    }
+  }
+  __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
+    float q = 0.f;
+#pragma unroll
+    for (int k = 0; k < DY; ++k) {
+      const float e = r0[k] - z[k];
+      q += e * e;
+    }
+    return P[L::cy] - 0.5f * P[L::inv_r] * q;
+  }
+  __device__ static float logpx(const float* P, const float* xn, const float* x, const float*) {
+    const float a = P[L::a], b = P[L::b];
+    float q = 0.f;
+#pragma unroll
+    for (int d = 0; d < DX; ++d) {
+      const float e = xn[d] - growth(a, b, x[d]);
+      q += e * e;
+    }
+    return P[L::cx] - 0.5f * P[L::inv_qx] * q;
+  }
+};
+
+// ----------------------------------------------------------------- HIGHDIM
+// z' = A z + B sin(x') + sqrt(qz) w with A tridiagonal ; y = C z + e with
+// per-component density (1-eps) N(0, r) + eps t_nu(e/sqrt r)/sqrt r.
+template <int DX_, int DZ_, int DY_>
+struct HighDim {
+  static constexpr int DX = DX_, DZ = DZ_, DY = DY_;
+  static constexpr bool kXdepZ = false;
+  struct Layout {
+    static constexpr int a = 0, b = 1, qx = 2, Alo = 3, Adg = Alo + DZ - 1, Aup = Adg + DZ,
+                         B = Aup + DZ - 1, qz = B + DZ * DX, C = qz + 1, r = C + DY * DZ,
+                         eps = r + 1, nu = eps + 1, gonly = nu + 1, n_raw = gonly + 1;
+    // derived: sx sz inv_qx cx ; Gaussian-only: inv_r, cy (all DY components) ;
+    // mixture: half_inv_r, lg0 = log(1-eps) - 0.5 log(2 pi r),
+    //          lt0 = log eps + lgamma((nu+1)/2) - lgamma(nu/2) - 0.5 log(nu pi r),
+    //          tnu = (nu+1)/2, inv_nur = 1/(nu r)
+    static constexpr int sx = n_raw, sz = sx + 1, inv_qx = sz + 1, cx = inv_qx + 1,
+                         inv_r = cx + 1, cy = inv_r + 1, lg0 = cy + 1, lt0 = lg0 + 1,
+                         tnu = lt0 + 1, inv_nur = tnu + 1, n_total = inv_nur + 1;
+  };
+  using L = Layout;
+
+  __device__ static void fx(const float* P, const float* x, const float*, const float* nu,
+                            float* xn) {
+    const float a = P[L::a], b = P[L::b], s = P[L::sx];
+#pragma unroll
+    for (int d = 0; d < DX; ++d) xn[d] = growth(a, b, x[d]) + s * nu[d];
+  }
+  __device__ static void fz_pre(const float* P, const float*, const float* xn, float* pre) {
+    float sn[DX];
+#pragma unroll
+    for (int d = 0; d < DX; ++d) sn[d] = __builtin_amdgcn_sinf(xn[d] * kInv2Pi);
+#pragma unroll
+    for (int k = 0; k < DZ; ++k) {
+      float s = 0.f;
+#pragma unroll
+      for (int d = 0; d < DX; ++d) s += P[L::B + k * DX + d] * sn[d];
+      pre[k] = s;
+    }
+  }
+  __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu,
+                                 float* zn) {
+    const float s = P[L::sz];
+#pragma unroll
+    for (int k = 0; k < DZ; ++k) {
+      float v = pre[k] + P[L::Adg + k] * z[k] + s * nu[k];
+      if (k > 0) v += P[L::Alo + k - 1] * z[k - 1];
+      if (k + 1 < DZ) v += P[L::Aup + k] * z[k + 1];
+      zn[k] = v;
+    }
+  }
+  __device__ static void obs_pre(const float*, const float* y, const float*, float* r0) {
+#pragma unroll
+    for (int k = 0; k < DY; ++k) r0[k] = y[k];
+  }
+  __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
+    const bool gonly = P[L::gonly] != 0.0f;
+    float acc = 0.f, q = 0.f;
+#pragma unroll 4
+    for (int k = 0; k < DY; ++k) {
+      float e = r0[k];
+#pragma unroll
+      for (int d = 0; d < DZ; ++d) e -= P[L::C + k * DZ + d] * z[d];
+      const float e2 = e * e;
+      q += e2;
+      if (!gonly) {
+        const float lg = P[L::lg0] - 0.5f * P[L::inv_r] * e2;
+        const float lt = P[L::lt0] - P[L::tnu] * fast_log(1.0f + e2 * P[L::inv_nur]);
+        const float mx = fmaxf(lg, lt);
+        acc += mx + fast_log(1.0f + fast_exp(-fabsf(lg - lt)));
+      }
+    }
+    return gonly ? P[L::cy] - 0.5f * P[L::inv_r] * q : acc;
+  }
+  __device__ static float logpx(const float* P, const float* xn, const float* x, const float*) {
+    const float a = P[L::a], b = P[L::b];
+    float q = 0.f;
+#pragma unroll
+    for (int d = 0; d < DX; ++d) {
+      const float e = xn[d] - growth(a, b, x[d]);
+      q += e * e;
+    }
+    return P[L::cx] - 0.5f * P[L::inv_qx] * q;
+  }
+};
+
+}  // namespace dpf

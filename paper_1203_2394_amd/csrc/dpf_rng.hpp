@@ -1,0 +1,125 @@
+// Counter-based random numbers on the device (gfx950).
+//
+// The paper does not say how random numbers are drawn; the library uses
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3", SC'11), written here from that published
+// definition.  A 4-word block is a pure function of
+//   key     = (seed_lo32, seed_hi32 ^ filter_id)
+//   counter = (t, a, b, purpose << 24 | block)
+// so any particle can regenerate any of its draws without storing them.
+//
+// Transforms (exact in FP32 / FP64):
+//   U24(w)      = (2 (w >> 9) + 1) 2^-24          in (0, 1)
+//   U53(w0, w1) = ((w0 << 21) | (w1 >> 11)) 2^-53  in [0, 1)
+// Normals: Box-Muller on word pairs (w0,w1) -> normals 4b, 4b+1 and
+// (w2,w3) -> 4b+2, 4b+3 of block b: r = sqrt(-2 ln U24(w_even)),
+// (r cos 2 pi U24(w_odd), r sin 2 pi U24(w_odd)).  The FP32 transform uses
+// the hardware log2 / sqrt / sin / cos (the sin and cos units take their
+// argument in revolutions, so 2 pi u is never formed).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dpf {
+
+enum Purpose : uint32_t {
+  P_INIT_X = 0, P_INIT_Z = 1, P_LA_X = 2, P_LA_Z = 3, P_OUTER_U = 4, P_CAND_U = 5,
+  P_INNER_U = 6, P_NEW_Z = 7, P_DPF_ANC_U = 8, P_DPF_X = 9, P_DPF_Z = 10,
+  P_MDN_U = 11, P_MDN_X = 12
+};
+
+struct Key {
+  uint32_t k0, k1;
+};
+
+__host__ __device__ inline Key make_key(uint64_t seed, uint32_t filter_id) {
+  Key k;
+  k.k0 = (uint32_t)seed;
+  k.k1 = (uint32_t)(seed >> 32) ^ filter_id;
+  return k;
+}
+
+struct Words {
+  uint32_t w[4];
+};
+
+// Ten Philox4x32 rounds.  Each 32x32->64 product is one v_mad_u64_u32.
+__device__ __forceinline__ Words philox(Key key, uint32_t c0, uint32_t c1, uint32_t c2,
+                                        uint32_t c3) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t p0 = (uint64_t)M0 * c0;
+    const uint64_t p1 = (uint64_t)M1 * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+  }
+  Words o;
+  o.w[0] = c0;
+  o.w[1] = c1;
+  o.w[2] = c2;
+  o.w[3] = c3;
+  return o;
+}
+
+__device__ __forceinline__ Words draw(Key key, uint32_t t, uint32_t a, uint32_t b,
+                                      uint32_t purpose, uint32_t block) {
+  return philox(key, t, a, b, (purpose << 24) | block);
+}
+
+__device__ __forceinline__ float u24f(uint32_t w) {
+  return (float)((w >> 9) * 2u + 1u) * 0x1p-24f;
+}
+
+__device__ __forceinline__ double u53(uint32_t w0, uint32_t w1) {
+  const uint64_t v = ((uint64_t)w0 << 21) | (uint64_t)(w1 >> 11);
+  return (double)v * 0x1p-53;
+}
+
+// The single U53 offset of a resampling / selection draw at counter (t, a, 0).
+__device__ __forceinline__ double uniform53(Key key, uint32_t t, uint32_t a, uint32_t purpose) {
+  const Words w = draw(key, t, a, 0u, purpose, 0u);
+  return u53(w.w[0], w.w[1]);
+}
+
+// Box-Muller pair in FP32 from two words.
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& n0, float& n1) {
+  constexpr float kMinus2Ln2 = -1.3862943611198906f;  // -2 ln 2
+  const float a = u24f(wa);
+  const float b = u24f(wb);
+  const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(a));
+  n0 = r * __builtin_amdgcn_cosf(b);
+  n1 = r * __builtin_amdgcn_sinf(b);
+}
+
+// D standard normals of the draw at counter (t, a, b) for one purpose.
+template <int D>
+__device__ __forceinline__ void normals(Key key, uint32_t t, uint32_t a, uint32_t b,
+                                        uint32_t purpose, float* out) {
+#pragma unroll
+  for (int blk = 0; blk < (D + 3) / 4; ++blk) {
+    const Words w = draw(key, t, a, b, purpose, (uint32_t)blk);
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {
+      const int d0 = 4 * blk + 2 * pr;
+      if (d0 < D) {
+        float n0, n1;
+        box_muller(w.w[2 * pr], w.w[2 * pr + 1], n0, n1);
+        out[d0] = n0;
+        if (d0 + 1 < D) out[d0 + 1] = n1;
+      }
+    }
+  }
+}
+
+}  // namespace dpf

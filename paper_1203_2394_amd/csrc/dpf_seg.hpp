@@ -1,0 +1,153 @@
+// Segment primitives for 256-thread workgroups on wave64 hardware.
+//
+// A workgroup is split into 256/SEG segments of SEG lanes (SEG in
+// {32, 64, 128, 256}); one segment serves one outer particle's inner cloud
+// of M <= SEG*JPT inner particles, lane l handling inner indices
+// l, l+SEG, ... (coalesced in the [N][dz][M] layout).  Segments of up to 64
+// lanes live inside one wavefront and reduce / scan with cross-lane
+// shuffles; wider segments combine per-wave results through LDS.
+//
+// Every function here must be reached by all 256 threads (they may contain
+// barriers); lanes with nothing to contribute pass the identity.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace dpf {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+
+// Shared scratch for cross-wave combination: one slot per wave (and a spare
+// set so that two consecutive primitives do not race).
+struct SegScratch {
+  float f[2][kBlock / kWave];
+  double d[2][kBlock / kWave];
+};
+
+template <int SEG>
+__device__ __forceinline__ float seg_max(float v, SegScratch& sh) {
+#pragma unroll
+  for (int off = (SEG < kWave ? SEG : kWave) / 2; off > 0; off >>= 1)
+    v = fmaxf(v, __shfl_xor(v, off, kWave));
+  if constexpr (SEG > kWave) {
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) sh.f[0][w] = v;
+    __syncthreads();
+    const int w0 = (threadIdx.x / SEG) * (SEG / kWave);
+    float r = sh.f[0][w0];
+#pragma unroll
+    for (int q = 1; q < SEG / kWave; ++q) r = fmaxf(r, sh.f[0][w0 + q]);
+    __syncthreads();
+    v = r;
+  }
+  return v;
+}
+
+template <int SEG>
+__device__ __forceinline__ float seg_sum(float v, SegScratch& sh) {
+#pragma unroll
+  for (int off = (SEG < kWave ? SEG : kWave) / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  if constexpr (SEG > kWave) {
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) sh.f[1][w] = v;
+    __syncthreads();
+    const int w0 = (threadIdx.x / SEG) * (SEG / kWave);
+    float r = sh.f[1][w0];
+#pragma unroll
+    for (int q = 1; q < SEG / kWave; ++q) r += sh.f[1][w0 + q];
+    __syncthreads();
+    v = r;
+  }
+  return v;
+}
+
+template <int SEG>
+__device__ __forceinline__ double seg_sum_d(double v, SegScratch& sh) {
+#pragma unroll
+  for (int off = (SEG < kWave ? SEG : kWave) / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  if constexpr (SEG > kWave) {
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) sh.d[1][w] = v;
+    __syncthreads();
+    const int w0 = (threadIdx.x / SEG) * (SEG / kWave);
+    double r = sh.d[1][w0];
+#pragma unroll
+    for (int q = 1; q < SEG / kWave; ++q) r += sh.d[1][w0 + q];
+    __syncthreads();
+    v = r;
+  }
+  return v;
+}
+
+// Inclusive FP64 scan within the segment; `total` receives the segment sum.
+template <int SEG>
+__device__ __forceinline__ double seg_scan_incl(double v, SegScratch& sh, double& total) {
+  constexpr int W = SEG < kWave ? SEG : kWave;
+  const int lw = threadIdx.x & (W - 1);
+#pragma unroll
+  for (int d = 1; d < W; d <<= 1) {
+    const double o = __shfl_up(v, d, W);
+    if (lw >= d) v += o;
+  }
+  if constexpr (SEG <= kWave) {
+    total = __shfl(v, W - 1, W);
+  } else {
+    const int w = threadIdx.x / kWave;
+    if (lw == kWave - 1) sh.d[0][w] = v;
+    __syncthreads();
+    const int w0 = (threadIdx.x / SEG) * (SEG / kWave);
+    double pre = 0.0, tot = 0.0;
+#pragma unroll
+    for (int q = 0; q < SEG / kWave; ++q) {
+      const double s = sh.d[0][w0 + q];
+      if (w0 + q < w) pre += s;
+      tot += s;
+    }
+    __syncthreads();
+    v += pre;
+    total = tot;
+  }
+  return v;
+}
+
+// Systematic search rule: the first index with C[i] > P; if rounding put the
+// point at or past the total, the first index with C[i] >= C[n-1].  Never
+// selects a zero weight.
+__device__ __forceinline__ int cdf_search(const double* C, int n, double P) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (C[mid] > P)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  if (lo == n) {
+    const double tot = C[n - 1];
+    lo = 0;
+    hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (C[mid] >= tot)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+  }
+  return lo;
+}
+
+// Point k of n_out systematic points over total C: ((k + u) * C) / n_out,
+// evaluated left to right in IEEE double precision (no contraction: the
+// multiply follows an add, never the reverse).
+__device__ __forceinline__ double sys_point(int k, double u, double total, int n_out) {
+  const double a = (double)k + u;
+  const double b = a * total;
+  return b / (double)n_out;
+}
+
+__device__ __forceinline__ bool finitef(float v) { return fabsf(v) <= 3.402823466e38f; }
+
+}  // namespace dpf

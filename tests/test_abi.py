@@ -1,0 +1,95 @@
+"""The C interface: the library loads on a machine without a GPU, exports every
+symbol include/dpf.h declares, and its host-side validation works (no
+compute calls here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import dpf_synth as S
+import paper_1203_2394_amd as dpf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dpf.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dpf_[a-z_]+)\s*\(", txt)))
+
+
+def _lib():
+    if not os.path.exists(dpf.LIB_PATH):
+        pytest.skip("libdpf.so not built")
+    return dpf.lib()
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(dpf.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def _cfg(spec, N, M, algo=0, n_params=None):
+    c = dpf._Config()
+    c.abi_version = 1
+    c.model, c.algo = spec.kind, algo
+    c.dx, c.dz, c.dy = spec.dx, spec.dz, spec.dy
+    blob = np.ascontiguousarray(spec.blob)
+    c.params = blob.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    c.n_params = blob.size if n_params is None else n_params
+    Na = np.asarray(N, dtype=np.int32)
+    Ma = np.asarray(M, dtype=np.int32)
+    c.n_filters = len(Na)
+    c.N = Na.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    c.M = Ma.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    c.seed = 1
+    return c, (blob, Na, Ma)
+
+
+def test_workspace_bytes_scales_with_sizes():
+    L = _lib()
+    spec = S.nonlin_c2()
+    c1, keep1 = _cfg(spec, [4096], [256])
+    c2, keep2 = _cfg(spec, [4096, 100], [256, 50])
+    b1 = L.dpf_workspace_bytes(ctypes.byref(c1))
+    b2 = L.dpf_workspace_bytes(ctypes.byref(c2))
+    # two copies of z (8 floats) and lam, plus ell: at least 76 bytes per inner particle
+    assert b1 >= 4096 * 256 * (2 * 8 * 4 + 3 * 4)
+    assert b2 > b1
+
+
+def test_validation_errors_are_reported():
+    L = _lib()
+    spec = S.nonlin_c2()
+    bad = [
+        _cfg(spec, [4096], [256], n_params=3),        # wrong parameter count
+        _cfg(spec, [4096], [5000]),                   # M too large
+        _cfg(spec, [0], [16]),                        # N = 0
+        _cfg(spec, [16], [16], algo=7),               # unknown algo
+    ]
+    for c, keep in bad:
+        assert L.dpf_workspace_bytes(ctypes.byref(c)) == 0
+        assert len(L.dpf_last_error()) > 0
+    c, keep = _cfg(S.ModelSpec(2, 3, 8, 8, spec.blob), [16], [16])
+    assert L.dpf_workspace_bytes(ctypes.byref(c)) == 0
+    assert b"not built" in L.dpf_last_error()
+
+
+def test_create_rejects_small_or_misaligned_workspace():
+    L = _lib()
+    spec = S.lingauss_c1()
+    c, keep = _cfg(spec, [100], [50])
+    need = L.dpf_workspace_bytes(ctypes.byref(c))
+    h = ctypes.c_void_p()
+    # host-side checks fail before any device work is queued
+    assert L.dpf_create(ctypes.byref(c), ctypes.c_void_p(256), need - 1, None, ctypes.byref(h)) == 2
+    assert L.dpf_create(ctypes.byref(c), ctypes.c_void_p(257), need, None, ctypes.byref(h)) == 1
+    assert L.dpf_create(ctypes.byref(c), None, need, None, ctypes.byref(h)) == 1

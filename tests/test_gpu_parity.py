@@ -1,0 +1,159 @@
+"""Step-level parity of the HIP look-ahead DPF and plain DPF with the oracle.
+
+Each case: the oracle initialises and runs a few steps; its state, rounded to
+FP32, is imported into the library; both sides take the next steps from the
+same FP32 state with the same Philox streams; the GPU's new state and
+intermediate buffers are compared with the oracle's (tests/parity_util.py).
+Sizes span several tiles with ragged tails in N and M.
+"""
+import numpy as np
+import pytest
+
+import dpf_synth as S
+import paper_1203_2394_amd as dpf
+from oracle import dpf as odpf
+from oracle import ladpf
+from oracle.models import make_model
+
+from parity_util import assert_clean, compare_la, compare_plain, to_state32
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+SPECS = {
+    "lingauss": lambda: S.lingauss_c1(False),
+    "lingauss_coupled": lambda: S.lingauss_c1(True),
+    "nonlin": lambda: S.nonlin_c2(1),
+    "nonlin_bmode1": lambda: S.nonlin_c2(2, bmode=1),
+    "highdim": lambda: S.highdim_c4(1),
+    "highdim_gauss": lambda: S.highdim_c4(1, gaussian_only=True),
+}
+
+
+def _gpu_filter(spec, N, M, seed, algo):
+    return dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N], [M], seed=seed, algo=algo)
+
+
+def _la_case(name, N, M, warm, steps, seed=4242, data_seed=3):
+    spec = SPECS[name]()
+    model = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
+    _, _, ys = S.simulate(spec, warm + steps, data_seed)
+    ys = ys.astype(np.float32).astype(np.float64)
+    st = ladpf.init_state(model, N, M, seed, 0)
+    for t in range(warm):
+        st, _ = ladpf.step(model, st, ys[t], seed, 0)
+    f = _gpu_filter(spec, N, M, seed, "lookahead")
+    reports = []
+    for t in range(warm, warm + steps):
+        st32 = to_state32(st)
+        f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["x"], st32["z"], st32["lam"])))
+        f.lookahead_step(torch.tensor(ys[t], dtype=torch.float32))
+        g = f.unpack_state(f.export_state())
+        ell = f.copy_buffer(dpf.BUF_ELL).cpu().numpy().reshape(N, M)
+        logw = f.copy_buffer(dpf.BUF_LOGW).cpu().numpy()
+        anc = f.copy_buffer(dpf.BUF_ANC).cpu().numpy()
+        sel = f.copy_buffer(dpf.BUF_SEL).cpu().numpy()
+        gs = {"x": g["x"][0], "z": g["z"][0], "lam": g["lam"][0]}
+        assert int(g["t"][0]) == st32["t"] + 1
+        r, st, info = compare_la(model, st32, ys[t], seed, 0, gs, ell, logw, anc, sel)
+        print("LA %s N=%d M=%d t=%d: %s" % (name, N, M, t + 1, r.line()), flush=True)
+        reports.append((r, info, f.estimate()))
+    return reports
+
+
+@pytest.mark.parametrize("name,N,M,warm,steps", [
+    ("lingauss", 103, 50, 2, 3),
+    ("lingauss", 40, 1, 1, 2),
+    ("lingauss_coupled", 64, 37, 2, 3),
+    ("lingauss_coupled", 9, 300, 1, 2),
+    ("nonlin", 300, 200, 2, 2),
+    ("nonlin", 100, 700, 1, 1),
+    ("nonlin", 70, 32, 1, 2),
+    ("nonlin_bmode1", 64, 128, 1, 1),
+    ("highdim", 8, 1024, 1, 1),
+    ("highdim_gauss", 12, 100, 1, 1),
+])
+def test_lookahead_step_parity(name, N, M, warm, steps):
+    for r, info, est in _la_case(name, N, M, warm, steps):
+        assert_clean(r, n=N)
+        if r["clean_frac"] == 1.0 and r["anc_flips"] == 0:
+            xg = est["xhat"][0].cpu().numpy()
+            assert np.allclose(xg, info["xhat"], rtol=1e-4, atol=1e-4), (xg, info["xhat"])
+            zg = est["zhat"][0].cpu().numpy()
+            assert np.allclose(zg, info["zhat"], rtol=1e-4, atol=1e-4)
+            assert abs(float(est["ess"][0]) - info["ess"]) <= 1e-3 * info["ess"]
+
+
+def test_lookahead_step_parity_full_size_nonlin():
+    """The benchmark's configuration (N=4096, M=256, dz=8), one step."""
+    for r, info, est in _la_case("nonlin", 4096, 256, 1, 1):
+        assert_clean(r)
+
+
+def _plain_case(name, N, M, warm, steps, seed=777, data_seed=5):
+    spec = SPECS[name]()
+    model = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
+    _, _, ys = S.simulate(spec, warm + steps, data_seed)
+    ys = ys.astype(np.float32).astype(np.float64)
+    st = odpf.init_state(model, N, M, seed, 0)
+    for t in range(warm):
+        st, _ = odpf.step(model, st, ys[t], seed, 0)
+    f = _gpu_filter(spec, N, M, seed, "plain")
+    out = []
+    for t in range(warm, warm + steps):
+        st32 = to_state32(st)
+        f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["xt"], st32["zt"], np.zeros((N, M)))))
+        f.step(torch.tensor(ys[t], dtype=torch.float32))
+        g = f.unpack_state(f.export_state())
+        ell = f.copy_buffer(dpf.BUF_ELL).cpu().numpy().reshape(N, M)
+        logw = f.copy_buffer(dpf.BUF_LOGW).cpu().numpy()
+        anc = f.copy_buffer(dpf.BUF_ANC).cpu().numpy()
+        sel = f.copy_buffer(dpf.BUF_SEL).cpu().numpy()
+        gs = {"x": g["x"][0], "z": g["z"][0]}
+        r, st, info = compare_plain(model, st32, ys[t], seed, 0, gs, ell, logw, anc, sel)
+        print("DPF %s N=%d M=%d t=%d: %s" % (name, N, M, t + 1, r.line()), flush=True)
+        out.append((r, info, f.estimate()))
+    return out
+
+
+@pytest.mark.parametrize("name,N,M,warm,steps", [
+    ("lingauss", 103, 50, 2, 3),
+    ("lingauss_coupled", 64, 37, 2, 2),
+    ("nonlin", 300, 200, 1, 2),
+    ("highdim", 8, 1024, 1, 1),
+])
+def test_plain_step_parity(name, N, M, warm, steps):
+    for r, info, est in _plain_case(name, N, M, warm, steps):
+        assert_clean(r, n=N)
+        # plain estimates are formed before resampling: they depend only on ell
+        xg = est["xhat"][0].cpu().numpy()
+        assert np.allclose(xg, info["xhat"], rtol=1e-4, atol=1e-4)
+        zg = est["zhat"][0].cpu().numpy()
+        assert np.allclose(zg, info["zhat"], rtol=1e-4, atol=1e-4)
+
+
+@pytest.mark.parametrize("algo", ["lookahead", "plain"])
+def test_initialisation_matches_oracle_prior(algo):
+    spec = S.nonlin_c2(1)
+    model = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
+    N, M, seed = 130, 70, 99
+    f = _gpu_filter(spec, N, M, seed, algo)
+    g = f.unpack_state(f.export_state())
+    assert int(g["t"][0]) == 0
+    if algo == "lookahead":
+        st = ladpf.init_state(model, N, M, seed, 0)
+        assert np.allclose(g["x"][0], st["x"], atol=2e-5)
+        assert np.allclose(g["z"][0], st["z"], atol=2e-5)
+        assert np.allclose(g["lam"][0], -np.log(M), atol=1e-6)
+    else:
+        st = odpf.init_state(model, N, M, seed, 0)
+        # the proposals for t = 1 come from the prior through steps 4-7
+        err = np.abs(g["x"][0] - st["xt"]) / np.maximum(1, np.abs(st["xt"]))
+        assert np.max(err) < 1e-4

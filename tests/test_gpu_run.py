@@ -1,0 +1,146 @@
+"""Multi-step runs on the GPU: many ragged filters in one handle against the
+oracle, graph replay against plain step calls (bit for bit), resume from an
+exported state, per-filter horizons, and the data-dependent flags."""
+import numpy as np
+import pytest
+
+import dpf_synth as S
+import paper_1203_2394_amd as dpf
+from oracle import ladpf
+from oracle.models import make_model
+
+from parity_util import assert_clean, compare_la, to_state32
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _filter(spec, N, M, seed=11, algo="lookahead"):
+    return dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, N, M, seed=seed, algo=algo)
+
+
+def test_ragged_batch_matches_oracle_per_filter():
+    """One handle, filters of uneven N and M (every tile class), each compared
+    with the oracle run under its own filter index."""
+    spec = S.lingauss_c1(True)
+    model = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
+    N = [37, 150, 70, 33, 5, 12]
+    M = [32, 64, 100, 300, 1500, 1]
+    F, seed = len(N), 2024
+    ys = np.stack([S.simulate(spec, 3, 50 + f)[2] for f in range(F)], axis=1)  # [T][F][1]
+    ys = ys.astype(np.float32).astype(np.float64)
+    states = []
+    for f in range(F):
+        st = ladpf.init_state(model, N[f], M[f], seed, f)
+        st, _ = ladpf.step(model, st, ys[0, f], seed, f)
+        states.append(to_state32(st))
+    g = _filter(spec, N, M, seed)
+    g.import_state(torch.from_numpy(g.pack_state([s["t"] for s in states], [s["x"] for s in states],
+                                                 [s["z"] for s in states], [s["lam"] for s in states])))
+    g.lookahead_step(torch.tensor(ys[1], dtype=torch.float32))
+    out = g.unpack_state(g.export_state())
+    ell = g.copy_buffer(dpf.BUF_ELL).cpu().numpy()
+    logw = g.copy_buffer(dpf.BUF_LOGW).cpu().numpy()
+    anc = g.copy_buffer(dpf.BUF_ANC).cpu().numpy()
+    sel = g.copy_buffer(dpf.BUF_SEL).cpu().numpy()
+    oo = io = 0
+    for f in range(F):
+        n, m = N[f], M[f]
+        gs = {"x": out["x"][f], "z": out["z"][f], "lam": out["lam"][f]}
+        r, _, _ = compare_la(model, states[f], ys[1, f], seed, f, gs, ell[io:io + n * m].reshape(n, m),
+                             logw[oo:oo + n], anc[oo:oo + n], sel[oo:oo + n])
+        print("filter %d N=%d M=%d: %s" % (f, n, m, r.line()), flush=True)
+        assert_clean(r, max_flip_frac=0.05)
+        oo += n
+        io += n * m
+
+
+def test_graph_run_equals_step_calls_bit_for_bit():
+    spec = S.nonlin_c2(1)
+    N, M, T = [300, 64], [256, 50], 6
+    Y = np.stack([S.simulate(spec, T, 9 + f)[2] for f in range(2)], axis=1).astype(np.float32)
+    a = _filter(spec, N, M)
+    for t in range(T):
+        a.lookahead_step(torch.from_numpy(Y[t]))
+    sa = a.export_state().cpu().numpy()
+    ea = a.estimate()
+    b = _filter(spec, N, M)
+    xt, zt = b.run(torch.from_numpy(Y), use_graph=True)
+    sb = b.export_state().cpu().numpy()
+    eb = b.estimate()
+    assert np.array_equal(sa, sb)
+    assert torch.equal(ea["xhat"], eb["xhat"]) and torch.equal(ea["loglik"], eb["loglik"])
+    assert torch.equal(xt[-1], eb["xhat"])
+    c = _filter(spec, N, M)
+    c.run(torch.from_numpy(Y), use_graph=False)
+    assert np.array_equal(sa, c.export_state().cpu().numpy())
+
+
+def test_per_filter_horizons_and_resume():
+    spec = S.lingauss_c1()
+    N, M, T = [64, 128, 32], [50, 64, 100], 8
+    Tf = [8, 3, 5]
+    Y = np.stack([S.simulate(spec, T, 20 + f)[2] for f in range(3)], axis=1).astype(np.float32)
+    a = _filter(spec, N, M, seed=5)
+    xt, _ = a.run(torch.from_numpy(Y), Tf=Tf, use_graph=True)
+    s = a.unpack_state(a.export_state())
+    assert list(s["t"]) == Tf
+    xt = xt.cpu().numpy()
+    for f in range(3):
+        assert np.all(np.isfinite(xt[:Tf[f], f])) and np.all(np.isnan(xt[Tf[f]:, f]))
+    # the same filters stepped one at a time with an activity mask
+    b = _filter(spec, N, M, seed=5)
+    for t in range(T):
+        act = np.array([t < Tf[f] for f in range(3)], dtype=np.uint8)
+        b.lookahead_step(torch.from_numpy(Y[t]), active=act)
+    assert np.array_equal(a.export_state().cpu().numpy(), b.export_state().cpu().numpy())
+    # resume: export after 4 steps, import into a fresh handle, continue
+    c = _filter(spec, N, M, seed=5)
+    for t in range(4):
+        c.lookahead_step(torch.from_numpy(Y[t]))
+    blob = c.export_state()
+    d = _filter(spec, N, M, seed=5)
+    d.import_state(blob)
+    e = _filter(spec, N, M, seed=5)
+    for t in range(6):
+        e.lookahead_step(torch.from_numpy(Y[t]))
+    for t in range(4, 6):
+        d.lookahead_step(torch.from_numpy(Y[t]))
+    assert np.array_equal(d.export_state().cpu().numpy(), e.export_state().cpu().numpy())
+
+
+@pytest.mark.parametrize("algo", ["lookahead", "plain"])
+def test_nonfinite_observation_sets_flags_and_keeps_state_finite(algo):
+    spec = S.nonlin_c2(1)
+    f = _filter(spec, [50, 60], [64, 32], algo=algo)
+    y = np.zeros((2, 8), dtype=np.float32)
+    y[1, 3] = np.nan
+    step = f.lookahead_step if algo == "lookahead" else f.step
+    step(torch.from_numpy(y))
+    est = f.estimate()
+    fl = est["flags"].cpu().numpy()
+    assert fl[0] == 0
+    assert fl[1] & dpf.FLAG_NONFINITE and fl[1] & dpf.FLAG_DEGENERATE_OUTER
+    s = f.unpack_state(f.export_state())
+    assert np.all(np.isfinite(s["x"][1])) and np.all(np.isfinite(s["z"][1]))
+    # a later finite observation continues normally
+    step(torch.from_numpy(np.zeros((2, 8), dtype=np.float32)))
+    assert np.all(np.isfinite(f.estimate()["xhat"].cpu().numpy()))
+
+
+def test_two_runs_are_bit_identical():
+    spec = S.highdim_c4(1)
+    N, M = [16], [1024]
+    Y = S.simulate(spec, 3, 1)[2][:, None, :].astype(np.float32)
+    outs = []
+    for _ in range(2):
+        f = _filter(spec, N, M, seed=3)
+        f.run(torch.from_numpy(Y), use_graph=False)
+        outs.append(f.export_state().cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
