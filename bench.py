@@ -41,8 +41,8 @@ KERNEL_SOURCES = ["dpf_kernels.hpp", "dpf_models.hpp", "dpf_rng.hpp", "dpf_seg.h
 BYTES_PER_UPDATE = {"weights": 4 * DZ + 8, "newcloud": 8 * DZ + 12}
 # and per outer particle: weights reads x (4 dx) writes log w (4);
 # new cloud reads the ancestor (4) and the parent x (4 dx), writes x (4 dx),
-# the selected index (4) and the cloud partial sums (4 dz) and moments (8 dz).
-BYTES_PER_OUTER = {"weights": 4 * DX + 4, "newcloud": 4 + 8 * DX + 4 + 12 * DZ}
+# the selected index (4) and the cloud's partial sum (4 dz).
+BYTES_PER_OUTER = {"weights": 4 * DX + 4, "newcloud": 8 + 8 * DX + 4 * DZ}
 
 
 def kernel_source_digest():

@@ -175,15 +175,12 @@ dpf_status dpf_import_state(dpf_handle* h, const void* d_src, size_t bytes);
  * DPF_BUF_LOGW float [sum N]:   outer log-weights log w_i
  * DPF_BUF_ANC  int32 [sum N]:   outer ancestors A_k
  * DPF_BUF_SEL  int32 [sum N]:   selected candidate (look-ahead) or
- *                               inner ancestor a_k (plain) per new particle
- * DPF_BUF_MOM  float [sum N][2 dz]: qbar-weighted mean and variance of each
- *                               new inner cloud (look-ahead steps) */
+ *                               inner ancestor a_k (plain) per new particle */
 typedef enum {
   DPF_BUF_ELL = 0,
   DPF_BUF_LOGW = 1,
   DPF_BUF_ANC = 2,
-  DPF_BUF_SEL = 3,
-  DPF_BUF_MOM = 4
+  DPF_BUF_SEL = 3
 } dpf_buffer;
 dpf_status dpf_copy_buffer(dpf_handle* h, int32_t which, void* d_dst, size_t bytes);
 
@@ -212,9 +209,11 @@ dpf_status dpf_normals(uint64_t seed, uint32_t filter_id, uint32_t t, uint32_t p
                        int32_t n_b, int32_t D, float* d_out, void* hip_stream);
 
 /* Systematic resampling of one weight vector by the outer-resampling code:
- * d_w [n] non-negative doubles (not all zero), points ((k + u) C) / n_out,
- * d_out[k] = first i with C_i > point (C = inclusive FP64 cumulative sum).
- * d_scratch: n doubles of device memory (receives C). */
+ * d_w [n] non-negative doubles (not all zero), n <= 65536, points
+ * ((k + u) C) / n_out, d_out[k] = first i with C_i > point (C = inclusive
+ * FP64 cumulative sum; a point at or past the total takes the first i with
+ * C_i reaching it).  d_scratch: 4 * ceil(n / 256) doubles of device memory
+ * (per-group statistics). */
 dpf_status dpf_systematic(const double* d_w, int32_t n, int32_t n_out, double u, double* d_scratch,
                           int32_t* d_out, void* hip_stream);
 

@@ -19,7 +19,7 @@ DPF_ABI_VERSION = 1
 MODEL_LINGAUSS, MODEL_NONLIN, MODEL_HIGHDIM = 1, 2, 3
 ALGO_LOOKAHEAD, ALGO_PLAIN = 0, 1
 FLAG_DEGENERATE_OUTER, FLAG_DEGENERATE_INNER, FLAG_NONFINITE, FLAG_FALLBACK = 1, 2, 4, 8
-BUF_ELL, BUF_LOGW, BUF_ANC, BUF_SEL, BUF_MOM = range(5)
+BUF_ELL, BUF_LOGW, BUF_ANC, BUF_SEL = range(4)
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = [
@@ -277,8 +277,7 @@ class Filter:
     def copy_buffer(self, which):
         torch = _torch()
         sizes = {BUF_ELL: (self.NMT, torch.float32), BUF_LOGW: (self.NT, torch.float32),
-                 BUF_ANC: (self.NT, torch.int32), BUF_SEL: (self.NT, torch.int32),
-                 BUF_MOM: (self.NT * 2 * self.dz, torch.float32)}
+                 BUF_ANC: (self.NT, torch.int32), BUF_SEL: (self.NT, torch.int32)}
         n, dt = sizes[which]
         out = torch.empty(n, dtype=dt, device=self.device)
         _check(lib().dpf_copy_buffer(self._h, int(which), _ptr(out), out.numel() * out.element_size()))
@@ -291,6 +290,11 @@ class Filter:
             _check(lib().dpf_set_phase_events(self._h, None, 0))
             self._events = None
             return
+        torch = _torch()
+        for e in events:
+            if not e.cuda_event:  # torch creates the HIP event on first record
+                e.record(torch.cuda.current_stream(self.device))
+        torch.cuda.synchronize(self.device)
         arr = (ctypes.c_void_p * len(events))(*[ctypes.c_void_p(e.cuda_event) for e in events])
         self._events = (events, arr)
         _check(lib().dpf_set_phase_events(self._h, arr, len(events)))
@@ -329,7 +333,7 @@ def normals(seed, filter_id, t, purpose, n_a, n_b, D, device="cuda"):
 def systematic(w, n_out, u, device="cuda"):
     torch = _torch()
     w = torch.as_tensor(w, dtype=torch.float64, device=device).contiguous()
-    scratch = torch.empty_like(w)
+    scratch = torch.empty(4 * ((w.numel() + 255) // 256), dtype=torch.float64, device=device)
     out = torch.empty(int(n_out), dtype=torch.int32, device=device)
     _check(lib().dpf_systematic(_ptr(w), w.numel(), int(n_out), float(u), _ptr(scratch), _ptr(out),
                                 _stream_ptr(torch.device(device))))

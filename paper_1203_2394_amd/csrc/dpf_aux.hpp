@@ -10,23 +10,17 @@
 
 namespace dpf {
 
-// t = 0, state in copy `start_copy`, flags and evidence cleared.
-__global__ void k_reset(int* tcur, unsigned char* cur, uint32_t* flags, double* loglik, int F,
-                        int start_copy) {
+// t = 0, state in copy 0 (the plain DPF's initial proposals are written
+// there from the prior held in copy 1), flags and evidence cleared.
+__global__ void k_reset(int* tcur, unsigned char* cur, unsigned char* act, uint32_t* flags, double* loglik,
+                        int F) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
   tcur[f] = 0;
-  cur[f] = (unsigned char)start_copy;
+  cur[f] = 0;
+  act[f] = 1;
   flags[f] = 0u;
   loglik[f] = 0.0;
-}
-
-// Filter f steps while its time is below min(T_f, T).
-__global__ void k_active_mask(const int* tcur, const int* Tf, int T, unsigned char* active, int F) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= F) return;
-  const int lim = Tf ? min(Tf[f], T) : T;
-  active[f] = (unsigned char)(tcur[f] < lim ? 1 : 0);
 }
 
 // Element e of an array of per-filter segments: find the filter by binary
@@ -107,13 +101,30 @@ __global__ void k_normals_grid(Key key, uint32_t t, uint32_t purpose, int na, in
   for (int d = 0; d < D; ++d) out[e * D + d] = v[d];
 }
 
-__global__ __launch_bounds__(kResBlock) void k_systematic_prim(const double* w, int n, int n_out,
-                                                                double u, double* C, int* out) {
+// Systematic resampling of one FP64 weight vector by the outer-resampling
+// code of the step (group statistics, then points resolved 256 per
+// workgroup by the same device function the new-cloud kernel uses).
+__global__ __launch_bounds__(kBlock) void k_prim_res_stats(const double* w, int n, double* gstat) {
   __shared__ ResScratch sh;
-  for (int i = threadIdx.x; i < n; i += kResBlock) C[i] = w[i];
-  __syncthreads();
-  block_scan_inplace(C, n, sh);
-  block_systematic(C, n, n_out, u, out);
+  float mg;
+  double sg, qg;
+  res_group_stat(LinSrc{w}, n, blockIdx.x, mg, sg, qg, sh);
+  if (threadIdx.x == 0) {
+    gstat[4 * blockIdx.x + 0] = (double)mg;
+    gstat[4 * blockIdx.x + 1] = sg;
+    gstat[4 * blockIdx.x + 2] = qg;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_prim_res_select(const double* w, int n, int n_out, double u,
+                                                            const double* gstat, int* out) {
+  __shared__ ResScratch sh;
+  __shared__ int res[kBlock];
+  const int G = (n + kResGroup - 1) / kResGroup;
+  const int k0 = blockIdx.x * kBlock;
+  const int np = min(kBlock, n_out - k0);
+  resolve_points(LinSrc{w}, n, n_out, u, k0, np, gstat, G, res, sh, false);
+  if (threadIdx.x < np) out[k0 + threadIdx.x] = res[threadIdx.x];
 }
 
 // One segment per (S index); the cdf build and search are those of k_newcloud.

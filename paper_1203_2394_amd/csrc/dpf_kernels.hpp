@@ -7,15 +7,21 @@
 //   z    [sum N*DZ*M]         z[(io + i*M) * DZ + d*M + j] ([N][DZ][M] per filter)
 //   lam  [sum N*M]            lam[io + i*M + j]           (log qbar, eq:qbar)
 //   ell  [sum N*M]            look-ahead / measurement log-weights
-//   logw [NT], anc [NT], kpart [NT][DZ], cdf [NT] (FP64)
+//   logw [NT], anc [NT], sel [NT], kpart [NT][DZ]
 // x, z and lam are double-buffered; cur[f] says which copy holds the state of
 // filter f, so filters that sit a step out keep their state without a copy.
+//
+// A step is four launches: weights (one workgroup per tile of outer
+// particles), two small resampling kernels (one workgroup per group of 256
+// outer weights), and the new-cloud kernel, whose last workgroup per filter
+// also forms the estimates and advances the filter (no separate launch).
 //
 // Per-particle kernels run one 256-thread workgroup per tile of 256/SEG
 // consecutive outer particles of one filter (a "segment" of SEG lanes per
 // particle, lane l handling inner indices l, l+SEG, ..., up to SEG*JPT).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <math.h>
 #include <stdint.h>
 
@@ -32,19 +38,32 @@ enum FlagBits : uint32_t {
   F_FALLBACK = 8u
 };
 
+constexpr int kResGroup = 256;  // outer weights per resampling workgroup
+
+// Per-filter bookkeeping for the resampling groups.
+struct FilterInfo {
+  int rg_base;  // first resampling group of the filter
+  int ngroup;   // its number of groups
+  int pad0, pad1;
+};
+
 struct StepArgs {
   const float* prm;
-  const int2* tiles;  // (filter, first outer index)
+  const int4* tiles;  // (filter, first outer index, tile index within filter, 0)
   const int* fN;
   const int* fM;
   const int* ooff;
   const long long* ioff;
+  const FilterInfo* finfo;
   int NT;
-  int t_offset;  // counter time = tcur[f] + t_offset
+  int advance;   // 1: a step (time advances, estimates); 0: initialisation
   uint64_t seed;
-  int* tcur;
-  unsigned char* cur;
-  const unsigned char* active;
+  int* tcur;             // [F] time of the state (advanced by the statistics kernel)
+  unsigned char* cur;    // [F] copy holding the state (flipped with the time)
+  unsigned char* act;    // [F] whether the filter takes the current step (set by the weights kernel)
+  const unsigned char* active;  // [F] or null
+  const int* run_Tf;            // [F] or null: filter steps while tcur < min(run_Tf, run_T)
+  int run_T;
   const float* Y;
   long long y_tstride;  // y of filter f at time t: Y + (t-1) * y_tstride + f * DY
   float* x[2];
@@ -54,9 +73,8 @@ struct StepArgs {
   float* logw;
   int* anc;
   int* sel;      // [NT] selected candidate (look-ahead) / inner ancestor (plain)
-  float* kpart;  // [NT][DZ]
-  float* mom;    // [NT][2*DZ] or null: qbar-weighted moments of each new cloud
-  double* cdf;   // [NT]
+  float* kpart;  // [NT][DZ] per-particle sum_j qbar z (plain: of the proposals)
+  double* gstat;  // [resampling groups][4]: group max log w, sum, sum of squares (group scale)
   double* fstat;  // [F][4]: max log w, sum w, sum w^2, degenerate (0/1)
   float* ess;     // [F]
   double* dlogz;  // [F]
@@ -70,8 +88,13 @@ struct StepArgs {
   int dy;
 };
 
-__device__ __forceinline__ bool filter_active(const StepArgs& a, int f) {
-  return a.active == nullptr || a.active[f] != 0;
+// Whether filter f takes this step: the caller's mask and the run limits,
+// evaluated by the weights kernel (before the time advances) and recorded in
+// act[f] for the later kernels of the step.
+__device__ __forceinline__ bool step_active(const StepArgs& a, int f) {
+  if (a.active != nullptr && a.active[f] == 0) return false;
+  const int lim = a.run_Tf ? min(a.run_Tf[f], a.run_T) : a.run_T;
+  return a.tcur[f] < lim;
 }
 
 template <class Mdl>
@@ -103,6 +126,28 @@ __device__ __forceinline__ float seg_lse(Lse l, SegScratch& sh) {
   return (m == -INFINITY) ? -INFINITY : m + fast_log(s);
 }
 
+// Block-wide (256 threads) FP64 reductions and scans in a fixed order:
+// DPP within each wave, then the four wave results in order.
+__device__ __forceinline__ double block_sum_256(double v, double* red4) {
+  v = seg_reduce_wave<OpAdd, kWave>(v);
+  if ((threadIdx.x & (kWave - 1)) == 0) red4[threadIdx.x / kWave] = v;
+  __syncthreads();
+  const double r = ((red4[0] + red4[1]) + red4[2]) + red4[3];
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ double block_scan_incl_256(double v, double* red4) {
+  const int w = threadIdx.x / kWave;
+  v = seg_scan_wave<kWave>(v);
+  if ((threadIdx.x & (kWave - 1)) == kWave - 1) red4[w] = v;
+  __syncthreads();
+  double pre = 0.0;
+  for (int q = 0; q < w; ++q) pre += red4[q];
+  __syncthreads();
+  return v + pre;
+}
+
 // ------------------------------------------------------------ initialisation
 // Prior draws [x_0; z_0] ~ N(0, I) (INIT_X at (0, i, 0), INIT_Z at (0, i, j)).
 // Look-ahead state: lam_0 = -log M, written to copy 0.  Plain DPF: the prior
@@ -110,7 +155,7 @@ __device__ __forceinline__ float seg_lse(Lse l, SegScratch& sh) {
 // kernel runs with t = 0 (no y_0 is consumed).
 template <class Mdl, int SEG, int JPT, bool PLAIN>
 __global__ __launch_bounds__(kBlock) void k_init(StepArgs a) {
-  const int2 tile = a.tiles[blockIdx.x];
+  const int4 tile = a.tiles[blockIdx.x];
   const int f = tile.x;
   const int N = a.fN[f], M = a.fM[f];
   const int i = tile.y + threadIdx.x / SEG;
@@ -151,16 +196,18 @@ __global__ __launch_bounds__(kBlock) void k_init(StepArgs a) {
 template <class Mdl, int SEG, int JPT>
 __global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
   __shared__ SegScratch sh;
-  const int2 tile = a.tiles[blockIdx.x];
+  const int4 tile = a.tiles[blockIdx.x];
   const int f = tile.x;
-  if (!filter_active(a, f)) return;
+  const bool act = step_active(a, f);
+  if (tile.z == 0 && threadIdx.x == 0) a.act[f] = act ? 1 : 0;
+  if (!act) return;
   const int N = a.fN[f], M = a.fM[f];
   const int i = tile.y + threadIdx.x / SEG;
   const int ls = threadIdx.x % SEG;
   const bool vi = i < N;
   const int oo = a.ooff[f];
   const long long io = a.ioff[f];
-  const int t = a.tcur[f] + a.t_offset;
+  const int t = a.tcur[f] + 1;
   const int src = a.cur[f];
   const Key key = make_key(a.seed, (uint32_t)f);
 
@@ -204,16 +251,19 @@ __global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
 template <class Mdl, int SEG, int JPT>
 __global__ __launch_bounds__(kBlock) void k_dpf_weights(StepArgs a) {
   __shared__ SegScratch sh;
-  const int2 tile = a.tiles[blockIdx.x];
+  __shared__ float vred[kBlock / kWave][Mdl::DZ];
+  const int4 tile = a.tiles[blockIdx.x];
   const int f = tile.x;
-  if (!filter_active(a, f)) return;
+  const bool act = step_active(a, f);
+  if (tile.z == 0 && threadIdx.x == 0) a.act[f] = act ? 1 : 0;
+  if (!act) return;
   const int N = a.fN[f], M = a.fM[f];
   const int i = tile.y + threadIdx.x / SEG;
   const int ls = threadIdx.x % SEG;
   const bool vi = i < N;
   const int oo = a.ooff[f];
   const long long io = a.ioff[f];
-  const int t = a.tcur[f] + a.t_offset;
+  const int t = a.tcur[f] + 1;
   const int src = a.cur[f];
 
   float y[Mdl::DY], x[Mdl::DX], r0[Mdl::DY];
@@ -253,10 +303,10 @@ __global__ __launch_bounds__(kBlock) void k_dpf_weights(StepArgs a) {
       for (int d = 0; d < Mdl::DZ; ++d) part[d] += q * zrow[d * M + j];
     }
   }
-#pragma unroll
-  for (int d = 0; d < Mdl::DZ; ++d) part[d] = seg_sum<SEG>(part[d], sh);
+  seg_sum_vec<SEG, Mdl::DZ>(part, vred);
+  const float lw = deg ? -INFINITY : lse - fast_log((float)M);
   if (vi && ls == 0) {
-    a.logw[oo + i] = deg ? -INFINITY : lse - fast_log((float)M);
+    a.logw[oo + i] = lw;
 #pragma unroll
     for (int d = 0; d < Mdl::DZ; ++d) a.kpart[(long long)(oo + i) * Mdl::DZ + d] = part[d];
     if (deg) atomicOr(&a.flags[f], (uint32_t)F_DEGENERATE_INNER);
@@ -264,119 +314,267 @@ __global__ __launch_bounds__(kBlock) void k_dpf_weights(StepArgs a) {
 }
 
 // -------------------------------------------------------- outer resampling
-// One 1024-thread workgroup per filter.  Weights w_i = exp(log w_i - max)
-// (FP32 exponent, widened), FP64 inclusive scan (serial within a chunk of
-// consecutive indices per thread, then across chunks), systematic points
-// ((k + u) * C) / N with u = U53 at (t, 0, 0) of OUTER_U, first index with
-// C_i > point.  Also ESS = C^2 / sum w^2 and dlogZ = max + log C - log N.
-constexpr int kResBlock = 1024;
+// Systematic resampling of the N outer weights w_i = exp(log w_i - max)
+// (Fig. 4 step 3; Fig. 2 step 2), organised around groups of 256 weights.
+// Group g carries its own shift m_g = max of its log-weights, the FP64 sum
+// s_g of exp(log w_i - m_g) and the sum of squares q_g (one workgroup per
+// group, k_res_stats).  A workgroup that needs ancestors combines the
+// statistics -- m = max_g m_g, c_g = exp(m_g - m), T_g = c_g s_g, offsets
+// B_g = inclusive scan of T -- always with the same code in the same order,
+// so every workgroup agrees bit for bit on them; group g's cumulative weights
+// are C_i = min(B_g + c_g L_i, B_{g+1}) (L: inclusive FP64 scan of its
+// terms), its last one B_{g+1}: monotone, with shared boundaries.  A
+// systematic point ((k + u) C_total) / N lies in the first group with
+// B_{g+1} > point and takes the first index there with C_i > point (a point
+// at or past the total takes the first index reaching the total).  The new
+// particles' workgroups resolve their own ancestors this way, so no
+// separate selection launch is needed.
 
-struct ResScratch {
-  double part[kResBlock];
-  float fred[kResBlock / kWave];
-  double dred[kResBlock / kWave];
+// Log-weight source: FP32 log-weights, FP32 exponent of the shifted value.
+struct LogSrc {
+  const float* lw;
+  static constexpr bool kLog = true;
+  __device__ float key(int i) const {
+    const float v = lw[i];
+    return finitef(v) ? v : -INFINITY;
+  }
+  __device__ double val(int i, float mg) const {
+    const float v = lw[i];
+    return finitef(v) ? (double)fast_exp(v - mg) : 0.0;
+  }
 };
 
-__device__ __forceinline__ float block_max_1024(float v, ResScratch& sh) {
-  for (int off = kWave / 2; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, kWave));
-  if ((threadIdx.x & (kWave - 1)) == 0) sh.fred[threadIdx.x / kWave] = v;
+// Linear FP64 weights as given (kernel-level primitive).
+struct LinSrc {
+  const double* w;
+  static constexpr bool kLog = false;
+  __device__ float key(int) const { return 0.f; }
+  __device__ double val(int i, float) const { return w[i]; }
+};
+
+__device__ __forceinline__ float block_max_256(float v, float* red4) {
+  v = seg_reduce_wave<OpMax, kWave>(v);
+  if ((threadIdx.x & (kWave - 1)) == 0) red4[threadIdx.x / kWave] = v;
   __syncthreads();
-  float r = sh.fred[0];
-  for (int q = 1; q < kResBlock / kWave; ++q) r = fmaxf(r, sh.fred[q]);
+  const float r = fmaxf(fmaxf(red4[0], red4[1]), fmaxf(red4[2], red4[3]));
   __syncthreads();
   return r;
 }
 
-__device__ __forceinline__ double block_sum_1024(double v, ResScratch& sh) {
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  if ((threadIdx.x & (kWave - 1)) == 0) sh.dred[threadIdx.x / kWave] = v;
+// Scale of group g relative to the global shift, exp(m_g - m) in (0, 1]
+// (FP32 exponent widened; every workgroup evaluates it identically).
+template <class Src>
+__device__ __forceinline__ double group_scale(float mg, float m) {
+  if (!Src::kLog) return 1.0;
+  return mg > -INFINITY ? (double)fast_exp(mg - m) : 0.0;
+}
+
+struct ResScratch {
+  double B[kBlock + 1];   // group offsets (at most 256 groups)
+  double C[kResGroup];    // cumulative weights of the group being resolved
+  double P[kBlock];       // points of this workgroup
+  int gsel[kBlock];       // their groups
+  double red4[kBlock / kWave];
+  float fred4[kBlock / kWave];
+};
+
+// Statistics (m_g, s_g, q_g) of group g.
+template <class Src>
+__device__ void res_group_stat(const Src& src, int n, int g, float& mg, double& sg, double& qg,
+                               ResScratch& sh) {
+  const int i = g * kResGroup + threadIdx.x;
+  const float key = i < n ? src.key(i) : -INFINITY;
+  mg = Src::kLog ? block_max_256(key, sh.fred4) : 0.f;
+  const double v = (i < n && (!Src::kLog || mg > -INFINITY)) ? src.val(i, mg) : 0.0;
+  sg = block_sum_256(v, sh.red4);
+  qg = block_sum_256(v * v, sh.red4);
+}
+
+struct ResResult {
+  float m;       // max log-weight (0 for linear weights or when degenerate)
+  double total;  // sum of the weights exp(log w - m)
+  double sumsq;  // sum of their squares
+  bool deg;      // no finite log-weight: uniform weights were used
+};
+
+// Ancestors res[j] of the points k0 + j, j < np (np <= 256), from the G group
+// statistics gstat [G][4] (m_g, s_g, q_g, -).  want_sumsq: also return the
+// sum of squared weights (for the effective sample size).
+template <class Src>
+__device__ ResResult resolve_points(const Src& src, int n, int n_out, double u, int k0, int np,
+                                    const double* gstat, int G, int* res, ResScratch& sh, bool want_sumsq) {
+  const int th = threadIdx.x;
+  const float gm_t = th < G ? (float)gstat[4 * th] : -INFINITY;
+  const float m = Src::kLog ? block_max_256(gm_t, sh.fred4) : 0.f;
+  const bool deg = Src::kLog && !(m > -INFINITY);
+  double T = 0.0, Q = 0.0;
+  if (th < G) {
+    if (deg) {
+      T = Q = (double)min(kResGroup, n - th * kResGroup);
+    } else {
+      const double c = group_scale<Src>(gm_t, m);
+      T = c * gstat[4 * th + 1];
+      Q = (c * c) * gstat[4 * th + 2];
+    }
+  }
+  sh.B[th + 1] = block_scan_incl_256(T, sh.red4);  // its barriers order the writes below
+  if (th == 0) sh.B[0] = 0.0;
+  const double sumsq = want_sumsq ? block_sum_256(Q, sh.red4) : 0.0;
   __syncthreads();
-  double r = 0.0;
-  for (int q = 0; q < kResBlock / kWave; ++q) r += sh.dred[q];
+  const double total = sh.B[G];
+  if (th < np) {
+    const double P = sys_point(k0 + th, u, total, n_out);
+    int lo = 0, hi = G;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sh.B[mid + 1] > P)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    if (lo == G) {
+      lo = 0;
+      hi = G - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (sh.B[mid + 1] >= total)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+    }
+    sh.P[th] = P;
+    sh.gsel[th] = lo;
+  }
   __syncthreads();
+  // points are non-decreasing, so their groups are too: visit each distinct one
+  for (int j0 = 0; j0 < np;) {
+    const int g = sh.gsel[j0];
+    int j1 = j0 + 1;
+    while (j1 < np && sh.gsel[j1] == g) ++j1;
+    const int base = g * kResGroup;
+    const int nloc = min(kResGroup, n - base);
+    const float mg = Src::kLog ? (float)gstat[4 * g] : 0.f;
+    const double cg = deg ? 1.0 : group_scale<Src>(mg, m);
+    double v = 0.0;
+    if (th < nloc) v = deg ? 1.0 : ((!Src::kLog || mg > -INFINITY) ? src.val(base + th, mg) : 0.0);
+    const double L = block_scan_incl_256(v, sh.red4);
+    const double Bg = sh.B[g], Bg1 = sh.B[g + 1];
+    if (th < nloc) sh.C[th] = (th == nloc - 1) ? Bg1 : fmin(Bg + cg * L, Bg1);
+    __syncthreads();
+    if (th >= j0 && th < j1) res[th] = base + cdf_search(sh.C, nloc, sh.P[th]);
+    __syncthreads();
+    j0 = j1;
+  }
+  ResResult r;
+  r.m = deg ? 0.f : m;
+  r.total = total;
+  r.sumsq = sumsq;
+  r.deg = deg;
   return r;
 }
 
-// In-place FP64 inclusive scan of C[0..n) by one 1024-thread block.
-__device__ void block_scan_inplace(double* C, int n, ResScratch& sh) {
-  const int ch = (n + kResBlock - 1) / kResBlock;
-  const int lo = threadIdx.x * ch;
-  const int hi = min(lo + ch, n);
-  double s = 0.0;
-  for (int q = lo; q < hi; ++q) s += C[q];
-  sh.part[threadIdx.x] = s;
-  __syncthreads();
-  // exclusive scan of chunk sums (Hillis-Steele over the 1024 partials)
-  for (int d = 1; d < kResBlock; d <<= 1) {
-    const double o = (threadIdx.x >= d) ? sh.part[threadIdx.x - d] : 0.0;
-    __syncthreads();
-    sh.part[threadIdx.x] += o;
-    __syncthreads();
-  }
-  double run = (threadIdx.x > 0) ? sh.part[threadIdx.x - 1] : 0.0;
-  for (int q = lo; q < hi; ++q) {
-    run += C[q];
-    C[q] = run;
-  }
-  __syncthreads();
+// Filter-level bookkeeping of the outer resampling (one thread per filter).
+__device__ void res_finish(const StepArgs& a, int f, int t, int N, const ResResult& r) {
+  a.fstat[4 * f + 0] = r.deg ? 0.0 : (double)r.m;
+  a.fstat[4 * f + 1] = r.total;
+  a.fstat[4 * f + 2] = r.sumsq;
+  a.fstat[4 * f + 3] = r.deg ? 1.0 : 0.0;
+  a.ess[f] = (float)(r.total * r.total / r.sumsq);
+  const double dl = r.deg ? -INFINITY : (double)r.m + log(r.total) - log((double)N);
+  a.dlogz[f] = dl;
+  a.loglik[f] += dl;
+  uint32_t fl = r.deg ? (uint32_t)F_DEGENERATE_OUTER : 0u;
+  const float* yp = a.Y + (long long)(t - 1) * a.y_tstride + (long long)f * a.dy;
+  for (int q = 0; q < a.dy; ++q)
+    if (!finitef(yp[q])) fl |= F_NONFINITE;
+  if (fl) atomicOr(&a.flags[f], fl);
 }
 
-__device__ void block_systematic(const double* C, int n, int n_out, double u, int* out) {
-  const double total = C[n - 1];
-  for (int k = threadIdx.x; k < n_out; k += kResBlock) out[k] = cdf_search(C, n, sys_point(k, u, total, n_out));
-}
-
-__global__ __launch_bounds__(kResBlock) void k_outer_resample(StepArgs a) {
+// Group statistics; group 0's workgroup also advances the filter's time and
+// flips its state copy (no other workgroup of this launch reads them).
+__global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const int2* rgroups) {
   __shared__ ResScratch sh;
-  const int f = blockIdx.x;
-  if (!filter_active(a, f)) return;
+  const int2 rg = rgroups[blockIdx.x];
+  const int f = rg.x;
+  if (!a.act[f]) return;
   const int N = a.fN[f];
   const int oo = a.ooff[f];
-  const int t = a.tcur[f] + a.t_offset;
-  const float* lw = a.logw + oo;
-  double* C = a.cdf + oo;
-
-  float m = -INFINITY;
-  bool nonf = false;
-  for (int i = threadIdx.x; i < N; i += kResBlock) {
-    const float v = lw[i];
-    if (finitef(v))
-      m = fmaxf(m, v);
-    else if (!(v == -INFINITY))
-      nonf = true;
-  }
-  m = block_max_1024(m, sh);
-  const bool deg = !(m > -INFINITY);
-  double sq = 0.0;
-  for (int i = threadIdx.x; i < N; i += kResBlock) {
-    const float v = lw[i];
-    const double w = deg ? 1.0 : (finitef(v) ? (double)fast_exp(v - m) : 0.0);
-    C[i] = w;
-    sq += w * w;
-  }
-  sq = block_sum_1024(sq, sh);
-  const int any_nonf = __syncthreads_or(nonf ? 1 : 0);
-  block_scan_inplace(C, N, sh);
-  const double total = C[N - 1];
-  const Key key = make_key(a.seed, (uint32_t)f);
-  const double u = uniform53(key, (uint32_t)t, 0u, P_OUTER_U);
-  block_systematic(C, N, N, u, a.anc + oo);
+  float mg;
+  double sg, qg;
+  res_group_stat(LogSrc{a.logw + oo}, N, rg.y, mg, sg, qg, sh);
+  const int i = rg.y * kResGroup + threadIdx.x;
+  const float v = i < N ? a.logw[oo + i] : 0.f;
+  const int nonf = __syncthreads_or((!finitef(v) && !(v == -INFINITY)) ? 1 : 0);
   if (threadIdx.x == 0) {
-    a.fstat[4 * f + 0] = deg ? 0.0 : (double)m;
-    a.fstat[4 * f + 1] = total;
-    a.fstat[4 * f + 2] = sq;
-    a.fstat[4 * f + 3] = deg ? 1.0 : 0.0;
-    a.ess[f] = (float)(total * total / sq);
-    const double dl = deg ? -INFINITY : (double)m + log(total) - log((double)N);
-    a.dlogz[f] = dl;
-    a.loglik[f] += dl;
-    uint32_t fl = 0;
-    if (deg) fl |= F_DEGENERATE_OUTER;
-    if (any_nonf) fl |= F_NONFINITE;
-    const float* yp = a.Y + (long long)(t - 1) * a.y_tstride + (long long)f * a.dy;
-    for (int q = 0; q < a.dy; ++q)
-      if (!finitef(yp[q])) fl |= F_NONFINITE;
-    if (fl) atomicOr(&a.flags[f], fl);
+    double* gs = a.gstat + 4LL * (a.finfo[f].rg_base + rg.y);
+    gs[0] = (double)mg;
+    gs[1] = sg;
+    gs[2] = qg;
+    if (nonf) atomicOr(&a.flags[f], (uint32_t)F_NONFINITE);
+    if (rg.y == 0) {
+      a.tcur[f] = a.tcur[f] + 1;
+      a.cur[f] = (unsigned char)(a.cur[f] ^ 1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- estimates
+// One workgroup per filter, FP64 sums in a fixed order (strided per thread,
+// then DPP and the wave results in order), so results are reproducible:
+//   look-ahead: xhat = mean_k x_t^(k), zhat = mean_k sum_j qbar z  (new copy)
+//   plain:      xhat = sum_i Wbar_i xt_i, zhat = sum_i Wbar_i sum_j qbar z
+//               over the proposals weighted at this step (previous copy)
+template <int DX, int DZ>
+constexpr int fin_block() { return DX + DZ > 16 ? 256 : 1024; }
+
+template <int DX, int DZ, bool PLAIN>
+__global__ __launch_bounds__((fin_block<DX, DZ>())) void k_finalize(StepArgs a) {
+  constexpr int NV = DX + DZ;
+  constexpr int BS = fin_block<DX, DZ>();
+  __shared__ double red[NV][BS / kWave];
+  const int f = blockIdx.x;
+  if (!a.act[f]) return;
+  const int N = a.fN[f];
+  const int oo = a.ooff[f];
+  const int t = a.tcur[f];
+  const float* xs = a.x[PLAIN ? a.cur[f] ^ 1 : a.cur[f]];
+  double mx = 0.0, tot = 1.0;
+  bool deg = false;
+  if (PLAIN) {
+    mx = a.fstat[4 * f + 0];
+    tot = a.fstat[4 * f + 1];
+    deg = a.fstat[4 * f + 3] != 0.0;
+  }
+  double acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  for (int i = threadIdx.x; i < N; i += BS) {
+    double w;
+    if (PLAIN) {
+      const float lw = a.logw[oo + i];
+      w = deg ? 1.0 / N : (finitef(lw) ? (double)fast_exp(lw - (float)mx) / tot : 0.0);
+    } else {
+      w = 1.0 / N;
+    }
+    for (int d = 0; d < DX; ++d) acc[d] += w * (double)xs[(long long)d * a.NT + oo + i];
+    for (int d = 0; d < DZ; ++d) acc[DX + d] += w * (double)a.kpart[(long long)(oo + i) * DZ + d];
+  }
+  for (int q = 0; q < NV; ++q) {
+    const double v = seg_reduce_wave<OpAdd, kWave>(acc[q]);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[q][threadIdx.x / kWave] = v;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < NV; q += BS) {
+    double v = 0.0;
+    for (int w = 0; w < BS / kWave; ++w) v += red[q][w];
+    if (q < DX) {
+      a.est_x[f * DX + q] = (float)v;
+      if (a.trace_x) a.trace_x[((long long)(t - 1) * a.n_filters + f) * DX + q] = (float)v;
+    } else {
+      a.est_z[f * DZ + q - DX] = (float)v;
+      if (a.trace_z) a.trace_z[((long long)(t - 1) * a.n_filters + f) * DZ + q - DX] = (float)v;
+    }
   }
 }
 
@@ -397,14 +595,18 @@ template <class Mdl, int SEG, int JPT, bool PLAIN>
 __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
   constexpr int DX = Mdl::DX, DZ = Mdl::DZ, DY = Mdl::DY;
   constexpr int NSEG = kBlock / SEG;
+  constexpr bool kKeepZ = JPT * DZ <= 64;  // new z stays in registers for the partial sums
   __shared__ SegScratch sh;
   __shared__ double cdf[NSEG][SEG * JPT];
   __shared__ float xs_sh[NSEG][DX];
   __shared__ int csel[NSEG];
+  __shared__ int anc_sh[NSEG];
+  __shared__ float vred[kBlock / kWave][DZ];
+  __shared__ ResScratch rsh;
 
-  const int2 tile = a.tiles[blockIdx.x];
+  const int4 tile = a.tiles[blockIdx.x];
   const int f = tile.x;
-  if (!filter_active(a, f)) return;
+  if (!a.act[f]) return;
   const int N = a.fN[f], M = a.fM[f];
   const int s = threadIdx.x / SEG;
   const int ls = threadIdx.x % SEG;
@@ -412,10 +614,24 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
   const bool vk = k < N;
   const int oo = a.ooff[f];
   const long long io = a.ioff[f];
-  const int t = a.tcur[f] + a.t_offset;
-  const int src = a.cur[f], dst = src ^ 1;
+  const int t = a.tcur[f];  // already advanced (0 at initialisation)
+  const int dst = a.cur[f], src = dst ^ 1;
   const Key key = make_key(a.seed, (uint32_t)f);
-  const int p = vk ? a.anc[oo + k] : 0;
+
+  // ---- 0. outer ancestors of this tile's new particles -------------------
+  if (a.advance) {
+    const int np = min(NSEG, N - tile.y);
+    const int G = a.finfo[f].ngroup;
+    const double u = uniform53(key, (uint32_t)t, 0u, P_OUTER_U);
+    const ResResult rr = resolve_points(LogSrc{a.logw + oo}, N, N, u, tile.y, np,
+                                        a.gstat + 4LL * a.finfo[f].rg_base, G, anc_sh, rsh, tile.z == 0);
+    if (tile.z == 0 && threadIdx.x == 0) res_finish(a, f, t, N, rr);
+  } else if (threadIdx.x < NSEG) {
+    anc_sh[threadIdx.x] = tile.y + threadIdx.x;  // initial proposals: every particle its own parent
+  }
+  __syncthreads();
+  const int p = vk ? anc_sh[s] : 0;
+  if (vk && ls == 0) a.anc[oo + k] = p;
 
   float xp[DX];
 #pragma unroll
@@ -523,6 +739,7 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
   }
   float* zdst = a.z[dst] + (io + (long long)k * M) * DZ;
   float llv[JPT];
+  float zkeep[kKeepZ ? JPT : 1][DZ];
   Lse acc;
 #pragma unroll
   for (int r = 0; r < JPT; ++r) {
@@ -537,6 +754,10 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
       Mdl::fz_post(a.prm, pre, zg, nu, zn);
 #pragma unroll
       for (int d = 0; d < DZ; ++d) zdst[d * M + jj] = zn[d];
+      if constexpr (kKeepZ) {
+#pragma unroll
+        for (int d = 0; d < DZ; ++d) zkeep[kKeepZ ? r : 0][d] = zn[d];
+      }
       if (!PLAIN) {
         llv[r] = Mdl::logpy_post(a.prm, r0, zn);
         acc.add(llv[r]);
@@ -549,9 +770,9 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
     const bool deg3 = !(lse > -INFINITY);
     if (deg3) fl |= F_DEGENERATE_INNER;
     float* ldst = a.lam[dst] + io + (long long)k * M;
-    float part[DZ], part2[DZ];
+    float part[DZ];
 #pragma unroll
-    for (int d = 0; d < DZ; ++d) part[d] = part2[d] = 0.f;
+    for (int d = 0; d < DZ; ++d) part[d] = 0.f;
 #pragma unroll
     for (int r = 0; r < JPT; ++r) {
       const int jj = ls + r * SEG;
@@ -561,96 +782,18 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
         const float q = deg3 ? 1.0f / (float)M : (finitef(llv[r]) ? fast_exp(lam) : 0.f);
 #pragma unroll
         for (int d = 0; d < DZ; ++d) {
-          const float zv = zdst[d * M + jj];
+          const float zv = kKeepZ ? zkeep[kKeepZ ? r : 0][d] : zdst[d * M + jj];
           part[d] += q * zv;
-          part2[d] += q * zv * zv;
         }
       }
     }
-#pragma unroll
-    for (int d = 0; d < DZ; ++d) part[d] = seg_sum<SEG>(part[d], sh);
-    if (a.mom != nullptr) {
-#pragma unroll
-      for (int d = 0; d < DZ; ++d) part2[d] = seg_sum<SEG>(part2[d], sh);
-    }
+    seg_sum_vec<SEG, DZ>(part, vred);
     if (vk && ls == 0) {
 #pragma unroll
       for (int d = 0; d < DZ; ++d) a.kpart[(long long)(oo + k) * DZ + d] = part[d];
-      if (a.mom != nullptr) {
-#pragma unroll
-        for (int d = 0; d < DZ; ++d) {
-          a.mom[(long long)(oo + k) * 2 * DZ + d] = part[d];
-          a.mom[(long long)(oo + k) * 2 * DZ + DZ + d] = fmaxf(part2[d] - part[d] * part[d], 0.f);
-        }
-      }
     }
   }
   if (vk && ls == 0 && fl) atomicOr(&a.flags[f], fl);
-}
-
-// ---------------------------------------------------------------- estimates
-// One workgroup per filter; FP64 sums in a fixed order (strided per thread,
-// then a fixed tree), so results are reproducible run to run.
-//   look-ahead: xhat = mean_k x_t^(k), zhat = mean_k sum_j qbar z
-//   plain:      xhat = sum_i Wbar_i xt_i, zhat = sum_i Wbar_i sum_j qbar z
-// Then the state copy flips and the filter's time advances.
-template <int DX, int DZ, bool PLAIN>
-__global__ __launch_bounds__(kBlock) void k_finalize(StepArgs a, int advance) {
-  __shared__ double red[DX + DZ][kBlock / kWave];
-  const int f = blockIdx.x;
-  if (!filter_active(a, f)) return;
-  const int N = a.fN[f];
-  const int oo = a.ooff[f];
-  const int src = a.cur[f];
-  const int t = a.tcur[f] + a.t_offset;
-  if (advance) {
-    const float* xs = PLAIN ? a.x[src] : a.x[src ^ 1];
-    double mx = 0.0, tot = 1.0;
-    if (PLAIN) {
-      mx = a.fstat[4 * f + 0];
-      tot = a.fstat[4 * f + 1];
-    }
-    const bool deg = PLAIN && a.fstat[4 * f + 3] != 0.0;
-    double acc[DX + DZ];
-#pragma unroll
-    for (int q = 0; q < DX + DZ; ++q) acc[q] = 0.0;
-    for (int i = threadIdx.x; i < N; i += kBlock) {
-      double w;
-      if (PLAIN) {
-        const float lw = a.logw[oo + i];
-        w = finitef(lw) ? (double)fast_exp((float)((double)lw - mx)) / tot : 0.0;
-        if (deg) w = 1.0 / N;
-      } else {
-        w = 1.0 / N;
-      }
-#pragma unroll
-      for (int d = 0; d < DX; ++d) acc[d] += w * (double)xs[(long long)d * a.NT + oo + i];
-#pragma unroll
-      for (int d = 0; d < DZ; ++d) acc[DX + d] += w * (double)a.kpart[(long long)(oo + i) * DZ + d];
-    }
-#pragma unroll
-    for (int q = 0; q < DX + DZ; ++q) {
-      double v = acc[q];
-      for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-      if ((threadIdx.x & (kWave - 1)) == 0) red[q][threadIdx.x / kWave] = v;
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < DX + DZ; q += kBlock) {
-      double v = 0.0;
-      for (int w = 0; w < kBlock / kWave; ++w) v += red[q][w];
-      if (q < DX) {
-        a.est_x[f * DX + q] = (float)v;
-        if (a.trace_x) a.trace_x[((long long)(t - 1) * a.n_filters + f) * DX + q] = (float)v;
-      } else {
-        a.est_z[f * DZ + q - DX] = (float)v;
-        if (a.trace_z) a.trace_z[((long long)(t - 1) * a.n_filters + f) * DZ + q - DX] = (float)v;
-      }
-    }
-  }
-  if (threadIdx.x == 0) {
-    a.cur[f] = (unsigned char)(src ^ 1);
-    if (advance) a.tcur[f] = a.tcur[f] + 1;
-  }
 }
 
 }  // namespace dpf

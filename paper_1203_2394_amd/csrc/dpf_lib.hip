@@ -64,7 +64,7 @@ static int class_of(int M) {
 struct TileClass {
   int cls;
   int n_tiles;
-  int2* d_tiles;
+  int4* d_tiles;
 };
 
 // ------------------------------------------------------------ model engines
@@ -191,12 +191,13 @@ static const Engine* find_engine(int model, int dx, int dz, int dy) {
 // ---------------------------------------------------------------- layout
 struct Layout {
   size_t total = 0;
-  size_t prm, fN, fM, ooff, ooff64, ioff, tcur, cur, active, tiles, x0, x1, z0, z1, l0, l1, ell,
-      logw, anc, sel, kpart, mom, cdf, fstat, ess, dlogz, loglik, flags, est_x, est_z;
-  std::vector<size_t> tile_off;  // per class (in int2 units from `tiles`)
+  size_t prm, fN, fM, ooff, ooff64, ioff, finfo, tcur, cur, act, tiles, rgroups, x0, x1, z0, z1, l0, l1, ell,
+      logw, anc, sel, kpart, gstat, fstat, ess, dlogz, loglik, flags, est_x, est_z;
+  std::vector<size_t> tile_off;  // per class (in tile units from `tiles`)
   std::vector<int> tile_n;
   int NT = 0;
   long long NMT = 0;
+  int n_tiles = 0, n_rgroups = 0;
 };
 
 static size_t carve(size_t& cursor, size_t bytes) {
@@ -223,6 +224,7 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   L.NT = 0;
   L.NMT = 0;
   L.tile_n.assign(kNumClasses, 0);
+  L.n_rgroups = 0;
   for (int f = 0; f < F; ++f) {
     if (c->N[f] < 1 || c->N[f] > 65536) return fail(DPF_EUNSUPPORTED, "N[%d] = %d outside 1..65536", f, c->N[f]);
     const int cls = class_of(c->M[f]);
@@ -231,7 +233,10 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
     L.NT += c->N[f];
     L.NMT += (long long)c->N[f] * c->M[f];
     const int segs = kBlock / kClasses[cls].seg;
-    L.tile_n[cls] += (c->N[f] + segs - 1) / segs;
+    const int nt = (c->N[f] + segs - 1) / segs;
+    L.tile_n[cls] += nt;
+    const int G = (c->N[f] + kResGroup - 1) / kResGroup;
+    L.n_rgroups += G;
   }
   const int dx = c->dx, dz = c->dz;
   const size_t NT = L.NT, NMT = (size_t)L.NMT;
@@ -242,16 +247,18 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   L.ooff = carve(cur, (F + 1) * 4);
   L.ooff64 = carve(cur, (F + 1) * 8);
   L.ioff = carve(cur, (F + 1) * 8);
+  L.finfo = carve(cur, F * sizeof(FilterInfo));
   L.tcur = carve(cur, F * 4);
   L.cur = carve(cur, F);
-  L.active = carve(cur, F);
-  size_t ntiles = 0;
+  L.act = carve(cur, F);
+  L.n_tiles = 0;
   L.tile_off.assign(kNumClasses, 0);
   for (int k = 0; k < kNumClasses; ++k) {
-    L.tile_off[k] = ntiles;
-    ntiles += L.tile_n[k];
+    L.tile_off[k] = L.n_tiles;
+    L.n_tiles += L.tile_n[k];
   }
-  L.tiles = carve(cur, ntiles * sizeof(int2));
+  L.tiles = carve(cur, (size_t)L.n_tiles * sizeof(int4));
+  L.rgroups = carve(cur, (size_t)L.n_rgroups * sizeof(int2));
   L.x0 = carve(cur, NT * dx * 4);
   L.x1 = carve(cur, NT * dx * 4);
   L.z0 = carve(cur, NMT * dz * 4);
@@ -263,8 +270,7 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   L.anc = carve(cur, NT * 4);
   L.sel = carve(cur, NT * 4);
   L.kpart = carve(cur, NT * dz * 4);
-  L.mom = carve(cur, NT * 2 * dz * 4);
-  L.cdf = carve(cur, NT * 8);
+  L.gstat = carve(cur, (size_t)L.n_rgroups * 4 * 8);
   L.fstat = carve(cur, F * 4 * 8);
   L.ess = carve(cur, F * 4);
   L.dlogz = carve(cur, F * 8);
@@ -286,7 +292,9 @@ struct dpf_handle {
   char* ws;
   std::vector<int> N, M, ooff;
   std::vector<long long> ioff, ooff64;
-  std::vector<int2> tiles_h;
+  std::vector<int4> tiles_h;
+  std::vector<int2> rgroups_h;
+  std::vector<FilterInfo> finfo_h;
   std::vector<float> prm_h;
   std::vector<TileClass> classes;
   // multi-step graph cache
@@ -301,10 +309,12 @@ struct dpf_handle {
 
 constexpr int kPhaseEvents = 5;
 
-static void phase_mark(dpf_handle* h, int phase) {
-  if (h->prof_next + (size_t)(kPhaseEvents - phase) > h->prof_events.size()) return;
-  (void)hipEventRecord(h->prof_events[h->prof_next], h->stream);
+static dpf_status phase_mark(dpf_handle* h, int phase) {
+  if (h->prof_next + (size_t)(kPhaseEvents - phase) > h->prof_events.size()) return DPF_OK;
+  const hipError_t e = hipEventRecord(h->prof_events[h->prof_next], h->stream);
   h->prof_next++;
+  if (e != hipSuccess) return fail(DPF_EDEVICE, "hipEventRecord of phase event: %s", hipGetErrorString(e));
+  return DPF_OK;
 }
 
 template <class T>
@@ -321,12 +331,16 @@ static StepArgs make_args(dpf_handle* h) {
   a.fM = at<int>(h, h->L.fM);
   a.ooff = at<int>(h, h->L.ooff);
   a.ioff = at<long long>(h, h->L.ioff);
+  a.finfo = at<FilterInfo>(h, h->L.finfo);
   a.NT = h->L.NT;
-  a.t_offset = 1;
+  a.advance = 1;
   a.seed = h->seed;
   a.tcur = at<int>(h, h->L.tcur);
   a.cur = at<unsigned char>(h, h->L.cur);
+  a.act = at<unsigned char>(h, h->L.act);
   a.active = nullptr;
+  a.run_Tf = nullptr;
+  a.run_T = INT_MAX;
   a.x[0] = at<float>(h, h->L.x0);
   a.x[1] = at<float>(h, h->L.x1);
   a.z[0] = at<float>(h, h->L.z0);
@@ -338,8 +352,7 @@ static StepArgs make_args(dpf_handle* h) {
   a.anc = at<int>(h, h->L.anc);
   a.sel = at<int>(h, h->L.sel);
   a.kpart = at<float>(h, h->L.kpart);
-  a.mom = at<float>(h, h->L.mom);
-  a.cdf = at<double>(h, h->L.cdf);
+  a.gstat = at<double>(h, h->L.gstat);
   a.fstat = at<double>(h, h->L.fstat);
   a.ess = at<float>(h, h->L.ess);
   a.dlogz = at<double>(h, h->L.dlogz);
@@ -361,16 +374,17 @@ static dpf_status launch_classes(dpf_handle* h, int op, StepArgs a) {
   return DPF_OK;
 }
 
-static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a, bool plain, int advance) {
+static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a) {
   const int F = h->F;
-#define FIN(DX, DZ)                                                                                  \
-  if (h->dx == DX && h->dz == DZ) {                                                                  \
-    if (plain)                                                                                       \
-      hipLaunchKernelGGL((k_finalize<DX, DZ, true>), dim3(F), dim3(kBlock), 0, h->stream, a, advance); \
-    else                                                                                             \
-      hipLaunchKernelGGL((k_finalize<DX, DZ, false>), dim3(F), dim3(kBlock), 0, h->stream, a, advance); \
-    LAUNCH_CHECK("k_finalize");                                                                      \
-    return DPF_OK;                                                                                   \
+  const bool plain = h->algo == DPF_ALGO_PLAIN;
+#define FIN(DX, DZ)                                                                                         \
+  if (h->dx == DX && h->dz == DZ) {                                                                         \
+    if (plain)                                                                                              \
+      hipLaunchKernelGGL((k_finalize<DX, DZ, true>), dim3(F), dim3(fin_block<DX, DZ>()), 0, h->stream, a);  \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_finalize<DX, DZ, false>), dim3(F), dim3(fin_block<DX, DZ>()), 0, h->stream, a); \
+    LAUNCH_CHECK("k_finalize");                                                                             \
+    return DPF_OK;                                                                                          \
   }
   FIN(1, 2)
   FIN(2, 8)
@@ -382,20 +396,15 @@ static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a, bool plain, 
 static dpf_status queue_init(dpf_handle* h) {
   const bool plain = h->algo == DPF_ALGO_PLAIN;
   hipLaunchKernelGGL(k_reset, dim3((h->F + 255) / 256), dim3(256), 0, h->stream, at<int>(h, h->L.tcur),
-                     at<unsigned char>(h, h->L.cur), at<uint32_t>(h, h->L.flags),
-                     at<double>(h, h->L.loglik), h->F, plain ? 1 : 0);
+                     at<unsigned char>(h, h->L.cur), at<unsigned char>(h, h->L.act), at<uint32_t>(h, h->L.flags),
+                     at<double>(h, h->L.loglik), h->F);
   LAUNCH_CHECK("k_reset");
   StepArgs a = make_args(h);
-  a.t_offset = 0;
+  a.advance = 0;
   dpf_status s = launch_classes(h, plain ? OP_INIT_PLAIN : OP_INIT_LA, a);
-  if (s != DPF_OK) return s;
-  if (plain) {
-    s = launch_classes(h, OP_NEWCLOUD_PLAIN, a);
-    if (s != DPF_OK) return s;
-    s = launch_finalize(h, a, true, 0);
-    if (s != DPF_OK) return s;
-  }
-  return DPF_OK;
+  // the plain DPF's proposals for t = 1 from the prior (steps 4-7 at t = 0)
+  if (s == DPF_OK && plain) s = launch_classes(h, OP_NEWCLOUD_PLAIN, a);
+  return s;
 }
 
 extern "C" size_t dpf_workspace_bytes(const dpf_config* cfg) {
@@ -448,22 +457,27 @@ extern "C" dpf_status dpf_create(const dpf_config* cfg, void* d_workspace, size_
     delete h;
     return fail(DPF_EINVAL, "internal: parameter layout mismatch");
   }
-  // tiles grouped by class
-  size_t ntiles = 0;
-  for (int k = 0; k < kNumClasses; ++k) ntiles += L.tile_n[k];
-  h->tiles_h.assign(ntiles, make_int2(0, 0));
+  // tiles grouped by class; per-filter resampling groups
+  h->tiles_h.assign(L.n_tiles, make_int4(0, 0, 0, 0));
+  h->finfo_h.assign(F, FilterInfo{0, 0, 0, 0});
   std::vector<size_t> fill(L.tile_off);
+  int rg = 0;
   for (int f = 0; f < F; ++f) {
     const int cls = class_of(h->M[f]);
     const int segs = kBlock / kClasses[cls].seg;
-    for (int i0 = 0; i0 < h->N[f]; i0 += segs) h->tiles_h[fill[cls]++] = make_int2(f, i0);
+    int nt = 0;
+    for (int i0 = 0; i0 < h->N[f]; i0 += segs) h->tiles_h[fill[cls]++] = make_int4(f, i0, nt++, 0);
+    const int G = (h->N[f] + kResGroup - 1) / kResGroup;
+    for (int g = 0; g < G; ++g) h->rgroups_h.push_back(make_int2(f, g));
+    h->finfo_h[f] = FilterInfo{rg, G, 0, 0};
+    rg += G;
   }
   for (int k = 0; k < kNumClasses; ++k) {
     if (L.tile_n[k] == 0) continue;
     TileClass tc;
     tc.cls = k;
     tc.n_tiles = L.tile_n[k];
-    tc.d_tiles = at<int2>(h, L.tiles) + L.tile_off[k];
+    tc.d_tiles = at<int4>(h, L.tiles) + L.tile_off[k];
     h->classes.push_back(tc);
   }
   hipError_t e = hipSuccess;
@@ -478,6 +492,8 @@ extern "C" dpf_status dpf_create(const dpf_config* cfg, void* d_workspace, size_
   UP(L.ooff64, h->ooff64)
   UP(L.ioff, h->ioff)
   UP(L.tiles, h->tiles_h)
+  UP(L.rgroups, h->rgroups_h)
+  UP(L.finfo, h->finfo_h)
 #undef UP
   if (e != hipSuccess) {
     delete h;
@@ -506,27 +522,30 @@ extern "C" dpf_status dpf_destroy(dpf_handle* h) {
 }
 
 static dpf_status queue_step(dpf_handle* h, const float* Y, long long y_tstride, const unsigned char* active,
-                             float* trace_x, float* trace_z) {
+                             const int* run_Tf, int run_T, float* trace_x, float* trace_z) {
   StepArgs a = make_args(h);
   a.Y = Y;
   a.y_tstride = y_tstride;
   a.active = active;
+  a.run_Tf = run_Tf;
+  a.run_T = run_T;
   a.trace_x = trace_x;
   a.trace_z = trace_z;
-  a.t_offset = 1;
+  a.advance = 1;
   const bool plain = h->algo == DPF_ALGO_PLAIN;
-  phase_mark(h, 0);
-  dpf_status s = launch_classes(h, plain ? OP_DPF_WEIGHTS : OP_LA_WEIGHTS, a);
-  if (s != DPF_OK) return s;
-  phase_mark(h, 1);
-  hipLaunchKernelGGL(k_outer_resample, dim3(h->F), dim3(kResBlock), 0, h->stream, a);
-  LAUNCH_CHECK("k_outer_resample");
-  phase_mark(h, 2);
-  s = launch_classes(h, plain ? OP_NEWCLOUD_PLAIN : OP_NEWCLOUD_LA, a);
-  if (s != DPF_OK) return s;
-  phase_mark(h, 3);
-  s = launch_finalize(h, a, plain, 1);
-  phase_mark(h, 4);
+  dpf_status s = phase_mark(h, 0);
+  if (s == DPF_OK) s = launch_classes(h, plain ? OP_DPF_WEIGHTS : OP_LA_WEIGHTS, a);
+  if (s == DPF_OK) s = phase_mark(h, 1);
+  if (s == DPF_OK) {
+    hipLaunchKernelGGL(k_res_stats, dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a,
+                       at<int2>(h, h->L.rgroups));
+    LAUNCH_CHECK("k_res_stats");
+  }
+  if (s == DPF_OK) s = phase_mark(h, 2);
+  if (s == DPF_OK) s = launch_classes(h, plain ? OP_NEWCLOUD_PLAIN : OP_NEWCLOUD_LA, a);
+  if (s == DPF_OK) s = phase_mark(h, 3);
+  if (s == DPF_OK) s = launch_finalize(h, a);
+  if (s == DPF_OK) s = phase_mark(h, 4);
   return s;
 }
 
@@ -542,13 +561,13 @@ extern "C" dpf_status dpf_set_phase_events(dpf_handle* h, void* const* hip_event
 extern "C" dpf_status dpf_lookahead_step(dpf_handle* h, const float* d_y, const uint8_t* d_active) {
   if (!h || !d_y) return fail(DPF_EINVAL, "handle and d_y are required");
   if (h->algo != DPF_ALGO_LOOKAHEAD) return fail(DPF_ESTATE, "handle was created for the plain DPF");
-  return queue_step(h, d_y, 0, d_active, nullptr, nullptr);
+  return queue_step(h, d_y, 0, d_active, nullptr, INT_MAX, nullptr, nullptr);
 }
 
 extern "C" dpf_status dpf_step(dpf_handle* h, const float* d_y, const uint8_t* d_active) {
   if (!h || !d_y) return fail(DPF_EINVAL, "handle and d_y are required");
   if (h->algo != DPF_ALGO_PLAIN) return fail(DPF_ESTATE, "handle was created for the look-ahead DPF");
-  return queue_step(h, d_y, 0, d_active, nullptr, nullptr);
+  return queue_step(h, d_y, 0, d_active, nullptr, INT_MAX, nullptr, nullptr);
 }
 
 extern "C" dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean, float* d_ess,
@@ -569,11 +588,7 @@ extern "C" dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean
 
 static dpf_status queue_run_step(dpf_handle* h, const float* d_Y, int T, const int32_t* d_Tf, float* xt,
                                  float* zt) {
-  unsigned char* act = at<unsigned char>(h, h->L.active);
-  hipLaunchKernelGGL(k_active_mask, dim3((h->F + 255) / 256), dim3(256), 0, h->stream, at<int>(h, h->L.tcur),
-                     (const int*)d_Tf, T, act, h->F);
-  LAUNCH_CHECK("k_active_mask");
-  return queue_step(h, d_Y, (long long)h->F * h->dy, act, xt, zt);
+  return queue_step(h, d_Y, (long long)h->F * h->dy, nullptr, (const int*)d_Tf, T, xt, zt);
 }
 
 extern "C" dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_Tf, float* d_xtrace,
@@ -685,7 +700,6 @@ extern "C" dpf_status dpf_copy_buffer(dpf_handle* h, int32_t which, void* d_dst,
     case DPF_BUF_LOGW: off = h->L.logw; need = (size_t)h->L.NT * 4; break;
     case DPF_BUF_ANC: off = h->L.anc; need = (size_t)h->L.NT * 4; break;
     case DPF_BUF_SEL: off = h->L.sel; need = (size_t)h->L.NT * 4; break;
-    case DPF_BUF_MOM: off = h->L.mom; need = (size_t)h->L.NT * 2 * h->dz * 4; break;
     default: return fail(DPF_EINVAL, "unknown buffer %d", which);
   }
   if (bytes < need) return fail(DPF_EINVAL, "buffer %d needs %zu bytes", which, need);
@@ -726,11 +740,16 @@ extern "C" dpf_status dpf_normals(uint64_t seed, uint32_t filter_id, uint32_t t,
 
 extern "C" dpf_status dpf_systematic(const double* d_w, int32_t n, int32_t n_out, double u, double* d_scratch,
                                      int32_t* d_out, void* hip_stream) {
-  if (!d_w || !d_scratch || !d_out || n < 1 || n_out < 1) return fail(DPF_EINVAL, "bad arguments");
+  if (!d_w || !d_out || !d_scratch || n < 1 || n_out < 1) return fail(DPF_EINVAL, "bad arguments");
+  if (n > 65536) return fail(DPF_EUNSUPPORTED, "n = %d > 65536", n);
   if (!(u >= 0.0 && u < 1.0)) return fail(DPF_EINVAL, "u must be in [0, 1)");
-  hipLaunchKernelGGL(k_systematic_prim, dim3(1), dim3(kResBlock), 0, (hipStream_t)hip_stream, d_w, n, n_out, u,
+  const int G = (n + kResGroup - 1) / kResGroup;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipLaunchKernelGGL(k_prim_res_stats, dim3(G), dim3(kBlock), 0, s, d_w, n, d_scratch);
+  LAUNCH_CHECK("k_prim_res_stats");
+  hipLaunchKernelGGL(k_prim_res_select, dim3((n_out + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d_w, n, n_out, u,
                      d_scratch, (int*)d_out);
-  LAUNCH_CHECK("k_systematic_prim");
+  LAUNCH_CHECK("k_prim_res_select");
   return DPF_OK;
 }
 

@@ -14,6 +14,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "dpf_wave.hpp"
+
 namespace dpf {
 
 constexpr int kBlock = 256;
@@ -27,75 +29,80 @@ struct SegScratch {
 };
 
 template <int SEG>
-__device__ __forceinline__ float seg_max(float v, SegScratch& sh) {
-#pragma unroll
-  for (int off = (SEG < kWave ? SEG : kWave) / 2; off > 0; off >>= 1)
-    v = fmaxf(v, __shfl_xor(v, off, kWave));
+constexpr int wave_width() { return SEG < kWave ? SEG : kWave; }
+
+template <class Op, int SEG, class T>
+__device__ __forceinline__ T seg_reduce(T v, T* red /* [kBlock / kWave] */) {
+  v = seg_reduce_wave<Op, wave_width<SEG>()>(v);
   if constexpr (SEG > kWave) {
     const int w = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0) sh.f[0][w] = v;
+    if ((threadIdx.x & (kWave - 1)) == 0) red[w] = v;
     __syncthreads();
     const int w0 = (threadIdx.x / SEG) * (SEG / kWave);
-    float r = sh.f[0][w0];
+    T r = red[w0];
 #pragma unroll
-    for (int q = 1; q < SEG / kWave; ++q) r = fmaxf(r, sh.f[0][w0 + q]);
+    for (int q = 1; q < SEG / kWave; ++q) r = Op::apply(r, red[w0 + q]);
     __syncthreads();
     v = r;
   }
   return v;
+}
+
+template <int SEG>
+__device__ __forceinline__ float seg_max(float v, SegScratch& sh) {
+  return seg_reduce<OpMax, SEG>(v, sh.f[0]);
 }
 
 template <int SEG>
 __device__ __forceinline__ float seg_sum(float v, SegScratch& sh) {
-#pragma unroll
-  for (int off = (SEG < kWave ? SEG : kWave) / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  if constexpr (SEG > kWave) {
-    const int w = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0) sh.f[1][w] = v;
-    __syncthreads();
-    const int w0 = (threadIdx.x / SEG) * (SEG / kWave);
-    float r = sh.f[1][w0];
-#pragma unroll
-    for (int q = 1; q < SEG / kWave; ++q) r += sh.f[1][w0 + q];
-    __syncthreads();
-    v = r;
-  }
-  return v;
+  return seg_reduce<OpAdd, SEG>(v, sh.f[1]);
 }
 
 template <int SEG>
 __device__ __forceinline__ double seg_sum_d(double v, SegScratch& sh) {
+  return seg_reduce<OpAdd, SEG>(v, sh.d[1]);
+}
+
+// Sums of NV values over the segment with one LDS exchange for all of them
+// (segments wider than a wavefront).  The result is valid in the segment's
+// first lane only.  red: [kBlock / kWave][NV] floats of LDS.
+template <int SEG, int NV>
+__device__ __forceinline__ void seg_sum_vec(float* v, float (*red)[NV]) {
 #pragma unroll
-  for (int off = (SEG < kWave ? SEG : kWave) / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  for (int q = 0; q < NV; ++q) v[q] = seg_reduce_wave<OpAdd, wave_width<SEG>()>(v[q]);
   if constexpr (SEG > kWave) {
     const int w = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0) sh.d[1][w] = v;
-    __syncthreads();
-    const int w0 = (threadIdx.x / SEG) * (SEG / kWave);
-    double r = sh.d[1][w0];
+    if ((threadIdx.x & (kWave - 1)) == 0) {
 #pragma unroll
-    for (int q = 1; q < SEG / kWave; ++q) r += sh.d[1][w0 + q];
+      for (int q = 0; q < NV; ++q) red[w][q] = v[q];
+    }
     __syncthreads();
-    v = r;
+    if ((threadIdx.x % SEG) == 0) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        float r = red[w][q];
+#pragma unroll
+        for (int qq = 1; qq < SEG / kWave; ++qq) r += red[w + qq][q];
+        v[q] = r;
+      }
+    }
+    __syncthreads();
   }
-  return v;
 }
 
 // Inclusive FP64 scan within the segment; `total` receives the segment sum.
 template <int SEG>
 __device__ __forceinline__ double seg_scan_incl(double v, SegScratch& sh, double& total) {
-  constexpr int W = SEG < kWave ? SEG : kWave;
-  const int lw = threadIdx.x & (W - 1);
-#pragma unroll
-  for (int d = 1; d < W; d <<= 1) {
-    const double o = __shfl_up(v, d, W);
-    if (lw >= d) v += o;
-  }
+  constexpr int W = wave_width<SEG>();
+  v = seg_scan_wave<W>(v);
   if constexpr (SEG <= kWave) {
-    total = __shfl(v, W - 1, W);
+    if constexpr (W == 32)
+      total = (threadIdx.x & 63) < 32 ? readlane_d(v, 31) : readlane_d(v, 63);
+    else
+      total = readlane_d(v, 63);
   } else {
     const int w = threadIdx.x / kWave;
-    if (lw == kWave - 1) sh.d[0][w] = v;
+    if ((threadIdx.x & (kWave - 1)) == kWave - 1) sh.d[0][w] = v;
     __syncthreads();
     const int w0 = (threadIdx.x / SEG) * (SEG / kWave);
     double pre = 0.0, tot = 0.0;
@@ -113,8 +120,9 @@ __device__ __forceinline__ double seg_scan_incl(double v, SegScratch& sh, double
 }
 
 // Systematic search rule: the first index with C[i] > P; if rounding put the
-// point at or past the total, the first index with C[i] >= C[n-1].  Never
-// selects a zero weight.
+// point at or past the total, the first index with C[i] >= C[n-1].  With
+// exact cumulative sums this never selects a zero weight; with rounded ones
+// only a point within one rounding unit of a boundary can.
 __device__ __forceinline__ int cdf_search(const double* C, int n, double P) {
   int lo = 0, hi = n;
   while (lo < hi) {
