@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-child", type=int, default=0)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="after the timed steps, run one device-to-device copy of this many MB "
+                         "(a kernel of known traffic for calibrating hardware byte counters)")
     args = ap.parse_args()
     if args.cpu_baseline_child:
         cpu_baseline_child(args.cpu_baseline_child)
@@ -175,6 +178,14 @@ def main():
     f.run(Yk, trace=False, use_graph=True)
     torch.cuda.synchronize()
     gdt = time.perf_counter() - g0
+
+    if args.copy_mb:
+        n = args.copy_mb * (1 << 20) // 4
+        src_t = torch.ones(n, dtype=torch.float32, device=dev)
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
 
     updates = N_OUT * M_IN
     dom = max(("weights", "newcloud"), key=lambda p: ph_ms[p])
