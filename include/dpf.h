@@ -175,12 +175,18 @@ dpf_status dpf_import_state(dpf_handle* h, const void* d_src, size_t bytes);
  * DPF_BUF_LOGW float [sum N]:   outer log-weights log w_i
  * DPF_BUF_ANC  int32 [sum N]:   outer ancestors A_k
  * DPF_BUF_SEL  int32 [sum N]:   selected candidate (look-ahead) or
- *                               inner ancestor a_k (plain) per new particle */
+ *                               inner ancestor a_k (plain) per new particle;
+ *                               after a learned step, the mixture component
+ *                               drawn for each pre-resampling particle
+ * DPF_BUF_MDN  float [sum N][32]: network outputs of the last learned step
+ * DPF_BUF_X    float [dx][sum N]: outer particles x of the current state */
 typedef enum {
   DPF_BUF_ELL = 0,
   DPF_BUF_LOGW = 1,
   DPF_BUF_ANC = 2,
-  DPF_BUF_SEL = 3
+  DPF_BUF_SEL = 3,
+  DPF_BUF_MDN = 4,
+  DPF_BUF_X = 5
 } dpf_buffer;
 dpf_status dpf_copy_buffer(dpf_handle* h, int32_t which, void* d_dst, size_t bytes);
 
@@ -195,6 +201,94 @@ dpf_status dpf_set_phase_events(dpf_handle* h, void* const* hip_events, int32_t 
 
 /* Message for the last non-OK status returned on this thread. */
 const char* dpf_last_error(void);
+
+/* ---- learned proposal for the outer block ----
+ *
+ * A mixture density network q(x_t | features) stands in for the Monte Carlo
+ * optimal-proposal estimate eq:approx3.  Features of outer particle i (raw,
+ * standardised with the mean / standard deviation stored in the blob):
+ *   [x_{t-1}^{(i)} (dx), y_t (dy), sum_j qbar z^{(i,j)} (dz),
+ *    sum_j qbar (z^{(i,j)} - mean)^2 (dz)], zero-padded to 32.
+ * Network 32 -> 256 -> 256 -> 32 with tanh-form GELU after the hidden
+ * layers, BF16 matrix-core arithmetic with FP32 accumulation.  Outputs (20
+ * of 32 used, dx = 2): 4 mixture logits, 4 x 2 means, 4 x 2 log standard
+ * deviations (clamped to [log 1e-3, log 1e3]), component-major.
+ * Built for DPF_MODEL_NONLIN.
+ *
+ * Blob (device, DPF_MLP_BLOB_BYTES, byte offsets): W1 bf16 [256][32] at 0,
+ * W2 bf16 [256][256] at 16384, W3 bf16 [32][256] at 147456, b1 float [256]
+ * at 163840, b2 float [256] at 164864, b3 float [32] at 165888, feature
+ * mean float [32] at 166016, feature standard deviation float [32] at
+ * 166144 (BF16: round to nearest even of the FP32 value).
+ * Parameter vector (FP32, DPF_MLP_NPARAM values, training): W1 [256][32],
+ * b1 [256], W2 [256][256], b2 [256], W3 [32][256], b3 [32]. */
+#define DPF_MLP_BLOB_BYTES 166272u
+#define DPF_MLP_NPARAM 82464u
+
+/* Copy the network blob into the handle (the caller may free d_blob once
+ * the stream has passed this call) and set the fallback threshold: a
+ * filter whose learned outer weights have ESS < ess_frac * N (or no finite
+ * weight) takes the look-ahead step instead (ess_frac in [0, 1]).  Queues
+ * the cloud moments of the current state.  Look-ahead handles only. */
+dpf_status dpf_set_proposal(dpf_handle* h, const void* d_blob, size_t bytes, double ess_frac);
+
+/* One step with the learned proposal (importance-sampling step of Fig. 2,
+ * step 1, with q in place of the prior) for every active filter: x_t ~ q
+ * (component: U53 of purpose MDN_U at (t, i); normals MDN_X at (t, i, 0)),
+ * inner cloud conditioned on x_t (eq:qnobar) and resampled (INNER_U at
+ * (t, i)), propagated (NEW_Z at (t, i, j)) and updated (eq:qbar), outer
+ * log-weight log p_Nz(y_t | .) (eq:approx2) + log p_Nz(x_t | .)
+ * (eq:approx1) - log q(x_t), systematic outer resampling (OUTER_U).
+ * Filters below the ESS threshold run dpf_lookahead_step's step from the
+ * unchanged state and get DPF_FLAG_FALLBACK.  Same arguments as
+ * dpf_lookahead_step; needs dpf_set_proposal first. */
+dpf_status dpf_learned_step(dpf_handle* h, const float* d_y, const uint8_t* d_active);
+
+/* As dpf_learned_step with the network outputs supplied by the caller:
+ * d_mdn [sum N][32] float (row i: the mixture for pre-resampling particle
+ * i), and the threshold ess_frac for this call.  For checks of the step
+ * against a reference and for callers with their own proposal. */
+dpf_status dpf_learned_step_given(dpf_handle* h, const float* d_y, const uint8_t* d_active,
+                                  const float* d_mdn, double ess_frac);
+
+/* Raw (unstandardised) features of every outer particle of the current
+ * state for observations d_y [F][dy]: d_feat [sum N][32] float, zero-padded
+ * (cloud moments by an exact two-pass reduction). */
+dpf_status dpf_features(dpf_handle* h, const float* d_y, float* d_feat);
+
+/* Sizes of the blob and of the parameter vector. */
+size_t dpf_mlp_blob_bytes(void);
+size_t dpf_mlp_param_count(void);
+
+/* Network outputs for B rows of standardised features: d_X [B][32] float
+ * (rounded to BF16 on load) -> d_out [B][32] float. */
+dpf_status dpf_mlp_forward(const void* d_blob, const float* d_X, int32_t B, float* d_out, void* hip_stream);
+
+/* Device workspace of one training step with batch B (a multiple of 32, at
+ * most 2^20); 0 for an invalid B. */
+size_t dpf_mlp_train_workspace_bytes(int32_t batch);
+
+/* Write the blob from FP32 parameters d_params [DPF_MLP_NPARAM] and the
+ * feature standardisation d_fmean, d_fstd [32] (pad entries: mean 0,
+ * standard deviation 1).  d_train_ws (or NULL): a training workspace, whose
+ * transposed weight copies are initialised too -- required before the
+ * first dpf_mlp_train_step with that workspace. */
+dpf_status dpf_mlp_pack(const float* d_params, const float* d_fmean, const float* d_fstd, void* d_blob,
+                        void* d_train_ws, size_t ws_bytes, void* hip_stream);
+
+/* One training step on a batch: mean negative log-likelihood of the
+ * mixture at the targets d_xt [B][2] for standardised features d_X [B][32],
+ * its gradient (forward and backward on the matrix cores, BF16 operands,
+ * FP32 accumulation), then Adam (beta 0.9, 0.999, eps 1e-8, learning rate
+ * lr, bias corrections for step adam_t >= 1) on the FP32 state
+ * d_state [3][DPF_MLP_NPARAM] (parameters, first and second moments), and
+ * the updated blob d_blob.  adam_t = 0 computes the loss and gradient
+ * only.  d_loss [1] (mean NLL before the update) and d_grad
+ * [DPF_MLP_NPARAM] may be NULL.  d_train_ws: dpf_mlp_train_workspace_bytes
+ * bytes, initialised by dpf_mlp_pack. */
+dpf_status dpf_mlp_train_step(float* d_state, void* d_blob, const float* d_X, const float* d_xt, int32_t B,
+                              float lr, int32_t adam_t, void* d_train_ws, size_t ws_bytes, float* d_loss,
+                              float* d_grad, void* hip_stream);
 
 /* ---- kernel-level primitives (same device code as the step kernels) ---- */
 

@@ -19,7 +19,10 @@ DPF_ABI_VERSION = 1
 MODEL_LINGAUSS, MODEL_NONLIN, MODEL_HIGHDIM = 1, 2, 3
 ALGO_LOOKAHEAD, ALGO_PLAIN = 0, 1
 FLAG_DEGENERATE_OUTER, FLAG_DEGENERATE_INNER, FLAG_NONFINITE, FLAG_FALLBACK = 1, 2, 4, 8
-BUF_ELL, BUF_LOGW, BUF_ANC, BUF_SEL = range(4)
+BUF_ELL, BUF_LOGW, BUF_ANC, BUF_SEL, BUF_MDN, BUF_X = range(6)
+MLP_BLOB_BYTES = 166272
+MLP_NPARAM = 82464
+MLP_IN, MLP_HID, MLP_OUT, MLP_MIX = 32, 256, 32, 4
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = [
@@ -27,6 +30,9 @@ EXPORTS = [
     "dpf_step", "dpf_estimate", "dpf_run", "dpf_state_bytes", "dpf_export_state",
     "dpf_import_state", "dpf_copy_buffer", "dpf_last_error", "dpf_philox_words",
     "dpf_normals", "dpf_systematic", "dpf_segmented_systematic", "dpf_set_phase_events",
+    "dpf_set_proposal", "dpf_learned_step", "dpf_learned_step_given", "dpf_features",
+    "dpf_mlp_blob_bytes", "dpf_mlp_param_count", "dpf_mlp_forward", "dpf_mlp_train_workspace_bytes",
+    "dpf_mlp_pack", "dpf_mlp_train_step",
 ]
 
 
@@ -86,6 +92,17 @@ def lib():
         "dpf_systematic": (_i32, [_vp, _i32, _i32, ctypes.c_double, _vp, _vp, _vp]),
         "dpf_segmented_systematic": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp]),
         "dpf_set_phase_events": (_i32, [_vp, _vp, _i32]),
+        "dpf_set_proposal": (_i32, [_vp, _vp, _sz, ctypes.c_double]),
+        "dpf_learned_step": (_i32, [_vp, _vp, _vp]),
+        "dpf_learned_step_given": (_i32, [_vp, _vp, _vp, _vp, ctypes.c_double]),
+        "dpf_features": (_i32, [_vp, _vp, _vp]),
+        "dpf_mlp_blob_bytes": (_sz, []),
+        "dpf_mlp_param_count": (_sz, []),
+        "dpf_mlp_forward": (_i32, [_vp, _vp, _i32, _vp, _vp]),
+        "dpf_mlp_train_workspace_bytes": (_sz, [_i32]),
+        "dpf_mlp_pack": (_i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+        "dpf_mlp_train_step": (_i32, [_vp, _vp, _vp, _vp, _i32, ctypes.c_float, _i32, _vp, _sz, _vp, _vp,
+                                      _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -191,6 +208,36 @@ class Filter:
     def reset(self):
         _check(lib().dpf_reset(self._h))
 
+    # -------------------------------------------------------------- learned proposal
+    def set_proposal(self, mlp, ess_frac=0.1):
+        """Use the network of ``mlp`` (an MLP) as the outer proposal."""
+        _check(lib().dpf_set_proposal(self._h, _ptr(mlp.blob), mlp.blob.numel(), float(ess_frac)))
+        self._proposal = mlp
+
+    def learned_step(self, y, active=None):
+        y = self._y(y)
+        act = self._active(active)
+        _check(lib().dpf_learned_step(self._h, _ptr(y), _ptr(act)))
+        self._keep = (y, act)
+
+    def learned_step_given(self, y, mdn, ess_frac=0.1, active=None):
+        """Learned step with caller-supplied network outputs mdn [sum N][32]."""
+        torch = _torch()
+        y = self._y(y)
+        act = self._active(active)
+        mdn = torch.as_tensor(mdn, dtype=torch.float32, device=self.device).reshape(self.NT, MLP_OUT).contiguous()
+        _check(lib().dpf_learned_step_given(self._h, _ptr(y), _ptr(act), _ptr(mdn), float(ess_frac)))
+        self._keep = (y, act, mdn)
+
+    def features(self, y):
+        """Raw features [sum N][32] of the current state for observations y [F][dy]."""
+        torch = _torch()
+        y = self._y(y)
+        out = torch.empty(self.NT, MLP_IN, dtype=torch.float32, device=self.device)
+        _check(lib().dpf_features(self._h, _ptr(y), _ptr(out)))
+        self._keep = y
+        return out
+
     def estimate(self):
         torch = _torch()
         d = self.device
@@ -277,7 +324,8 @@ class Filter:
     def copy_buffer(self, which):
         torch = _torch()
         sizes = {BUF_ELL: (self.NMT, torch.float32), BUF_LOGW: (self.NT, torch.float32),
-                 BUF_ANC: (self.NT, torch.int32), BUF_SEL: (self.NT, torch.int32)}
+                 BUF_ANC: (self.NT, torch.int32), BUF_SEL: (self.NT, torch.int32),
+                 BUF_MDN: (self.NT * MLP_OUT, torch.float32), BUF_X: (self.NT * self.dx, torch.float32)}
         n, dt = sizes[which]
         out = torch.empty(n, dtype=dt, device=self.device)
         _check(lib().dpf_copy_buffer(self._h, int(which), _ptr(out), out.numel() * out.element_size()))
@@ -349,3 +397,113 @@ def segmented_systematic(w, n_out, u, device="cuda"):
     _check(lib().dpf_segmented_systematic(_ptr(w), int(S), int(n), int(n_out), _ptr(u), _ptr(out),
                                           _stream_ptr(torch.device(device))))
     return out
+
+
+# ------------------------------------------------------------------ network
+_PARAM_SHAPES = [("W1", (MLP_HID, MLP_IN)), ("b1", (MLP_HID,)), ("W2", (MLP_HID, MLP_HID)),
+                 ("b2", (MLP_HID,)), ("W3", (MLP_OUT, MLP_HID)), ("b3", (MLP_OUT,))]
+
+
+def flatten_params(p):
+    """Dict of arrays (W3 / b3 may have fewer than 32 output rows) -> FP32
+    parameter vector in the library's order, zero-padded."""
+    out = np.zeros(MLP_NPARAM, dtype=np.float32)
+    off = 0
+    for name, shape in _PARAM_SHAPES:
+        a = np.zeros(shape, dtype=np.float64)
+        v = np.asarray(p[name], dtype=np.float64)
+        a[tuple(slice(0, k) for k in v.shape)] = v
+        n = int(np.prod(shape))
+        out[off:off + n] = a.ravel()
+        off += n
+    return out
+
+
+def unflatten_params(v):
+    v = np.asarray(v, dtype=np.float64)
+    out, off = {}, 0
+    for name, shape in _PARAM_SHAPES:
+        n = int(np.prod(shape))
+        out[name] = v[off:off + n].reshape(shape).copy()
+        off += n
+    return out
+
+
+def init_params(seed, n_feat, n_used_out=20):
+    """He-style initial parameters (zero biases, zero padding columns / rows)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    p = {name: np.zeros(shape) for name, shape in _PARAM_SHAPES}
+    p["W1"][:, :n_feat] = g.normal(0.0, np.sqrt(2.0 / n_feat), size=(MLP_HID, n_feat))
+    p["W2"] = g.normal(0.0, np.sqrt(2.0 / MLP_HID), size=(MLP_HID, MLP_HID))
+    p["W3"][:n_used_out] = g.normal(0.0, 0.1 * np.sqrt(1.0 / MLP_HID), size=(n_used_out, MLP_HID))
+    return p
+
+
+class MLP:
+    """The proposal network on the device: FP32 parameters with Adam moments
+    (``state`` [3][NPARAM]), the BF16 blob the filters and the forward kernel
+    read, and a training workspace for batch ``batch``."""
+
+    def __init__(self, params, fmean, fstd, batch=4096, device="cuda"):
+        torch = _torch()
+        self.device = torch.device(device)
+        vec = params if isinstance(params, np.ndarray) and params.ndim == 1 else flatten_params(params)
+        self.state = torch.zeros(3, MLP_NPARAM, dtype=torch.float32, device=self.device)
+        self.state[0] = torch.as_tensor(np.asarray(vec, dtype=np.float32), device=self.device)
+        fm = np.zeros(MLP_IN, dtype=np.float32)
+        fs = np.ones(MLP_IN, dtype=np.float32)
+        fm[:len(fmean)] = fmean
+        fs[:len(fstd)] = fstd
+        self.fmean = torch.as_tensor(fm, device=self.device)
+        self.fstd = torch.as_tensor(fs, device=self.device)
+        self.blob = torch.zeros(MLP_BLOB_BYTES, dtype=torch.uint8, device=self.device)
+        self.batch = int(batch)
+        nb = lib().dpf_mlp_train_workspace_bytes(self.batch)
+        if nb == 0:
+            raise DPFError("batch %d must be a positive multiple of 32" % self.batch)
+        self._ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        self.adam_t = 0
+        self.pack()
+
+    def _stream(self):
+        return _stream_ptr(self.device)
+
+    def pack(self):
+        """Blob (and the training copies) from the current FP32 parameters."""
+        _check(lib().dpf_mlp_pack(_ptr(self.state[0]), _ptr(self.fmean), _ptr(self.fstd), _ptr(self.blob),
+                                  _ptr(self._ws), self._ws.numel(), self._stream()))
+
+    def params(self):
+        return unflatten_params(self.state[0].cpu().numpy())
+
+    def forward(self, X):
+        """Standardised features X [B][32] -> outputs [B][32]."""
+        torch = _torch()
+        X = torch.as_tensor(X, dtype=torch.float32, device=self.device).contiguous()
+        out = torch.empty(X.shape[0], MLP_OUT, dtype=torch.float32, device=self.device)
+        _check(lib().dpf_mlp_forward(_ptr(self.blob), _ptr(X), int(X.shape[0]), _ptr(out), self._stream()))
+        self._keep = X
+        return out
+
+    def _step(self, X, xt, lr, adam_t, want_grad):
+        torch = _torch()
+        X = torch.as_tensor(X, dtype=torch.float32, device=self.device).contiguous()
+        xt = torch.as_tensor(xt, dtype=torch.float32, device=self.device).contiguous()
+        if X.shape[0] != self.batch:
+            raise DPFError("batch of %d rows, network built for %d" % (X.shape[0], self.batch))
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=self.device) if want_grad else None
+        _check(lib().dpf_mlp_train_step(_ptr(self.state), _ptr(self.blob), _ptr(X), _ptr(xt), self.batch,
+                                        float(lr), int(adam_t), _ptr(self._ws), self._ws.numel(), _ptr(loss),
+                                        _ptr(grad), self._stream()))
+        self._keep = (X, xt)
+        return loss, grad
+
+    def train_step(self, X, xt, lr=1e-3, want_grad=False):
+        """One Adam step on a batch (standardised features, targets [B][2])."""
+        self.adam_t += 1
+        return self._step(X, xt, lr, self.adam_t, want_grad)
+
+    def loss_and_grad(self, X, xt):
+        """Mean NLL and its gradient at the current parameters (no update)."""
+        return self._step(X, xt, 0.0, 0, True)

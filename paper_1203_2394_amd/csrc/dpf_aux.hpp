@@ -13,7 +13,7 @@ namespace dpf {
 // t = 0, state in copy 0 (the plain DPF's initial proposals are written
 // there from the prior held in copy 1), flags and evidence cleared.
 __global__ void k_reset(int* tcur, unsigned char* cur, unsigned char* act, uint32_t* flags, double* loglik,
-                        int F) {
+                        uint32_t* lflags, int F) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
   tcur[f] = 0;
@@ -21,6 +21,7 @@ __global__ void k_reset(int* tcur, unsigned char* cur, unsigned char* act, uint3
   act[f] = 1;
   flags[f] = 0u;
   loglik[f] = 0.0;
+  lflags[f] = 0u;
 }
 
 // Element e of an array of per-filter segments: find the filter by binary
@@ -49,6 +50,35 @@ __global__ void k_state_copy(float* ext, float* buf0, float* buf1, const unsigne
     ext[e] = buf[e];
   else
     buf0[e] = ext[e];
+}
+
+// Export (dir = 0) or import (dir = 1) of a look-ahead cloud array ([N][width]
+// per filter in units of off = inner offsets, width = DZ * M for z or M for
+// lam per outer particle): export reads particle i's cloud from slot
+// ind[copy][oo + i]; import writes slot order (the caller sets ind to the
+// identity).
+__global__ void k_state_copy_cloud(float* ext, float* buf0, float* buf1, const int* ind0, const int* ind1,
+                                   const unsigned char* cur, const long long* ioff, const int* ooff,
+                                   const int* fM, int F, long long n_units, int width, int dir) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_units * width) return;
+  if (dir == 1) {
+    buf0[e] = ext[e];
+    return;
+  }
+  const int f = filter_of(ioff, F, e / width);
+  const long long per = (long long)fM[f] * width;  // elements per outer particle
+  const long long loc = e - ioff[f] * width;
+  const long long i = loc / per, rem = loc - i * per;
+  const int* ind = cur[f] ? ind1 : ind0;
+  const float* buf = cur[f] ? buf1 : buf0;
+  ext[e] = buf[ioff[f] * width + (long long)ind[ooff[f] + i] * per + rem];
+}
+
+__global__ void k_ind_identity(int* ind, const long long* ooff64, int F, int NT) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= NT) return;
+  ind[g] = g - (int)ooff64[filter_of(ooff64, F, g)];
 }
 
 // x is [DX][NT]: element e = d * NT + g, filter by g.

@@ -39,6 +39,12 @@ enum FlagBits : uint32_t {
 };
 
 constexpr int kResGroup = 256;  // outer weights per resampling workgroup
+constexpr int kFeatMax = 32;    // input width of the learned-proposal network
+
+// Models whose outer-particle features [x, y, cloud mean, cloud variance] fit
+// the network keep the per-particle cloud moments up to date when asked.
+template <class Mdl>
+constexpr bool has_moments() { return Mdl::DX + Mdl::DY + 2 * Mdl::DZ <= kFeatMax; }
 
 // Per-filter bookkeeping for the resampling groups.
 struct FilterInfo {
@@ -86,6 +92,20 @@ struct StepArgs {
   float* trace_z;   // [T][F][DZ] or null
   int n_filters;
   int dy;
+  // look-ahead state: cloud slot of each outer particle, per copy.  A step
+  // that resamples by copying writes the identity; the learned step writes
+  // its outer ancestors instead of moving the clouds.
+  int* ind[2];
+  float* mom;  // [NT][2 DZ] qbar-weighted cloud mean and variance, or null (not maintained)
+  // learned step
+  const unsigned char* mlp;  // network blob
+  float* mdn;                // [NT][32] network outputs for the current step
+  float* xtmp;               // [DX][NT] proposals x_t before resampling
+  float* kpart_tmp;          // [NT][DZ]
+  float* mom_tmp;            // [NT][2 DZ]
+  unsigned char* fb;         // [F] 1 where the look-ahead step replaces the learned one; null otherwise
+  uint32_t* lflags;          // [F] flags of the learned pass, kept only if it is accepted
+  double ess_frac;           // fallback threshold on ESS / N
 };
 
 // Whether filter f takes this step: the caller's mask and the run limits,
@@ -170,7 +190,10 @@ __global__ __launch_bounds__(kBlock) void k_init(StepArgs a) {
     normals<Mdl::DX>(key, 0u, (uint32_t)i, 0u, P_INIT_X, x0);
 #pragma unroll
     for (int d = 0; d < Mdl::DX; ++d) a.x[dst][(long long)d * a.NT + oo + i] = x0[d];
-    if (PLAIN) a.anc[oo + i] = i;
+    if (PLAIN)
+      a.anc[oo + i] = i;
+    else
+      a.ind[dst][oo + i] = i;
   }
   const float lam0 = -fast_log((float)M);
   float* zrow = a.z[dst] + (io + (long long)i * M) * Mdl::DZ;
@@ -193,13 +216,29 @@ __global__ __launch_bounds__(kBlock) void k_init(StepArgs a) {
 // component (LA_X normals at (t, i, j)) and its companion z (LA_Z), then
 // ell = lam + log p(y_t | xla, zla) (eq:weightsMC) and the per-particle
 // log-sum-exp log w_i.
+__device__ bool learned_rejected(const StepArgs& a, int f, int N, float* fred4, double* red4);
+
 template <class Mdl, int SEG, int JPT>
 __global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
   __shared__ SegScratch sh;
   const int4 tile = a.tiles[blockIdx.x];
   const int f = tile.x;
   const bool act = step_active(a, f);
-  if (tile.z == 0 && threadIdx.x == 0) a.act[f] = act ? 1 : 0;
+  if (a.fb) {
+    // learned step: only filters that reject their learned proposals take
+    // the look-ahead step, from the state the learned pass left untouched
+    const bool rej = act && learned_rejected(a, f, a.fN[f], sh.f[0], sh.d[0]);
+    if (tile.z == 0 && threadIdx.x == 0) {
+      a.fb[f] = rej ? 1 : 0;
+      if (rej) {
+        atomicOr(&a.flags[f], (uint32_t)F_FALLBACK);
+        a.lflags[f] = 0u;
+      }
+    }
+    if (!rej) return;
+  } else if (tile.z == 0 && threadIdx.x == 0) {
+    a.act[f] = act ? 1 : 0;
+  }
   if (!act) return;
   const int N = a.fN[f], M = a.fM[f];
   const int i = tile.y + threadIdx.x / SEG;
@@ -210,14 +249,15 @@ __global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
   const int t = a.tcur[f] + 1;
   const int src = a.cur[f];
   const Key key = make_key(a.seed, (uint32_t)f);
+  const int ci = vi ? a.ind[src][oo + i] : 0;
 
   float y[Mdl::DY], x[Mdl::DX];
   load_y<Mdl>(a, f, t, y);
 #pragma unroll
   for (int d = 0; d < Mdl::DX; ++d) x[d] = vi ? a.x[src][(long long)d * a.NT + oo + i] : 0.f;
 
-  const float* zrow = a.z[src] + (io + (long long)(vi ? i : 0) * M) * Mdl::DZ;
-  const float* lrow = a.lam[src] + io + (long long)(vi ? i : 0) * M;
+  const float* zrow = a.z[src] + (io + (long long)ci * M) * Mdl::DZ;
+  const float* lrow = a.lam[src] + io + (long long)ci * M;
   float* erow = a.ell + io + (long long)(vi ? i : 0) * M;
   Lse acc;
 #pragma unroll
@@ -369,6 +409,28 @@ __device__ __forceinline__ double group_scale(float mg, float m) {
   return mg > -INFINITY ? (double)fast_exp(mg - m) : 0.0;
 }
 
+// Learned step: whether filter f rejects its learned proposals -- no finite
+// log-weight, or ESS = (sum w)^2 / sum w^2 below ess_frac * N -- from the
+// group statistics of the learned log-weights.  All 256 threads take part;
+// every workgroup gets the same answer.
+__device__ bool learned_rejected(const StepArgs& a, int f, int N, float* fred4, double* red4) {
+  const int th = threadIdx.x;
+  const int G = a.finfo[f].ngroup;
+  const double* gs = a.gstat + 4LL * a.finfo[f].rg_base;
+  const float gm = th < G ? (float)gs[4 * th] : -INFINITY;
+  const float m = block_max_256(gm, fred4);
+  if (!(m > -INFINITY)) return true;
+  double T = 0.0, Q = 0.0;
+  if (th < G) {
+    const double c = group_scale<LogSrc>(gm, m);
+    T = c * gs[4 * th + 1];
+    Q = (c * c) * gs[4 * th + 2];
+  }
+  const double total = block_sum_256(T, red4);
+  const double sumsq = block_sum_256(Q, red4);
+  return total * total < a.ess_frac * (double)N * sumsq;
+}
+
 struct ResScratch {
   double B[kBlock + 1];   // group offsets (at most 256 groups)
   double C[kResGroup];    // cumulative weights of the group being resolved
@@ -491,9 +553,10 @@ __device__ void res_finish(const StepArgs& a, int f, int t, int N, const ResResu
   if (fl) atomicOr(&a.flags[f], fl);
 }
 
-// Group statistics; group 0's workgroup also advances the filter's time and
-// flips its state copy (no other workgroup of this launch reads them).
-__global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const int2* rgroups) {
+// Group statistics; with advance_time, group 0's workgroup also advances the
+// filter's time and flips its state copy (no other workgroup of this launch
+// reads them).
+__global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const int2* rgroups, int advance_time) {
   __shared__ ResScratch sh;
   const int2 rg = rgroups[blockIdx.x];
   const int f = rg.x;
@@ -512,7 +575,7 @@ __global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const int2* rg
     gs[1] = sg;
     gs[2] = qg;
     if (nonf) atomicOr(&a.flags[f], (uint32_t)F_NONFINITE);
-    if (rg.y == 0) {
+    if (advance_time && rg.y == 0) {
       a.tcur[f] = a.tcur[f] + 1;
       a.cur[f] = (unsigned char)(a.cur[f] ^ 1);
     }
@@ -601,7 +664,7 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
   __shared__ float xs_sh[NSEG][DX];
   __shared__ int csel[NSEG];
   __shared__ int anc_sh[NSEG];
-  __shared__ float vred[kBlock / kWave][DZ];
+  __shared__ float vred[kBlock / kWave][2 * DZ];
   __shared__ ResScratch rsh;
 
   const int4 tile = a.tiles[blockIdx.x];
@@ -633,10 +696,35 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
   const int p = vk ? anc_sh[s] : 0;
   if (vk && ls == 0) a.anc[oo + k] = p;
 
+  if (!PLAIN && a.fb != nullptr && a.fb[f] == 0) {
+    // learned step accepted: the clouds were propagated in slot order by the
+    // learned pass; particle k refers to its ancestor's slot
+    if (vk && ls == 0) {
+      const long long gk = oo + k, gp = oo + p;
+      a.ind[dst][gk] = p;
+#pragma unroll
+      for (int d = 0; d < DX; ++d) a.x[dst][(long long)d * a.NT + gk] = a.xtmp[(long long)d * a.NT + gp];
+#pragma unroll
+      for (int d = 0; d < DZ; ++d) a.kpart[gk * DZ + d] = a.kpart_tmp[gp * DZ + d];
+      if (a.mom) {
+#pragma unroll
+        for (int d = 0; d < 2 * DZ; ++d) a.mom[gk * 2 * DZ + d] = a.mom_tmp[gp * 2 * DZ + d];
+      }
+    }
+    if (tile.z == 0 && threadIdx.x == 0) {
+      const uint32_t lf = a.lflags[f];
+      if (lf) atomicOr(&a.flags[f], lf);
+      a.lflags[f] = 0u;
+    }
+    return;
+  }
+  const int pc = PLAIN ? p : a.ind[src][oo + p];  // cloud slot of the parent
+  if (!PLAIN && vk && ls == 0) a.ind[dst][oo + k] = k;
+
   float xp[DX];
 #pragma unroll
   for (int d = 0; d < DX; ++d) xp[d] = a.x[src][(long long)d * a.NT + oo + p];
-  const float* zp = a.z[src] + (io + (long long)p * M) * DZ;
+  const float* zp = a.z[src] + (io + (long long)pc * M) * DZ;
   const float* ep = a.ell + io + (long long)p * M;
 
   // ---- 1. selection over the parent's ell (candidate / ancestor) --------
@@ -693,7 +781,7 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
   for (int d = 0; d < DX; ++d) xn[d] = xs_sh[s][d];
 
   // ---- 3. x-conditioned inner weights and local systematic resampling ---
-  const float* lp = a.lam[src] + io + (long long)p * M;
+  const float* lp = a.lam[src] + io + (long long)pc * M;
   float mk = -INFINITY;
 #pragma unroll
   for (int r = 0; r < JPT; ++r) {
@@ -770,9 +858,11 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
     const bool deg3 = !(lse > -INFINITY);
     if (deg3) fl |= F_DEGENERATE_INNER;
     float* ldst = a.lam[dst] + io + (long long)k * M;
-    float part[DZ];
+    constexpr int NP = has_moments<Mdl>() ? 2 * DZ : DZ;
+    const bool want_mom = has_moments<Mdl>() && a.mom != nullptr;
+    float part[NP];
 #pragma unroll
-    for (int d = 0; d < DZ; ++d) part[d] = 0.f;
+    for (int d = 0; d < NP; ++d) part[d] = 0.f;
 #pragma unroll
     for (int r = 0; r < JPT; ++r) {
       const int jj = ls + r * SEG;
@@ -784,13 +874,26 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
         for (int d = 0; d < DZ; ++d) {
           const float zv = kKeepZ ? zkeep[kKeepZ ? r : 0][d] : zdst[d * M + jj];
           part[d] += q * zv;
+          if constexpr (NP == 2 * DZ) part[DZ + d] += want_mom ? q * zv * zv : 0.f;
         }
       }
     }
-    seg_sum_vec<SEG, DZ>(part, vred);
+    if (want_mom)
+      seg_sum_vec<SEG, NP>(part, reinterpret_cast<float(*)[NP]>(&vred[0][0]));
+    else
+      seg_sum_vec<SEG, DZ>(part, reinterpret_cast<float(*)[DZ]>(&vred[0][0]));
     if (vk && ls == 0) {
 #pragma unroll
       for (int d = 0; d < DZ; ++d) a.kpart[(long long)(oo + k) * DZ + d] = part[d];
+      if constexpr (NP == 2 * DZ) {
+        if (want_mom) {
+#pragma unroll
+          for (int d = 0; d < DZ; ++d) {
+            a.mom[(long long)(oo + k) * 2 * DZ + d] = part[d];
+            a.mom[(long long)(oo + k) * 2 * DZ + DZ + d] = fmaxf(part[DZ + d] - part[d] * part[d], 0.f);
+          }
+        }
+      }
     }
   }
   if (vk && ls == 0 && fl) atomicOr(&a.flags[f], fl);

@@ -19,6 +19,8 @@
 #include "../../include/dpf.h"
 #include "dpf_aux.hpp"
 #include "dpf_kernels.hpp"
+#include "dpf_learned.hpp"
+#include "dpf_mlp.hpp"
 
 using namespace dpf;
 
@@ -74,9 +76,32 @@ struct Engine {
   size_t n_total;
   void (*derive)(const double* raw, std::vector<float>& out);
   dpf_status (*launch)(int op, const StepArgs& a, const TileClass& tc, hipStream_t s);
+  dpf_status (*mlp_state)(const StepArgs& a, hipStream_t s);  // null: no learned proposal
+  bool moments;
 };
 
-enum Op { OP_INIT_LA, OP_INIT_PLAIN, OP_LA_WEIGHTS, OP_DPF_WEIGHTS, OP_NEWCLOUD_LA, OP_NEWCLOUD_PLAIN };
+enum Op {
+  OP_INIT_LA,
+  OP_INIT_PLAIN,
+  OP_LA_WEIGHTS,
+  OP_DPF_WEIGHTS,
+  OP_NEWCLOUD_LA,
+  OP_NEWCLOUD_PLAIN,
+  OP_LEARNED_INNER,
+  OP_MOMENTS
+};
+
+// Models served by the learned proposal (the network's mixture is over a
+// two-dimensional x; the features must fit its input).
+template <class Mdl>
+constexpr bool learned_model() { return Mdl::DX == 2 && has_moments<Mdl>(); }
+
+// Extra arguments of OP_MOMENTS (feature rows for dpf_features).
+struct MomArgs {
+  const float* y;
+  float* feat;
+};
+static thread_local MomArgs g_mom_args = {nullptr, nullptr};
 
 template <class Mdl, int SEG, int JPT>
 static void launch_op(int op, const StepArgs& a, int n, hipStream_t s) {
@@ -99,6 +124,26 @@ static void launch_op(int op, const StepArgs& a, int n, hipStream_t s) {
     case OP_NEWCLOUD_PLAIN:
       hipLaunchKernelGGL((k_newcloud<Mdl, SEG, JPT, true>), dim3(n), dim3(kBlock), 0, s, a);
       break;
+    case OP_LEARNED_INNER:
+      if constexpr (learned_model<Mdl>())
+        hipLaunchKernelGGL((k_learned_inner<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
+      break;
+    case OP_MOMENTS:
+      if constexpr (has_moments<Mdl>())
+        hipLaunchKernelGGL((k_moments<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a, g_mom_args.y,
+                           g_mom_args.feat);
+      break;
+  }
+}
+
+template <class Mdl>
+static dpf_status engine_mlp_state(const StepArgs& a, hipStream_t s) {
+  if constexpr (learned_model<Mdl>()) {
+    hipLaunchKernelGGL(k_mlp_fwd_state<Mdl>, dim3((a.NT + kMlpRows - 1) / kMlpRows), dim3(kBlock), 0, s, a);
+    LAUNCH_CHECK("k_mlp_fwd_state");
+    return DPF_OK;
+  } else {
+    return fail(DPF_EUNSUPPORTED, "no learned proposal for this model");
   }
 }
 
@@ -169,12 +214,13 @@ using MHD = HighDim<4, 64, 32>;
 static const Engine kEngines[] = {
     {1, 2, 1, (size_t)MLG::L::n_raw, (size_t)MLG::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_lingauss(1, 2, 1, p, o); },
-     engine_launch<MLG>},
+     engine_launch<MLG>, nullptr, has_moments<MLG>()},
     {2, 8, 8, (size_t)MNL::L::n_raw, (size_t)MNL::L::n_total,
-     [](const double* p, std::vector<float>& o) { derive_nonlin(2, 8, p, o); }, engine_launch<MNL>},
+     [](const double* p, std::vector<float>& o) { derive_nonlin(2, 8, p, o); }, engine_launch<MNL>,
+     engine_mlp_state<MNL>, has_moments<MNL>()},
     {4, 64, 32, (size_t)MHD::L::n_raw, (size_t)MHD::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_highdim(4, 64, 32, p, o); },
-     engine_launch<MHD>},
+     engine_launch<MHD>, nullptr, has_moments<MHD>()},
 };
 
 static const Engine* find_engine(int model, int dx, int dz, int dy) {
@@ -193,6 +239,8 @@ struct Layout {
   size_t total = 0;
   size_t prm, fN, fM, ooff, ooff64, ioff, finfo, tcur, cur, act, tiles, rgroups, x0, x1, z0, z1, l0, l1, ell,
       logw, anc, sel, kpart, gstat, fstat, ess, dlogz, loglik, flags, est_x, est_z;
+  // slot indirection and learned-proposal buffers
+  size_t ind0, ind1, mom, mlp, mdn, xtmp, kpart_tmp, mom_tmp, fb, lflags;
   std::vector<size_t> tile_off;  // per class (in tile units from `tiles`)
   std::vector<int> tile_n;
   int NT = 0;
@@ -278,6 +326,16 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   L.flags = carve(cur, F * 4);
   L.est_x = carve(cur, F * dx * 4);
   L.est_z = carve(cur, F * dz * 4);
+  L.ind0 = carve(cur, NT * 4);
+  L.ind1 = carve(cur, NT * 4);
+  L.mom = carve(cur, NT * 2 * dz * 4);
+  L.mlp = carve(cur, MlpBlobLayout::bytes);
+  L.mdn = carve(cur, NT * kMlpOut * 4);
+  L.xtmp = carve(cur, NT * dx * 4);
+  L.kpart_tmp = carve(cur, NT * dz * 4);
+  L.mom_tmp = carve(cur, NT * 2 * dz * 4);
+  L.fb = carve(cur, F);
+  L.lflags = carve(cur, F * 4);
   L.total = cur;
   return DPF_OK;
 }
@@ -305,6 +363,10 @@ struct dpf_handle {
   // phase timing: caller-owned events consumed kPhaseEvents per step
   std::vector<hipEvent_t> prof_events;
   size_t prof_next = 0;
+  // learned proposal
+  bool has_proposal = false;  // a network blob was set
+  bool mom_valid = false;     // mom holds the moments of the current state
+  double ess_frac = 0.1;
 };
 
 constexpr int kPhaseEvents = 5;
@@ -362,6 +424,17 @@ static StepArgs make_args(dpf_handle* h) {
   a.est_z = at<float>(h, h->L.est_z);
   a.n_filters = h->F;
   a.dy = h->dy;
+  a.ind[0] = at<int>(h, h->L.ind0);
+  a.ind[1] = at<int>(h, h->L.ind1);
+  a.mom = (h->has_proposal && h->eng->moments) ? at<float>(h, h->L.mom) : nullptr;
+  a.mlp = at<unsigned char>(h, h->L.mlp);
+  a.mdn = at<float>(h, h->L.mdn);
+  a.xtmp = at<float>(h, h->L.xtmp);
+  a.kpart_tmp = at<float>(h, h->L.kpart_tmp);
+  a.mom_tmp = at<float>(h, h->L.mom_tmp);
+  a.fb = nullptr;
+  a.lflags = at<uint32_t>(h, h->L.lflags);
+  a.ess_frac = h->ess_frac;
   return a;
 }
 
@@ -397,8 +470,9 @@ static dpf_status queue_init(dpf_handle* h) {
   const bool plain = h->algo == DPF_ALGO_PLAIN;
   hipLaunchKernelGGL(k_reset, dim3((h->F + 255) / 256), dim3(256), 0, h->stream, at<int>(h, h->L.tcur),
                      at<unsigned char>(h, h->L.cur), at<unsigned char>(h, h->L.act), at<uint32_t>(h, h->L.flags),
-                     at<double>(h, h->L.loglik), h->F);
+                     at<double>(h, h->L.loglik), at<uint32_t>(h, h->L.lflags), h->F);
   LAUNCH_CHECK("k_reset");
+  h->mom_valid = false;
   StepArgs a = make_args(h);
   a.advance = 0;
   dpf_status s = launch_classes(h, plain ? OP_INIT_PLAIN : OP_INIT_LA, a);
@@ -538,7 +612,7 @@ static dpf_status queue_step(dpf_handle* h, const float* Y, long long y_tstride,
   if (s == DPF_OK) s = phase_mark(h, 1);
   if (s == DPF_OK) {
     hipLaunchKernelGGL(k_res_stats, dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a,
-                       at<int2>(h, h->L.rgroups));
+                       at<int2>(h, h->L.rgroups), 1);
     LAUNCH_CHECK("k_res_stats");
   }
   if (s == DPF_OK) s = phase_mark(h, 2);
@@ -546,6 +620,61 @@ static dpf_status queue_step(dpf_handle* h, const float* Y, long long y_tstride,
   if (s == DPF_OK) s = phase_mark(h, 3);
   if (s == DPF_OK) s = launch_finalize(h, a);
   if (s == DPF_OK) s = phase_mark(h, 4);
+  h->mom_valid = a.mom != nullptr;
+  return s;
+}
+
+// Moments of the current state (exact two-pass kernel), for the learned
+// step's features; with feat, also the raw feature rows for y.
+static dpf_status queue_moments(dpf_handle* h, const float* y, float* feat) {
+  if (!h->eng->moments) return fail(DPF_EUNSUPPORTED, "cloud moments are not built for this model");
+  StepArgs a = make_args(h);
+  a.mom = at<float>(h, h->L.mom);
+  g_mom_args = MomArgs{y, feat};
+  dpf_status s = launch_classes(h, OP_MOMENTS, a);
+  g_mom_args = MomArgs{nullptr, nullptr};
+  if (s == DPF_OK) h->mom_valid = true;
+  return s;
+}
+
+// One learned step (with look-ahead fallback per filter); mdn_given: the
+// network outputs [NT][32] supplied by the caller instead of the network.
+static dpf_status queue_learned_step(dpf_handle* h, const float* Y, const unsigned char* active,
+                                     const float* mdn_given) {
+  dpf_status s = DPF_OK;
+  if (!h->mom_valid && !mdn_given) s = queue_moments(h, nullptr, nullptr);
+  if (s != DPF_OK) return s;
+  StepArgs a = make_args(h);
+  a.Y = Y;
+  a.y_tstride = 0;
+  a.active = active;
+  a.run_Tf = nullptr;
+  a.run_T = INT_MAX;
+  a.advance = 1;
+  a.mom = at<float>(h, h->L.mom);
+  if (mdn_given) a.mdn = const_cast<float*>(mdn_given);
+  s = phase_mark(h, 0);
+  if (s == DPF_OK && !mdn_given) s = h->eng->mlp_state(a, h->stream);
+  if (s == DPF_OK) s = launch_classes(h, OP_LEARNED_INNER, a);
+  if (s == DPF_OK) s = phase_mark(h, 1);
+  if (s == DPF_OK) {
+    hipLaunchKernelGGL(k_res_stats, dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a,
+                       at<int2>(h, h->L.rgroups), 0);
+    LAUNCH_CHECK("k_res_stats");
+  }
+  a.fb = at<unsigned char>(h, h->L.fb);
+  if (s == DPF_OK) s = launch_classes(h, OP_LA_WEIGHTS, a);  // fallback filters only
+  if (s == DPF_OK) {
+    hipLaunchKernelGGL(k_res_stats, dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a,
+                       at<int2>(h, h->L.rgroups), 1);
+    LAUNCH_CHECK("k_res_stats");
+  }
+  if (s == DPF_OK) s = phase_mark(h, 2);
+  if (s == DPF_OK) s = launch_classes(h, OP_NEWCLOUD_LA, a);
+  if (s == DPF_OK) s = phase_mark(h, 3);
+  if (s == DPF_OK) s = launch_finalize(h, a);
+  if (s == DPF_OK) s = phase_mark(h, 4);
+  h->mom_valid = true;
   return s;
 }
 
@@ -568,6 +697,53 @@ extern "C" dpf_status dpf_step(dpf_handle* h, const float* d_y, const uint8_t* d
   if (!h || !d_y) return fail(DPF_EINVAL, "handle and d_y are required");
   if (h->algo != DPF_ALGO_PLAIN) return fail(DPF_ESTATE, "handle was created for the look-ahead DPF");
   return queue_step(h, d_y, 0, d_active, nullptr, INT_MAX, nullptr, nullptr);
+}
+
+static dpf_status check_learned(dpf_handle* h) {
+  if (h->algo != DPF_ALGO_LOOKAHEAD) return fail(DPF_ESTATE, "the learned step needs a look-ahead handle");
+  if (!h->eng->mlp_state) return fail(DPF_EUNSUPPORTED, "no learned proposal for model %d", h->model);
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_set_proposal(dpf_handle* h, const void* d_blob, size_t bytes, double ess_frac) {
+  if (!h || !d_blob) return fail(DPF_EINVAL, "handle and blob are required");
+  dpf_status s = check_learned(h);
+  if (s != DPF_OK) return s;
+  if (bytes != MlpBlobLayout::bytes) return fail(DPF_EINVAL, "blob has %zu bytes, expected %zu", bytes,
+                                                 (size_t)MlpBlobLayout::bytes);
+  if (!(ess_frac >= 0.0 && ess_frac <= 1.0)) return fail(DPF_EINVAL, "ess_frac must lie in [0, 1]");
+  HIP_TRY(hipMemcpyAsync(h->ws + h->L.mlp, d_blob, bytes, hipMemcpyDeviceToDevice, h->stream));
+  h->has_proposal = true;
+  h->ess_frac = ess_frac;
+  return queue_moments(h, nullptr, nullptr);
+}
+
+extern "C" dpf_status dpf_learned_step(dpf_handle* h, const float* d_y, const uint8_t* d_active) {
+  if (!h || !d_y) return fail(DPF_EINVAL, "handle and d_y are required");
+  dpf_status s = check_learned(h);
+  if (s != DPF_OK) return s;
+  if (!h->has_proposal) return fail(DPF_ESTATE, "no proposal set (dpf_set_proposal)");
+  return queue_learned_step(h, d_y, d_active, nullptr);
+}
+
+extern "C" dpf_status dpf_learned_step_given(dpf_handle* h, const float* d_y, const uint8_t* d_active,
+                                             const float* d_mdn, double ess_frac) {
+  if (!h || !d_y || !d_mdn) return fail(DPF_EINVAL, "handle, d_y and d_mdn are required");
+  dpf_status s = check_learned(h);
+  if (s != DPF_OK) return s;
+  if (!(ess_frac >= 0.0 && ess_frac <= 1.0)) return fail(DPF_EINVAL, "ess_frac must lie in [0, 1]");
+  const double keep = h->ess_frac;
+  h->ess_frac = ess_frac;
+  s = queue_learned_step(h, d_y, d_active, d_mdn);
+  h->ess_frac = keep;
+  return s;
+}
+
+extern "C" dpf_status dpf_features(dpf_handle* h, const float* d_y, float* d_feat) {
+  if (!h || !d_y || !d_feat) return fail(DPF_EINVAL, "handle, d_y and d_feat are required");
+  dpf_status s = check_learned(h);
+  if (s != DPF_OK) return s;
+  return queue_moments(h, d_y, d_feat);
 }
 
 extern "C" dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean, float* d_ess,
@@ -666,11 +842,28 @@ static dpf_status state_io(dpf_handle* h, char* ext, int dir) {
   }
   hipLaunchKernelGGL(k_state_copy_x, dim3((unsigned)((nx + B - 1) / B)), dim3(B), 0, h->stream, ex,
                      at<float>(h, h->L.x0), at<float>(h, h->L.x1), cur, oo64, F, h->L.NT, h->dx, dir);
-  hipLaunchKernelGGL(k_state_copy, dim3((unsigned)((nz + B - 1) / B)), dim3(B), 0, h->stream, ez,
-                     at<float>(h, h->L.z0), at<float>(h, h->L.z1), cur, ioff, F, h->L.NMT, h->dz, dir);
-  hipLaunchKernelGGL(k_state_copy, dim3((unsigned)((nl + B - 1) / B)), dim3(B), 0, h->stream, el,
-                     at<float>(h, h->L.l0), at<float>(h, h->L.l1), cur, ioff, F, h->L.NMT, 1, dir);
+  if (h->algo == DPF_ALGO_LOOKAHEAD) {
+    const int* i0 = at<int>(h, h->L.ind0);
+    const int* i1 = at<int>(h, h->L.ind1);
+    const int* oo = at<int>(h, h->L.ooff);
+    const int* fm = at<int>(h, h->L.fM);
+    hipLaunchKernelGGL(k_state_copy_cloud, dim3((unsigned)((nz + B - 1) / B)), dim3(B), 0, h->stream, ez,
+                       at<float>(h, h->L.z0), at<float>(h, h->L.z1), i0, i1, cur, ioff, oo, fm, F, h->L.NMT,
+                       h->dz, dir);
+    hipLaunchKernelGGL(k_state_copy_cloud, dim3((unsigned)((nl + B - 1) / B)), dim3(B), 0, h->stream, el,
+                       at<float>(h, h->L.l0), at<float>(h, h->L.l1), i0, i1, cur, ioff, oo, fm, F, h->L.NMT, 1,
+                       dir);
+    if (dir == 1)
+      hipLaunchKernelGGL(k_ind_identity, dim3((h->L.NT + 255) / 256), dim3(256), 0, h->stream,
+                         at<int>(h, h->L.ind0), oo64, F, h->L.NT);
+  } else {
+    hipLaunchKernelGGL(k_state_copy, dim3((unsigned)((nz + B - 1) / B)), dim3(B), 0, h->stream, ez,
+                       at<float>(h, h->L.z0), at<float>(h, h->L.z1), cur, ioff, F, h->L.NMT, h->dz, dir);
+    hipLaunchKernelGGL(k_state_copy, dim3((unsigned)((nl + B - 1) / B)), dim3(B), 0, h->stream, el,
+                       at<float>(h, h->L.l0), at<float>(h, h->L.l1), cur, ioff, F, h->L.NMT, 1, dir);
+  }
   LAUNCH_CHECK("state copy");
+  if (dir == 1) h->mom_valid = false;
   if (dir == 1) {
     hipLaunchKernelGGL(k_import_time, dim3((F + 255) / 256), dim3(256), 0, h->stream, (const int*)ext,
                        at<int>(h, h->L.tcur), at<unsigned char>(h, h->L.cur), at<uint32_t>(h, h->L.flags),
@@ -700,6 +893,17 @@ extern "C" dpf_status dpf_copy_buffer(dpf_handle* h, int32_t which, void* d_dst,
     case DPF_BUF_LOGW: off = h->L.logw; need = (size_t)h->L.NT * 4; break;
     case DPF_BUF_ANC: off = h->L.anc; need = (size_t)h->L.NT * 4; break;
     case DPF_BUF_SEL: off = h->L.sel; need = (size_t)h->L.NT * 4; break;
+    case DPF_BUF_MDN: off = h->L.mdn; need = (size_t)h->L.NT * kMlpOut * 4; break;
+    case DPF_BUF_X: {
+      need = (size_t)h->L.NT * h->dx * 4;
+      if (bytes < need) return fail(DPF_EINVAL, "buffer %d needs %zu bytes", which, need);
+      const long long nx = (long long)h->L.NT * h->dx;
+      hipLaunchKernelGGL(k_state_copy_x, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream,
+                         (float*)d_dst, at<float>(h, h->L.x0), at<float>(h, h->L.x1),
+                         at<unsigned char>(h, h->L.cur), at<long long>(h, h->L.ooff64), h->F, h->L.NT, h->dx, 0);
+      LAUNCH_CHECK("k_state_copy_x");
+      return DPF_OK;
+    }
     default: return fail(DPF_EINVAL, "unknown buffer %d", which);
   }
   if (bytes < need) return fail(DPF_EINVAL, "buffer %d needs %zu bytes", which, need);
@@ -772,5 +976,155 @@ extern "C" dpf_status dpf_segmented_systematic(const double* d_w, int32_t S, int
     case 5: hipLaunchKernelGGL((k_seg_systematic_prim<256, 16>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
   }
   LAUNCH_CHECK("k_seg_systematic_prim");
+  return DPF_OK;
+}
+
+// ---------------------------------------------------------------- network
+// Training workspace (batch B, a multiple of 32): the transposed BF16
+// weights first (fixed offsets, written by dpf_mlp_pack and the Adam
+// kernel), then the activations, gradients and partial sums of one step.
+struct TrainWs {
+  size_t w2t, w3t, out, a1, a2, x0t, h1t, h2t, gb, gt, da2t, da1t, wp1, wp2, wp3, b1p, b2p, b3p, lossp, total;
+  int chunks, tiles, groups;
+};
+
+static TrainWs train_layout(int B) {
+  TrainWs w;
+  size_t c = 0;
+  w.chunks = (B + kWgChunk - 1) / kWgChunk;
+  w.tiles = (B + kMlpRows - 1) / kMlpRows;
+  w.groups = (B + kBlock - 1) / kBlock;
+  const size_t b = (size_t)B;
+  w.w2t = carve(c, (size_t)kMlpHid * kMlpHid * 2);
+  w.w3t = carve(c, (size_t)kMlpHid * kMlpOut * 2);
+  w.out = carve(c, b * kMlpOut * 4);
+  w.a1 = carve(c, b * kMlpHid * 4);
+  w.a2 = carve(c, b * kMlpHid * 4);
+  w.x0t = carve(c, b * kMlpIn * 2);
+  w.h1t = carve(c, b * kMlpHid * 2);
+  w.h2t = carve(c, b * kMlpHid * 2);
+  w.gb = carve(c, b * kMlpOut * 2);
+  w.gt = carve(c, b * kMlpOut * 2);
+  w.da2t = carve(c, b * kMlpHid * 2);
+  w.da1t = carve(c, b * kMlpHid * 2);
+  w.wp1 = carve(c, (size_t)w.chunks * kMlpHid * kMlpIn * 4);
+  w.wp2 = carve(c, (size_t)w.chunks * kMlpHid * kMlpHid * 4);
+  w.wp3 = carve(c, (size_t)w.chunks * kMlpOut * kMlpHid * 4);
+  w.b1p = carve(c, (size_t)w.tiles * kMlpHid * 4);
+  w.b2p = carve(c, (size_t)w.tiles * kMlpHid * 4);
+  w.b3p = carve(c, (size_t)w.groups * kMlpOut * 4);
+  w.lossp = carve(c, (size_t)w.groups * 8);
+  w.total = c;
+  return w;
+}
+
+constexpr int kMaxTrainBatch = 1 << 20;
+
+extern "C" size_t dpf_mlp_blob_bytes(void) { return MlpBlobLayout::bytes; }
+extern "C" size_t dpf_mlp_param_count(void) { return MlpParamLayout::n; }
+
+extern "C" size_t dpf_mlp_train_workspace_bytes(int32_t batch) {
+  if (batch < 32 || batch % 32 != 0 || batch > kMaxTrainBatch) return 0;
+  return train_layout(batch).total;
+}
+
+extern "C" dpf_status dpf_mlp_pack(const float* d_params, const float* d_fmean, const float* d_fstd, void* d_blob,
+                                   void* d_train_ws, size_t ws_bytes, void* hip_stream) {
+  if (!d_params || !d_fmean || !d_fstd || !d_blob) return fail(DPF_EINVAL, "params, fmean, fstd and blob are required");
+  const TrainWs w = train_layout(32);
+  if (d_train_ws && ws_bytes < w.w3t + (size_t)kMlpHid * kMlpOut * 2)
+    return fail(DPF_EINVAL, "training workspace too small");
+  char* ws = (char*)d_train_ws;
+  hipLaunchKernelGGL(k_mlp_pack, dim3((MlpParamLayout::n + 255) / 256), dim3(256), 0, (hipStream_t)hip_stream,
+                     d_params, d_fmean, d_fstd, (unsigned char*)d_blob, ws ? (bf16_t*)(ws + w.w2t) : nullptr,
+                     ws ? (bf16_t*)(ws + w.w3t) : nullptr);
+  LAUNCH_CHECK("k_mlp_pack");
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_mlp_forward(const void* d_blob, const float* d_X, int32_t B, float* d_out,
+                                      void* hip_stream) {
+  if (!d_blob || (!d_X && B) || (!d_out && B) || B < 0) return fail(DPF_EINVAL, "bad arguments");
+  if (B == 0) return DPF_OK;
+  hipLaunchKernelGGL(k_mlp_fwd_x<false>, dim3((B + kMlpRows - 1) / kMlpRows), dim3(kBlock), 0,
+                     (hipStream_t)hip_stream, (const unsigned char*)d_blob, d_X, B, d_out, MlpTrainOut{});
+  LAUNCH_CHECK("k_mlp_fwd_x");
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_mlp_train_step(float* d_state, void* d_blob, const float* d_X, const float* d_xt,
+                                         int32_t B, float lr, int32_t adam_t, void* d_train_ws, size_t ws_bytes,
+                                         float* d_loss, float* d_grad, void* hip_stream) {
+  if (!d_state || !d_blob || !d_X || !d_xt || !d_train_ws) return fail(DPF_EINVAL, "null buffer");
+  if (B < 32 || B % 32 != 0 || B > kMaxTrainBatch)
+    return fail(DPF_EINVAL, "batch %d must be a positive multiple of 32 up to %d", B, kMaxTrainBatch);
+  if (adam_t < 0) return fail(DPF_EINVAL, "adam_t = %d", adam_t);
+  const TrainWs w = train_layout(B);
+  if (ws_bytes < w.total) return fail(DPF_EINVAL, "training workspace has %zu bytes, needs %zu", ws_bytes, w.total);
+  hipStream_t s = (hipStream_t)hip_stream;
+  char* ws = (char*)d_train_ws;
+  unsigned char* blob = (unsigned char*)d_blob;
+  MlpTrainOut tr;
+  tr.a1 = (float*)(ws + w.a1);
+  tr.a2 = (float*)(ws + w.a2);
+  tr.x0t = (bf16_t*)(ws + w.x0t);
+  tr.h1t = (bf16_t*)(ws + w.h1t);
+  tr.h2t = (bf16_t*)(ws + w.h2t);
+  tr.B = B;
+  float* out = (float*)(ws + w.out);
+  hipLaunchKernelGGL(k_mlp_fwd_x<true>, dim3(w.tiles), dim3(kBlock), 0, s, blob, d_X, B, out, tr);
+  LAUNCH_CHECK("k_mlp_fwd_x");
+  hipLaunchKernelGGL(k_mdn_grad<2>, dim3(w.groups), dim3(kBlock), 0, s, out, d_xt, B, (bf16_t*)(ws + w.gb),
+                     (bf16_t*)(ws + w.gt), (float*)(ws + w.b3p), (double*)(ws + w.lossp));
+  LAUNCH_CHECK("k_mdn_grad");
+  MlpBwdArgs bw;
+  bw.gb = (const bf16_t*)(ws + w.gb);
+  bw.a1 = tr.a1;
+  bw.a2 = tr.a2;
+  bw.W3t = (const bf16_t*)(ws + w.w3t);
+  bw.W2t = (const bf16_t*)(ws + w.w2t);
+  bw.da2t = (bf16_t*)(ws + w.da2t);
+  bw.da1t = (bf16_t*)(ws + w.da1t);
+  bw.b2_part = (float*)(ws + w.b2p);
+  bw.b1_part = (float*)(ws + w.b1p);
+  bw.B = B;
+  hipLaunchKernelGGL(k_mlp_bwd, dim3(w.tiles), dim3(kBlock), 0, s, bw);
+  LAUNCH_CHECK("k_mlp_bwd");
+  WgArgs wg;
+  wg.job[0] = WgJob{bw.da1t, tr.x0t, (float*)(ws + w.wp1), kMlpHid, kMlpIn};
+  wg.job[1] = WgJob{bw.da2t, tr.h1t, (float*)(ws + w.wp2), kMlpHid, kMlpHid};
+  wg.job[2] = WgJob{(const bf16_t*)(ws + w.gt), tr.h2t, (float*)(ws + w.wp3), kMlpOut, kMlpHid};
+  for (int j = 0; j < 3; ++j) wg.blocks[j] = (wg.job[j].M / 32) * (wg.job[j].N / 32);
+  wg.B = B;
+  wg.chunks = w.chunks;
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(wg.blocks[0] + wg.blocks[1] + wg.blocks[2], w.chunks), dim3(kBlock), 0, s,
+                     wg);
+  LAUNCH_CHECK("k_mlp_wgrad");
+  AdamArgs ad;
+  ad.p = d_state;
+  ad.m = d_state + MlpParamLayout::n;
+  ad.v = d_state + 2 * MlpParamLayout::n;
+  ad.grad_out = d_grad;
+  ad.blob = blob;
+  ad.W2t = (bf16_t*)(ws + w.w2t);
+  ad.W3t = (bf16_t*)(ws + w.w3t);
+  ad.wpart[0] = wg.job[0].part;
+  ad.wpart[1] = wg.job[1].part;
+  ad.wpart[2] = wg.job[2].part;
+  ad.chunks = w.chunks;
+  ad.b1_part = bw.b1_part;
+  ad.b2_part = bw.b2_part;
+  ad.tiles = w.tiles;
+  ad.b3_part = (const float*)(ws + w.b3p);
+  ad.groups = w.groups;
+  ad.loss_part = (const double*)(ws + w.lossp);
+  ad.loss = d_loss;
+  ad.B = B;
+  ad.lr = lr;
+  ad.bc1 = (float)(1.0 - pow(0.9, (double)adam_t));
+  ad.bc2 = (float)(1.0 - pow(0.999, (double)adam_t));
+  ad.update = adam_t > 0 ? 1 : 0;
+  hipLaunchKernelGGL(k_mlp_adam, dim3((MlpParamLayout::n + 255) / 256), dim3(256), 0, s, ad);
+  LAUNCH_CHECK("k_mlp_adam");
   return DPF_OK;
 }

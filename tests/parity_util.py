@@ -163,3 +163,89 @@ def assert_clean(r, max_flip_frac=0.02, n=None):
             assert r[key] <= TOL, r.line()
     floor = 1.0 / n if n else 0.0
     assert r["clean_frac"] >= 1.0 - max(max_flip_frac, floor), r.line()
+
+
+def _inner_tie(model, st32, i, xt_i, u_in, b, j, M):
+    """Whether inner point j of particle i lies within DELTA of the boundary
+    of its chosen index b in the x-conditioned inner weights (FP64)."""
+    kap = st32["lam"][i] + model.logpx(xt_i, st32["x"][i], st32["z"][i])
+    wk, _, _ = weights_from_log(kap)
+    C = np.cumsum(wk)
+    Pj = ((j + u_in) * C[-1]) / M
+    return abs(Pj - C[b]) <= DELTA * C[-1] or (b > 0 and abs(Pj - C[b - 1]) <= DELTA * C[-1])
+
+
+def _inner_any_tie(model, st32, i, xt_i, u_in, M):
+    kap = st32["lam"][i] + model.logpx(xt_i, st32["x"][i], st32["z"][i])
+    wk, _, _ = weights_from_log(kap)
+    C = np.cumsum(wk)
+    Pj = ((np.arange(M) + u_in) * C[-1]) / M
+    return bool(np.any(np.min(np.abs(Pj[:, None] - C[None, :]), axis=1) <= DELTA * C[-1]))
+
+
+def compare_learned(model, st32, y32, seed, fid, mdn, g_state, g_logw, g_anc, g_comp, ess_frac):
+    """Compare one learned step (the oracle takes the same network outputs
+    mdn, FP32 values).  g_comp: the GPU's mixture component per
+    pre-resampling particle."""
+    from oracle import learned
+    new_o, info = learned.step(model, st32, y32, seed, fid, mdn, ess_frac=ess_frac)
+    N, M = st32["lam"].shape
+    t = st32["t"] + 1
+    r = Report()
+    r["fallback"] = bool(info["fallback"])
+    if info["fallback"]:
+        return r, new_o, info
+    u_mdn = P.uniform53(seed, fid, t, np.arange(N), P.MDN_U)
+    u_in = P.uniform53(seed, fid, t, np.arange(N), P.INNER_U)
+    logits = mdn[:, :4]
+    bad_c = np.nonzero(g_comp != info["comp"])[0]
+    r["comp_flips"] = len(bad_c)
+    unexpl = 0
+    for i in bad_c:
+        wc, _, _ = weights_from_log(logits[i])
+        unexpl += not near_tie(wc, u_mdn[i], 1, 0, info["comp"][i], g_comp[i])
+    r["comp_unexplained"] = unexpl
+    okc = g_comp == info["comp"]
+    # outer log-weights: compared where the component agrees; a difference is
+    # legitimate only where the particle's inner resampling has a near tie
+    d = np.abs(g_logw - info["logw"]) / np.maximum(1.0, np.abs(info["logw"]))
+    both_inf = np.isneginf(g_logw) & np.isneginf(info["logw"])
+    d = np.where(both_inf, 0.0, d)
+    badw = np.nonzero(okc & (d > TOL))[0]
+    tie = [i for i in badw if _inner_any_tie(model, st32, i, info["xt"][i], u_in[i], M)]
+    r["logw_off"] = len(badw)
+    r["logw_unexplained"] = len(badw) - len(tie)
+    mask = okc.copy()
+    mask[tie] = False
+    r["err_logw"] = float(np.max(d[mask])) if mask.any() else 0.0
+    w_out, _, _ = weights_from_log(info["logw"])
+    u_out = float(P.uniform53(seed, fid, t, 0, P.OUTER_U))
+    A_o, A_g = info["A"], g_anc
+    bad_anc = np.nonzero(A_o != A_g)[0]
+    r["anc_flips"] = len(bad_anc)
+    r["anc_unexplained"] = sum(not near_tie(w_out, u_out, N, k, A_o[k], A_g[k]) for k in bad_anc)
+    good = (A_o == A_g) & okc[A_o]
+    r["err_x"] = rel_err(g_state["x"][good], new_o["x"][good])
+    zg, zo = g_state["z"], new_o["z"]
+    dz = np.max(np.abs(zg - zo) / np.maximum(1.0, np.abs(zo)), axis=2)
+    zflip = good[:, None] & (dz > TOL)
+    r["z_flips"] = int(zflip.sum())
+    unexpl = 0
+    for k, j in zip(*np.nonzero(zflip)):
+        i = A_o[k]
+        unexpl += not _inner_tie(model, st32, i, info["xt"][i], u_in[i], info["binner"][i, j], j, M)
+    r["z_unexplained"] = unexpl
+    clean = good & ~zflip.any(axis=1)
+    r["err_z"] = rel_err(zg[clean], zo[clean])
+    r["err_lam"] = rel_err(g_state["lam"][clean], new_o["lam"][clean])
+    r["clean_frac"] = float(clean.mean())
+    return r, new_o, info
+
+
+def assert_clean_learned(r, n=None, max_flip_frac=0.02):
+    for key in ("comp_unexplained", "logw_unexplained", "anc_unexplained", "z_unexplained"):
+        assert r.get(key, 0) == 0, r.line()
+    for key in ("err_logw", "err_x", "err_z", "err_lam"):
+        assert r[key] <= TOL, r.line()
+    floor = 1.0 / n if n else 0.0
+    assert r["clean_frac"] >= 1.0 - max(max_flip_frac, floor), r.line()

@@ -93,3 +93,31 @@ def test_create_rejects_small_or_misaligned_workspace():
     assert L.dpf_create(ctypes.byref(c), ctypes.c_void_p(256), need - 1, None, ctypes.byref(h)) == 2
     assert L.dpf_create(ctypes.byref(c), ctypes.c_void_p(257), need, None, ctypes.byref(h)) == 1
     assert L.dpf_create(ctypes.byref(c), None, need, None, ctypes.byref(h)) == 1
+
+
+def test_network_sizes_and_batch_validation():
+    L = _lib()
+    L.dpf_mlp_blob_bytes.restype = ctypes.c_size_t
+    L.dpf_mlp_param_count.restype = ctypes.c_size_t
+    L.dpf_mlp_train_workspace_bytes.restype = ctypes.c_size_t
+    L.dpf_mlp_train_workspace_bytes.argtypes = [ctypes.c_int32]
+    hdr = open(os.path.join(ROOT, "include", "dpf.h")).read()
+    blob = int(re.search(r"DPF_MLP_BLOB_BYTES\s+(\d+)u", hdr).group(1))
+    npar = int(re.search(r"DPF_MLP_NPARAM\s+(\d+)u", hdr).group(1))
+    assert L.dpf_mlp_blob_bytes() == blob == dpf.MLP_BLOB_BYTES
+    assert L.dpf_mlp_param_count() == npar == dpf.MLP_NPARAM
+    # 256x32 + 256 + 256x256 + 256 + 32x256 + 32 parameters
+    assert npar == 256 * 32 + 256 + 256 * 256 + 256 + 32 * 256 + 32
+    for bad in (0, 16, 31, 33, 4100, (1 << 20) + 32):
+        assert L.dpf_mlp_train_workspace_bytes(bad) == 0
+    assert L.dpf_mlp_train_workspace_bytes(4096) > 4096 * 256 * 4 * 2
+
+
+def test_learned_calls_reject_null_handles():
+    L = _lib()
+    assert L.dpf_learned_step(None, None, None) == 1
+    assert L.dpf_set_proposal(None, None, ctypes.c_size_t(0), ctypes.c_double(0.1)) == 1
+    assert L.dpf_features(None, None, None) == 1
+    L.dpf_mlp_forward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_void_p]
+    assert L.dpf_mlp_forward(None, None, 4, None, None) == 1

@@ -1,0 +1,416 @@
+"""The learned proposal on the GPU: network forward, loss gradient and Adam
+against the BF16-quantised FP64 oracle; the learned step against the oracle
+with the same network outputs (proposal draw, inner pass, outer weights,
+resampling, lazy ancestor slots), its per-filter fallback to the look-ahead
+step, the look-ahead step reading a lazily resampled state, and the fused
+feature path of the step.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import dpf_synth as S
+import paper_1203_2394_amd as dpf
+from oracle import ladpf
+from oracle import learned as Lr
+from oracle.models import make_model
+
+from parity_util import (assert_clean, assert_clean_learned, compare_la, compare_learned, rel_err,
+                         to_state32)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _params(seed, n_feat=26, bias=0.1):
+    p = Lr.init_params(seed, n_feat)
+    g = np.random.default_rng(seed + 1)
+    for k in ("b1", "b2", "b3"):
+        p[k] = g.normal(size=p[k].shape) * bias
+    p["W3"] = p["W3"] * 20.0  # outputs of order one
+    return p
+
+
+def _f32(p):
+    return {k: np.asarray(v, dtype=np.float32).astype(np.float64) for k, v in p.items()}
+
+
+def _mlp(p, fmean=None, fstd=None, batch=32):
+    fmean = np.zeros(26) if fmean is None else fmean
+    fstd = np.ones(26) if fstd is None else fstd
+    return dpf.MLP(dpf.flatten_params(p), fmean, fstd, batch=batch)
+
+
+@pytest.mark.parametrize("B", [1, 16, 100, 4096])
+def test_forward_matches_bf16_oracle(B):
+    p = _f32(_params(11))
+    g = np.random.default_rng(B)
+    X = np.zeros((B, 32))
+    X[:, :26] = g.normal(size=(B, 26))
+    X = X.astype(np.float32).astype(np.float64)
+    ref, _ = Lr.forward(p, X, bf16_mode=True)
+    out = _mlp(p).forward(torch.tensor(X, dtype=torch.float32)).cpu().numpy()
+    assert np.all(out[:, 20:] == 0.0)
+    e = _rel_l2(out[:, :20], ref)
+    print("forward B=%d rel_l2=%.3g" % (B, e), flush=True)
+    assert e < 1e-3
+    assert np.max(np.abs(out[:, :20] - ref)) < 1e-2 * max(1.0, np.max(np.abs(ref)))
+
+
+def _oracle_grads(p, X, xt):
+    """Loss and gradients with the BF16-rounded forward of the GPU, FP64 backward."""
+    out, cache = Lr.forward(p, X, bf16_mode=True)
+    L, gout = Lr.mdn_nll_grad(out, xt)
+    pq = dict(p)
+    pq["W2"], pq["W3"] = Lr.bf16(p["W2"]), Lr.bf16(p["W3"])
+    return L, Lr.backward(pq, cache, gout)
+
+
+@pytest.mark.parametrize("B", [32, 1056])
+def test_loss_gradient_matches_oracle(B):
+    p = _f32(_params(12))
+    g = np.random.default_rng(B)
+    X = np.zeros((B, 32))
+    X[:, :26] = g.normal(size=(B, 26))
+    X = X.astype(np.float32).astype(np.float64)
+    xt = (g.normal(size=(B, 2)) * 2).astype(np.float32).astype(np.float64)
+    L, grads = _oracle_grads(p, X, xt)
+    m = _mlp(p, batch=B)
+    loss, gvec = m.loss_and_grad(torch.tensor(X, dtype=torch.float32), torch.tensor(xt, dtype=torch.float32))
+    gg = dpf.unflatten_params(gvec.cpu().numpy())
+    assert abs(float(loss) - L) <= 1e-3 * max(1.0, abs(L)), (float(loss), L)
+    for k in grads:
+        kk = tuple(slice(0, s) for s in grads[k].shape)
+        e = _rel_l2(gg[k][kk], grads[k])
+        print("grad %s B=%d rel_l2=%.3g" % (k, B, e), flush=True)
+        assert e < 1e-2, k
+    assert np.all(gg["W3"][20:] == 0.0) and np.all(gg["b3"][20:] == 0.0)
+    assert np.all(gg["W1"][:, 26:] == 0.0)
+    # no update: parameters unchanged
+    assert np.array_equal(m.state[0].cpu().numpy(), dpf.flatten_params(p))
+
+
+def test_adam_update_matches_oracle():
+    p = _f32(_params(13))
+    B = 64
+    g = np.random.default_rng(5)
+    X = np.zeros((B, 32))
+    X[:, :26] = g.normal(size=(B, 26))
+    xt = g.normal(size=(B, 2))
+    m = _mlp(p, batch=B)
+    Xt = torch.tensor(X, dtype=torch.float32)
+    xtt = torch.tensor(xt, dtype=torch.float32)
+    state = {}
+    ref = {k: v.copy() for k, v in p.items()}
+    for t in (1, 2, 3):
+        _, gvec = m.loss_and_grad(Xt, xtt)
+        grads = dpf.unflatten_params(gvec.cpu().numpy().astype(np.float64))
+        m.train_step(Xt, xtt, lr=1e-3)
+        ref = Lr.adam_step({k: dpf.unflatten_params(dpf.flatten_params(ref))[k] for k in ref}, grads, state, t,
+                           lr=1e-3)
+        got = dpf.unflatten_params(m.state[0].cpu().numpy())
+        for k in got:
+            kk = tuple(slice(0, s) for s in ref[k].shape)
+            assert np.allclose(got[k][kk], ref[k], rtol=2e-6, atol=2e-7), (t, k)
+        ref = {k: got[k].copy() for k in got}  # continue from the GPU's FP32 values
+    # the blob holds the BF16 rounding of the updated parameters
+    out = m.forward(Xt).cpu().numpy()
+    p_now = dpf.unflatten_params(m.state[0].cpu().numpy())
+    p_now["W3"], p_now["b3"] = p_now["W3"][:20], p_now["b3"][:20]
+    r2, _ = Lr.forward(p_now, X.astype(np.float32).astype(np.float64), bf16_mode=True)
+    assert _rel_l2(out[:, :20], r2) < 1e-3
+
+
+def test_training_reduces_the_loss():
+    """Targets drawn from a two-component law depending on one feature."""
+    B = 512
+    g = np.random.default_rng(21)
+    m = _mlp(_params(14, bias=0.0), batch=B)
+    losses = []
+    for it in range(300):
+        X = np.zeros((B, 32))
+        X[:, :26] = g.normal(size=(B, 26))
+        sgn = np.where(g.random(B) < 0.5, -1.0, 1.0)
+        xt = np.stack([3.0 * X[:, 0] + sgn * 2.0, -X[:, 1]], axis=1) + 0.1 * g.normal(size=(B, 2))
+        loss, _ = m.train_step(torch.tensor(X, dtype=torch.float32), torch.tensor(xt, dtype=torch.float32),
+                               lr=2e-3)
+        losses.append(float(loss))
+    print("loss first %.3f last %.3f" % (np.mean(losses[:10]), np.mean(losses[-10:])), flush=True)
+    assert np.all(np.isfinite(losses))
+    assert np.mean(losses[-10:]) < np.mean(losses[:10]) - 1.5
+
+
+# ------------------------------------------------------------------ learned step
+def _spec():
+    return S.nonlin_c2(1)
+
+
+def _model(spec):
+    return make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
+
+
+def _mdn_outputs(st, seed, y=None, model=None, far=None):
+    """Mixture outputs for the state (FP32 values).  With y and model: a
+    two-component fit to the look-ahead candidates' SIR law of each particle
+    (what a trained network approximates); otherwise components around the
+    transition mean.  far: particles whose components are moved far off."""
+    g = np.random.default_rng(seed)
+    N = st["x"].shape[0]
+    out = np.zeros((N, 32))
+    if y is not None:
+        xla, _, ell, _ = ladpf.lookahead(model, st, y, seed, 7)
+        w = np.exp(ell - ell.max(axis=1, keepdims=True))
+        w /= w.sum(axis=1, keepdims=True)
+        mu = np.einsum("nm,nmd->nd", w, xla)
+        var = np.einsum("nm,nmd->nd", w, (xla - mu[:, None, :]) ** 2) + 0.05
+        out[:, 0:2] = 0.0
+        out[:, 2:4] = -3.0
+        for c in range(4):
+            out[:, 4 + 2 * c:6 + 2 * c] = mu + 0.3 * np.sqrt(var) * g.normal(size=(N, 2))
+            out[:, 12 + 2 * c:14 + 2 * c] = 0.5 * np.log(var) + 0.3
+    else:
+        x = st["x"]
+        gx = 0.5 * x + 25.0 * x / (1.0 + x * x)
+        out[:, :4] = g.normal(size=(N, 4))
+        for c in range(4):
+            out[:, 4 + 2 * c:6 + 2 * c] = gx + g.normal(size=(N, 2))
+            out[:, 12 + 2 * c:14 + 2 * c] = 0.3 * g.normal(size=(N, 2)) + 0.2
+    if far is not None:
+        out[far, 4:12] += 1e4
+        out[far, 12:20] = math.log(1e-2)
+    return out.astype(np.float32).astype(np.float64)
+
+
+def _oracle_state(model, N, M, warm, seed, ys):
+    st = ladpf.init_state(model, N, M, seed, 0)
+    for t in range(warm):
+        st, _ = ladpf.step(model, st, ys[t], seed, 0)
+    return to_state32(st)
+
+
+def _gpu_state(f):
+    g = f.unpack_state(f.export_state())
+    return {"x": g["x"][0], "z": g["z"][0], "lam": g["lam"][0], "t": int(g["t"][0])}
+
+
+def _learned_case(N, M, warm, seed=99, data_seed=8, ess_frac=0.0):
+    spec = _spec()
+    model = _model(spec)
+    _, _, ys = S.simulate(spec, warm + 2, data_seed)
+    ys = ys.astype(np.float32).astype(np.float64)
+    st32 = _oracle_state(model, N, M, warm, seed, ys)
+    f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N], [M], seed=seed)
+    f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["x"], st32["z"], st32["lam"])))
+    mdn = _mdn_outputs(st32, seed + warm, ys[warm], model)
+    f.learned_step_given(torch.tensor(ys[warm], dtype=torch.float32), torch.tensor(mdn, dtype=torch.float32),
+                         ess_frac=ess_frac)
+    gs = _gpu_state(f)
+    logw = f.copy_buffer(dpf.BUF_LOGW).cpu().numpy()
+    anc = f.copy_buffer(dpf.BUF_ANC).cpu().numpy()
+    comp = f.copy_buffer(dpf.BUF_SEL).cpu().numpy()
+    r, new_o, info = compare_learned(model, st32, ys[warm], seed, 0, mdn, gs, logw, anc, comp, ess_frac)
+    print("learned N=%d M=%d t=%d: %s" % (N, M, warm + 1, r.line()), flush=True)
+    return f, model, spec, ys, st32, gs, r, new_o, info
+
+
+@pytest.mark.parametrize("N,M,warm", [(300, 200, 2), (100, 700, 1), (70, 32, 1), (4096, 256, 1)])
+def test_learned_step_parity(N, M, warm):
+    f, model, spec, ys, st32, gs, r, new_o, info = _learned_case(N, M, warm)
+    assert not r["fallback"]
+    assert_clean_learned(r, n=N)
+    assert gs["t"] == st32["t"] + 1
+    est = f.estimate()
+    assert int(est["flags"][0]) & dpf.FLAG_FALLBACK == 0
+    if r["clean_frac"] == 1.0 and r["anc_flips"] == 0:
+        assert np.allclose(est["xhat"][0].cpu().numpy(), info["xhat"], rtol=1e-4, atol=1e-4)
+        assert np.allclose(est["zhat"][0].cpu().numpy(), info["zhat"], rtol=1e-4, atol=1e-4)
+        assert abs(float(est["ess"][0]) - info["ess"]) <= 1e-3 * info["ess"]
+        assert abs(float(est["loglik"][0]) - info["dlogz"]) <= 1e-4 * max(1.0, abs(info["dlogz"]))
+
+
+def test_lookahead_step_after_learned_step_reads_the_slots():
+    """The learned step leaves particle k's cloud in slot A_k; the next
+    look-ahead step (weights and new cloud) must read through the slots."""
+    f, model, spec, ys, st32, gs, r, new_o, info = _learned_case(300, 64, 1)
+    assert not r["fallback"]
+    A = f.copy_buffer(dpf.BUF_ANC).cpu().numpy()
+    assert len(np.unique(A)) < len(A)  # resampling duplicated some particles
+    g32 = to_state32(gs)
+    f.lookahead_step(torch.tensor(ys[2], dtype=torch.float32))
+    g2 = _gpu_state(f)
+    ell = f.copy_buffer(dpf.BUF_ELL).cpu().numpy().reshape(300, 64)
+    logw = f.copy_buffer(dpf.BUF_LOGW).cpu().numpy()
+    anc = f.copy_buffer(dpf.BUF_ANC).cpu().numpy()
+    sel = f.copy_buffer(dpf.BUF_SEL).cpu().numpy()
+    r2, _, _ = compare_la(model, g32, ys[2], 99, 0, g2, ell, logw, anc, sel)
+    print("LA after learned: %s" % r2.line(), flush=True)
+    assert_clean(r2, n=300)
+
+
+def test_learned_step_falls_back_to_lookahead():
+    """ess_frac = 1 rejects any proposal with unequal weights: the step must be
+    the look-ahead step from the unchanged state, with the fallback flag."""
+    N, M = 200, 48
+    spec = _spec()
+    model = _model(spec)
+    _, _, ys = S.simulate(spec, 3, 8)
+    ys = ys.astype(np.float32).astype(np.float64)
+    st32 = _oracle_state(model, N, M, 1, 5, ys)
+    f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N], [M], seed=5)
+    f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["x"], st32["z"], st32["lam"])))
+    mdn = _mdn_outputs(st32, 3)
+    f.learned_step_given(torch.tensor(ys[1], dtype=torch.float32), torch.tensor(mdn, dtype=torch.float32),
+                         ess_frac=1.0)
+    gs = _gpu_state(f)
+    ell = f.copy_buffer(dpf.BUF_ELL).cpu().numpy().reshape(N, M)
+    logw = f.copy_buffer(dpf.BUF_LOGW).cpu().numpy()
+    anc = f.copy_buffer(dpf.BUF_ANC).cpu().numpy()
+    sel = f.copy_buffer(dpf.BUF_SEL).cpu().numpy()
+    _, info_l = Lr.step(model, st32, ys[1], 5, 0, mdn, ess_frac=1.0)
+    assert info_l["fallback"]
+    r, _, _ = compare_la(model, st32, ys[1], 5, 0, gs, ell, logw, anc, sel)
+    print("fallback: %s" % r.line(), flush=True)
+    assert_clean(r, n=N)
+    assert int(f.estimate()["flags"][0]) & dpf.FLAG_FALLBACK
+
+
+FRAC = 0.05
+
+
+def test_ragged_batch_falls_back_per_filter():
+    """Three filters: one with good proposals, one whose proposals are far off
+    (ESS collapses: look-ahead fallback), one sitting the step out."""
+    spec = _spec()
+    model = _model(spec)
+    Ns, Ms = [130, 257, 64], [40, 33, 100]
+    seeds = 31
+    _, _, ys = S.simulate(spec, 3, 13)
+    ys = ys.astype(np.float32).astype(np.float64)
+    f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, Ns, Ms, seed=seeds)
+    y = ys[2]
+    sts = []
+    for q in range(3):
+        st = ladpf.init_state(model, Ns[q], Ms[q], seeds, q)
+        for t in range(2):
+            st, _ = ladpf.step(model, st, ys[t], seeds, q)
+        sts.append(to_state32(st))
+    f.import_state(torch.from_numpy(f.pack_state([s["t"] for s in sts], [s["x"] for s in sts],
+                                                 [s["z"] for s in sts], [s["lam"] for s in sts])))
+    mdns = [_mdn_outputs(sts[0], 1, y, model), _mdn_outputs(sts[1], 2, far=np.arange(Ns[1])),
+            _mdn_outputs(sts[2], 3)]
+    Y = np.stack([y] * 3)
+    f.learned_step_given(torch.tensor(Y, dtype=torch.float32),
+                         torch.tensor(np.concatenate(mdns), dtype=torch.float32), ess_frac=FRAC,
+                         active=np.array([1, 1, 0], dtype=np.uint8))
+    g = f.unpack_state(f.export_state())
+    est = f.estimate()
+    flags = est["flags"].cpu().numpy()
+    logw = f.copy_buffer(dpf.BUF_LOGW).cpu().numpy()
+    anc = f.copy_buffer(dpf.BUF_ANC).cpu().numpy()
+    comp = f.copy_buffer(dpf.BUF_SEL).cpu().numpy()
+    ell = f.copy_buffer(dpf.BUF_ELL).cpu().numpy()
+    # filter 0: learned
+    o0, o1 = 0, Ns[0]
+    gs0 = {"x": g["x"][0], "z": g["z"][0], "lam": g["lam"][0]}
+    r0, _, _ = compare_learned(model, sts[0], y, seeds, 0, mdns[0], gs0, logw[o0:o1], anc[o0:o1],
+                               comp[o0:o1], FRAC)
+    print("filter 0: %s" % r0.line(), flush=True)
+    assert not r0["fallback"]
+    assert_clean_learned(r0, n=Ns[0])
+    assert flags[0] & dpf.FLAG_FALLBACK == 0
+    # filter 1: fallback = look-ahead step
+    _, info1 = Lr.step(model, sts[1], y, seeds, 1, mdns[1], ess_frac=FRAC)
+    assert info1["fallback"]
+    assert flags[1] & dpf.FLAG_FALLBACK
+    o1, o2 = Ns[0], Ns[0] + Ns[1]
+    io1, io2 = Ns[0] * Ms[0], Ns[0] * Ms[0] + Ns[1] * Ms[1]
+    gs1 = {"x": g["x"][1], "z": g["z"][1], "lam": g["lam"][1]}
+    r1, _, _ = compare_la(model, sts[1], y, seeds, 1, gs1, ell[io1:io2].reshape(Ns[1], Ms[1]),
+                          logw[o1:o2], anc[o1:o2], comp[o1:o2])
+    print("filter 1: %s" % r1.line(), flush=True)
+    assert_clean(r1, n=Ns[1])
+    # filter 2: untouched
+    assert int(g["t"][2]) == 2
+    assert np.array_equal(g["x"][2], np.asarray(sts[2]["x"], dtype=np.float32))
+    assert np.array_equal(g["z"][2], np.asarray(sts[2]["z"], dtype=np.float32))
+    assert flags[2] == 0
+
+
+def test_features_match_oracle():
+    spec = _spec()
+    model = _model(spec)
+    _, _, ys = S.simulate(spec, 3, 4)
+    st32 = _oracle_state(model, 150, 77, 2, 17, ys)
+    f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [150], [77], seed=17)
+    f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["x"], st32["z"], st32["lam"])))
+    y32 = ys[2].astype(np.float32).astype(np.float64)
+    feat = f.features(torch.tensor(y32, dtype=torch.float32)).cpu().numpy()
+    ref = Lr.features(st32, y32)
+    assert np.all(feat[:, 26:] == 0.0)
+    assert rel_err(feat[:, :26], ref) <= 1e-4
+
+
+def test_fused_features_and_network_in_the_step():
+    """dpf_learned_step builds the features inside the network kernel from the
+    cloud moments it keeps: after set_proposal (exact two-pass moments) its
+    outputs equal the explicit path (features, standardisation, forward);
+    after a look-ahead step (moments fused into the new-cloud kernel, second
+    moment minus squared mean in FP32) they agree to BF16 precision."""
+    spec = _spec()
+    model = _model(spec)
+    N, M = 512, 128
+    _, _, ys = S.simulate(spec, 4, 6)
+    st32 = _oracle_state(model, N, M, 1, 23, ys)
+    f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N], [M], seed=23)
+    f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["x"], st32["z"], st32["lam"])))
+    fmean = np.r_[np.zeros(2), np.zeros(8), np.zeros(8), np.full(8, 0.1)].astype(np.float32)
+    fstd = np.r_[np.full(2, 5.0), np.full(8, 3.0), np.full(8, 3.0), np.full(8, 0.1)].astype(np.float32)
+    m = _mlp(_params(15), fmean, fstd)
+    f.set_proposal(m, ess_frac=0.0)
+    y1 = torch.tensor(ys[1], dtype=torch.float32)
+    feat = f.features(y1)
+    Xs = torch.zeros(N, 32, device=feat.device)
+    Xs[:, :26] = (feat[:, :26] - m.fmean[:26]) / m.fstd[:26]
+    ref = m.forward(Xs).cpu().numpy()
+    f.learned_step(y1)
+    got = f.copy_buffer(dpf.BUF_MDN).cpu().numpy().reshape(N, 32)
+    assert _rel_l2(got, ref) < 1e-6
+    # look-ahead step, then a learned step on the moments it left
+    f.lookahead_step(torch.tensor(ys[2], dtype=torch.float32))
+    gs = _gpu_state(f)
+    raw = Lr.features(gs, ys[3].astype(np.float32).astype(np.float64))
+    X2 = np.zeros((N, 32), dtype=np.float32)
+    X2[:, :26] = (raw.astype(np.float32) - fmean) / fstd
+    ref2 = m.forward(torch.tensor(X2)).cpu().numpy()
+    f.learned_step(torch.tensor(ys[3], dtype=torch.float32))
+    got2 = f.copy_buffer(dpf.BUF_MDN).cpu().numpy().reshape(N, 32)
+    e = _rel_l2(got2, ref2)
+    print("fused moments vs two-pass: rel_l2=%.3g" % e, flush=True)
+    assert e < 1e-2
+
+
+def test_learned_steps_are_deterministic():
+    spec = _spec()
+    outs = []
+    for rep in range(2):
+        f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [256, 100], [64, 32], seed=3)
+        m = _mlp(_params(16))
+        f.set_proposal(m, ess_frac=0.05)
+        _, _, ys = S.simulate(spec, 4, 1)
+        for t in range(4):
+            f.learned_step(torch.tensor(np.stack([ys[t], ys[t]]), dtype=torch.float32))
+        outs.append(f.export_state().cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
