@@ -179,14 +179,18 @@ dpf_status dpf_import_state(dpf_handle* h, const void* d_src, size_t bytes);
  *                               after a learned step, the mixture component
  *                               drawn for each pre-resampling particle
  * DPF_BUF_MDN  float [sum N][32]: network outputs of the last learned step
- * DPF_BUF_X    float [dx][sum N]: outer particles x of the current state */
+ * DPF_BUF_X    float [dx][sum N]: outer particles x of the current state
+ * DPF_BUF_FALLBACK uint8 [F]:   1 where the last learned step fell back to
+ *                               the look-ahead step (0 for filters that were
+ *                               inactive or kept the learned proposals) */
 typedef enum {
   DPF_BUF_ELL = 0,
   DPF_BUF_LOGW = 1,
   DPF_BUF_ANC = 2,
   DPF_BUF_SEL = 3,
   DPF_BUF_MDN = 4,
-  DPF_BUF_X = 5
+  DPF_BUF_X = 5,
+  DPF_BUF_FALLBACK = 6
 } dpf_buffer;
 dpf_status dpf_copy_buffer(dpf_handle* h, int32_t which, void* d_dst, size_t bytes);
 

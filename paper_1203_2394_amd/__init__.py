@@ -19,7 +19,7 @@ DPF_ABI_VERSION = 1
 MODEL_LINGAUSS, MODEL_NONLIN, MODEL_HIGHDIM = 1, 2, 3
 ALGO_LOOKAHEAD, ALGO_PLAIN = 0, 1
 FLAG_DEGENERATE_OUTER, FLAG_DEGENERATE_INNER, FLAG_NONFINITE, FLAG_FALLBACK = 1, 2, 4, 8
-BUF_ELL, BUF_LOGW, BUF_ANC, BUF_SEL, BUF_MDN, BUF_X = range(6)
+BUF_ELL, BUF_LOGW, BUF_ANC, BUF_SEL, BUF_MDN, BUF_X, BUF_FALLBACK = range(7)
 MLP_BLOB_BYTES = 166272
 MLP_NPARAM = 82464
 MLP_IN, MLP_HID, MLP_OUT, MLP_MIX = 32, 256, 32, 4
@@ -325,7 +325,8 @@ class Filter:
         torch = _torch()
         sizes = {BUF_ELL: (self.NMT, torch.float32), BUF_LOGW: (self.NT, torch.float32),
                  BUF_ANC: (self.NT, torch.int32), BUF_SEL: (self.NT, torch.int32),
-                 BUF_MDN: (self.NT * MLP_OUT, torch.float32), BUF_X: (self.NT * self.dx, torch.float32)}
+                 BUF_MDN: (self.NT * MLP_OUT, torch.float32), BUF_X: (self.NT * self.dx, torch.float32),
+                 BUF_FALLBACK: (self.F, torch.uint8)}
         n, dt = sizes[which]
         out = torch.empty(n, dtype=dt, device=self.device)
         _check(lib().dpf_copy_buffer(self._h, int(which), _ptr(out), out.numel() * out.element_size()))

@@ -17,7 +17,7 @@ __global__ void k_reset(int* tcur, unsigned char* cur, unsigned char* act, uint3
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
   tcur[f] = 0;
-  cur[f] = 0;
+  cur[f] = 6;  // copy 0; identity cloud slots in both copies
   act[f] = 1;
   flags[f] = 0u;
   loglik[f] = 0.0;
@@ -45,7 +45,7 @@ __global__ void k_state_copy(float* ext, float* buf0, float* buf1, const unsigne
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_units * width) return;
   const int f = filter_of(off, F, e / width);
-  float* buf = cur[f] ? buf1 : buf0;
+  float* buf = (cur[f] & 1) ? buf1 : buf0;
   if (dir == 0)
     ext[e] = buf[e];
   else
@@ -58,8 +58,9 @@ __global__ void k_state_copy(float* ext, float* buf0, float* buf1, const unsigne
 // ind[copy][oo + i]; import writes slot order (the caller sets ind to the
 // identity).
 __global__ void k_state_copy_cloud(float* ext, float* buf0, float* buf1, const int* ind0, const int* ind1,
-                                   const unsigned char* cur, const long long* ioff, const int* ooff,
-                                   const int* fM, int F, long long n_units, int width, int dir) {
+                                   const unsigned char* cur,
+                                   const long long* ioff, const int* ooff, const int* fM, int F, long long n_units,
+                                   int width, int dir) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_units * width) return;
   if (dir == 1) {
@@ -70,15 +71,11 @@ __global__ void k_state_copy_cloud(float* ext, float* buf0, float* buf1, const i
   const long long per = (long long)fM[f] * width;  // elements per outer particle
   const long long loc = e - ioff[f] * width;
   const long long i = loc / per, rem = loc - i * per;
-  const int* ind = cur[f] ? ind1 : ind0;
-  const float* buf = cur[f] ? buf1 : buf0;
-  ext[e] = buf[ioff[f] * width + (long long)ind[ooff[f] + i] * per + rem];
-}
-
-__global__ void k_ind_identity(int* ind, const long long* ooff64, int F, int NT) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= NT) return;
-  ind[g] = g - (int)ooff64[filter_of(ooff64, F, g)];
+  const int c = cur[f] & 1;
+  const int* ind = c ? ind1 : ind0;
+  const bool ident = (cur[f] >> (1 + c)) & 1;
+  const float* buf = c ? buf1 : buf0;
+  ext[e] = buf[ioff[f] * width + (ident ? i : (long long)ind[ooff[f] + i]) * per + rem];
 }
 
 // x is [DX][NT]: element e = d * NT + g, filter by g.
@@ -87,7 +84,7 @@ __global__ void k_state_copy_x(float* ext, float* buf0, float* buf1, const unsig
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)NT * DX) return;
   const int f = filter_of(ooff64, F, e % NT);
-  float* buf = cur[f] ? buf1 : buf0;
+  float* buf = (cur[f] & 1) ? buf1 : buf0;
   if (dir == 0)
     ext[e] = buf[e];
   else
@@ -106,7 +103,7 @@ __global__ void k_import_time(const int* ext_t, int* tcur, unsigned char* cur, u
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
   tcur[f] = ext_t[f];
-  cur[f] = 0;
+  cur[f] = 6;  // state in copy 0 in slot order
   flags[f] = 0u;
   loglik[f] = 0.0;
 }

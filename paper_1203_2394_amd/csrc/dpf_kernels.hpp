@@ -65,7 +65,8 @@ struct StepArgs {
   int advance;   // 1: a step (time advances, estimates); 0: initialisation
   uint64_t seed;
   int* tcur;             // [F] time of the state (advanced by the statistics kernel)
-  unsigned char* cur;    // [F] copy holding the state (flipped with the time)
+  unsigned char* cur;    // [F] bit 0: copy holding the state (flipped with the time);
+                         // bits 1, 2: copy 0 / copy 1 has identity cloud slots
   unsigned char* act;    // [F] whether the filter takes the current step (set by the weights kernel)
   const unsigned char* active;  // [F] or null
   const int* run_Tf;            // [F] or null: filter steps while tcur < min(run_Tf, run_T)
@@ -92,6 +93,11 @@ struct StepArgs {
   float* trace_z;   // [T][F][DZ] or null
   int n_filters;
   int dy;
+  int dx, dz;
+  int n_tiles;  // tiles of the class being launched (tile-looping kernels)
+  int anc_ready;  // outer ancestors already in anc
+  const int2* rgroups;  // (filter, group) of each resampling workgroup
+  int n_commit;         // learned-step commit workgroups at the head of the launch
   // look-ahead state: cloud slot of each outer particle, per copy.  A step
   // that resamples by copying writes the identity; the learned step writes
   // its outer ancestors instead of moving the clouds.
@@ -101,12 +107,41 @@ struct StepArgs {
   const unsigned char* mlp;  // network blob
   float* mdn;                // [NT][32] network outputs for the current step
   float* xtmp;               // [DX][NT] proposals x_t before resampling
+  float* logq;               // [NT] log q of the proposals
   float* kpart_tmp;          // [NT][DZ]
   float* mom_tmp;            // [NT][2 DZ]
   unsigned char* fb;         // [F] 1 where the look-ahead step replaces the learned one; null otherwise
   uint32_t* lflags;          // [F] flags of the learned pass, kept only if it is accepted
   double ess_frac;           // fallback threshold on ESS / N
 };
+
+__device__ __forceinline__ int copy_of(unsigned char c) { return c & 1; }
+__device__ __forceinline__ bool ident_slots(unsigned char c, int copy) { return (c >> (1 + copy)) & 1; }
+
+// fz_pre for a whole segment whose lanes share the outer particle: lane q of
+// each wave's part of the segment evaluates component q once, and the
+// components are broadcast (readlane within a wave, lane permutes when two
+// segments share a wave) instead of every lane evaluating all of them.
+template <class Mdl, int SEG>
+__device__ __forceinline__ void fz_pre_seg(const float* P, const float* xp, const float* xn, float* pre) {
+  constexpr int DZ = Mdl::DZ;
+  constexpr int W = SEG < 64 ? SEG : 64;
+  if constexpr (DZ > W) {
+    Mdl::fz_pre(P, xp, xn, pre);
+  } else {
+    const int lane = threadIdx.x & 63;
+    const int q = lane % W;
+    const float mine = Mdl::fz_pre_k(P, xp, xn, q < DZ ? q : 0);
+    if constexpr (W == 64) {
+#pragma unroll
+      for (int k = 0; k < DZ; ++k) pre[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine), k));
+    } else {
+      const int base = lane - q;
+#pragma unroll
+      for (int k = 0; k < DZ; ++k) pre[k] = __shfl(mine, base + k);
+    }
+  }
+}
 
 // Whether filter f takes this step: the caller's mask and the run limits,
 // evaluated by the weights kernel (before the time advances) and recorded in
@@ -168,6 +203,28 @@ __device__ __forceinline__ double block_scan_incl_256(double v, double* red4) {
   return v + pre;
 }
 
+// Block-wide stream compaction in thread order: the values of threads with
+// pred go to out[0..total); returns total; incl receives the number of pred
+// threads up to and including this one.
+__device__ __forceinline__ int block_compact(bool pred, int value, int* out, int* wcnt, int* incl) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const unsigned long long b = __ballot(pred);
+  const int r = __popcll(b & ((1ull << lane) - 1ull));
+  if (lane == 0) wcnt[w] = __popcll(b);
+  __syncthreads();
+  int off = 0, total = 0;
+#pragma unroll
+  for (int q = 0; q < kBlock / kWave; ++q) {
+    const int c = wcnt[q];
+    if (q < w) off += c;
+    total += c;
+  }
+  if (pred) out[off + r] = value;
+  if (incl) *incl = off + r + (pred ? 1 : 0);
+  __syncthreads();
+  return total;
+}
+
 // ------------------------------------------------------------ initialisation
 // Prior draws [x_0; z_0] ~ N(0, I) (INIT_X at (0, i, 0), INIT_Z at (0, i, j)).
 // Look-ahead state: lam_0 = -log M, written to copy 0.  Plain DPF: the prior
@@ -190,10 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_init(StepArgs a) {
     normals<Mdl::DX>(key, 0u, (uint32_t)i, 0u, P_INIT_X, x0);
 #pragma unroll
     for (int d = 0; d < Mdl::DX; ++d) a.x[dst][(long long)d * a.NT + oo + i] = x0[d];
-    if (PLAIN)
-      a.anc[oo + i] = i;
-    else
-      a.ind[dst][oo + i] = i;
+    if (PLAIN) a.anc[oo + i] = i;
   }
   const float lam0 = -fast_log((float)M);
   float* zrow = a.z[dst] + (io + (long long)i * M) * Mdl::DZ;
@@ -216,29 +270,13 @@ __global__ __launch_bounds__(kBlock) void k_init(StepArgs a) {
 // component (LA_X normals at (t, i, j)) and its companion z (LA_Z), then
 // ell = lam + log p(y_t | xla, zla) (eq:weightsMC) and the per-particle
 // log-sum-exp log w_i.
-__device__ bool learned_rejected(const StepArgs& a, int f, int N, float* fred4, double* red4);
-
 template <class Mdl, int SEG, int JPT>
-__global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
+__device__ __forceinline__ void la_weights_tile(const StepArgs& a, int ti, bool fallback) {
   __shared__ SegScratch sh;
-  const int4 tile = a.tiles[blockIdx.x];
+  const int4 tile = a.tiles[ti];
   const int f = tile.x;
   const bool act = step_active(a, f);
-  if (a.fb) {
-    // learned step: only filters that reject their learned proposals take
-    // the look-ahead step, from the state the learned pass left untouched
-    const bool rej = act && learned_rejected(a, f, a.fN[f], sh.f[0], sh.d[0]);
-    if (tile.z == 0 && threadIdx.x == 0) {
-      a.fb[f] = rej ? 1 : 0;
-      if (rej) {
-        atomicOr(&a.flags[f], (uint32_t)F_FALLBACK);
-        a.lflags[f] = 0u;
-      }
-    }
-    if (!rej) return;
-  } else if (tile.z == 0 && threadIdx.x == 0) {
-    a.act[f] = act ? 1 : 0;
-  }
+  if (!fallback && tile.z == 0 && threadIdx.x == 0) a.act[f] = act ? 1 : 0;
   if (!act) return;
   const int N = a.fN[f], M = a.fM[f];
   const int i = tile.y + threadIdx.x / SEG;
@@ -247,9 +285,10 @@ __global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
   const int oo = a.ooff[f];
   const long long io = a.ioff[f];
   const int t = a.tcur[f] + 1;
-  const int src = a.cur[f];
+  const unsigned char cb = a.cur[f];
+  const int src = copy_of(cb);
   const Key key = make_key(a.seed, (uint32_t)f);
-  const int ci = vi ? a.ind[src][oo + i] : 0;
+  const int ci = vi ? (ident_slots(cb, src) ? i : a.ind[src][oo + i]) : 0;
 
   float y[Mdl::DY], x[Mdl::DX];
   load_y<Mdl>(a, f, t, y);
@@ -284,6 +323,60 @@ __global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
   if (vi && ls == 0) a.logw[oo + i] = lw;
 }
 
+__device__ bool learned_rejected(const StepArgs& a, int f, int N, float* fred4, double* red4);
+
+// One workgroup per tile.  (A kernel that loops over tiles compiles to
+// markedly slower code for the single-tile case, so the learned step's
+// fallback has kernels of its own.)
+template <class Mdl, int SEG, int JPT>
+__global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
+  la_weights_tile<Mdl, SEG, JPT>(a, blockIdx.x, false);
+}
+
+// Learned step's fallback, a smaller grid looping over the tiles: each
+// workgroup loads its tiles' filters at once, decides per filter whether the
+// learned proposals are rejected (the workgroup holding a filter's first
+// tile records the decision and the fallback flag), and runs the look-ahead
+// weights only for the tiles of rejecting filters.
+template <class Mdl, int SEG, int JPT>
+__global__ __launch_bounds__(kBlock) void k_la_weights_fallback(StepArgs a) {
+  __shared__ int tfl[kBlock], runs[kBlock], todo[kBlock], wcnt[kBlock / kWave];
+  __shared__ unsigned char rejr[kBlock];
+  __shared__ float fred4[kBlock / kWave];
+  __shared__ double red4[kBlock / kWave];
+  const int th = threadIdx.x;
+  for (int base = blockIdx.x; base < a.n_tiles; base += kBlock * gridDim.x) {
+    const int mine = base + th * gridDim.x;
+    const bool have = mine < a.n_tiles;
+    const int4 tl = have ? a.tiles[mine] : make_int4(-1, 0, 0, 0);
+    tfl[th] = tl.x;
+    __syncthreads();
+    // runs of equal filters (tiles are ordered by filter within a class)
+    const bool start = have && (th == 0 || tfl[th - 1] != tl.x);
+    int myrun;
+    const int nr = block_compact(start, th, runs, wcnt, &myrun);
+    for (int r = 0; r < nr; ++r) {
+      const int f = tfl[runs[r]];
+      const bool rej = step_active(a, f) && learned_rejected(a, f, a.fN[f], fred4, red4);
+      if (th == 0) rejr[r] = rej ? 1 : 0;
+      __syncthreads();
+    }
+    const bool rj = have && rejr[myrun - 1] != 0;
+    if (have && tl.z == 0) {
+      a.fb[tl.x] = rj ? 1 : 0;
+      if (rj) {
+        atomicOr(&a.flags[tl.x], (uint32_t)F_FALLBACK);
+        a.lflags[tl.x] = 0u;
+      }
+    }
+    const int nt = block_compact(rj, mine, todo, wcnt, nullptr);
+    for (int q = 0; q < nt; ++q) {
+      la_weights_tile<Mdl, SEG, JPT>(a, todo[q], true);
+      __syncthreads();
+    }
+  }
+}
+
 // --------------------------------------------------------- plain weights
 // Fig. 2 step 1 (eq:approx2 with unit inner weights): ell = log p(y_t | xt, zt),
 // log w_i = logsumexp_j ell - log M, and the per-particle partial
@@ -304,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_dpf_weights(StepArgs a) {
   const int oo = a.ooff[f];
   const long long io = a.ioff[f];
   const int t = a.tcur[f] + 1;
-  const int src = a.cur[f];
+  const int src = copy_of(a.cur[f]);
 
   float y[Mdl::DY], x[Mdl::DX], r0[Mdl::DY];
   load_y<Mdl>(a, f, t, y);
@@ -343,12 +436,21 @@ __global__ __launch_bounds__(kBlock) void k_dpf_weights(StepArgs a) {
       for (int d = 0; d < Mdl::DZ; ++d) part[d] += q * zrow[d * M + j];
     }
   }
-  seg_sum_vec<SEG, Mdl::DZ>(part, vred);
   const float lw = deg ? -INFINITY : lse - fast_log((float)M);
+  float* kp = a.kpart + (long long)(oo + i) * Mdl::DZ;
+  if constexpr (Mdl::DZ <= 16) {
+    int slot;
+    const float tot = seg_sum_vec_t<SEG, Mdl::DZ>(part, vred, slot);
+    if (vi && slot >= 0) kp[slot] = tot;
+  } else {
+    seg_sum_vec<SEG, Mdl::DZ>(part, vred);
+    if (vi && ls == 0) {
+#pragma unroll
+      for (int d = 0; d < Mdl::DZ; ++d) kp[d] = part[d];
+    }
+  }
   if (vi && ls == 0) {
     a.logw[oo + i] = lw;
-#pragma unroll
-    for (int d = 0; d < Mdl::DZ; ++d) a.kpart[(long long)(oo + i) * Mdl::DZ + d] = part[d];
     if (deg) atomicOr(&a.flags[f], (uint32_t)F_DEGENERATE_INNER);
   }
 }
@@ -436,6 +538,8 @@ struct ResScratch {
   double C[kResGroup];    // cumulative weights of the group being resolved
   double P[kBlock];       // points of this workgroup
   int gsel[kBlock];       // their groups
+  int run0[kBlock];       // first point of each run of points sharing a group
+  int wcnt[kBlock / kWave];
   double red4[kBlock / kWave];
   float fred4[kBlock / kWave];
 };
@@ -509,11 +613,26 @@ __device__ ResResult resolve_points(const Src& src, int n, int n_out, double u, 
     sh.gsel[th] = lo;
   }
   __syncthreads();
-  // points are non-decreasing, so their groups are too: visit each distinct one
-  for (int j0 = 0; j0 < np;) {
+  // points are non-decreasing, so their groups are too: list the runs of
+  // points per group and visit each distinct group once (few points: a
+  // scan by every thread; many: ranks of the run starts by compaction)
+  int nruns;
+  if (np <= 16) {
+    nruns = 0;
+    for (int j = 0; j < np; ++j)
+      if (j == 0 || sh.gsel[j] != sh.gsel[j - 1]) {
+        if (th == 0) sh.run0[nruns] = j;
+        ++nruns;
+      }
+    __syncthreads();
+  } else {
+    const bool start = th < np && (th == 0 || sh.gsel[th - 1] != sh.gsel[th]);
+    nruns = block_compact(start, th, sh.run0, sh.wcnt, nullptr);
+  }
+  for (int r = 0; r < nruns; ++r) {
+    const int j0 = sh.run0[r];
+    const int j1 = r + 1 < nruns ? sh.run0[r + 1] : np;
     const int g = sh.gsel[j0];
-    int j1 = j0 + 1;
-    while (j1 < np && sh.gsel[j1] == g) ++j1;
     const int base = g * kResGroup;
     const int nloc = min(kResGroup, n - base);
     const float mg = Src::kLog ? (float)gstat[4 * g] : 0.f;
@@ -526,7 +645,6 @@ __device__ ResResult resolve_points(const Src& src, int n, int n_out, double u, 
     __syncthreads();
     if (th >= j0 && th < j1) res[th] = base + cdf_search(sh.C, nloc, sh.P[th]);
     __syncthreads();
-    j0 = j1;
   }
   ResResult r;
   r.m = deg ? 0.f : m;
@@ -582,6 +700,67 @@ __global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const int2* rg
   }
 }
 
+// Outer ancestors of 256 new particles per workgroup (the grid of k_res_stats,
+// after the time advance), by the group-statistics rule of resolve_points;
+// group 0 also records the filter's ESS, evidence and flags.  In a learned
+// step whose proposals were accepted (fb[f] == 0) the workgroup also
+// commits the resampled particles: slot indirection, x, and the per-particle
+// moments gathered from the learned pass.
+// Learned step with accepted proposals (fb[f] == 0): outer ancestors of 256
+// new particles per workgroup b (the grid of k_res_stats) by the
+// group-statistics rule of resolve_points, and the commit of the resampled
+// particles: the learned pass propagated particle i's cloud into slot i of
+// the new copy, so particle k refers to its ancestor's slot; x and the
+// per-particle moments are gathered (all loads first).  Group 0 records the
+// filter's ESS, evidence and flags.  Filters that fell back are skipped
+// (their new-cloud tiles resolve their own ancestors).
+template <int DX, int DZ>
+__device__ void commit_group(const StepArgs& a, int b) {
+  __shared__ ResScratch rsh;
+  __shared__ int res[kBlock];
+  const int2 rg = a.rgroups[b];
+  const int f = rg.x;
+  if (!a.act[f] || a.fb[f]) return;
+  const int N = a.fN[f];
+  const int oo = a.ooff[f];
+  const int t = a.tcur[f];
+  const int k0 = rg.y * kResGroup;
+  const int np = min(kResGroup, N - k0);
+  const Key key = make_key(a.seed, (uint32_t)f);
+  const double u = uniform53(key, (uint32_t)t, 0u, P_OUTER_U);
+  const ResResult rr = resolve_points(LogSrc{a.logw + oo}, N, N, u, k0, np, a.gstat + 4LL * a.finfo[f].rg_base,
+                                      a.finfo[f].ngroup, res, rsh, rg.y == 0);
+  if (rg.y == 0 && threadIdx.x == 0) res_finish(a, f, t, N, rr);
+  const int th = threadIdx.x;
+  const int dst = copy_of(a.cur[f]);
+  if (th < np) {
+    const long long gk = oo + k0 + th, gp = oo + res[th];
+    float xv[DX], kv[DZ], mv[2 * DZ];
+#pragma unroll
+    for (int d = 0; d < DX; ++d) xv[d] = a.xtmp[(long long)d * a.NT + gp];
+#pragma unroll
+    for (int d = 0; d < DZ; ++d) kv[d] = a.kpart_tmp[gp * DZ + d];
+#pragma unroll
+    for (int d = 0; d < 2 * DZ; ++d) mv[d] = a.mom_tmp[gp * 2 * DZ + d];
+    a.anc[gk] = res[th];
+    a.ind[dst][gk] = res[th];
+#pragma unroll
+    for (int d = 0; d < DX; ++d) a.x[dst][(long long)d * a.NT + gk] = xv[d];
+#pragma unroll
+    for (int d = 0; d < DZ; ++d) a.kpart[gk * DZ + d] = kv[d];
+    if (a.mom) {
+#pragma unroll
+      for (int d = 0; d < 2 * DZ; ++d) a.mom[gk * 2 * DZ + d] = mv[d];
+    }
+    if (k0 == 0 && th == 0) a.cur[f] = (unsigned char)(a.cur[f] & ~(2 << dst));
+  }
+  if (rg.y == 0 && th == 0) {
+    const uint32_t lf = a.lflags[f];
+    if (lf) atomicOr(&a.flags[f], lf);
+    a.lflags[f] = 0u;
+  }
+}
+
 // ---------------------------------------------------------------- estimates
 // One workgroup per filter, FP64 sums in a fixed order (strided per thread,
 // then DPP and the wave results in order), so results are reproducible:
@@ -601,7 +780,7 @@ __global__ __launch_bounds__((fin_block<DX, DZ>())) void k_finalize(StepArgs a) 
   const int N = a.fN[f];
   const int oo = a.ooff[f];
   const int t = a.tcur[f];
-  const float* xs = a.x[PLAIN ? a.cur[f] ^ 1 : a.cur[f]];
+  const float* xs = a.x[PLAIN ? copy_of(a.cur[f]) ^ 1 : copy_of(a.cur[f])];
   double mx = 0.0, tot = 1.0;
   bool deg = false;
   if (PLAIN) {
@@ -655,7 +834,7 @@ __global__ __launch_bounds__((fin_block<DX, DZ>())) void k_finalize(StepArgs a) 
 // log p(x_{t+1} | x_p, z_pj), systematic inner resampling, DPF_Z normals;
 // no measurement update (that happens at the next step).
 template <class Mdl, int SEG, int JPT, bool PLAIN>
-__global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
+__device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
   constexpr int DX = Mdl::DX, DZ = Mdl::DZ, DY = Mdl::DY;
   constexpr int NSEG = kBlock / SEG;
   constexpr bool kKeepZ = JPT * DZ <= 64;  // new z stays in registers for the partial sums
@@ -663,13 +842,15 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
   __shared__ double cdf[NSEG][SEG * JPT];
   __shared__ float xs_sh[NSEG][DX];
   __shared__ int csel[NSEG];
-  __shared__ int anc_sh[NSEG];
   __shared__ float vred[kBlock / kWave][2 * DZ];
+  __shared__ int anc_sh[NSEG];
   __shared__ ResScratch rsh;
 
-  const int4 tile = a.tiles[blockIdx.x];
+  const int4 tile = a.tiles[ti];
   const int f = tile.x;
   if (!a.act[f]) return;
+  // learned step with accepted proposals: committed by commit_group
+  if (!PLAIN && a.fb != nullptr && a.fb[f] == 0) return;
   const int N = a.fN[f], M = a.fM[f];
   const int s = threadIdx.x / SEG;
   const int ls = threadIdx.x % SEG;
@@ -678,11 +859,13 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
   const int oo = a.ooff[f];
   const long long io = a.ioff[f];
   const int t = a.tcur[f];  // already advanced (0 at initialisation)
-  const int dst = a.cur[f], src = dst ^ 1;
+  const unsigned char cb = a.cur[f];
+  const int dst = copy_of(cb), src = dst ^ 1;
   const Key key = make_key(a.seed, (uint32_t)f);
 
   // ---- 0. outer ancestors of this tile's new particles -------------------
-  if (a.advance) {
+  // (resolved here, also for the learned step's fallback filters)
+  if (a.advance && !a.anc_ready) {
     const int np = min(NSEG, N - tile.y);
     const int G = a.finfo[f].ngroup;
     const double u = uniform53(key, (uint32_t)t, 0u, P_OUTER_U);
@@ -690,36 +873,16 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
                                         a.gstat + 4LL * a.finfo[f].rg_base, G, anc_sh, rsh, tile.z == 0);
     if (tile.z == 0 && threadIdx.x == 0) res_finish(a, f, t, N, rr);
   } else if (threadIdx.x < NSEG) {
-    anc_sh[threadIdx.x] = tile.y + threadIdx.x;  // initial proposals: every particle its own parent
+    const int kk = tile.y + threadIdx.x;
+    anc_sh[threadIdx.x] = a.advance ? (kk < N ? a.anc[oo + kk] : 0) : kk;  // identity at initialisation
   }
   __syncthreads();
   const int p = vk ? anc_sh[s] : 0;
-  if (vk && ls == 0) a.anc[oo + k] = p;
-
-  if (!PLAIN && a.fb != nullptr && a.fb[f] == 0) {
-    // learned step accepted: the clouds were propagated in slot order by the
-    // learned pass; particle k refers to its ancestor's slot
-    if (vk && ls == 0) {
-      const long long gk = oo + k, gp = oo + p;
-      a.ind[dst][gk] = p;
-#pragma unroll
-      for (int d = 0; d < DX; ++d) a.x[dst][(long long)d * a.NT + gk] = a.xtmp[(long long)d * a.NT + gp];
-#pragma unroll
-      for (int d = 0; d < DZ; ++d) a.kpart[gk * DZ + d] = a.kpart_tmp[gp * DZ + d];
-      if (a.mom) {
-#pragma unroll
-        for (int d = 0; d < 2 * DZ; ++d) a.mom[gk * 2 * DZ + d] = a.mom_tmp[gp * 2 * DZ + d];
-      }
-    }
-    if (tile.z == 0 && threadIdx.x == 0) {
-      const uint32_t lf = a.lflags[f];
-      if (lf) atomicOr(&a.flags[f], lf);
-      a.lflags[f] = 0u;
-    }
-    return;
-  }
-  const int pc = PLAIN ? p : a.ind[src][oo + p];  // cloud slot of the parent
-  if (!PLAIN && vk && ls == 0) a.ind[dst][oo + k] = k;
+  if (vk && ls == 0 && !a.anc_ready) a.anc[oo + k] = p;
+  // cloud slot of the parent; the new clouds are written in slot order
+  const int pc = (PLAIN || ident_slots(cb, src)) ? p : a.ind[src][oo + p];
+  if (!PLAIN && tile.z == 0 && threadIdx.x == 0 && !ident_slots(cb, dst))
+    a.cur[f] = (unsigned char)(cb | (2 << dst));
 
   float xp[DX];
 #pragma unroll
@@ -819,7 +982,7 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
 
   // ---- 4. gather + propagate (+ measurement update in look-ahead mode) ---
   float pre[DZ];
-  Mdl::fz_pre(a.prm, xp, xn, pre);
+  fz_pre_seg<Mdl, SEG>(a.prm, xp, xn, pre);
   float y[DY], r0[DY];
   if (!PLAIN) {
     load_y<Mdl>(a, f, t, y);
@@ -878,25 +1041,68 @@ __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
         }
       }
     }
-    if (want_mom)
-      seg_sum_vec<SEG, NP>(part, reinterpret_cast<float(*)[NP]>(&vred[0][0]));
-    else
-      seg_sum_vec<SEG, DZ>(part, reinterpret_cast<float(*)[DZ]>(&vred[0][0]));
-    if (vk && ls == 0) {
-#pragma unroll
-      for (int d = 0; d < DZ; ++d) a.kpart[(long long)(oo + k) * DZ + d] = part[d];
-      if constexpr (NP == 2 * DZ) {
-        if (want_mom) {
-#pragma unroll
-          for (int d = 0; d < DZ; ++d) {
-            a.mom[(long long)(oo + k) * 2 * DZ + d] = part[d];
-            a.mom[(long long)(oo + k) * 2 * DZ + DZ + d] = fmaxf(part[DZ + d] - part[d] * part[d], 0.f);
+    float* kp = a.kpart + (long long)(oo + k) * DZ;
+    if constexpr (NP <= 16) {
+      // transpose reduction: each owning lane stores its slot
+      int slot;
+      if (want_mom) {
+        const float tot = seg_sum_vec_t<SEG, NP>(part, reinterpret_cast<float(*)[NP]>(&vred[0][0]), slot);
+        const float mean = seg_vec_fetch<SEG, NP>(tot, slot >= DZ ? slot - DZ : -1);
+        if (vk && slot >= 0) {
+          float* mp = a.mom + (long long)(oo + k) * 2 * DZ;
+          if (slot < DZ) {
+            kp[slot] = tot;
+            mp[slot] = tot;
+          } else {
+            mp[slot] = fmaxf(tot - mean * mean, 0.f);
           }
         }
+      } else {
+        const float tot = seg_sum_vec_t<SEG, DZ>(part, reinterpret_cast<float(*)[DZ]>(&vred[0][0]), slot);
+        if (vk && slot >= 0) kp[slot] = tot;
+      }
+    } else {
+      seg_sum_vec<SEG, DZ>(part, reinterpret_cast<float(*)[DZ]>(&vred[0][0]));
+      if (vk && ls == 0) {
+#pragma unroll
+        for (int d = 0; d < DZ; ++d) kp[d] = part[d];
       }
     }
   }
   if (vk && ls == 0 && fl) atomicOr(&a.flags[f], fl);
+}
+
+template <class Mdl, int SEG, int JPT, bool PLAIN>
+__global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
+  newcloud_tile<Mdl, SEG, JPT, PLAIN>(a, blockIdx.x);
+}
+
+// Learned step: the new clouds of the filters that fell back only (smaller
+// grid looping over the tiles, tiles checked at once).
+template <class Mdl, int SEG, int JPT>
+__global__ __launch_bounds__(kBlock) void k_newcloud_fallback(StepArgs a) {
+  constexpr bool PLAIN = false;
+  // the first n_commit workgroups commit the filters that kept their
+  // learned proposals
+  if ((int)blockIdx.x < a.n_commit) {
+    commit_group<Mdl::DX, Mdl::DZ>(a, blockIdx.x);
+    return;
+  }
+  const int bid = blockIdx.x - a.n_commit, nb = gridDim.x - a.n_commit;
+  __shared__ int todo[kBlock], wcnt[kBlock / kWave];
+  for (int base = bid; base < a.n_tiles; base += kBlock * nb) {
+    const int mine = base + threadIdx.x * nb;
+    bool need = false;
+    if (mine < a.n_tiles) {
+      const int f = a.tiles[mine].x;
+      need = a.act[f] && a.fb[f];
+    }
+    const int nt = block_compact(need, mine, todo, wcnt, nullptr);
+    for (int q = 0; q < nt; ++q) {
+      newcloud_tile<Mdl, SEG, JPT, PLAIN>(a, todo[q]);
+      __syncthreads();
+    }
+  }
 }
 
 }  // namespace dpf

@@ -4,21 +4,24 @@
 // whose effective sample size drops below a set fraction of N.
 //
 // Launch sequence of one step (each kernel gated per filter):
-//   k_mlp_fwd_state     features of every outer particle -> mixture outputs
-//   k_learned_inner     draw x_t ~ q (MDN_U, MDN_X at (t, i)), condition the
-//                       particle's inner cloud on it (eq:qnobar, eq:approx1),
-//                       resample it locally (INNER_U), propagate (NEW_Z at
-//                       (t, i, j)), measurement update (eq:approx2, eq:qbar),
-//                       log w_i = log p_Nz(y_t | .) + log p_Nz(x_t | .) - log q
-//   k_res_stats         group statistics of log w (no time advance)
-//   k_la_weights        every workgroup derives its filter's ESS from the
-//                       group statistics; filters below the threshold run the
-//                       look-ahead weights from the unchanged state
-//   k_res_stats         statistics (look-ahead weights or the same learned
-//                       ones again) and the time advance
-//   k_newcloud          fallback filters: the look-ahead new cloud; the others
-//                       commit the resampled learned particles
-//   k_finalize          estimates
+//   k_mlp_fwd_state        features of every outer particle -> mixture
+//                          outputs; its epilogue draws x_t ~ q (MDN_U, MDN_X
+//                          at (t, i)) and log q (k_mdn_draw instead when the
+//                          caller supplies the outputs)
+//   k_learned_inner        condition particle i's inner cloud on x_t
+//                          (eq:qnobar, eq:approx1), resample it locally
+//                          (INNER_U), propagate (NEW_Z at (t, i, j)),
+//                          measurement update (eq:approx2, eq:qbar), and
+//                          log w_i = log p_Nz(y_t | .) + log p_Nz(x_t | .) - log q
+//   k_res_stats            group statistics of log w (no time advance)
+//   k_la_weights_fallback  per filter: reject when ESS < ess_frac N; the
+//                          rejecting filters' look-ahead weights
+//   k_res_stats            statistics (look-ahead weights, or the same
+//                          learned ones again) and the time advance
+//   k_newcloud_fallback    head workgroups: resample and commit the accepted
+//                          filters; the rest: look-ahead new clouds of the
+//                          filters that fell back
+//   k_finalize             estimates
 // Accepted particles are not copied: particle i's new cloud is written to
 // its own slot of the next state copy and the resampled particle k refers to
 // slot A_k through ind (lazy resampling); x and the per-particle moments are
@@ -49,35 +52,9 @@ __device__ __forceinline__ int filter_of_outer(const int* off, int F, int g) {
 template <class Mdl>
 __device__ __forceinline__ float raw_feature(const StepArgs& a, int f, int g, int c) {
   constexpr int DX = Mdl::DX, DY = Mdl::DY, DZ = Mdl::DZ;
-  if (c < DX) return a.x[a.cur[f]][(long long)c * a.NT + g];
+  if (c < DX) return a.x[copy_of(a.cur[f])][(long long)c * a.NT + g];
   if (c < DX + DY) return a.Y[(long long)a.tcur[f] * a.y_tstride + (long long)f * DY + (c - DX)];
   return a.mom[(long long)g * 2 * DZ + (c - DX - DY)];
-}
-
-// Network on the current state of every stepping filter: one 16-row tile of
-// outer particles per workgroup; rows of filters that sit the step out get
-// zero features (their outputs are not used).
-template <class Mdl>
-__global__ __launch_bounds__(kBlock) void k_mlp_fwd_state(StepArgs a) {
-  constexpr int NF = Mdl::DX + Mdl::DY + 2 * Mdl::DZ;
-  static_assert(NF <= kMlpIn, "features do not fit the input layer");
-  __shared__ MlpShared sh;
-  const int row0 = blockIdx.x * kMlpRows;
-  const int nrows = min(kMlpRows, a.NT - row0);
-  const float* fmean = reinterpret_cast<const float*>(a.mlp + MlpBlobLayout::fmean);
-  const float* fstd = reinterpret_cast<const float*>(a.mlp + MlpBlobLayout::fstd);
-  for (int e = threadIdx.x; e < kMlpRows * kMlpIn; e += kBlock) {
-    const int r = e / kMlpIn, c = e % kMlpIn;
-    float v = 0.f;
-    if (r < nrows && c < NF) {
-      const int g = row0 + r;
-      const int f = filter_of_outer(a.ooff, a.n_filters, g);
-      if (step_active(a, f)) v = (raw_feature<Mdl>(a, f, g, c) - fmean[c]) / fstd[c];
-    }
-    sh.x0[r][c] = f2bf(v);
-  }
-  __syncthreads();
-  mlp_rows<false>(a.mlp, sh, row0, nrows, a.mdn, MlpTrainOut{});
 }
 
 // Draw from the mixture of output row o: component by one inverse-CDF draw
@@ -128,6 +105,75 @@ __device__ float mdn_draw(const float* o, Key key, int t, int i, float* x, int& 
   return mdn_logpdf<DX>(o, x);
 }
 
+// The proposal of outer particle g (filter f, local index i) from its
+// mixture outputs o: x_t -> xtmp, log q -> logq, component -> sel.
+template <int DX>
+__device__ __forceinline__ void mdn_propose(const StepArgs& a, int f, int g, const float* o) {
+  const int i = g - a.ooff[f];
+  const int t = a.tcur[f] + 1;
+  float xn[DX];
+  int comp;
+  const float lq = mdn_draw<DX>(o, make_key(a.seed, (uint32_t)f), t, i, xn, comp);
+#pragma unroll
+  for (int d = 0; d < DX; ++d) a.xtmp[(long long)d * a.NT + g] = xn[d];
+  a.logq[g] = lq;
+  a.sel[g] = comp;
+}
+
+// Network on the current state of every stepping filter: one 16-row tile of
+// outer particles per workgroup; rows of filters that sit the step out get
+// zero features (their outputs are not used).  The epilogue draws each
+// row's proposal from its mixture.
+template <class Mdl>
+__global__ __launch_bounds__(kBlock) void k_mlp_fwd_state(StepArgs a) {
+  constexpr int NF = Mdl::DX + Mdl::DY + 2 * Mdl::DZ;
+  static_assert(NF <= kMlpIn, "features do not fit the input layer");
+  __shared__ MlpShared sh;
+  MlpFrags fr;
+  mlp_load_frags(a.mlp, fr);
+  const int row0 = blockIdx.x * kMlpRows;
+  const int nrows = min(kMlpRows, a.NT - row0);
+  const float* fmean = reinterpret_cast<const float*>(a.mlp + MlpBlobLayout::fmean);
+  const float* fstd = reinterpret_cast<const float*>(a.mlp + MlpBlobLayout::fstd);
+  for (int e = threadIdx.x; e < kMlpRows * kMlpIn; e += kBlock) {
+    const int r = e / kMlpIn, c = e % kMlpIn;
+    float v = 0.f;
+    if (r < nrows && c < NF) {
+      const int g = row0 + r;
+      const int f = filter_of_outer(a.ooff, a.n_filters, g);
+      if (step_active(a, f)) v = (raw_feature<Mdl>(a, f, g, c) - fmean[c]) / fstd[c];
+    }
+    sh.x0[r][c] = f2bf(v);
+  }
+  __syncthreads();
+  mlp_rows<false>(fr, sh, row0, nrows, a.mdn, MlpTrainOut{});
+  __syncthreads();
+  if (threadIdx.x < nrows) {
+    const int g = row0 + threadIdx.x;
+    const int f = filter_of_outer(a.ooff, a.n_filters, g);
+    if (step_active(a, f)) {
+      float o[Mdn<Mdl::DX>::kUsed];
+#pragma unroll
+      for (int c = 0; c < Mdn<Mdl::DX>::kUsed; ++c) o[c] = sh.o[threadIdx.x][c];
+      mdn_propose<Mdl::DX>(a, f, g, o);
+    }
+  }
+}
+
+// Proposals from caller-supplied mixture outputs (a.mdn), one thread per
+// outer particle.
+template <class Mdl>
+__global__ __launch_bounds__(kBlock) void k_mdn_draw(StepArgs a) {
+  const int g = blockIdx.x * kBlock + threadIdx.x;
+  if (g >= a.NT) return;
+  const int f = filter_of_outer(a.ooff, a.n_filters, g);
+  if (!step_active(a, f)) return;
+  float o[Mdn<Mdl::DX>::kUsed];
+#pragma unroll
+  for (int c = 0; c < Mdn<Mdl::DX>::kUsed; ++c) o[c] = a.mdn[(long long)g * kMlpOut + c];
+  mdn_propose<Mdl::DX>(a, f, g, o);
+}
+
 // Proposal draw and inner pass of the learned step for one tile of outer
 // particles (pre-resampling index i; results go to slot i of the next copy).
 template <class Mdl, int SEG, int JPT>
@@ -137,8 +183,6 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
   constexpr bool kKeepZ = JPT * DZ <= 64;
   __shared__ SegScratch sh;
   __shared__ double cdf[NSEG][SEG * JPT];
-  __shared__ float xs_sh[NSEG][DX];
-  __shared__ float lq_sh[NSEG];
   __shared__ float vred[kBlock / kWave][2 * DZ];
 
   const int4 tile = a.tiles[blockIdx.x];
@@ -154,9 +198,10 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
   const int oo = a.ooff[f];
   const long long io = a.ioff[f];
   const int t = a.tcur[f] + 1;
-  const int src = a.cur[f], dst = src ^ 1;
+  const unsigned char cb = a.cur[f];
+  const int src = copy_of(cb), dst = src ^ 1;
   const Key key = make_key(a.seed, (uint32_t)f);
-  const int ci = vi ? a.ind[src][oo + i] : 0;
+  const int ci = vi ? (ident_slots(cb, src) ? i : a.ind[src][oo + i]) : 0;
 
   float xp[DX];
 #pragma unroll
@@ -164,28 +209,13 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
   const float* zp = a.z[src] + (io + (long long)ci * M) * DZ;
   const float* lp = a.lam[src] + io + (long long)ci * M;
 
-  // ---- 1. x_t ~ q(. | features of particle i) ----------------------------
-  if (ls == 0) {
-    float o[Mdn<DX>::kUsed], xn[DX];
-    const float* orow = a.mdn + (long long)(vi ? oo + i : 0) * kMlpOut;
-#pragma unroll
-    for (int c = 0; c < Mdn<DX>::kUsed; ++c) o[c] = orow[c];
-    int comp;
-    const float lq = mdn_draw<DX>(o, key, t, i, xn, comp);
-#pragma unroll
-    for (int d = 0; d < DX; ++d) xs_sh[s][d] = xn[d];
-    lq_sh[s] = lq;
-    if (vi) {
-#pragma unroll
-      for (int d = 0; d < DX; ++d) a.xtmp[(long long)d * a.NT + oo + i] = xn[d];
-      a.sel[oo + i] = comp;
-    }
-  }
-  __syncthreads();
+  // ---- 1. x_t ~ q(. | features of particle i), drawn by the network's
+  //         epilogue (or k_mdn_draw) -------------------------------------
   float xn[DX];
+  const long long gi = oo + (vi ? i : 0);
 #pragma unroll
-  for (int d = 0; d < DX; ++d) xn[d] = xs_sh[s][d];
-  const float lq = lq_sh[s];
+  for (int d = 0; d < DX; ++d) xn[d] = a.xtmp[(long long)d * a.NT + gi];
+  const float lq = a.logq[gi];
 
   // ---- 2. kappa = lam + log p(x_t | x_{t-1}, z) and its log-sum-exp ------
   float zd[DZ];
@@ -232,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
 
   // ---- 3. local resampling, propagation, measurement update --------------
   float pre[DZ];
-  Mdl::fz_pre(a.prm, xp, xn, pre);
+  fz_pre_seg<Mdl, SEG>(a.prm, xp, xn, pre);
   float y[DY], r0[DY];
   load_y<Mdl>(a, f, t, y);
   Mdl::obs_pre(a.prm, y, xn, r0);
@@ -282,17 +312,23 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
       }
     }
   }
-  seg_sum_vec<SEG, 2 * DZ>(part, vred);
+  static_assert(2 * DZ <= 16, "moment vector too long for the transpose reduction");
+  int slot;
+  const float tot = seg_sum_vec_t<SEG, 2 * DZ>(part, vred, slot);
+  const float mean = seg_vec_fetch<SEG, 2 * DZ>(tot, slot >= DZ ? slot - DZ : -1);
+  if (vi && slot >= 0) {
+    float* mp = a.mom_tmp + (long long)(oo + i) * 2 * DZ;
+    if (slot < DZ) {
+      a.kpart_tmp[(long long)(oo + i) * DZ + slot] = tot;
+      mp[slot] = tot;
+    } else {
+      mp[slot] = fmaxf(tot - mean * mean, 0.f);
+    }
+  }
   if (vi && ls == 0) {
     // Fig. 2 step 1 weight: eq:approx2 (unit inner weights) x eq:approx1 / q
     const float log_py = deg3 ? -INFINITY : lse - fast_log((float)M);
     a.logw[oo + i] = (log_py + log_px) - lq;
-#pragma unroll
-    for (int d = 0; d < DZ; ++d) {
-      a.kpart_tmp[(long long)(oo + i) * DZ + d] = part[d];
-      a.mom_tmp[(long long)(oo + i) * 2 * DZ + d] = part[d];
-      a.mom_tmp[(long long)(oo + i) * 2 * DZ + DZ + d] = fmaxf(part[DZ + d] - part[d] * part[d], 0.f);
-    }
     if (deg2 || deg3) atomicOr(&a.lflags[f], (uint32_t)F_DEGENERATE_INNER);
   }
 }
@@ -315,8 +351,9 @@ __global__ __launch_bounds__(kBlock) void k_moments(StepArgs a, const float* y, 
   const bool vi = i < N;
   const int oo = a.ooff[f];
   const long long io = a.ioff[f];
-  const int c = a.cur[f];
-  const int ci = vi ? a.ind[c][oo + i] : 0;
+  const unsigned char cb = a.cur[f];
+  const int c = copy_of(cb);
+  const int ci = vi ? (ident_slots(cb, c) ? i : a.ind[c][oo + i]) : 0;
   const float* zp = a.z[c] + (io + (long long)ci * M) * DZ;
   const float* lp = a.lam[c] + io + (long long)ci * M;
   float part[DZ];

@@ -77,6 +77,7 @@ struct Engine {
   void (*derive)(const double* raw, std::vector<float>& out);
   dpf_status (*launch)(int op, const StepArgs& a, const TileClass& tc, hipStream_t s);
   dpf_status (*mlp_state)(const StepArgs& a, hipStream_t s);  // null: no learned proposal
+  dpf_status (*mdn_draw)(const StepArgs& a, hipStream_t s);
   bool moments;
 };
 
@@ -88,7 +89,9 @@ enum Op {
   OP_NEWCLOUD_LA,
   OP_NEWCLOUD_PLAIN,
   OP_LEARNED_INNER,
-  OP_MOMENTS
+  OP_MOMENTS,
+  OP_LA_WEIGHTS_FALLBACK,
+  OP_NEWCLOUD_FALLBACK
 };
 
 // Models served by the learned proposal (the network's mixture is over a
@@ -128,6 +131,14 @@ static void launch_op(int op, const StepArgs& a, int n, hipStream_t s) {
       if constexpr (learned_model<Mdl>())
         hipLaunchKernelGGL((k_learned_inner<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
       break;
+    case OP_LA_WEIGHTS_FALLBACK:
+      if constexpr (learned_model<Mdl>())
+        hipLaunchKernelGGL((k_la_weights_fallback<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
+      break;
+    case OP_NEWCLOUD_FALLBACK:
+      if constexpr (learned_model<Mdl>())
+        hipLaunchKernelGGL((k_newcloud_fallback<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
+      break;
     case OP_MOMENTS:
       if constexpr (has_moments<Mdl>())
         hipLaunchKernelGGL((k_moments<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a, g_mom_args.y,
@@ -141,6 +152,17 @@ static dpf_status engine_mlp_state(const StepArgs& a, hipStream_t s) {
   if constexpr (learned_model<Mdl>()) {
     hipLaunchKernelGGL(k_mlp_fwd_state<Mdl>, dim3((a.NT + kMlpRows - 1) / kMlpRows), dim3(kBlock), 0, s, a);
     LAUNCH_CHECK("k_mlp_fwd_state");
+    return DPF_OK;
+  } else {
+    return fail(DPF_EUNSUPPORTED, "no learned proposal for this model");
+  }
+}
+
+template <class Mdl>
+static dpf_status engine_mdn_draw(const StepArgs& a, hipStream_t s) {
+  if constexpr (learned_model<Mdl>()) {
+    hipLaunchKernelGGL(k_mdn_draw<Mdl>, dim3((a.NT + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
+    LAUNCH_CHECK("k_mdn_draw");
     return DPF_OK;
   } else {
     return fail(DPF_EUNSUPPORTED, "no learned proposal for this model");
@@ -214,13 +236,13 @@ using MHD = HighDim<4, 64, 32>;
 static const Engine kEngines[] = {
     {1, 2, 1, (size_t)MLG::L::n_raw, (size_t)MLG::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_lingauss(1, 2, 1, p, o); },
-     engine_launch<MLG>, nullptr, has_moments<MLG>()},
+     engine_launch<MLG>, nullptr, nullptr, has_moments<MLG>()},
     {2, 8, 8, (size_t)MNL::L::n_raw, (size_t)MNL::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_nonlin(2, 8, p, o); }, engine_launch<MNL>,
-     engine_mlp_state<MNL>, has_moments<MNL>()},
+     engine_mlp_state<MNL>, engine_mdn_draw<MNL>, has_moments<MNL>()},
     {4, 64, 32, (size_t)MHD::L::n_raw, (size_t)MHD::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_highdim(4, 64, 32, p, o); },
-     engine_launch<MHD>, nullptr, has_moments<MHD>()},
+     engine_launch<MHD>, nullptr, nullptr, has_moments<MHD>()},
 };
 
 static const Engine* find_engine(int model, int dx, int dz, int dy) {
@@ -240,7 +262,7 @@ struct Layout {
   size_t prm, fN, fM, ooff, ooff64, ioff, finfo, tcur, cur, act, tiles, rgroups, x0, x1, z0, z1, l0, l1, ell,
       logw, anc, sel, kpart, gstat, fstat, ess, dlogz, loglik, flags, est_x, est_z;
   // slot indirection and learned-proposal buffers
-  size_t ind0, ind1, mom, mlp, mdn, xtmp, kpart_tmp, mom_tmp, fb, lflags;
+  size_t ind0, ind1, mom, mlp, mdn, xtmp, logq, kpart_tmp, mom_tmp, fb, lflags;
   std::vector<size_t> tile_off;  // per class (in tile units from `tiles`)
   std::vector<int> tile_n;
   int NT = 0;
@@ -332,6 +354,7 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   L.mlp = carve(cur, MlpBlobLayout::bytes);
   L.mdn = carve(cur, NT * kMlpOut * 4);
   L.xtmp = carve(cur, NT * dx * 4);
+  L.logq = carve(cur, NT * 4);
   L.kpart_tmp = carve(cur, NT * dz * 4);
   L.mom_tmp = carve(cur, NT * 2 * dz * 4);
   L.fb = carve(cur, F);
@@ -424,12 +447,15 @@ static StepArgs make_args(dpf_handle* h) {
   a.est_z = at<float>(h, h->L.est_z);
   a.n_filters = h->F;
   a.dy = h->dy;
+  a.dx = h->dx;
+  a.dz = h->dz;
   a.ind[0] = at<int>(h, h->L.ind0);
   a.ind[1] = at<int>(h, h->L.ind1);
   a.mom = (h->has_proposal && h->eng->moments) ? at<float>(h, h->L.mom) : nullptr;
   a.mlp = at<unsigned char>(h, h->L.mlp);
   a.mdn = at<float>(h, h->L.mdn);
   a.xtmp = at<float>(h, h->L.xtmp);
+  a.logq = at<float>(h, h->L.logq);
   a.kpart_tmp = at<float>(h, h->L.kpart_tmp);
   a.mom_tmp = at<float>(h, h->L.mom_tmp);
   a.fb = nullptr;
@@ -438,14 +464,23 @@ static StepArgs make_args(dpf_handle* h) {
   return a;
 }
 
-static dpf_status launch_classes(dpf_handle* h, int op, StepArgs a) {
+// grid_cap > 0: at most grid_cap workgroups per class, looping over the
+// tiles (for launches that most tiles skip).
+static dpf_status launch_classes(dpf_handle* h, int op, StepArgs a, int grid_cap = 0) {
   for (const TileClass& tc : h->classes) {
     a.tiles = tc.d_tiles;
-    dpf_status s = h->eng->launch(op, a, tc, h->stream);
+    a.n_tiles = tc.n_tiles;
+    TileClass g = tc;
+    if (grid_cap > 0 && g.n_tiles > grid_cap) g.n_tiles = grid_cap;
+    g.n_tiles += a.n_commit;  // extra head workgroups (first class only)
+    dpf_status s = h->eng->launch(op, a, g, h->stream);
+    a.n_commit = 0;
     if (s != DPF_OK) return s;
   }
   return DPF_OK;
 }
+
+constexpr int kGatedGrid = 512;
 
 static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a) {
   const int F = h->F;
@@ -654,7 +689,7 @@ static dpf_status queue_learned_step(dpf_handle* h, const float* Y, const unsign
   a.mom = at<float>(h, h->L.mom);
   if (mdn_given) a.mdn = const_cast<float*>(mdn_given);
   s = phase_mark(h, 0);
-  if (s == DPF_OK && !mdn_given) s = h->eng->mlp_state(a, h->stream);
+  if (s == DPF_OK) s = mdn_given ? h->eng->mdn_draw(a, h->stream) : h->eng->mlp_state(a, h->stream);
   if (s == DPF_OK) s = launch_classes(h, OP_LEARNED_INNER, a);
   if (s == DPF_OK) s = phase_mark(h, 1);
   if (s == DPF_OK) {
@@ -663,14 +698,18 @@ static dpf_status queue_learned_step(dpf_handle* h, const float* Y, const unsign
     LAUNCH_CHECK("k_res_stats");
   }
   a.fb = at<unsigned char>(h, h->L.fb);
-  if (s == DPF_OK) s = launch_classes(h, OP_LA_WEIGHTS, a);  // fallback filters only
+  if (s == DPF_OK) s = launch_classes(h, OP_LA_WEIGHTS_FALLBACK, a, kGatedGrid);
   if (s == DPF_OK) {
     hipLaunchKernelGGL(k_res_stats, dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a,
                        at<int2>(h, h->L.rgroups), 1);
     LAUNCH_CHECK("k_res_stats");
   }
   if (s == DPF_OK) s = phase_mark(h, 2);
-  if (s == DPF_OK) s = launch_classes(h, OP_NEWCLOUD_LA, a);
+  // one launch per class: the commit of accepted filters (first class) and the
+  // look-ahead new clouds of the filters that fell back
+  a.rgroups = at<int2>(h, h->L.rgroups);
+  a.n_commit = h->L.n_rgroups;
+  if (s == DPF_OK) s = launch_classes(h, OP_NEWCLOUD_FALLBACK, a, kGatedGrid);
   if (s == DPF_OK) s = phase_mark(h, 3);
   if (s == DPF_OK) s = launch_finalize(h, a);
   if (s == DPF_OK) s = phase_mark(h, 4);
@@ -848,14 +887,11 @@ static dpf_status state_io(dpf_handle* h, char* ext, int dir) {
     const int* oo = at<int>(h, h->L.ooff);
     const int* fm = at<int>(h, h->L.fM);
     hipLaunchKernelGGL(k_state_copy_cloud, dim3((unsigned)((nz + B - 1) / B)), dim3(B), 0, h->stream, ez,
-                       at<float>(h, h->L.z0), at<float>(h, h->L.z1), i0, i1, cur, ioff, oo, fm, F, h->L.NMT,
-                       h->dz, dir);
+                       at<float>(h, h->L.z0), at<float>(h, h->L.z1), i0, i1, cur, ioff, oo, fm, F,
+                       h->L.NMT, h->dz, dir);
     hipLaunchKernelGGL(k_state_copy_cloud, dim3((unsigned)((nl + B - 1) / B)), dim3(B), 0, h->stream, el,
-                       at<float>(h, h->L.l0), at<float>(h, h->L.l1), i0, i1, cur, ioff, oo, fm, F, h->L.NMT, 1,
-                       dir);
-    if (dir == 1)
-      hipLaunchKernelGGL(k_ind_identity, dim3((h->L.NT + 255) / 256), dim3(256), 0, h->stream,
-                         at<int>(h, h->L.ind0), oo64, F, h->L.NT);
+                       at<float>(h, h->L.l0), at<float>(h, h->L.l1), i0, i1, cur, ioff, oo, fm, F,
+                       h->L.NMT, 1, dir);
   } else {
     hipLaunchKernelGGL(k_state_copy, dim3((unsigned)((nz + B - 1) / B)), dim3(B), 0, h->stream, ez,
                        at<float>(h, h->L.z0), at<float>(h, h->L.z1), cur, ioff, F, h->L.NMT, h->dz, dir);
@@ -894,6 +930,7 @@ extern "C" dpf_status dpf_copy_buffer(dpf_handle* h, int32_t which, void* d_dst,
     case DPF_BUF_ANC: off = h->L.anc; need = (size_t)h->L.NT * 4; break;
     case DPF_BUF_SEL: off = h->L.sel; need = (size_t)h->L.NT * 4; break;
     case DPF_BUF_MDN: off = h->L.mdn; need = (size_t)h->L.NT * kMlpOut * 4; break;
+    case DPF_BUF_FALLBACK: off = h->L.fb; need = (size_t)h->F; break;
     case DPF_BUF_X: {
       need = (size_t)h->L.NT * h->dx * 4;
       if (bytes < need) return fail(DPF_EINVAL, "buffer %d needs %zu bytes", which, need);

@@ -102,6 +102,7 @@ struct alignas(16) MlpShared {
   bf16_t h1[kMlpRows][kHidStride];
   bf16_t h2[kMlpRows][kHidStride];
   float part[2][kMlpRows][16];
+  float o[kMlpRows][kMlpOut + 1];  // outputs of the tile (for an epilogue per row)
 };
 
 // Optional outputs of the training forward pass (batch B, row-major a1 / a2,
@@ -115,10 +116,46 @@ struct MlpTrainOut {
   int B;
 };
 
-// Hidden layer: rows of `in` (LDS, K = KIN) times W^T ([256][KIN] bf16) plus
-// bias, GELU, rounded into `out` (LDS).  Wave w writes columns 64w..64w+63.
+// Weight fragments and biases of one wave, loaded before the layer inputs
+// are ready so that the three layers find their operands in registers.
+// Wave w owns hidden columns 64w..64w+63 (4 column tiles) and, in the output
+// layer, column tile w & 1 over k-steps 4 (w >> 1) .. 4 (w >> 1) + 3.
+struct MlpFrags {
+  bf16x8 w1[1][4];
+  bf16x8 w2[8][4];
+  bf16x8 w3[4];
+  float b1[4], b2[4], b3;
+};
+
+__device__ __forceinline__ void mlp_load_frags(const unsigned char* blob, MlpFrags& fr) {
+  using BL = MlpBlobLayout;
+  const bf16_t* W1 = reinterpret_cast<const bf16_t*>(blob + BL::W1);
+  const bf16_t* W2 = reinterpret_cast<const bf16_t*>(blob + BL::W2);
+  const bf16_t* W3 = reinterpret_cast<const bf16_t*>(blob + BL::W3);
+  const float* b1 = reinterpret_cast<const float*>(blob + BL::b1);
+  const float* b2 = reinterpret_cast<const float*>(blob + BL::b2);
+  const float* b3 = reinterpret_cast<const float*>(blob + BL::b3);
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = l & 15, lk = 8 * (l >> 4);
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int n = 64 * w + 16 * nt + lr;
+    fr.w1[0][nt] = ld8(W1 + (size_t)n * kMlpIn + lk);
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) fr.w2[ks][nt] = ld8(W2 + (size_t)n * kMlpHid + 32 * ks + lk);
+    fr.b1[nt] = b1[n];
+    fr.b2[nt] = b2[n];
+  }
+  const int n3 = 16 * (w & 1) + lr, k3 = 4 * (w >> 1);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) fr.w3[q] = ld8(W3 + (size_t)n3 * kMlpHid + 32 * (k3 + q) + lk);
+  fr.b3 = b3[n3];
+}
+
+// Hidden layer: rows of `in` (LDS, K = KIN) times the wave's weight
+// fragments plus bias, GELU, rounded into `out` (LDS).
 template <int KIN, int SIN, bool TRAIN>
-__device__ __forceinline__ void mlp_hidden(const bf16_t (*in)[SIN], const bf16_t* W, const float* bias,
+__device__ __forceinline__ void mlp_hidden(const bf16_t (*in)[SIN], const bf16x8 (*wf)[4], const float* bias,
                                            bf16_t (*out)[kHidStride], int row0, float* a_out,
                                            bf16_t* h_t, int B) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -130,15 +167,12 @@ __device__ __forceinline__ void mlp_hidden(const bf16_t (*in)[SIN], const bf16_t
   for (int ks = 0; ks < KIN / 32; ++ks) {
     const bf16x8 a = ld8(&in[lr][32 * ks + lk]);
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const int n = 64 * w + 16 * nt + lr;
-      acc[nt] = mfma16(a, ld8(W + (size_t)n * KIN + 32 * ks + lk), acc[nt]);
-    }
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma16(a, wf[ks][nt], acc[nt]);
   }
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
     const int n = 64 * w + 16 * nt + lr;
-    const float bn = bias[n];
+    const float bn = bias[nt];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 4 * (l >> 4) + r;
@@ -158,18 +192,11 @@ __device__ __forceinline__ void mlp_hidden(const bf16_t (*in)[SIN], const bf16_t
 
 // The three layers for the 16 rows in sh.x0; outputs [rows][32] FP32.
 template <bool TRAIN>
-__device__ void mlp_rows(const unsigned char* blob, MlpShared& sh, int row0, int nrows, float* out,
+__device__ void mlp_rows(const MlpFrags& fr, MlpShared& sh, int row0, int nrows, float* out,
                          const MlpTrainOut& tr) {
-  using BL = MlpBlobLayout;
-  const bf16_t* W1 = reinterpret_cast<const bf16_t*>(blob + BL::W1);
-  const bf16_t* W2 = reinterpret_cast<const bf16_t*>(blob + BL::W2);
-  const bf16_t* W3 = reinterpret_cast<const bf16_t*>(blob + BL::W3);
-  const float* b1 = reinterpret_cast<const float*>(blob + BL::b1);
-  const float* b2 = reinterpret_cast<const float*>(blob + BL::b2);
-  const float* b3 = reinterpret_cast<const float*>(blob + BL::b3);
-  mlp_hidden<kMlpIn, kInStride, TRAIN>(sh.x0, W1, b1, sh.h1, row0, tr.a1, tr.h1t, tr.B);
+  mlp_hidden<kMlpIn, kInStride, TRAIN>(sh.x0, fr.w1, fr.b1, sh.h1, row0, tr.a1, tr.h1t, tr.B);
   __syncthreads();
-  mlp_hidden<kMlpHid, kHidStride, TRAIN>(sh.h1, W2, b2, sh.h2, row0, tr.a2, tr.h2t, tr.B);
+  mlp_hidden<kMlpHid, kHidStride, TRAIN>(sh.h1, fr.w2, fr.b2, sh.h2, row0, tr.a2, tr.h2t, tr.B);
   __syncthreads();
   // output layer: 2 column tiles x 8 k-steps, split over the 4 waves
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -177,10 +204,7 @@ __device__ void mlp_rows(const unsigned char* blob, MlpShared& sh, int row0, int
   const int nt = w & 1, kh = w >> 1;
   f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int ks = 4 * kh; ks < 4 * kh + 4; ++ks) {
-    const int n = 16 * nt + lr;
-    acc = mfma16(ld8(&sh.h2[lr][32 * ks + lk]), ld8(W3 + (size_t)n * kMlpHid + 32 * ks + lk), acc);
-  }
+  for (int q = 0; q < 4; ++q) acc = mfma16(ld8(&sh.h2[lr][32 * (4 * kh + q) + lk]), fr.w3[q], acc);
   if (kh == 1) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) sh.part[nt][4 * (l >> 4) + r][lr] = acc[r];
@@ -191,7 +215,9 @@ __device__ void mlp_rows(const unsigned char* blob, MlpShared& sh, int row0, int
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 4 * (l >> 4) + r;
-      if (row < nrows) out[(size_t)(row0 + row) * kMlpOut + n] = (acc[r] + sh.part[nt][row][lr]) + b3[n];
+      const float v = (acc[r] + sh.part[nt][row][lr]) + fr.b3;
+      sh.o[row][n] = v;
+      if (row < nrows) out[(size_t)(row0 + row) * kMlpOut + n] = v;
     }
   }
 }
@@ -202,6 +228,8 @@ template <bool TRAIN>
 __global__ __launch_bounds__(kBlock) void k_mlp_fwd_x(const unsigned char* blob, const float* X, int B,
                                                       float* out, MlpTrainOut tr) {
   __shared__ MlpShared sh;
+  MlpFrags fr;
+  mlp_load_frags(blob, fr);
   const int row0 = blockIdx.x * kMlpRows;
   const int nrows = min(kMlpRows, B - row0);
   for (int e = threadIdx.x; e < kMlpRows * kMlpIn; e += kBlock) {
@@ -211,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_fwd_x(const unsigned char* blob,
     if (TRAIN && r < nrows) tr.x0t[(size_t)c * B + row0 + r] = v;
   }
   __syncthreads();
-  mlp_rows<TRAIN>(blob, sh, row0, nrows, out, tr);
+  mlp_rows<TRAIN>(fr, sh, row0, nrows, out, tr);
 }
 
 // ---------------------------------------------------------------- MDN

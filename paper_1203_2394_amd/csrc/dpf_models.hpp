@@ -70,12 +70,13 @@ struct LinGauss {
   }
   __device__ static void fz_pre(const float* P, const float* x, const float* xn, float* pre) {
 #pragma unroll
-    for (int a = 0; a < DZ; ++a) {
-      float s = 0.f;
+    for (int a = 0; a < DZ; ++a) pre[a] = fz_pre_k(P, x, xn, a);
+  }
+  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int a) {
+    float s = 0.f;
 #pragma unroll
-      for (int b = 0; b < DX; ++b) s += P[L::Bzx + a * DX + b] * xn[b];
-      pre[a] = s;
-    }
+    for (int b = 0; b < DX; ++b) s += P[L::Bzx + a * DX + b] * xn[b];
+    return s;
   }
   __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu,
                                  float* zn) {
@@ -149,14 +150,15 @@ struct NonLin {
 #pragma unroll
     for (int d = 0; d < DX; ++d) xn[d] = growth(a, b, x[d]) + s * nu[d];
   }
-  __device__ static void fz_pre(const float* P, const float*, const float* xn, float* pre) {
+  __device__ static void fz_pre(const float* P, const float* x, const float* xn, float* pre) {
 #pragma unroll
-    for (int k = 0; k < DZ; ++k) {
-      float s = 0.f;
+    for (int k = 0; k < DZ; ++k) pre[k] = fz_pre_k(P, x, xn, k);
+  }
+  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int k) {
+    float s = 0.f;
 #pragma unroll
-      for (int d = 0; d < DX; ++d) s += P[L::W + k * DX + d] * xn[d];
-      pre[k] = tanh_f(s);
-    }
+    for (int d = 0; d < DX; ++d) s += P[L::W + k * DX + d] * xn[d];
+    return tanh_f(s);
   }
   __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu,
                                  float* zn) {
@@ -236,6 +238,12 @@ struct HighDim {
       for (int d = 0; d < DX; ++d) s += P[L::B + k * DX + d] * sn[d];
       pre[k] = s;
     }
+  }
+  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int k) {
+    float s = 0.f;
+#pragma unroll
+    for (int d = 0; d < DX; ++d) s += P[L::B + k * DX + d] * __builtin_amdgcn_sinf(xn[d] * kInv2Pi);
+    return s;
   }
   __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu,
                                  float* zn) {

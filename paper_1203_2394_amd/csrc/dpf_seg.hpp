@@ -90,6 +90,91 @@ __device__ __forceinline__ void seg_sum_vec(float* v, float (*red)[NV]) {
   }
 }
 
+// Transpose reduction of NV values (NV a power of two, at most 16) over the
+// segment.  Each in-row step pairs lane i with a partner of the same history
+// -- row mirror (15 - i), half-row mirror, quad reversal, quad swap, which
+// split on lane bits 3, 2, 1, 0 -- and exchanges half of the values still
+// held, so a lane adds NV/2 + NV/4 + ... values instead of NV per step; after
+// the four steps lane i holds its row's total of slot (i & 15) >> (4 - P)
+// (NV = 2^P).  Rows, then waves (through red), are combined in a fixed order.
+// Returns the segment total of value `slot` in the lanes that own one
+// (slot = -1 elsewhere): lanes 0, 2^(4-P), ... of the segment's first row
+// (SEG <= 64), lanes 0..NV-1 of the segment (SEG > 64).
+template <int NV>
+constexpr int log2_nv() { return NV == 1 ? 0 : NV == 2 ? 1 : NV == 4 ? 2 : NV == 8 ? 3 : 4; }
+
+template <int CTRL, int BIT, int H>
+__device__ __forceinline__ void tr_step(float* v, int lane) {
+  if constexpr (H == 0) {
+    v[0] += dpp_f<CTRL>(v[0], v[0]);
+  } else {
+    const bool up = (lane >> BIT) & 1;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      const float lo = v[q], hi = v[q + H];
+      const float send = up ? lo : hi;
+      const float keep = up ? hi : lo;
+      v[q] = keep + dpp_f<CTRL>(send, send);
+    }
+  }
+}
+
+template <int SEG, int NV>
+__device__ __forceinline__ float seg_sum_vec_t(const float* vin, float (*red)[NV], int& slot) {
+  static_assert(NV == 1 || NV == 2 || NV == 4 || NV == 8 || NV == 16, "NV must be a power of two <= 16");
+  constexpr int P = log2_nv<NV>();
+  constexpr int SH = 4 - P;  // owner lanes are multiples of 2^SH within the row
+  float v[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = vin[q];
+  const int lane = threadIdx.x & (kWave - 1);
+  tr_step<kDppRowMirror, 3, (P >= 1 ? NV / 2 : 0)>(v, lane);
+  tr_step<kDppRowHalfMirror, 2, (P >= 2 ? NV / 4 : 0)>(v, lane);
+  tr_step<0x1B, 1, (P >= 3 ? NV / 8 : 0)>(v, lane);  // quad_perm [3,2,1,0]
+  tr_step<kDppQuadXor1, 0, (P >= 4 ? NV / 16 : 0)>(v, lane);
+  float r = v[0];
+  constexpr int W = SEG < kWave ? SEG : kWave;
+  if constexpr (W >= 32) r += __shfl_xor(r, 16);
+  if constexpr (W >= 64) r += __shfl_xor(r, 32);
+  const int ls = threadIdx.x % SEG;
+  if constexpr (SEG <= kWave) {
+    slot = (ls < 16 && (ls & ((1 << SH) - 1)) == 0) ? (ls >> SH) : -1;
+    return r;
+  } else {
+    const int w = threadIdx.x / kWave;
+    if (lane < 16 && (lane & ((1 << SH) - 1)) == 0) red[w][lane >> SH] = r;
+    __syncthreads();
+    float t = 0.f;
+    slot = -1;
+    if (ls < NV) {
+      const int w0 = (threadIdx.x / SEG) * (SEG / kWave);
+#pragma unroll
+      for (int q = 0; q < SEG / kWave; ++q) t += red[w0 + q][ls];
+      slot = ls;
+    }
+    __syncthreads();
+    return t;
+  }
+}
+
+// For lanes that own a slot of seg_sum_vec_t<SEG, NV>: the total of slot
+// `want` (0 <= want < NV; other lanes pass want < 0 and get their own value).
+template <int SEG, int NV>
+__device__ __forceinline__ float seg_vec_fetch(float tot, int want) {
+  constexpr int SH = 4 - log2_nv<NV>();
+  const int lane = threadIdx.x & (kWave - 1);
+  int src = lane;
+  if (want >= 0) {
+    if constexpr (SEG <= kWave) {
+      const int base = lane - (threadIdx.x % SEG);  // first lane of the segment in this wave
+      src = base + (want << SH);
+    } else {
+      src = (lane & ~15) + want;  // owners are lanes 0..NV-1 of the segment's first wave
+    }
+  }
+  return __shfl(tot, src);
+}
+
 // Inclusive FP64 scan within the segment; `total` receives the segment sum.
 template <int SEG>
 __device__ __forceinline__ double seg_scan_incl(double v, SegScratch& sh, double& total) {
