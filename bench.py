@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
-"""Throughput benchmark of the look-ahead DPF step on one MI355X.
+"""Throughput benchmark of the look-ahead DPF step on one MI355X, with the
+learned-proposal step beside it.
 
 Workload: the nonlinear model (dx=2, dz=8, dy=8; growth-model outer block,
 tanh-coupled inner block, z + 0.05 x^2 observed), N=4096 outer particles x
 M=256 inner particles per outer particle, synthetic seeded observations.
-A step is one call of dpf_lookahead_step (Fig. 4: look-ahead weights, outer
+A step is one look-ahead DPF step (Fig. 4: look-ahead weights, outer
 resampling, new particles, inner resampling, propagation, inner measurement
-update, estimates) with the observations already resident in HBM.
+update, estimates) with the observations already resident in HBM; the K
+timed steps run as replays of a captured 16-step HIP graph (dpf_run).
 
 Prints one JSON line: inner-particle updates/s over the K timed steps, the
-roofline of the dominant kernel (algorithmic bytes per launch over its
-average duration, timed with HIP events recorded by the library on its own
-stream), and the FP64 oracle timed on a bounded sample on the host.
+RMSE of the x estimate against the simulated truth, the roofline of the
+dominant kernel (algorithmic bytes per launch over its average duration,
+timed with HIP events recorded by the library on its own stream), the FP64
+oracle timed on a bounded sample on the host, and the learned proposal
+(trained on look-ahead pairs, then run at the same N and M): its updates/s
+and RMSE beside the look-ahead step's on the same fresh sequences.
 """
 import argparse
 import hashlib
@@ -31,6 +36,8 @@ HBM_PEAK_GBS = 8000.0
 N_OUT, M_IN, T_TRAJ = 4096, 256, 200
 DX, DZ, DY = 2, 8, 8
 PARAM_SEED, DATA_SEED, FILTER_SEED = 1, 2024, 7
+LEARNED_PAIRS, LEARNED_EPOCHS = 1_000_000, 10
+EVAL_SEQS, EVAL_SEED, ESS_FRAC = 8, 5000, 0.1
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nonlin_N4096_M256.txt")
 KERNEL_SOURCES = ["dpf_kernels.hpp", "dpf_models.hpp", "dpf_rng.hpp", "dpf_seg.hpp"]
 
@@ -110,6 +117,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--cpu-baseline-child", type=int, default=0)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, run one device-to-device copy of this many MB "
@@ -142,42 +150,50 @@ def main():
     L = dpf.lib()
     h = f._h
     yptr = [ctypes.c_void_p(Y[t].data_ptr()) for t in range(n_obs)]
+    updates = N_OUT * M_IN
 
     # accuracy pass (not timed): one trajectory, RMSE of the x estimate vs truth
     xt, _ = f.run(Y[:T_TRAJ].reshape(T_TRAJ, 1, DY), use_graph=True)
     torch.cuda.synchronize()
-    rmse_x = float(np.sqrt(np.mean((xt[:, 0].cpu().numpy() - xs[1:T_TRAJ + 1]) ** 2)))
+    rmse_x = float(np.sqrt(np.mean(np.sum((xt[:, 0].cpu().numpy() - xs[1:T_TRAJ + 1]) ** 2, axis=1))))
 
+    # warm-up, then the K timed steps: replays of a captured chunk of steps
     f.reset()
     for t in range(W):
         assert L.dpf_lookahead_step(h, yptr[t], None) == 0
     f.reset()
-    events = [torch.cuda.Event(enable_timing=True) for _ in range(5 * K)]
-    f.set_phase_events(events)
+    Yk = Y[:K].reshape(K, 1, DY).contiguous()
+    f.run(Yk, trace=False, use_graph=True)  # capture
+    f.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    f.run(Yk, trace=False, use_graph=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    # the same K steps as individual calls (no graph)
+    f.reset()
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
     for t in range(K):
         if L.dpf_lookahead_step(h, yptr[t], None) != 0:
             raise RuntimeError(L.dpf_last_error().decode())
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    edt = time.perf_counter() - e0
+
+    # phase times: events recorded by the library between its launches
+    f.reset()
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(5 * K)]
+    f.set_phase_events(events)
+    for t in range(K):
+        assert L.dpf_lookahead_step(h, yptr[t], None) == 0
+    torch.cuda.synchronize()
     f.set_phase_events(None)
     phases = ["weights", "resample", "newcloud", "estimate"]
     ph_ms = {p: 0.0 for p in phases}
     for s in range(K):
         for i, p in enumerate(phases):
             ph_ms[p] += events[5 * s + i].elapsed_time(events[5 * s + i + 1]) / K
-
-    # graph-replayed variant of the same K steps (one capture, K replays)
-    f.reset()
-    Yk = Y[:K].reshape(K, 1, DY).contiguous()
-    f.run(Yk, trace=False, use_graph=True)  # capture + warm
-    f.reset()
-    torch.cuda.synchronize()
-    g0 = time.perf_counter()
-    f.run(Yk, trace=False, use_graph=True)
-    torch.cuda.synchronize()
-    gdt = time.perf_counter() - g0
 
     if args.copy_mb:
         n = args.copy_mb * (1 << 20) // 4
@@ -187,7 +203,6 @@ def main():
         dst_t.copy_(src_t)
         torch.cuda.synchronize()
 
-    updates = N_OUT * M_IN
     dom = max(("weights", "newcloud"), key=lambda p: ph_ms[p])
     bytes_launch = updates * BYTES_PER_UPDATE[dom] + N_OUT * BYTES_PER_OUTER[dom]
     achieved = bytes_launch / (ph_ms[dom] * 1e-3) / 1e9
@@ -196,6 +211,9 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_newcloud" if dom == "newcloud" else "k_la_weights",
                 "bytes_per_launch": bytes_launch, "avg_ms": round(ph_ms[dom], 5)}
+    f.close()
+
+    learned = None if args.no_learned else run_learned(S, dpf, torch, np, dev, K, W)
     cpu = None if args.no_cpu_baseline else run_cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
@@ -212,14 +230,74 @@ def main():
         "data": "synthetic",
         "config": {"workload": "look-ahead DPF step, nonlinear model dx=2 dz=8 dy=8, N=4096 outer x M=256 inner",
                    "algo": "lookahead", "N": N_OUT, "M": M_IN, "dx": DX, "dz": DZ, "dy": DY,
+                   "execution": "HIP graph replays of a captured 16-step chunk",
                    "rmse_x_T200": round(rmse_x, 4)},
+        "eager_value": updates * K / edt,
         "phase_ms": {p: round(v, 5) for p, v in ph_ms.items()},
-        "graph_value": updates * K / gdt,
         "roofline": roofline,
+        "learned": learned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
     return 0
+
+
+def run_learned(S, dpf, torch, np, dev, K, W):
+    """The learned proposal on the same workload: train on pairs from the
+    look-ahead DPF (fresh sequences), compare RMSE with the look-ahead step on
+    fresh evaluation sequences at the same N and M, time K learned steps."""
+    from paper_1203_2394_amd import proposal as PR
+
+    spec = S.nonlin_c2(PARAM_SEED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X, xt = PR.generate_pairs(spec, LEARNED_PAIRS, simulate=S.simulate, device=dev)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    mlp, losses = PR.train(X, xt, epochs=LEARNED_EPOCHS, batch=4096, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    ev = PR.evaluate(spec, mlp, N=N_OUT, M=M_IN, T=T_TRAJ, n_seq=EVAL_SEQS, data_seed=EVAL_SEED,
+                     ess_frac=ESS_FRAC, simulate=S.simulate, device=dev, timing_reps=1)
+
+    # K timed learned steps, graph-replayed like the look-ahead steps
+    xs, _, ys = S.simulate(spec, max(K, W), DATA_SEED)
+    Yk = torch.tensor(ys[:K], dtype=torch.float32, device=dev).reshape(K, 1, DY).contiguous()
+    f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N_OUT], [M_IN], seed=FILTER_SEED,
+                   device=dev)
+    f.set_proposal(mlp, ess_frac=ESS_FRAC)
+    f.run(Yk, trace=False, use_graph=True, learned=True)  # capture
+    f.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.run(Yk, trace=False, use_graph=True, learned=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    f.reset()
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    for t in range(K):
+        f.learned_step(Yk[t])
+    torch.cuda.synchronize()
+    edt = time.perf_counter() - e0
+    f.close()
+    updates = N_OUT * M_IN
+    return {
+        "value": updates * K / dt,
+        "ms_per_step": dt * 1e3 / K,
+        "eager_value": updates * K / edt,
+        "rmse_x": round(ev["learned"]["rmse_x"], 4),
+        "rmse_x_lookahead": round(ev["lookahead"]["rmse_x"], 4),
+        "rmse_ratio": round(ev["learned"]["rmse_x"] / ev["lookahead"]["rmse_x"], 4),
+        "fallback_frac": round(ev["learned"]["fallback_frac"], 4),
+        "eval": "%d fresh sequences x T=%d, N=%d, M=%d, fallback when ESS < %.2g N" % (
+            EVAL_SEQS, T_TRAJ, N_OUT, M_IN, ESS_FRAC),
+        "train": {"pairs": LEARNED_PAIRS, "epochs": LEARNED_EPOCHS, "batch": 4096, "lr": 1e-3,
+                  "nll_first_epoch": round(losses[0], 4), "nll_last_epoch": round(losses[-1], 4),
+                  "generate_s": round(gen_s, 3), "train_s": round(train_s, 3)},
+        "dtype": "bf16 network (MFMA, FP32 accumulate), f32 filter",
+    }
 
 
 if __name__ == "__main__":

@@ -154,9 +154,10 @@ dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean, float* d_
  * min(T_f, T).  d_Y: [T][F][dy] float, row t-1 holding y_t of every filter
  * (absolute time).  d_Tf: [F] int32 or NULL (all T).  d_xtrace [T][F][dx]
  * and d_ztrace [T][F][dz] (or NULL) receive the per-step estimates at row
- * t-1.  use_graph != 0 captures one step into a HIP graph once and replays
- * it T times (the step's launches read every per-filter time and buffer
- * choice from device memory, so replays need no host work). */
+ * t-1.  use_graph != 0 captures a chunk of 16 steps into a HIP graph once
+ * and replays it (the step's launches read every per-filter time and buffer
+ * choice from device memory, so replays need no host work); the T mod 16
+ * remaining steps are queued directly. */
 dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_Tf,
                    float* d_xtrace, float* d_ztrace, int32_t use_graph);
 
@@ -254,6 +255,12 @@ dpf_status dpf_learned_step(dpf_handle* h, const float* d_y, const uint8_t* d_ac
  * against a reference and for callers with their own proposal. */
 dpf_status dpf_learned_step_given(dpf_handle* h, const float* d_y, const uint8_t* d_active,
                                   const float* d_mdn, double ess_frac);
+
+/* dpf_run with the learned step: up to T learned steps over device-resident
+ * observations d_Y [T][F][dy] (same arguments and graph replay as dpf_run);
+ * needs dpf_set_proposal first. */
+dpf_status dpf_learned_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_Tf,
+                           float* d_xtrace, float* d_ztrace, int32_t use_graph);
 
 /* Raw (unstandardised) features of every outer particle of the current
  * state for observations d_y [F][dy]: d_feat [sum N][32] float, zero-padded

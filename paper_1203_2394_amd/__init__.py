@@ -32,7 +32,7 @@ EXPORTS = [
     "dpf_normals", "dpf_systematic", "dpf_segmented_systematic", "dpf_set_phase_events",
     "dpf_set_proposal", "dpf_learned_step", "dpf_learned_step_given", "dpf_features",
     "dpf_mlp_blob_bytes", "dpf_mlp_param_count", "dpf_mlp_forward", "dpf_mlp_train_workspace_bytes",
-    "dpf_mlp_pack", "dpf_mlp_train_step",
+    "dpf_mlp_pack", "dpf_mlp_train_step", "dpf_learned_run",
 ]
 
 
@@ -96,6 +96,7 @@ def lib():
         "dpf_learned_step": (_i32, [_vp, _vp, _vp]),
         "dpf_learned_step_given": (_i32, [_vp, _vp, _vp, _vp, ctypes.c_double]),
         "dpf_features": (_i32, [_vp, _vp, _vp]),
+        "dpf_learned_run": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _i32]),
         "dpf_mlp_blob_bytes": (_sz, []),
         "dpf_mlp_param_count": (_sz, []),
         "dpf_mlp_forward": (_i32, [_vp, _vp, _i32, _vp, _vp]),
@@ -252,8 +253,10 @@ class Filter:
                                   _ptr(out["loglik"]), _ptr(out["flags"])))
         return out
 
-    def run(self, Y, Tf=None, trace=True, use_graph=True):
-        """Run over device-resident observations Y [T][F][dy]; returns traces."""
+    def run(self, Y, Tf=None, trace=True, use_graph=True, learned=False):
+        """Run over device-resident observations Y [T][F][dy]; returns traces.
+        learned: the learned step (dpf_learned_run) instead of the handle's
+        algorithm."""
         torch = _torch()
         Y = torch.as_tensor(Y, dtype=torch.float32, device=self.device).contiguous()
         T = Y.shape[0]
@@ -262,7 +265,8 @@ class Filter:
         if trace:
             xt = torch.full((T, self.F, self.dx), float("nan"), dtype=torch.float32, device=self.device)
             zt = torch.full((T, self.F, self.dz), float("nan"), dtype=torch.float32, device=self.device)
-        _check(lib().dpf_run(self._h, _ptr(Y), int(T), _ptr(Tf_t), _ptr(xt), _ptr(zt), int(bool(use_graph))))
+        fn = lib().dpf_learned_run if learned else lib().dpf_run
+        _check(fn(self._h, _ptr(Y), int(T), _ptr(Tf_t), _ptr(xt), _ptr(zt), int(bool(use_graph))))
         self._keep = (Y, Tf_t, xt, zt)
         return xt, zt
 

@@ -381,7 +381,7 @@ struct dpf_handle {
   // multi-step graph cache
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
-  const void* g_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const void* g_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int g_T = -1;
   // phase timing: caller-owned events consumed kPhaseEvents per step
   std::vector<hipEvent_t> prof_events;
@@ -674,17 +674,20 @@ static dpf_status queue_moments(dpf_handle* h, const float* y, float* feat) {
 
 // One learned step (with look-ahead fallback per filter); mdn_given: the
 // network outputs [NT][32] supplied by the caller instead of the network.
-static dpf_status queue_learned_step(dpf_handle* h, const float* Y, const unsigned char* active,
-                                     const float* mdn_given) {
+static dpf_status queue_learned_step(dpf_handle* h, const float* Y, long long y_tstride,
+                                     const unsigned char* active, const int* run_Tf, int run_T, float* trace_x,
+                                     float* trace_z, const float* mdn_given) {
   dpf_status s = DPF_OK;
   if (!h->mom_valid && !mdn_given) s = queue_moments(h, nullptr, nullptr);
   if (s != DPF_OK) return s;
   StepArgs a = make_args(h);
   a.Y = Y;
-  a.y_tstride = 0;
+  a.y_tstride = y_tstride;
   a.active = active;
-  a.run_Tf = nullptr;
-  a.run_T = INT_MAX;
+  a.run_Tf = run_Tf;
+  a.run_T = run_T;
+  a.trace_x = trace_x;
+  a.trace_z = trace_z;
   a.advance = 1;
   a.mom = at<float>(h, h->L.mom);
   if (mdn_given) a.mdn = const_cast<float*>(mdn_given);
@@ -762,7 +765,7 @@ extern "C" dpf_status dpf_learned_step(dpf_handle* h, const float* d_y, const ui
   dpf_status s = check_learned(h);
   if (s != DPF_OK) return s;
   if (!h->has_proposal) return fail(DPF_ESTATE, "no proposal set (dpf_set_proposal)");
-  return queue_learned_step(h, d_y, d_active, nullptr);
+  return queue_learned_step(h, d_y, 0, d_active, nullptr, INT_MAX, nullptr, nullptr, nullptr);
 }
 
 extern "C" dpf_status dpf_learned_step_given(dpf_handle* h, const float* d_y, const uint8_t* d_active,
@@ -773,7 +776,7 @@ extern "C" dpf_status dpf_learned_step_given(dpf_handle* h, const float* d_y, co
   if (!(ess_frac >= 0.0 && ess_frac <= 1.0)) return fail(DPF_EINVAL, "ess_frac must lie in [0, 1]");
   const double keep = h->ess_frac;
   h->ess_frac = ess_frac;
-  s = queue_learned_step(h, d_y, d_active, d_mdn);
+  s = queue_learned_step(h, d_y, 0, d_active, nullptr, INT_MAX, nullptr, nullptr, d_mdn);
   h->ess_frac = keep;
   return s;
 }
@@ -801,24 +804,38 @@ extern "C" dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean
   return DPF_OK;
 }
 
-static dpf_status queue_run_step(dpf_handle* h, const float* d_Y, int T, const int32_t* d_Tf, float* xt,
-                                 float* zt) {
-  return queue_step(h, d_Y, (long long)h->F * h->dy, nullptr, (const int*)d_Tf, T, xt, zt);
+static dpf_status queue_run_step(dpf_handle* h, int mode, const float* d_Y, int T, const int32_t* d_Tf,
+                                 float* xt, float* zt) {
+  const long long stride = (long long)h->F * h->dy;
+  if (mode == 1) return queue_learned_step(h, d_Y, stride, nullptr, (const int*)d_Tf, T, xt, zt, nullptr);
+  return queue_step(h, d_Y, stride, nullptr, (const int*)d_Tf, T, xt, zt);
 }
 
-extern "C" dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_Tf, float* d_xtrace,
-                              float* d_ztrace, int32_t use_graph) {
+// T steps of mode 0 (the handle's algorithm) or 1 (learned), eagerly or as
+// replays of a captured chunk of kGraphChunk steps (every step reads the
+// per-filter time and state copy from device memory, so one capture serves
+// every chunk); the T % kGraphChunk remaining steps run eagerly.
+constexpr int kGraphChunk = 16;
+
+static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T, const int32_t* d_Tf,
+                            float* d_xtrace, float* d_ztrace, int32_t use_graph) {
   if (!h || !d_Y) return fail(DPF_EINVAL, "handle and d_Y are required");
   if (T < 0) return fail(DPF_EINVAL, "T = %d", T);
   if (T == 0) return DPF_OK;
+  if (mode == 1 && !h->mom_valid) {
+    // moments of the starting state, outside any captured step
+    dpf_status st = queue_moments(h, nullptr, nullptr);
+    if (st != DPF_OK) return st;
+  }
   if (!use_graph) {
     for (int s = 0; s < T; ++s) {
-      dpf_status st = queue_run_step(h, d_Y, T, d_Tf, d_xtrace, d_ztrace);
+      dpf_status st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace);
       if (st != DPF_OK) return st;
     }
     return DPF_OK;
   }
-  const void* key[5] = {d_Y, d_Tf, d_xtrace, d_ztrace, (const void*)h->stream};
+  const int S = T < kGraphChunk ? T : kGraphChunk;
+  const void* key[6] = {d_Y, d_Tf, d_xtrace, d_ztrace, (const void*)h->stream, (const void*)(intptr_t)mode};
   const bool cached = h->gexec && h->g_T == T && memcmp(key, h->g_key, sizeof(key)) == 0;
   if (!cached) {
     if (h->gexec) {
@@ -831,7 +848,8 @@ extern "C" dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const 
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
     dpf_status st = DPF_OK;
-    if (e == hipSuccess) st = queue_run_step(h, d_Y, T, d_Tf, d_xtrace, d_ztrace);
+    for (int q = 0; e == hipSuccess && st == DPF_OK && q < S; ++q)
+      st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace);
     hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
     h->stream = user;
     if (e != hipSuccess) return fail(DPF_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
@@ -849,8 +867,26 @@ extern "C" dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const 
     memcpy(h->g_key, key, sizeof(key));
     h->g_T = T;
   }
-  for (int s = 0; s < T; ++s) HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
+  for (int s = 0; s + S <= T; s += S) HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
+  for (int s = (T / S) * S; s < T; ++s) {
+    dpf_status st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace);
+    if (st != DPF_OK) return st;
+  }
   return DPF_OK;
+}
+
+extern "C" dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_Tf, float* d_xtrace,
+                              float* d_ztrace, int32_t use_graph) {
+  return run_steps(h, 0, d_Y, T, d_Tf, d_xtrace, d_ztrace, use_graph);
+}
+
+extern "C" dpf_status dpf_learned_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_Tf,
+                                      float* d_xtrace, float* d_ztrace, int32_t use_graph) {
+  if (!h) return fail(DPF_EINVAL, "handle is NULL");
+  dpf_status s = check_learned(h);
+  if (s != DPF_OK) return s;
+  if (!h->has_proposal) return fail(DPF_ESTATE, "no proposal set (dpf_set_proposal)");
+  return run_steps(h, 1, d_Y, T, d_Tf, d_xtrace, d_ztrace, use_graph);
 }
 
 // ---------------------------------------------------------------- state I/O

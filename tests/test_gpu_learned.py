@@ -414,3 +414,30 @@ def test_learned_steps_are_deterministic():
             f.learned_step(torch.tensor(np.stack([ys[t], ys[t]]), dtype=torch.float32))
         outs.append(f.export_state().cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_learned_run_graph_equals_steps():
+    """dpf_learned_run: graph replays, eager steps and single learned steps
+    give the same bits, also with per-filter horizons."""
+    spec = _spec()
+    _, _, ys1 = S.simulate(spec, 12, 41)
+    _, _, ys2 = S.simulate(spec, 12, 42)
+    Y = torch.tensor(np.stack([ys1, ys2], axis=1), dtype=torch.float32, device="cuda")
+    Tf = torch.tensor([12, 7], dtype=torch.int32, device="cuda")
+    m = _mlp(_params(17))
+    outs = []
+    for mode in ("graph", "eager", "steps"):
+        f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [300, 128], [64, 40], seed=9)
+        f.set_proposal(m, ess_frac=0.05)
+        if mode == "steps":
+            for t in range(12):
+                f.learned_step(Y[t], active=np.array([1, int(t < 7)], dtype=np.uint8))
+            xt = None
+        else:
+            xt, zt = f.run(Y, Tf=Tf, learned=True, use_graph=(mode == "graph"))
+            xt = xt.cpu().numpy()
+        outs.append((f.export_state().cpu().numpy(), xt))
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][0], outs[2][0])
+    assert np.array_equal(outs[0][1], outs[1][1], equal_nan=True)
+    assert np.all(np.isnan(outs[0][1][7:, 1])) and np.all(np.isfinite(outs[0][1][:7]))
