@@ -38,6 +38,7 @@ DX, DZ, DY = 2, 8, 8
 PARAM_SEED, DATA_SEED, FILTER_SEED = 1, 2024, 7
 LEARNED_PAIRS, LEARNED_EPOCHS = 1_000_000, 10
 EVAL_SEQS, EVAL_SEED, ESS_FRAC = 8, 5000, 0.1
+BATCH_F, BATCH_SEED = 1024, 7
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nonlin_N4096_M256.txt")
 KERNEL_SOURCES = ["dpf_kernels.hpp", "dpf_models.hpp", "dpf_rng.hpp", "dpf_seg.hpp"]
 
@@ -118,6 +119,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched ragged-filter run")
     ap.add_argument("--cpu-baseline-child", type=int, default=0)
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, run one device-to-device copy of this many MB "
@@ -214,6 +216,7 @@ def main():
     f.close()
 
     learned = None if args.no_learned else run_learned(S, dpf, torch, np, dev, K, W)
+    batched = None if args.no_batched else run_batched(S, dpf, torch, np, dev)
     cpu = None if args.no_cpu_baseline else run_cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
@@ -236,10 +239,61 @@ def main():
         "phase_ms": {p: round(v, 5) for p, v in ph_ms.items()},
         "roofline": roofline,
         "learned": learned,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
     return 0
+
+
+def run_batched(S, dpf, torch, np, dev):
+    """1024 independent filters of the linear-Gaussian model with ragged N, M
+    and horizons T_f in one handle, run to the end as graph replays; tile
+    classes for each inner size from the autotuner, and the default tiling
+    beside it."""
+    from paper_1203_2394_amd import autotune as AT
+
+    spec = S.lingauss_c1(False)
+    rb = S.ragged_batch(F=BATCH_F, seed=BATCH_SEED)
+    F, T = BATCH_F, int(rb.T.max())
+    ys = np.zeros((T, F, spec.dy), dtype=np.float32)
+    for q in range(F):
+        ys[:rb.T[q], q] = S.simulate(spec, int(rb.T[q]), int(rb.data_seeds[q]))[2]
+    Y = torch.tensor(ys, device=dev)
+    Tf = torch.tensor(rb.T, dtype=torch.int32, device=dev)
+    updates = float(np.sum(rb.N.astype(np.float64) * rb.M * rb.T))
+    t0 = time.perf_counter()
+    table = AT.tune(spec, np.unique(rb.M), N=1024, steps=16, reps=2, simulate=S.simulate, device=dev)
+    tune_s = time.perf_counter() - t0
+    out = {}
+    for mode in ("default", "tuned"):
+        f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, rb.N, rb.M, seed=BATCH_SEED, device=dev)
+        if mode == "tuned":
+            f.set_tiling(AT.classes_for(table, rb.M))
+        f.run(Y, Tf=Tf, trace=False, use_graph=True)  # capture and warm up
+        f.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.run(Y, Tf=Tf, trace=False, use_graph=True)
+        torch.cuda.synchronize()
+        out[mode] = time.perf_counter() - t0
+        f.close()
+    cls = dpf.tile_classes()
+    return {
+        "value": updates / out["tuned"],
+        "unit": UNIT,
+        "seconds": round(out["tuned"], 4),
+        "default_tiling_value": updates / out["default"],
+        "inner_updates": updates,
+        "config": {"workload": "F=%d linear-Gaussian filters (dx=1 dz=2 dy=1), N log-uniform in [256, 4096], "
+                               "M in {32, 64, 128}, T in [50, 500], one handle, graph replays" % F,
+                   "sum_N": int(rb.N.sum()), "sum_NM": int(np.sum(rb.N.astype(np.int64) * rb.M)),
+                   "T_max": T},
+        "tiling": {str(m): {"class": v["class"], "seg_jpt": cls[v["class"]],
+                            "ms_per_step": {str(k): round(t, 4) for k, t in v["ms"].items()}}
+                   for m, v in table.items()},
+        "tune_s": round(tune_s, 2),
+    }
 
 
 def run_learned(S, dpf, torch, np, dev, K, W):

@@ -207,6 +207,21 @@ dpf_status dpf_set_phase_events(dpf_handle* h, void* const* hip_events, int32_t 
 /* Message for the last non-OK status returned on this thread. */
 const char* dpf_last_error(void);
 
+/* ---- tiling ----
+ * Per-particle kernels run 256-thread workgroups split into segments of SEG
+ * lanes, one outer particle per segment, each lane handling JPT inner
+ * particles (a class holds M <= SEG * JPT).  dpf_tile_classes writes the
+ * built classes' (SEG, JPT) into seg / jpt (up to n entries, either may be
+ * NULL) and returns their number.  By default a filter uses the first of
+ * classes 0..5 that holds its M. */
+int32_t dpf_tile_classes(int32_t* seg, int32_t* jpt, int32_t n);
+
+/* Choose the class of each filter: h_cls [F] host, a class index holding the
+ * filter's M, or -1 for the default.  Takes effect for the following calls
+ * (results then depend on the class only through floating-point reduction
+ * order); a captured run graph is rebuilt. */
+dpf_status dpf_set_tiling(dpf_handle* h, const int32_t* h_cls);
+
 /* ---- learned proposal for the outer block ----
  *
  * A mixture density network q(x_t | features) stands in for the Monte Carlo

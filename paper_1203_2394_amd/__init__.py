@@ -32,7 +32,7 @@ EXPORTS = [
     "dpf_normals", "dpf_systematic", "dpf_segmented_systematic", "dpf_set_phase_events",
     "dpf_set_proposal", "dpf_learned_step", "dpf_learned_step_given", "dpf_features",
     "dpf_mlp_blob_bytes", "dpf_mlp_param_count", "dpf_mlp_forward", "dpf_mlp_train_workspace_bytes",
-    "dpf_mlp_pack", "dpf_mlp_train_step", "dpf_learned_run",
+    "dpf_mlp_pack", "dpf_mlp_train_step", "dpf_learned_run", "dpf_tile_classes", "dpf_set_tiling",
 ]
 
 
@@ -97,6 +97,8 @@ def lib():
         "dpf_learned_step_given": (_i32, [_vp, _vp, _vp, _vp, ctypes.c_double]),
         "dpf_features": (_i32, [_vp, _vp, _vp]),
         "dpf_learned_run": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _i32]),
+        "dpf_tile_classes": (_i32, [_vp, _vp, _i32]),
+        "dpf_set_tiling": (_i32, [_vp, _vp]),
         "dpf_mlp_blob_bytes": (_sz, []),
         "dpf_mlp_param_count": (_sz, []),
         "dpf_mlp_forward": (_i32, [_vp, _vp, _i32, _vp, _vp]),
@@ -208,6 +210,11 @@ class Filter:
 
     def reset(self):
         _check(lib().dpf_reset(self._h))
+
+    def set_tiling(self, classes):
+        """Tile class per filter (index into tile_classes(), or -1 = default)."""
+        c = np.ascontiguousarray(np.broadcast_to(np.asarray(classes, dtype=np.int32), (self.F,)))
+        _check(lib().dpf_set_tiling(self._h, c.ctypes.data_as(ctypes.c_void_p)))
 
     # -------------------------------------------------------------- learned proposal
     def set_proposal(self, mlp, ess_frac=0.1):
@@ -365,6 +372,14 @@ class Filter:
 
 
 # ------------------------------------------------------------------ primitives
+def tile_classes():
+    """[(SEG, JPT)] of the built tile classes, by class index."""
+    seg = (ctypes.c_int32 * 32)()
+    jpt = (ctypes.c_int32 * 32)()
+    n = lib().dpf_tile_classes(seg, jpt, 32)
+    return [(seg[k], jpt[k]) for k in range(n)]
+
+
 def philox_words(seed, filter_id, ctr, device="cuda"):
     torch = _torch()
     ctr = torch.as_tensor(np.asarray(ctr, dtype=np.uint32).view(np.int32), device=device).contiguous()

@@ -54,11 +54,16 @@ extern "C" const char* dpf_last_error(void) { return g_err.c_str(); }
 struct ClassShape {
   int seg, jpt;
 };
-static const ClassShape kClasses[] = {{32, 1}, {64, 1}, {128, 1}, {256, 1}, {256, 4}, {256, 16}};
-constexpr int kNumClasses = 6;
+// The first six are the defaults (the first that holds M); the last three
+// trade lanes for inner particles per lane and are chosen only by
+// dpf_set_tiling (an autotuner).
+static const ClassShape kClasses[] = {{32, 1},  {64, 1}, {128, 1}, {256, 1}, {256, 4},
+                                      {256, 16}, {32, 2}, {32, 4},  {64, 2}};
+constexpr int kNumClasses = 9;
+constexpr int kNumDefaultClasses = 6;
 
 static int class_of(int M) {
-  for (int c = 0; c < kNumClasses; ++c)
+  for (int c = 0; c < kNumDefaultClasses; ++c)
     if (M <= kClasses[c].seg * kClasses[c].jpt) return c;
   return -1;
 }
@@ -179,6 +184,9 @@ static dpf_status engine_launch(int op, const StepArgs& a, const TileClass& tc, 
     case 3: launch_op<Mdl, 256, 1>(op, a, n, s); break;
     case 4: launch_op<Mdl, 256, 4>(op, a, n, s); break;
     case 5: launch_op<Mdl, 256, 16>(op, a, n, s); break;
+    case 6: launch_op<Mdl, 32, 2>(op, a, n, s); break;
+    case 7: launch_op<Mdl, 32, 4>(op, a, n, s); break;
+    case 8: launch_op<Mdl, 64, 2>(op, a, n, s); break;
     default: return fail(DPF_EUNSUPPORTED, "no kernel class %d", tc.cls);
   }
   LAUNCH_CHECK("step kernel");
@@ -263,8 +271,6 @@ struct Layout {
       logw, anc, sel, kpart, gstat, fstat, ess, dlogz, loglik, flags, est_x, est_z;
   // slot indirection and learned-proposal buffers
   size_t ind0, ind1, mom, mlp, mdn, xtmp, logq, kpart_tmp, mom_tmp, fb, lflags;
-  std::vector<size_t> tile_off;  // per class (in tile units from `tiles`)
-  std::vector<int> tile_n;
   int NT = 0;
   long long NMT = 0;
   int n_tiles = 0, n_rgroups = 0;
@@ -293,8 +299,8 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   const int F = c->n_filters;
   L.NT = 0;
   L.NMT = 0;
-  L.tile_n.assign(kNumClasses, 0);
   L.n_rgroups = 0;
+  L.n_tiles = 0;  // room for any class: at most one tile per outer particle
   for (int f = 0; f < F; ++f) {
     if (c->N[f] < 1 || c->N[f] > 65536) return fail(DPF_EUNSUPPORTED, "N[%d] = %d outside 1..65536", f, c->N[f]);
     const int cls = class_of(c->M[f]);
@@ -302,9 +308,7 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
     if ((long long)L.NT + c->N[f] > 0x7fffffffLL) return fail(DPF_EUNSUPPORTED, "total N too large");
     L.NT += c->N[f];
     L.NMT += (long long)c->N[f] * c->M[f];
-    const int segs = kBlock / kClasses[cls].seg;
-    const int nt = (c->N[f] + segs - 1) / segs;
-    L.tile_n[cls] += nt;
+    L.n_tiles += c->N[f];  // at most one tile per outer particle (SEG = 256)
     const int G = (c->N[f] + kResGroup - 1) / kResGroup;
     L.n_rgroups += G;
   }
@@ -321,12 +325,6 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   L.tcur = carve(cur, F * 4);
   L.cur = carve(cur, F);
   L.act = carve(cur, F);
-  L.n_tiles = 0;
-  L.tile_off.assign(kNumClasses, 0);
-  for (int k = 0; k < kNumClasses; ++k) {
-    L.tile_off[k] = L.n_tiles;
-    L.n_tiles += L.tile_n[k];
-  }
   L.tiles = carve(cur, (size_t)L.n_tiles * sizeof(int4));
   L.rgroups = carve(cur, (size_t)L.n_rgroups * sizeof(int2));
   L.x0 = carve(cur, NT * dx * 4);
@@ -363,6 +361,9 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   return DPF_OK;
 }
 
+// ---------------------------------------------------------------- tiling
+struct dpf_handle;
+static dpf_status build_tiles(dpf_handle* h);
 // ---------------------------------------------------------------- handle
 struct dpf_handle {
   const Engine* eng;
@@ -378,6 +379,7 @@ struct dpf_handle {
   std::vector<FilterInfo> finfo_h;
   std::vector<float> prm_h;
   std::vector<TileClass> classes;
+  std::vector<int> fcls;  // tile class of each filter
   // multi-step graph cache
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -566,29 +568,17 @@ extern "C" dpf_status dpf_create(const dpf_config* cfg, void* d_workspace, size_
     delete h;
     return fail(DPF_EINVAL, "internal: parameter layout mismatch");
   }
-  // tiles grouped by class; per-filter resampling groups
-  h->tiles_h.assign(L.n_tiles, make_int4(0, 0, 0, 0));
+  // per-filter resampling groups; tiles grouped by class (default classes)
   h->finfo_h.assign(F, FilterInfo{0, 0, 0, 0});
-  std::vector<size_t> fill(L.tile_off);
   int rg = 0;
   for (int f = 0; f < F; ++f) {
-    const int cls = class_of(h->M[f]);
-    const int segs = kBlock / kClasses[cls].seg;
-    int nt = 0;
-    for (int i0 = 0; i0 < h->N[f]; i0 += segs) h->tiles_h[fill[cls]++] = make_int4(f, i0, nt++, 0);
     const int G = (h->N[f] + kResGroup - 1) / kResGroup;
     for (int g = 0; g < G; ++g) h->rgroups_h.push_back(make_int2(f, g));
     h->finfo_h[f] = FilterInfo{rg, G, 0, 0};
     rg += G;
   }
-  for (int k = 0; k < kNumClasses; ++k) {
-    if (L.tile_n[k] == 0) continue;
-    TileClass tc;
-    tc.cls = k;
-    tc.n_tiles = L.tile_n[k];
-    tc.d_tiles = at<int4>(h, L.tiles) + L.tile_off[k];
-    h->classes.push_back(tc);
-  }
+  h->fcls.resize(F);
+  for (int f = 0; f < F; ++f) h->fcls[f] = class_of(h->M[f]);
   hipError_t e = hipSuccess;
 #define UP(off, vec)                                                                                   \
   if (e == hipSuccess && !(vec).empty())                                                               \
@@ -600,13 +590,17 @@ extern "C" dpf_status dpf_create(const dpf_config* cfg, void* d_workspace, size_
   UP(L.ooff, h->ooff)
   UP(L.ooff64, h->ooff64)
   UP(L.ioff, h->ioff)
-  UP(L.tiles, h->tiles_h)
   UP(L.rgroups, h->rgroups_h)
   UP(L.finfo, h->finfo_h)
 #undef UP
   if (e != hipSuccess) {
     delete h;
     return fail(DPF_EDEVICE, "parameter upload failed: %s", hipGetErrorString(e));
+  }
+  st = build_tiles(h);
+  if (st != DPF_OK) {
+    delete h;
+    return st;
   }
   st = queue_init(h);
   if (st != DPF_OK) {
@@ -615,6 +609,60 @@ extern "C" dpf_status dpf_create(const dpf_config* cfg, void* d_workspace, size_
   }
   *out = h;
   return DPF_OK;
+}
+
+// Tiles of every filter in the class h->fcls[f], grouped by class, uploaded
+// to the workspace (room for one tile per outer particle was reserved).
+static dpf_status build_tiles(dpf_handle* h) {
+  const int F = h->F;
+  std::vector<std::vector<int4>> by(kNumClasses);
+  for (int f = 0; f < F; ++f) {
+    const int segs = kBlock / kClasses[h->fcls[f]].seg;
+    int nt = 0;
+    for (int i0 = 0; i0 < h->N[f]; i0 += segs) by[h->fcls[f]].push_back(make_int4(f, i0, nt++, 0));
+  }
+  h->tiles_h.clear();
+  h->classes.clear();
+  for (int k = 0; k < kNumClasses; ++k) {
+    if (by[k].empty()) continue;
+    TileClass tc;
+    tc.cls = k;
+    tc.n_tiles = (int)by[k].size();
+    tc.d_tiles = at<int4>(h, h->L.tiles) + h->tiles_h.size();
+    h->tiles_h.insert(h->tiles_h.end(), by[k].begin(), by[k].end());
+    h->classes.push_back(tc);
+  }
+  if ((int)h->tiles_h.size() > h->L.n_tiles) return fail(DPF_EINVAL, "internal: tile room exceeded");
+  HIP_TRY(hipMemcpyAsync(h->ws + h->L.tiles, h->tiles_h.data(), h->tiles_h.size() * sizeof(int4),
+                         hipMemcpyHostToDevice, h->stream));
+  if (h->gexec) {
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
+  return DPF_OK;
+}
+
+extern "C" int32_t dpf_tile_classes(int32_t* seg, int32_t* jpt, int32_t n) {
+  for (int k = 0; k < kNumClasses && k < n; ++k) {
+    if (seg) seg[k] = kClasses[k].seg;
+    if (jpt) jpt[k] = kClasses[k].jpt;
+  }
+  return kNumClasses;
+}
+
+extern "C" dpf_status dpf_set_tiling(dpf_handle* h, const int32_t* h_cls) {
+  if (!h || !h_cls) return fail(DPF_EINVAL, "handle and class array are required");
+  std::vector<int> c(h->F);
+  for (int f = 0; f < h->F; ++f) {
+    const int k = h_cls[f] < 0 ? class_of(h->M[f]) : h_cls[f];
+    if (k >= kNumClasses) return fail(DPF_EINVAL, "class %d of filter %d is not built", k, f);
+    if (kClasses[k].seg * kClasses[k].jpt < h->M[f])
+      return fail(DPF_EINVAL, "class %d holds %d inner particles, filter %d has M = %d", k,
+                  kClasses[k].seg * kClasses[k].jpt, f, h->M[f]);
+    c[f] = k;
+  }
+  h->fcls = c;
+  return build_tiles(h);
 }
 
 extern "C" dpf_status dpf_reset(dpf_handle* h) {

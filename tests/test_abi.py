@@ -121,3 +121,11 @@ def test_learned_calls_reject_null_handles():
     L.dpf_mlp_forward.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_void_p]
     assert L.dpf_mlp_forward(None, None, 4, None, None) == 1
+
+
+def test_tile_class_table():
+    classes = dpf.tile_classes()
+    assert classes[:6] == [(32, 1), (64, 1), (128, 1), (256, 1), (256, 4), (256, 16)]
+    assert set(classes[6:]) == {(32, 2), (32, 4), (64, 2)}
+    assert all(256 % seg == 0 for seg, _ in classes)
+    assert _lib().dpf_set_tiling(None, None) == 1

@@ -206,13 +206,15 @@ def _gpu_state(f):
     return {"x": g["x"][0], "z": g["z"][0], "lam": g["lam"][0], "t": int(g["t"][0])}
 
 
-def _learned_case(N, M, warm, seed=99, data_seed=8, ess_frac=0.0):
+def _learned_case(N, M, warm, seed=99, data_seed=8, ess_frac=0.0, tiling=None):
     spec = _spec()
     model = _model(spec)
     _, _, ys = S.simulate(spec, warm + 2, data_seed)
     ys = ys.astype(np.float32).astype(np.float64)
     st32 = _oracle_state(model, N, M, warm, seed, ys)
     f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N], [M], seed=seed)
+    if tiling is not None:
+        f.set_tiling([tiling])
     f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["x"], st32["z"], st32["lam"])))
     mdn = _mdn_outputs(st32, seed + warm, ys[warm], model)
     f.learned_step_given(torch.tensor(ys[warm], dtype=torch.float32), torch.tensor(mdn, dtype=torch.float32),
@@ -239,6 +241,13 @@ def test_learned_step_parity(N, M, warm):
         assert np.allclose(est["zhat"][0].cpu().numpy(), info["zhat"], rtol=1e-4, atol=1e-4)
         assert abs(float(est["ess"][0]) - info["ess"]) <= 1e-3 * info["ess"]
         assert abs(float(est["loglik"][0]) - info["dlogz"]) <= 1e-4 * max(1.0, abs(info["dlogz"]))
+
+
+@pytest.mark.parametrize("cls,M", [(8, 100), (6, 64), (7, 128)])
+def test_learned_step_parity_under_other_tilings(cls, M):
+    f, model, spec, ys, st32, gs, r, new_o, info = _learned_case(200, M, 2, tiling=cls)
+    assert not r["fallback"]
+    assert_clean_learned(r, n=200)
 
 
 def test_lookahead_step_after_learned_step_reads_the_slots():

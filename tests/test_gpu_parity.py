@@ -157,3 +157,50 @@ def test_initialisation_matches_oracle_prior(algo):
         # the proposals for t = 1 come from the prior through steps 4-7
         err = np.abs(g["x"][0] - st["xt"]) / np.maximum(1, np.abs(st["xt"]))
         assert np.max(err) < 1e-4
+
+
+@pytest.mark.parametrize("cls,M", [(6, 50), (7, 128), (8, 100), (8, 64), (3, 40), (2, 7)])
+@pytest.mark.parametrize("algo", ["lookahead", "plain"])
+def test_step_parity_under_every_tiling(cls, M, algo):
+    """The same step under a non-default tile class (SEG, JPT) matches the oracle."""
+    spec = SPECS["nonlin"]()
+    model = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
+    N, seed = 150, 515
+    _, _, ys = S.simulate(spec, 3, 9)
+    ys = ys.astype(np.float32).astype(np.float64)
+    f = _gpu_filter(spec, N, M, seed, algo)
+    f.set_tiling([cls])
+    if algo == "lookahead":
+        st = ladpf.init_state(model, N, M, seed, 0)
+        st, _ = ladpf.step(model, st, ys[0], seed, 0)
+        st32 = to_state32(st)
+        f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["x"], st32["z"], st32["lam"])))
+        f.lookahead_step(torch.tensor(ys[1], dtype=torch.float32))
+    else:
+        st = odpf.init_state(model, N, M, seed, 0)
+        st, _ = odpf.step(model, st, ys[0], seed, 0)
+        st32 = to_state32(st)
+        f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["xt"], st32["zt"], np.zeros((N, M)))))
+        f.step(torch.tensor(ys[1], dtype=torch.float32))
+    g = f.unpack_state(f.export_state())
+    ell = f.copy_buffer(dpf.BUF_ELL).cpu().numpy().reshape(N, M)
+    logw = f.copy_buffer(dpf.BUF_LOGW).cpu().numpy()
+    anc = f.copy_buffer(dpf.BUF_ANC).cpu().numpy()
+    sel = f.copy_buffer(dpf.BUF_SEL).cpu().numpy()
+    if algo == "lookahead":
+        gs = {"x": g["x"][0], "z": g["z"][0], "lam": g["lam"][0]}
+        r, _, _ = compare_la(model, st32, ys[1], seed, 0, gs, ell, logw, anc, sel)
+    else:
+        gs = {"x": g["x"][0], "z": g["z"][0]}
+        r, _, _ = compare_plain(model, st32, ys[1], seed, 0, gs, ell, logw, anc, sel)
+    print("%s class %d M=%d: %s" % (algo, cls, M, r.line()), flush=True)
+    assert_clean(r, n=N)
+
+
+def test_set_tiling_rejects_classes_too_small():
+    spec = SPECS["nonlin"]()
+    f = _gpu_filter(spec, 20, 100, 1, "lookahead")
+    with pytest.raises(dpf.DPFError):
+        f.set_tiling([6])  # (32, 2) holds 64 < 100
+    with pytest.raises(dpf.DPFError):
+        f.set_tiling([42])

