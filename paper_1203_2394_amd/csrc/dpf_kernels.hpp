@@ -55,7 +55,7 @@ struct FilterInfo {
 
 struct StepArgs {
   const float* prm;
-  const int4* tiles;  // (filter, first outer index, tile index within filter, 0)
+  const int4* tiles;  // (filter, first outer index, tile index within filter, first resampling group)
   const int* fN;
   const int* fM;
   const int* ooff;
@@ -81,7 +81,7 @@ struct StepArgs {
   int* anc;
   int* sel;      // [NT] selected candidate (look-ahead) / inner ancestor (plain)
   float* kpart;  // [NT][DZ] per-particle sum_j qbar z (plain: of the proposals)
-  double* gstat;  // [resampling groups][4]: group max log w, sum, sum of squares (group scale)
+  double* gstat;  // [resampling groups + 64][4]: group max log w, sum, sum of squares (group scale)
   double* fstat;  // [F][4]: max log w, sum w, sum w^2, degenerate (0/1)
   float* ess;     // [F]
   double* dlogz;  // [F]
@@ -113,9 +113,40 @@ struct StepArgs {
   unsigned char* fb;         // [F] 1 where the look-ahead step replaces the learned one; null otherwise
   uint32_t* lflags;          // [F] flags of the learned pass, kept only if it is accepted
   double ess_frac;           // fallback threshold on ESS / N
+  // look-ahead run: the new-cloud kernel also computes the next step's
+  // look-ahead weights from the clouds it builds (null: it does not), and the
+  // estimates kernel records which filters take the next step
+  float* ell_next;
+  float* logw_next;
+  int next_act;
 };
 
 __device__ __forceinline__ int copy_of(unsigned char c) { return c & 1; }
+
+// Every per-filter value a tile reads, fetched together: the empty asm needs
+// them all before the early exits, so the loads go out in one round instead
+// of a chain of dependent ones behind each branch.
+struct FilterView {
+  long long io;
+  int N, M, oo, t, ngroup;
+  int act, fb, cur;
+};
+
+__device__ __forceinline__ FilterView load_filter(const StepArgs& a, int f) {
+  FilterView v;
+  v.act = a.act[f];
+  v.fb = a.fb != nullptr ? a.fb[f] : 1;
+  v.N = a.fN[f];
+  v.M = a.fM[f];
+  v.oo = a.ooff[f];
+  v.io = a.ioff[f];
+  v.t = a.tcur[f];
+  v.cur = a.cur[f];
+  v.ngroup = a.finfo[f].ngroup;
+  asm volatile("" ::"v"(v.act), "v"(v.fb), "v"(v.N), "v"(v.M), "v"(v.oo), "v"(v.io), "v"(v.t), "v"(v.cur),
+               "v"(v.ngroup));
+  return v;
+}
 __device__ __forceinline__ bool ident_slots(unsigned char c, int copy) { return (c >> (1 + copy)) & 1; }
 
 // fz_pre for a whole segment whose lanes share the outer particle: lane q of
@@ -270,22 +301,70 @@ __global__ __launch_bounds__(kBlock) void k_init(StepArgs a) {
 // component (LA_X normals at (t, i, j)) and its companion z (LA_Z), then
 // ell = lam + log p(y_t | xla, zla) (eq:weightsMC) and the per-particle
 // log-sum-exp log w_i.
+
+// log p(y_t | xla, zla) of inner particle (i, j) at time t from its outer x
+// and its z; ell = lam + that (la_ell).
+//
+// The inputs pass through empty asm first: the compiler cannot merge this
+// arithmetic with the caller's on the same values, so the weights kernel and
+// the new-cloud kernel (a look-ahead run) compile it alike and get the same
+// bits.
+template <class Mdl>
+__device__ __forceinline__ float la_logpy(const StepArgs& a, const Key& key, int t, int i, int j, const float* xi,
+                                          const float* zi, const float* yi) {
+  float x[Mdl::DX], z[Mdl::DZ], y[Mdl::DY];
+#pragma unroll
+  for (int d = 0; d < Mdl::DX; ++d) {
+    x[d] = xi[d];
+    asm volatile("" : "+v"(x[d]));
+  }
+#pragma unroll
+  for (int d = 0; d < Mdl::DZ; ++d) {
+    z[d] = zi[d];
+    asm volatile("" : "+v"(z[d]));
+  }
+#pragma unroll
+  for (int d = 0; d < Mdl::DY; ++d) {
+    y[d] = yi[d];
+    asm volatile("" : "+v"(y[d]));
+  }
+  float nu_x[Mdl::DX], nu_z[Mdl::DZ], xl[Mdl::DX], pre[Mdl::DZ], zl[Mdl::DZ], r0[Mdl::DY];
+  normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
+  normals<Mdl::DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, nu_z);
+  Mdl::fx(a.prm, x, z, nu_x, xl);
+  Mdl::fz_pre(a.prm, x, xl, pre);
+  Mdl::fz_post(a.prm, pre, z, nu_z, zl);
+  Mdl::obs_pre(a.prm, y, xl, r0);
+  return Mdl::logpy_post(a.prm, r0, zl);
+}
+
+// lam + g as a separate rounding: g is opaque to the compiler, so no
+// multiply inside it is fused into this add (the weights kernel and the
+// new-cloud kernel, which adds lam later, get the same bits).
+__device__ __forceinline__ float la_ell(float lam, float g) {
+  asm volatile("" : "+v"(g));
+  return lam + g;
+}
 template <class Mdl, int SEG, int JPT>
 __device__ __forceinline__ void la_weights_tile(const StepArgs& a, int ti, bool fallback) {
   __shared__ SegScratch sh;
   const int4 tile = a.tiles[ti];
   const int f = tile.x;
-  const bool act = step_active(a, f);
+  const int am = a.active != nullptr ? a.active[f] : 1;
+  const int tf = a.run_Tf != nullptr ? a.run_Tf[f] : 0x7fffffff;
+  asm volatile("" ::"v"(am), "v"(tf));
+  const FilterView fv = load_filter(a, f);
+  const bool act = am != 0 && fv.t < min(tf, a.run_T);  // step_active
   if (!fallback && tile.z == 0 && threadIdx.x == 0) a.act[f] = act ? 1 : 0;
   if (!act) return;
-  const int N = a.fN[f], M = a.fM[f];
+  const int N = fv.N, M = fv.M;
   const int i = tile.y + threadIdx.x / SEG;
   const int ls = threadIdx.x % SEG;
   const bool vi = i < N;
-  const int oo = a.ooff[f];
-  const long long io = a.ioff[f];
-  const int t = a.tcur[f] + 1;
-  const unsigned char cb = a.cur[f];
+  const int oo = fv.oo;
+  const long long io = fv.io;
+  const int t = fv.t + 1;
+  const unsigned char cb = (unsigned char)fv.cur;
   const int src = copy_of(cb);
   const Key key = make_key(a.seed, (uint32_t)f);
   const int ci = vi ? (ident_slots(cb, src) ? i : a.ind[src][oo + i]) : 0;
@@ -303,18 +382,10 @@ __device__ __forceinline__ void la_weights_tile(const StepArgs& a, int ti, bool 
   for (int r = 0; r < JPT; ++r) {
     const int j = ls + r * SEG;
     if (vi && j < M) {
-      float z[Mdl::DZ], nu_x[Mdl::DX], nu_z[Mdl::DZ], xl[Mdl::DX], pre[Mdl::DZ], zl[Mdl::DZ],
-          r0[Mdl::DY];
+      float z[Mdl::DZ];
 #pragma unroll
       for (int d = 0; d < Mdl::DZ; ++d) z[d] = zrow[d * M + j];
-      const float lam = lrow[j];
-      normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
-      normals<Mdl::DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, nu_z);
-      Mdl::fx(a.prm, x, z, nu_x, xl);
-      Mdl::fz_pre(a.prm, x, xl, pre);
-      Mdl::fz_post(a.prm, pre, z, nu_z, zl);
-      Mdl::obs_pre(a.prm, y, xl, r0);
-      const float e = lam + Mdl::logpy_post(a.prm, r0, zl);
+      const float e = la_ell(lrow[j], la_logpy<Mdl>(a, key, t, i, j, x, z, y));
       erow[j] = e;
       acc.add(e);
     }
@@ -654,6 +725,169 @@ __device__ ResResult resolve_points(const Src& src, int n, int n_out, double u, 
   return r;
 }
 
+// ------------------------------------------------ wave-level draws (wave 0)
+// When a workgroup serves one outer particle, its ancestor and candidate are
+// single draws: one wave does them with wave-wide DPP scans (no LDS rounds,
+// no barriers) while the other waves get on with independent work.
+
+// Inclusive FP64 scan over the 64 lanes; excl receives the exclusive value.
+__device__ __forceinline__ double wave_scan_d(double v, double& excl) {
+  const double incl = seg_scan_wave<kWave>(v);
+  const double up = __shfl_up(incl, 1);
+  excl = (threadIdx.x & (kWave - 1)) == 0 ? 0.0 : up;
+  return incl;
+}
+
+__device__ __forceinline__ int first_lane(unsigned long long mask) { return __ffsll((long long)mask) - 1; }
+
+// The ancestor of point k0 (one systematic point) from the group statistics
+// (lane l holds group l's (m, s, q) in gs), by one wave; G <= 64.  Same rule
+// and group offsets B as resolve_points (whose wave 0 computes B with the
+// same scan); the group's cumulative weights are summed four per lane then
+// scanned across lanes.
+template <class Src>
+__device__ int resolve_point_w0(const Src& src, int n, int n_out, double u, int k0, const double* gs, int G,
+                                bool want_sumsq, ResResult& rr) {
+  const int l = threadIdx.x & (kWave - 1);
+  const float gm = l < G ? (float)gs[0] : -INFINITY;
+  const float m = Src::kLog ? seg_reduce_wave<OpMax, kWave>(gm) : 0.f;
+  const bool deg = Src::kLog && !(m > -INFINITY);
+  double T = 0.0, Q = 0.0;
+  if (l < G) {
+    if (deg) {
+      T = Q = (double)min(kResGroup, n - l * kResGroup);
+    } else {
+      const double c = group_scale<Src>(gm, m);
+      T = c * gs[1];
+      Q = (c * c) * gs[2];
+    }
+  }
+  const double Binc = seg_scan_wave<kWave>(T);  // B[l + 1]
+  const double total = readlane_d(Binc, G - 1);
+  rr.m = deg ? 0.f : m;
+  rr.total = total;
+  rr.sumsq = want_sumsq ? seg_reduce_wave<OpAdd, kWave>(Q) : 0.0;
+  rr.deg = deg;
+  const double P = sys_point(k0, u, total, n_out);
+  unsigned long long bm = __ballot(l < G && Binc > P);
+  if (!bm) bm = __ballot(l < G && Binc >= total);
+  const int g = first_lane(bm);
+  const int base = g * kResGroup;
+  const int nloc = min(kResGroup, n - base);
+  const float mg = Src::kLog ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gm), g)) : 0.f;
+  const double cg = deg ? 1.0 : group_scale<Src>(mg, m);
+  const double Bg = g > 0 ? readlane_d(Binc, g - 1) : 0.0;
+  const double Bg1 = readlane_d(Binc, g);
+  // the four weights are read at clamped indices first (loads in flight
+  // together; a guarded load would wait inside its own branch), then masked
+  double L[4], vv[4], acc = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = 4 * l + q;
+    vv[q] = src.val(base + (i < nloc ? i : 0), mg);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = 4 * l + q;
+    const double v = i < nloc ? (deg ? 1.0 : ((!Src::kLog || mg > -INFINITY) ? vv[q] : 0.0)) : 0.0;
+    acc += v;
+    L[q] = acc;
+  }
+  double ex;
+  wave_scan_d(acc, ex);
+  double C[4];
+  int hit = 4, hit_eq = 4;
+#pragma unroll
+  for (int q = 3; q >= 0; --q) {
+    const int i = 4 * l + q;
+    C[q] = (i == nloc - 1) ? Bg1 : fmin(Bg + cg * (ex + L[q]), Bg1);
+    if (i < nloc && C[q] > P) hit = q;
+    if (i < nloc && C[q] >= Bg1) hit_eq = q;
+  }
+  bm = __ballot(hit < 4);
+  int idx;
+  if (bm) {
+    const int fl = first_lane(bm);
+    idx = 4 * fl + __builtin_amdgcn_readlane(hit, fl);
+  } else {
+    const int fl = first_lane(__ballot(hit_eq < 4));
+    idx = 4 * fl + __builtin_amdgcn_readlane(hit_eq, fl);
+  }
+  return base + idx;
+}
+
+// One systematic draw (offset u) over weights exp(e_j - max), j < M (non-
+// finite: 0; none finite: uniform), by one wave: each lane sums a chunk of
+// ceil(M / 64) <= CMAX consecutive weights, the chunk totals are scanned
+// across lanes, and the lane holding the point walks its chunk.  Chunks of
+// up to 16 stay in registers; longer ones are read again.
+template <int CMAX>
+__device__ int select_w0(const float* e, int M, double u, bool& deg_out) {
+  constexpr bool kReg = CMAX <= 16;
+  constexpr int R = kReg ? CMAX : 1;
+  const int l = threadIdx.x & (kWave - 1);
+  const int C = (M + kWave - 1) / kWave;
+  const int j0 = l * C;
+  const int nv = max(0, min(C, M - j0));  // entries of this lane's chunk
+  float ev[R];
+  float mloc = -INFINITY;
+  if constexpr (kReg) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      ev[q] = q < nv ? e[j0 + q] : -INFINITY;
+      if (finitef(ev[q])) mloc = fmaxf(mloc, ev[q]);
+    }
+  } else {
+    for (int q = 0; q < nv; ++q) {
+      const float v = e[j0 + q];
+      if (finitef(v)) mloc = fmaxf(mloc, v);
+    }
+  }
+  const float m = seg_reduce_wave<OpMax, kWave>(mloc);
+  const bool deg = !(m > -INFINITY);
+  deg_out = deg;
+  auto wt = [&](float v) { return deg ? 1.0 : (finitef(v) ? (double)fast_exp(v - m) : 0.0); };
+  double acc = 0.0;
+  double wv[R];
+  if constexpr (kReg) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      wv[q] = q < nv ? wt(ev[q]) : 0.0;
+      acc += wv[q];
+    }
+  } else {
+    for (int q = 0; q < nv; ++q) acc += wt(e[j0 + q]);
+  }
+  double ex;
+  const double incl = wave_scan_d(acc, ex);
+  const double total = readlane_d(incl, (M - 1) / C);  // the last lane with entries
+  const double P = sys_point(0, u, total, 1);
+  // the first lane with entries whose cumulative weight passes the point
+  // (else reaches the total); its last entry's cumulative weight is its
+  // scanned value, so the walk below always ends inside the chunk
+  unsigned long long bm = __ballot(nv > 0 && incl > P);
+  const bool clamp = bm == 0;
+  if (clamp) bm = __ballot(nv > 0 && incl >= total);
+  const int fl = first_lane(bm);
+  double cum = ex;
+  int hit = -1;
+  if constexpr (kReg) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      cum += wv[q];
+      const double cq = q == nv - 1 ? incl : fmin(cum, incl);
+      if (q < nv && hit < 0 && (clamp ? cq >= total : cq > P)) hit = j0 + q;
+    }
+  } else {
+    for (int q = 0; q < nv; ++q) {
+      cum += wt(e[j0 + q]);
+      const double cq = q == nv - 1 ? incl : fmin(cum, incl);
+      if (hit < 0 && (clamp ? cq >= total : cq > P)) hit = j0 + q;
+    }
+  }
+  return __builtin_amdgcn_readlane(hit, fl);
+}
+
 // Filter-level bookkeeping of the outer resampling (one thread per filter).
 __device__ void res_finish(const StepArgs& a, int f, int t, int N, const ResResult& r) {
   a.fstat[4 * f + 0] = r.deg ? 0.0 : (double)r.m;
@@ -666,8 +900,10 @@ __device__ void res_finish(const StepArgs& a, int f, int t, int N, const ResResu
   a.loglik[f] += dl;
   uint32_t fl = r.deg ? (uint32_t)F_DEGENERATE_OUTER : 0u;
   const float* yp = a.Y + (long long)(t - 1) * a.y_tstride + (long long)f * a.dy;
-  for (int q = 0; q < a.dy; ++q)
-    if (!finitef(yp[q])) fl |= F_NONFINITE;
+  bool nonf = false;
+#pragma unroll 8
+  for (int q = 0; q < a.dy; ++q) nonf |= !finitef(yp[q]);
+  if (nonf) fl |= F_NONFINITE;
   if (fl) atomicOr(&a.flags[f], fl);
 }
 
@@ -791,6 +1027,9 @@ __global__ __launch_bounds__((fin_block<DX, DZ>())) void k_finalize(StepArgs a) 
   double acc[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+  // unrolled so that the loads of several particles are in flight together
+  // (same summation order as the plain loop)
+#pragma unroll 4
   for (int i = threadIdx.x; i < N; i += BS) {
     double w;
     if (PLAIN) {
@@ -817,6 +1056,12 @@ __global__ __launch_bounds__((fin_block<DX, DZ>())) void k_finalize(StepArgs a) 
       a.est_z[f * DZ + q - DX] = (float)v;
       if (a.trace_z) a.trace_z[((long long)(t - 1) * a.n_filters + f) * DZ + q - DX] = (float)v;
     }
+  }
+  // look-ahead run: whether the filter takes the next step (the weights
+  // kernel, which records it otherwise, is skipped there)
+  if (a.next_act && threadIdx.x == 0) {
+    const int lim = a.run_Tf ? min(a.run_Tf[f], a.run_T) : a.run_T;
+    a.act[f] = t < lim ? 1 : 0;
   }
 }
 
@@ -848,21 +1093,179 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
 
   const int4 tile = a.tiles[ti];
   const int f = tile.x;
-  if (!a.act[f]) return;
+  // group statistics for the wave-level ancestor draw, lane l: group l of
+  // the filter (fetched with the filter's values; the array is padded)
+  double gst[3] = {0.0, 0.0, 0.0};
+  if constexpr (SEG >= kWave) {
+    const double* gp = a.gstat + 4LL * (tile.w + (threadIdx.x & (kWave - 1)));
+    gst[0] = gp[0];
+    gst[1] = gp[1];
+    gst[2] = gp[2];
+  }
+  // the next step's horizon (look-ahead run)
+  const int tf_next = (!PLAIN && a.ell_next != nullptr && a.run_Tf != nullptr) ? a.run_Tf[f] : 0x7fffffff;
+  const FilterView fv = load_filter(a, f);
+  if (!fv.act) return;
   // learned step with accepted proposals: committed by commit_group
-  if (!PLAIN && a.fb != nullptr && a.fb[f] == 0) return;
-  const int N = a.fN[f], M = a.fM[f];
+  if (!PLAIN && fv.fb == 0) return;
+  // look-ahead run: this kernel also computes the next step's weights (Fig. 4
+  // steps 1-2 at t + 1) for the filters that take it; y_{t+1} fetched early
+  const bool fuse = !PLAIN && a.ell_next != nullptr && fv.t < min(tf_next, a.run_T);
+  float yn[DY];
+  if (!PLAIN && a.ell_next != nullptr) load_y<Mdl>(a, f, min(fv.t, a.run_T - 1) + 1, yn);
+  const int N = fv.N, M = fv.M;
   const int s = threadIdx.x / SEG;
   const int ls = threadIdx.x % SEG;
   const int k = tile.y + s;
   const bool vk = k < N;
-  const int oo = a.ooff[f];
-  const long long io = a.ioff[f];
-  const int t = a.tcur[f];  // already advanced (0 at initialisation)
-  const unsigned char cb = a.cur[f];
+  const int oo = fv.oo;
+  const long long io = fv.io;
+  const int t = fv.t;  // already advanced (0 at initialisation)
+  const unsigned char cb = (unsigned char)fv.cur;
   const int dst = copy_of(cb), src = dst ^ 1;
   const Key key = make_key(a.seed, (uint32_t)f);
 
+  // With a wave or more per outer particle, the ancestor and the candidate
+  // are single draws done by the segment's first wave with wave-wide scans.
+  // The NEW_Z / DPF_Z normals of the inner particles do not depend on them:
+  // the segment's other waves draw theirs meanwhile.
+  constexpr bool kWaveDraw = SEG >= kWave;
+  constexpr bool kEarly = SEG > kWave && JPT * DZ <= 16;
+  float nue[kEarly ? JPT : 1][DZ];
+  // One wave per outer particle: the parent's kappa inputs (lam, or ell in
+  // plain mode, and z when p(x'|x, z) depends on z) are fetched together
+  // with its ell row for the candidate draw, in the same memory round.
+  constexpr bool kPre = SEG == kWave;
+  constexpr bool kPreZ = kPre && Mdl::kXdepZ;
+  float kpre[kPre ? JPT : 1];
+  float zpre[kPreZ ? JPT : 1][kPreZ ? DZ : 1];
+#pragma unroll
+  for (int r = 0; r < (kPre ? JPT : 1); ++r) {
+    kpre[r] = 0.f;
+#pragma unroll
+    for (int d = 0; d < (kPreZ ? DZ : 1); ++d) zpre[r][d] = 0.f;
+  }
+  int p, c, pc;
+  bool deg1;
+  float xp[DX], xn[DX];
+  if constexpr (kWaveDraw) {
+    // ---- 0-2. ancestor, candidate and new x by the segment's first wave --
+    __shared__ int pc_sh[NSEG][2];
+    __shared__ float xw_sh[NSEG][DX];
+    __shared__ int d1_sh[NSEG];
+    const int G = fv.ngroup;
+    const bool resolve = a.advance && !a.anc_ready;
+    const bool blk = resolve && G > kWave;  // many groups: the whole workgroup resolves
+    if (blk) {
+      const double u = uniform53(key, (uint32_t)t, 0u, P_OUTER_U);
+      const ResResult rr = resolve_points(LogSrc{a.logw + oo}, N, N, u, tile.y, min(NSEG, N - tile.y),
+                                          a.gstat + 4LL * a.finfo[f].rg_base, G, anc_sh, rsh, tile.z == 0);
+      if (tile.z == 0 && threadIdx.x == 0) res_finish(a, f, t, N, rr);
+    }
+    int pw = 0, cw = 0, pcw = 0;
+    bool d1 = false;
+    float xpw[DX], xw[DX];
+#pragma unroll
+    for (int d = 0; d < DX; ++d) xpw[d] = xw[d] = 0.f;
+    if (ls < kWave && vk) {
+      if (blk) {
+        pw = anc_sh[s];
+      } else if (resolve) {
+        ResResult rr;
+        const double u = uniform53(key, (uint32_t)t, 0u, P_OUTER_U);
+        const bool first = tile.z == 0 && s == 0;
+        pw = resolve_point_w0(LogSrc{a.logw + oo}, N, N, u, k, gst, G, first, rr);
+        if (first && ls == 0) res_finish(a, f, t, N, rr);
+      } else {
+        pw = a.advance ? a.anc[oo + k] : k;  // identity at initialisation
+      }
+      // the parent's slot and x do not depend on the candidate: fetched first
+      pcw = (PLAIN || ident_slots(cb, src)) ? pw : a.ind[src][oo + pw];
+#pragma unroll
+      for (int d = 0; d < DX; ++d) xpw[d] = a.x[src][(long long)d * a.NT + oo + pw];
+      const float* zpw = a.z[src] + (io + (long long)pcw * M) * DZ;
+      if constexpr (kPre) {
+        const float* kr = PLAIN ? a.ell + io + (long long)pw * M : a.lam[src] + io + (long long)pcw * M;
+#pragma unroll
+        for (int r = 0; r < JPT; ++r) {
+          const int j = ls + r * SEG;
+          if (j < M) {
+            kpre[r] = kr[j];
+            if constexpr (kPreZ) {
+#pragma unroll
+              for (int d = 0; d < DZ; ++d) zpre[kPreZ ? r : 0][kPreZ ? d : 0] = zpw[d * M + j];
+            }
+          }
+        }
+      }
+      // candidate (look-ahead) / inner ancestor (plain) over the parent's ell
+      const double uc = uniform53(key, (uint32_t)t, (uint32_t)k, PLAIN ? P_DPF_ANC_U : P_CAND_U);
+      cw = select_w0<(SEG * JPT + kWave - 1) / kWave>(a.ell + io + (long long)pw * M, M, uc, d1);
+      // every lane of the wave computes the new x (same counters)
+      float zc[DZ], nu[DX];
+      if constexpr (kPreZ) {
+        // z of the candidate: held by lane cw % 64 in its slot cw / 64
+        const int rr = cw / SEG;
+#pragma unroll
+        for (int d = 0; d < DZ; ++d) {
+          float v = zpre[0][kPreZ ? d : 0];
+#pragma unroll
+          for (int r = 1; r < JPT; ++r)
+            if (rr == r) v = zpre[kPreZ ? r : 0][kPreZ ? d : 0];
+          zc[d] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), cw % SEG));
+        }
+      } else {
+#pragma unroll
+        for (int d = 0; d < DZ; ++d) zc[d] = zpw[d * M + cw];
+      }
+      if (PLAIN)
+        normals<DX>(key, (uint32_t)t, (uint32_t)k, 0u, P_DPF_X, nu);
+      else
+        normals<DX>(key, (uint32_t)t, (uint32_t)pw, (uint32_t)cw, P_LA_X, nu);
+      Mdl::fx(a.prm, xpw, zc, nu, xw);
+      if (ls == 0) {
+        if (!a.anc_ready) a.anc[oo + k] = pw;
+        a.sel[oo + k] = cw;
+#pragma unroll
+        for (int d = 0; d < DX; ++d) a.x[dst][(long long)d * a.NT + oo + k] = xw[d];
+      }
+    }
+    if constexpr (SEG == kWave) {
+      p = pw;
+      c = cw;
+      pc = pcw;
+      deg1 = d1;
+#pragma unroll
+      for (int d = 0; d < DX; ++d) {
+        xn[d] = xw[d];
+        xp[d] = xpw[d];
+      }
+    } else {
+      if (ls == 0) {
+#pragma unroll
+        for (int d = 0; d < DX; ++d) xw_sh[s][d] = xw[d];
+        pc_sh[s][0] = pw;
+        pc_sh[s][1] = cw;
+        d1_sh[s] = d1 ? 1 : 0;
+      }
+      if constexpr (kEarly) {
+#pragma unroll
+        for (int r = 0; r < JPT; ++r) {
+          const int jj = ls + r * SEG;
+          if (jj < M) normals<DZ>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, nue[r]);
+        }
+      }
+      __syncthreads();
+      p = pc_sh[s][0];
+      c = pc_sh[s][1];
+      deg1 = d1_sh[s] != 0;
+#pragma unroll
+      for (int d = 0; d < DX; ++d) xn[d] = xw_sh[s][d];
+      pc = (PLAIN || ident_slots(cb, src)) ? p : a.ind[src][oo + p];
+#pragma unroll
+      for (int d = 0; d < DX; ++d) xp[d] = a.x[src][(long long)d * a.NT + oo + p];
+    }
+  } else {
   // ---- 0. outer ancestors of this tile's new particles -------------------
   // (resolved here, also for the learned step's fallback filters)
   if (a.advance && !a.anc_ready) {
@@ -877,17 +1280,12 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
     anc_sh[threadIdx.x] = a.advance ? (kk < N ? a.anc[oo + kk] : 0) : kk;  // identity at initialisation
   }
   __syncthreads();
-  const int p = vk ? anc_sh[s] : 0;
+  p = vk ? anc_sh[s] : 0;
   if (vk && ls == 0 && !a.anc_ready) a.anc[oo + k] = p;
-  // cloud slot of the parent; the new clouds are written in slot order
-  const int pc = (PLAIN || ident_slots(cb, src)) ? p : a.ind[src][oo + p];
-  if (!PLAIN && tile.z == 0 && threadIdx.x == 0 && !ident_slots(cb, dst))
-    a.cur[f] = (unsigned char)(cb | (2 << dst));
-
-  float xp[DX];
+  pc = (PLAIN || ident_slots(cb, src)) ? p : a.ind[src][oo + p];
 #pragma unroll
   for (int d = 0; d < DX; ++d) xp[d] = a.x[src][(long long)d * a.NT + oo + p];
-  const float* zp = a.z[src] + (io + (long long)pc * M) * DZ;
+  const float* zp0 = a.z[src] + (io + (long long)pc * M) * DZ;
   const float* ep = a.ell + io + (long long)p * M;
 
   // ---- 1. selection over the parent's ell (candidate / ancestor) --------
@@ -900,7 +1298,7 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
     if (finitef(ev[r])) mloc = fmaxf(mloc, ev[r]);
   }
   const float m1 = seg_max<SEG>(mloc, sh);
-  const bool deg1 = !(m1 > -INFINITY);
+  deg1 = !(m1 > -INFINITY);
   double carry = 0.0;
 #pragma unroll
   for (int r = 0; r < JPT; ++r) {
@@ -919,42 +1317,52 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
     if (vk) a.sel[oo + k] = csel[s];
   }
   __syncthreads();
-  const int c = csel[s];
+  c = csel[s];
 
   // ---- 2. the new outer particle ----------------------------------------
   if (ls == 0) {
-    float zc[DZ], nu[DX], xn[DX];
+    float zc[DZ], nu[DX];
 #pragma unroll
-    for (int d = 0; d < DZ; ++d) zc[d] = zp[d * M + c];
+    for (int d = 0; d < DZ; ++d) zc[d] = zp0[d * M + c];
     if (PLAIN)
       normals<DX>(key, (uint32_t)t, (uint32_t)k, 0u, P_DPF_X, nu);
     else
       normals<DX>(key, (uint32_t)t, (uint32_t)p, (uint32_t)c, P_LA_X, nu);
-    Mdl::fx(a.prm, xp, zc, nu, xn);
+    float xw[DX];
+    Mdl::fx(a.prm, xp, zc, nu, xw);
 #pragma unroll
-    for (int d = 0; d < DX; ++d) xs_sh[s][d] = xn[d];
+    for (int d = 0; d < DX; ++d) xs_sh[s][d] = xw[d];
     if (vk) {
 #pragma unroll
-      for (int d = 0; d < DX; ++d) a.x[dst][(long long)d * a.NT + oo + k] = xn[d];
+      for (int d = 0; d < DX; ++d) a.x[dst][(long long)d * a.NT + oo + k] = xw[d];
     }
   }
   __syncthreads();
-  float xn[DX];
 #pragma unroll
   for (int d = 0; d < DX; ++d) xn[d] = xs_sh[s][d];
 
+  }
+  // the new clouds are written in slot order: the slots of copy dst become
+  // the identity
+  if (!PLAIN && tile.z == 0 && threadIdx.x == 0 && !ident_slots(cb, dst))
+    a.cur[f] = (unsigned char)(cb | (2 << dst));
+  const float* zp = a.z[src] + (io + (long long)pc * M) * DZ;
+  const float* ep = a.ell + io + (long long)p * M;
+  (void)c;
+
   // ---- 3. x-conditioned inner weights and local systematic resampling ---
   const float* lp = a.lam[src] + io + (long long)pc * M;
+  float ev[JPT];
   float mk = -INFINITY;
 #pragma unroll
   for (int r = 0; r < JPT; ++r) {
     const int j = ls + r * SEG;
     if (vk && j < M) {
-      float kap = PLAIN ? ev[r] : lp[j];
+      float kap = kPre ? kpre[kPre ? r : 0] : (PLAIN ? ep[j] : lp[j]);
       if (Mdl::kXdepZ) {
         float zj[DZ];
 #pragma unroll
-        for (int d = 0; d < DZ; ++d) zj[d] = zp[d * M + j];
+        for (int d = 0; d < DZ; ++d) zj[d] = kPreZ ? zpre[kPreZ ? r : 0][kPreZ ? d : 0] : zp[d * M + j];
         kap += Mdl::logpx(a.prm, xn, xp, zj);
       }
       ev[r] = kap;
@@ -965,7 +1373,7 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
   }
   const float m2 = seg_max<SEG>(mk, sh);
   const bool deg2 = !(m2 > -INFINITY);
-  carry = 0.0;
+  double carry = 0.0;
 #pragma unroll
   for (int r = 0; r < JPT; ++r) {
     const int j = ls + r * SEG;
@@ -976,7 +1384,7 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
     cdf[s][r * SEG + ls] = carry + cc;
     carry += tot;
   }
-  __syncthreads();
+  seg_lds_sync<SEG>();
   const double u_in = uniform53(key, (uint32_t)t, (uint32_t)k, P_INNER_U);
   const double tot2 = cdf[s][M - 1];
 
@@ -989,7 +1397,7 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
     Mdl::obs_pre(a.prm, y, xn, r0);
   }
   float* zdst = a.z[dst] + (io + (long long)k * M) * DZ;
-  float llv[JPT];
+  float llv[JPT], gn[JPT];
   float zkeep[kKeepZ ? JPT : 1][DZ];
   Lse acc;
 #pragma unroll
@@ -1001,7 +1409,12 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
       float zg[DZ], nu[DZ], zn[DZ];
 #pragma unroll
       for (int d = 0; d < DZ; ++d) zg[d] = zp[d * M + b];
-      normals<DZ>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, nu);
+      if constexpr (kEarly) {
+#pragma unroll
+        for (int d = 0; d < DZ; ++d) nu[d] = nue[kEarly ? r : 0][d];
+      } else {
+        normals<DZ>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, nu);
+      }
       Mdl::fz_post(a.prm, pre, zg, nu, zn);
 #pragma unroll
       for (int d = 0; d < DZ; ++d) zdst[d * M + jj] = zn[d];
@@ -1012,6 +1425,9 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
       if (!PLAIN) {
         llv[r] = Mdl::logpy_post(a.prm, r0, zn);
         acc.add(llv[r]);
+        // the next step's look-ahead likelihood of this new inner particle
+        // (ALU work that overlaps the gathers of the others)
+        if (fuse) gn[r] = la_logpy<Mdl>(a, key, t + 1, k, jj, xn, zn, yn);
       }
     }
   }
@@ -1024,13 +1440,16 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
     constexpr int NP = has_moments<Mdl>() ? 2 * DZ : DZ;
     const bool want_mom = has_moments<Mdl>() && a.mom != nullptr;
     float part[NP];
+    float lamv[JPT];
 #pragma unroll
     for (int d = 0; d < NP; ++d) part[d] = 0.f;
 #pragma unroll
     for (int r = 0; r < JPT; ++r) {
       const int jj = ls + r * SEG;
+      lamv[r] = 0.f;
       if (vk && jj < M) {
         const float lam = deg3 ? -fast_log((float)M) : (finitef(llv[r]) ? llv[r] - lse : -INFINITY);
+        lamv[r] = lam;
         ldst[jj] = lam;
         const float q = deg3 ? 1.0f / (float)M : (finitef(llv[r]) ? fast_exp(lam) : 0.f);
 #pragma unroll
@@ -1067,6 +1486,23 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
 #pragma unroll
         for (int d = 0; d < DZ; ++d) kp[d] = part[d];
       }
+    }
+    // ---- 5. look-ahead run: the next step's weights ell = lam + g, in the
+    // weights kernel's lane layout and summation order
+    if (fuse) {
+      float* en = a.ell_next + io + (long long)(vk ? k : 0) * M;
+      Lse acc2;
+#pragma unroll
+      for (int r = 0; r < JPT; ++r) {
+        const int jj = ls + r * SEG;
+        if (vk && jj < M) {
+          const float e = la_ell(lamv[r], gn[r]);
+          en[jj] = e;
+          acc2.add(e);
+        }
+      }
+      const float lw = seg_lse<SEG>(acc2, sh);
+      if (vk && ls == 0) a.logw_next[oo + k] = lw;
     }
   }
   if (vk && ls == 0 && fl) atomicOr(&a.flags[f], fl);

@@ -54,12 +54,13 @@ extern "C" const char* dpf_last_error(void) { return g_err.c_str(); }
 struct ClassShape {
   int seg, jpt;
 };
-// The first six are the defaults (the first that holds M); the last three
-// trade lanes for inner particles per lane and are chosen only by
-// dpf_set_tiling (an autotuner).
-static const ClassShape kClasses[] = {{32, 1},  {64, 1}, {128, 1}, {256, 1}, {256, 4},
-                                      {256, 16}, {32, 2}, {32, 4},  {64, 2}};
-constexpr int kNumClasses = 9;
+// The first six are the defaults (the first that holds M); the others are
+// chosen only by dpf_set_tiling (an autotuner).  For 129..256 inner particles
+// the default is one wave per outer particle with four inner particles per
+// lane, which measured faster than a 256-lane workgroup per particle.
+static const ClassShape kClasses[] = {{32, 1}, {64, 1}, {128, 1}, {64, 4},  {256, 4}, {256, 16},
+                                      {32, 2}, {32, 4}, {64, 2},  {256, 1}, {128, 2}};
+constexpr int kNumClasses = 11;
 constexpr int kNumDefaultClasses = 6;
 
 static int class_of(int M) {
@@ -181,12 +182,14 @@ static dpf_status engine_launch(int op, const StepArgs& a, const TileClass& tc, 
     case 0: launch_op<Mdl, 32, 1>(op, a, n, s); break;
     case 1: launch_op<Mdl, 64, 1>(op, a, n, s); break;
     case 2: launch_op<Mdl, 128, 1>(op, a, n, s); break;
-    case 3: launch_op<Mdl, 256, 1>(op, a, n, s); break;
+    case 3: launch_op<Mdl, 64, 4>(op, a, n, s); break;
     case 4: launch_op<Mdl, 256, 4>(op, a, n, s); break;
     case 5: launch_op<Mdl, 256, 16>(op, a, n, s); break;
     case 6: launch_op<Mdl, 32, 2>(op, a, n, s); break;
     case 7: launch_op<Mdl, 32, 4>(op, a, n, s); break;
     case 8: launch_op<Mdl, 64, 2>(op, a, n, s); break;
+    case 9: launch_op<Mdl, 256, 1>(op, a, n, s); break;
+    case 10: launch_op<Mdl, 128, 2>(op, a, n, s); break;
     default: return fail(DPF_EUNSUPPORTED, "no kernel class %d", tc.cls);
   }
   LAUNCH_CHECK("step kernel");
@@ -271,6 +274,8 @@ struct Layout {
       logw, anc, sel, kpart, gstat, fstat, ess, dlogz, loglik, flags, est_x, est_z;
   // slot indirection and learned-proposal buffers
   size_t ind0, ind1, mom, mlp, mdn, xtmp, logq, kpart_tmp, mom_tmp, fb, lflags;
+  // second weight buffers: a look-ahead run alternates between the two
+  size_t ell1, logw1;
   int NT = 0;
   long long NMT = 0;
   int n_tiles = 0, n_rgroups = 0;
@@ -335,10 +340,14 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   L.l1 = carve(cur, NMT * 4);
   L.ell = carve(cur, NMT * 4);
   L.logw = carve(cur, NT * 4);
+  L.ell1 = carve(cur, NMT * 4);
+  L.logw1 = carve(cur, NT * 4);
   L.anc = carve(cur, NT * 4);
   L.sel = carve(cur, NT * 4);
   L.kpart = carve(cur, NT * dz * 4);
-  L.gstat = carve(cur, (size_t)L.n_rgroups * 4 * 8);
+  // (a wave reads the statistics of 64 groups from the filter's first on,
+  // whatever the filter's count: padded so those reads stay inside)
+  L.gstat = carve(cur, ((size_t)L.n_rgroups + kWave) * 4 * 8);
   L.fstat = carve(cur, F * 4 * 8);
   L.ess = carve(cur, F * 4);
   L.dlogz = carve(cur, F * 8);
@@ -392,6 +401,9 @@ struct dpf_handle {
   bool has_proposal = false;  // a network blob was set
   bool mom_valid = false;     // mom holds the moments of the current state
   double ess_frac = 0.1;
+  // which weight buffers (0: ell/logw, 1: ell1/logw1) hold the weights of
+  // the last step taken
+  int ell_sel = 0;
 };
 
 constexpr int kPhaseEvents = 5;
@@ -619,7 +631,8 @@ static dpf_status build_tiles(dpf_handle* h) {
   for (int f = 0; f < F; ++f) {
     const int segs = kBlock / kClasses[h->fcls[f]].seg;
     int nt = 0;
-    for (int i0 = 0; i0 < h->N[f]; i0 += segs) by[h->fcls[f]].push_back(make_int4(f, i0, nt++, 0));
+    for (int i0 = 0; i0 < h->N[f]; i0 += segs)
+      by[h->fcls[f]].push_back(make_int4(f, i0, nt++, h->finfo_h[f].rg_base));
   }
   h->tiles_h.clear();
   h->classes.clear();
@@ -678,8 +691,14 @@ extern "C" dpf_status dpf_destroy(dpf_handle* h) {
   return DPF_OK;
 }
 
+// fuse (look-ahead runs only): 0 a plain step; 1 the first step of a run,
+// whose new-cloud kernel also computes the next step's weights; 2 a later
+// step of the run, whose weights the previous step computed (no weights
+// kernel).  par: the weight buffers this step reads (the next step's go to
+// the other pair).
 static dpf_status queue_step(dpf_handle* h, const float* Y, long long y_tstride, const unsigned char* active,
-                             const int* run_Tf, int run_T, float* trace_x, float* trace_z) {
+                             const int* run_Tf, int run_T, float* trace_x, float* trace_z, int fuse = 0,
+                             int par = 0) {
   StepArgs a = make_args(h);
   a.Y = Y;
   a.y_tstride = y_tstride;
@@ -690,8 +709,18 @@ static dpf_status queue_step(dpf_handle* h, const float* Y, long long y_tstride,
   a.trace_z = trace_z;
   a.advance = 1;
   const bool plain = h->algo == DPF_ALGO_PLAIN;
+  if (fuse) {
+    float* e[2] = {at<float>(h, h->L.ell), at<float>(h, h->L.ell1)};
+    float* w[2] = {at<float>(h, h->L.logw), at<float>(h, h->L.logw1)};
+    a.ell = e[par];
+    a.logw = w[par];
+    a.ell_next = e[par ^ 1];
+    a.logw_next = w[par ^ 1];
+    a.next_act = 1;
+  }
+  h->ell_sel = fuse ? par : 0;
   dpf_status s = phase_mark(h, 0);
-  if (s == DPF_OK) s = launch_classes(h, plain ? OP_DPF_WEIGHTS : OP_LA_WEIGHTS, a);
+  if (s == DPF_OK && fuse != 2) s = launch_classes(h, plain ? OP_DPF_WEIGHTS : OP_LA_WEIGHTS, a);
   if (s == DPF_OK) s = phase_mark(h, 1);
   if (s == DPF_OK) {
     hipLaunchKernelGGL(k_res_stats, dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a,
@@ -728,6 +757,7 @@ static dpf_status queue_learned_step(dpf_handle* h, const float* Y, long long y_
   dpf_status s = DPF_OK;
   if (!h->mom_valid && !mdn_given) s = queue_moments(h, nullptr, nullptr);
   if (s != DPF_OK) return s;
+  h->ell_sel = 0;
   StepArgs a = make_args(h);
   a.Y = Y;
   a.y_tstride = y_tstride;
@@ -852,17 +882,24 @@ extern "C" dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean
   return DPF_OK;
 }
 
+// Step q (0-based) of a run; look-ahead runs fuse the weights of each step
+// into the previous step's new-cloud kernel.
 static dpf_status queue_run_step(dpf_handle* h, int mode, const float* d_Y, int T, const int32_t* d_Tf,
-                                 float* xt, float* zt) {
+                                 float* xt, float* zt, int q) {
   const long long stride = (long long)h->F * h->dy;
   if (mode == 1) return queue_learned_step(h, d_Y, stride, nullptr, (const int*)d_Tf, T, xt, zt, nullptr);
+  if (h->algo == DPF_ALGO_LOOKAHEAD && T > 1)
+    return queue_step(h, d_Y, stride, nullptr, (const int*)d_Tf, T, xt, zt, q == 0 ? 1 : 2, q & 1);
   return queue_step(h, d_Y, stride, nullptr, (const int*)d_Tf, T, xt, zt);
 }
 
 // T steps of mode 0 (the handle's algorithm) or 1 (learned), eagerly or as
 // replays of a captured chunk of kGraphChunk steps (every step reads the
 // per-filter time and state copy from device memory, so one capture serves
-// every chunk); the T % kGraphChunk remaining steps run eagerly.
+// every chunk); the steps the chunks do not cover run eagerly.  The first
+// step always runs eagerly (in a look-ahead run it is the only one with a
+// weights kernel); kGraphChunk is even, so the chunks see the same
+// alternation of weight buffers.
 constexpr int kGraphChunk = 16;
 
 static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T, const int32_t* d_Tf,
@@ -877,12 +914,16 @@ static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T
   }
   if (!use_graph) {
     for (int s = 0; s < T; ++s) {
-      dpf_status st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace);
+      dpf_status st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace, s);
       if (st != DPF_OK) return st;
     }
     return DPF_OK;
   }
-  const int S = T < kGraphChunk ? T : kGraphChunk;
+  {
+    dpf_status st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace, 0);
+    if (st != DPF_OK || T == 1) return st;
+  }
+  const int S = T - 1 < kGraphChunk ? T - 1 : kGraphChunk;
   const void* key[6] = {d_Y, d_Tf, d_xtrace, d_ztrace, (const void*)h->stream, (const void*)(intptr_t)mode};
   const bool cached = h->gexec && h->g_T == T && memcmp(key, h->g_key, sizeof(key)) == 0;
   if (!cached) {
@@ -896,8 +937,8 @@ static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
     dpf_status st = DPF_OK;
-    for (int q = 0; e == hipSuccess && st == DPF_OK && q < S; ++q)
-      st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace);
+    for (int q = 1; e == hipSuccess && st == DPF_OK && q <= S; ++q)
+      st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace, q);
     hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
     h->stream = user;
     if (e != hipSuccess) return fail(DPF_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
@@ -915,11 +956,14 @@ static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T
     memcpy(h->g_key, key, sizeof(key));
     h->g_T = T;
   }
-  for (int s = 0; s + S <= T; s += S) HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
-  for (int s = (T / S) * S; s < T; ++s) {
-    dpf_status st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace);
+  int q = 1;
+  for (; q + S <= T; q += S) HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
+  for (; q < T; ++q) {
+    dpf_status st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace, q);
     if (st != DPF_OK) return st;
   }
+  // (the captured steps do not update the host's record of the buffers)
+  if (mode == 0 && h->algo == DPF_ALGO_LOOKAHEAD) h->ell_sel = (T - 1) & 1;
   return DPF_OK;
 }
 
@@ -1009,8 +1053,8 @@ extern "C" dpf_status dpf_copy_buffer(dpf_handle* h, int32_t which, void* d_dst,
   if (!h || !d_dst) return fail(DPF_EINVAL, "handle and destination are required");
   size_t off = 0, need = 0;
   switch (which) {
-    case DPF_BUF_ELL: off = h->L.ell; need = (size_t)h->L.NMT * 4; break;
-    case DPF_BUF_LOGW: off = h->L.logw; need = (size_t)h->L.NT * 4; break;
+    case DPF_BUF_ELL: off = h->ell_sel ? h->L.ell1 : h->L.ell; need = (size_t)h->L.NMT * 4; break;
+    case DPF_BUF_LOGW: off = h->ell_sel ? h->L.logw1 : h->L.logw; need = (size_t)h->L.NT * 4; break;
     case DPF_BUF_ANC: off = h->L.anc; need = (size_t)h->L.NT * 4; break;
     case DPF_BUF_SEL: off = h->L.sel; need = (size_t)h->L.NT * 4; break;
     case DPF_BUF_MDN: off = h->L.mdn; need = (size_t)h->L.NT * kMlpOut * 4; break;
@@ -1092,7 +1136,7 @@ extern "C" dpf_status dpf_segmented_systematic(const double* d_w, int32_t S, int
     case 0: hipLaunchKernelGGL((k_seg_systematic_prim<32, 1>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
     case 1: hipLaunchKernelGGL((k_seg_systematic_prim<64, 1>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
     case 2: hipLaunchKernelGGL((k_seg_systematic_prim<128, 1>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
-    case 3: hipLaunchKernelGGL((k_seg_systematic_prim<256, 1>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
+    case 3: hipLaunchKernelGGL((k_seg_systematic_prim<64, 4>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
     case 4: hipLaunchKernelGGL((k_seg_systematic_prim<256, 4>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
     case 5: hipLaunchKernelGGL((k_seg_systematic_prim<256, 16>), g, dim3(kBlock), 0, s, d_w, S, n, n_out, d_u, (int*)d_out); break;
   }

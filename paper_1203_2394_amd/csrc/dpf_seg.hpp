@@ -48,6 +48,20 @@ __device__ __forceinline__ T seg_reduce(T v, T* red /* [kBlock / kWave] */) {
   return v;
 }
 
+// Orders a segment's LDS writes before its reads: a workgroup barrier when
+// the segment spans waves, else a wave-level fence (segments in one wave do
+// not wait for the other waves of the workgroup).
+template <int SEG>
+__device__ __forceinline__ void seg_lds_sync() {
+  if constexpr (SEG > kWave) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 template <int SEG>
 __device__ __forceinline__ float seg_max(float v, SegScratch& sh) {
   return seg_reduce<OpMax, SEG>(v, sh.f[0]);

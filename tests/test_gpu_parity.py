@@ -6,6 +6,9 @@ same FP32 state with the same Philox streams; the GPU's new state and
 intermediate buffers are compared with the oracle's (tests/parity_util.py).
 Sizes span several tiles with ragged tails in N and M.
 """
+import copy
+import functools
+
 import numpy as np
 import pytest
 
@@ -159,27 +162,46 @@ def test_initialisation_matches_oracle_prior(algo):
         assert np.max(err) < 1e-4
 
 
-@pytest.mark.parametrize("cls,M", [(6, 50), (7, 128), (8, 100), (8, 64), (3, 40), (2, 7)])
-@pytest.mark.parametrize("algo", ["lookahead", "plain"])
-def test_step_parity_under_every_tiling(cls, M, algo):
-    """The same step under a non-default tile class (SEG, JPT) matches the oracle."""
-    spec = SPECS["nonlin"]()
+def _tiling_start(name, algo, N, M, seed):
+    """The oracle's state after one step (shared by the classes of a size)."""
+    return copy.deepcopy(_tiling_start_cached(name, algo, N, M, seed))
+
+
+@functools.lru_cache(maxsize=32)
+def _tiling_start_cached(name, algo, N, M, seed):
+    spec = SPECS[name]()
     model = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
-    N, seed = 150, 515
+    _, _, ys = S.simulate(spec, 3, 9)
+    ys = ys.astype(np.float32).astype(np.float64)
+    mod = ladpf if algo == "lookahead" else odpf
+    st = mod.init_state(model, N, M, seed, 0)
+    st, _ = mod.step(model, st, ys[0], seed, 0)
+    return to_state32(st)
+
+
+@pytest.mark.parametrize("name,cls,M,N", [
+    ("nonlin", 6, 50, 150), ("nonlin", 7, 128, 150), ("nonlin", 8, 100, 150), ("nonlin", 8, 64, 150),
+    ("nonlin", 3, 40, 150), ("nonlin", 2, 7, 150), ("nonlin", 9, 256, 150), ("nonlin", 9, 130, 150),
+    ("nonlin", 10, 200, 150), ("nonlin", 10, 256, 150),
+    ("lingauss_coupled", 9, 200, 90), ("lingauss_coupled", 10, 150, 90), ("lingauss_coupled", 3, 100, 90),
+    ("nonlin", 9, 8, 16700), ("nonlin", 3, 8, 16700), ("nonlin", 0, 8, 16700)])
+@pytest.mark.parametrize("algo", ["lookahead", "plain"])
+def test_step_parity_under_every_tiling(name, cls, M, N, algo):
+    """The same step under a non-default tile class (SEG, JPT) matches the
+    oracle (lingauss_coupled: p(x'|x, z) depends on z); N = 16700 gives 66
+    groups of 256 outer weights (more than one wave resolves alone)."""
+    spec = SPECS[name]()
+    model = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
+    seed = 515
     _, _, ys = S.simulate(spec, 3, 9)
     ys = ys.astype(np.float32).astype(np.float64)
     f = _gpu_filter(spec, N, M, seed, algo)
     f.set_tiling([cls])
+    st32 = _tiling_start(name, algo, N, M, seed)
     if algo == "lookahead":
-        st = ladpf.init_state(model, N, M, seed, 0)
-        st, _ = ladpf.step(model, st, ys[0], seed, 0)
-        st32 = to_state32(st)
         f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["x"], st32["z"], st32["lam"])))
         f.lookahead_step(torch.tensor(ys[1], dtype=torch.float32))
     else:
-        st = odpf.init_state(model, N, M, seed, 0)
-        st, _ = odpf.step(model, st, ys[0], seed, 0)
-        st32 = to_state32(st)
         f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["xt"], st32["zt"], np.zeros((N, M)))))
         f.step(torch.tensor(ys[1], dtype=torch.float32))
     g = f.unpack_state(f.export_state())
@@ -193,7 +215,7 @@ def test_step_parity_under_every_tiling(cls, M, algo):
     else:
         gs = {"x": g["x"][0], "z": g["z"][0]}
         r, _, _ = compare_plain(model, st32, ys[1], seed, 0, gs, ell, logw, anc, sel)
-    print("%s class %d M=%d: %s" % (algo, cls, M, r.line()), flush=True)
+    print("%s %s class %d N=%d M=%d: %s" % (name, algo, cls, N, M, r.line()), flush=True)
     assert_clean(r, n=N)
 
 

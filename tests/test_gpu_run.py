@@ -77,9 +77,20 @@ def test_graph_run_equals_step_calls_bit_for_bit():
     assert np.array_equal(sa, sb)
     assert torch.equal(ea["xhat"], eb["xhat"]) and torch.equal(ea["loglik"], eb["loglik"])
     assert torch.equal(xt[-1], eb["xhat"])
+    # a look-ahead run computes each step's weights in the previous step's
+    # new-cloud kernel: the last step's weights must be the step calls' ones
+    for buf in (dpf.BUF_ELL, dpf.BUF_LOGW, dpf.BUF_ANC, dpf.BUF_SEL):
+        assert torch.equal(a.copy_buffer(buf), b.copy_buffer(buf)), buf
     c = _filter(spec, N, M)
     c.run(torch.from_numpy(Y), use_graph=False)
     assert np.array_equal(sa, c.export_state().cpu().numpy())
+    for buf in (dpf.BUF_ELL, dpf.BUF_LOGW):
+        assert torch.equal(a.copy_buffer(buf), c.copy_buffer(buf)), buf
+    # and a step call after a run continues from the same state
+    a.lookahead_step(torch.from_numpy(Y[T - 1]))
+    b.lookahead_step(torch.from_numpy(Y[T - 1]))
+    assert np.array_equal(a.export_state().cpu().numpy(), b.export_state().cpu().numpy())
+    assert torch.equal(a.copy_buffer(dpf.BUF_ELL), b.copy_buffer(dpf.BUF_ELL))
 
 
 def test_per_filter_horizons_and_resume():
