@@ -10,13 +10,19 @@ resampling, new particles, inner resampling, propagation, inner measurement
 update, estimates) with the observations already resident in HBM; the K
 timed steps run as replays of a captured 16-step HIP graph (dpf_run).
 
+In a run the new-cloud kernel of each step also computes the next step's
+look-ahead weights, and a step-end kernel takes the estimates and prepares
+the next step's resampling, so a step after the first is two kernels.
+
 Prints one JSON line: inner-particle updates/s over the K timed steps, the
 RMSE of the x estimate against the simulated truth, the roofline of the
-dominant kernel (algorithmic bytes per launch over its average duration,
-timed with HIP events recorded by the library on its own stream), the FP64
-oracle timed on a bounded sample on the host, and the learned proposal
-(trained on look-ahead pairs, then run at the same N and M): its updates/s
-and RMSE beside the look-ahead step's on the same fresh sequences.
+dominant kernel (the new-cloud kernel of a run, timed with HIP events that
+the library records on its own stream around its launches; it is bound by
+vector-ALU issue, so the roofline counts its algorithmic VALU issue slots
+per launch, with the algorithmic-bytes view beside it), the FP64 oracle
+timed on a bounded sample on the host, and the learned proposal (trained on
+look-ahead pairs, then run at the same N and M): its updates/s and RMSE
+beside the look-ahead step's on the same fresh sequences.
 """
 import argparse
 import hashlib
@@ -42,15 +48,46 @@ BATCH_F, BATCH_SEED = 1024, 7
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_nonlin_N4096_M256.txt")
 KERNEL_SOURCES = ["dpf_kernels.hpp", "dpf_models.hpp", "dpf_rng.hpp", "dpf_seg.hpp"]
 
-# Algorithmic bytes per inner particle of each phase (FP32 state, dz = DZ):
-#   weights:   read z (4 dz) + lam (4), write ell (4)
-#   new cloud: read parent ell (4) + lam (4) + gathered z (4 dz),
-#              write z (4 dz) + lam (4)
-BYTES_PER_UPDATE = {"weights": 4 * DZ + 8, "newcloud": 8 * DZ + 12}
-# and per outer particle: weights reads x (4 dx) writes log w (4);
-# new cloud reads the ancestor (4) and the parent x (4 dx), writes x (4 dx),
-# the selected index (4) and the cloud's partial sum (4 dz).
-BYTES_PER_OUTER = {"weights": 4 * DX + 4, "newcloud": 8 + 8 * DX + 4 * DZ}
+# Algorithmic bytes per inner particle of the new-cloud kernel of a run
+# (FP32 state, dz = DZ): read the parent's ell (4) and lam (4) and the
+# gathered z (4 dz); write z (4 dz), lam (4) and the next step's ell (4).
+BYTES_PER_UPDATE = 8 * DZ + 16
+# and per outer particle: read the ancestor's weight group (4) and x (4 dx);
+# write x (4 dx), the ancestor and candidate (8), the cloud's partial sum
+# (4 dz) and the next log-weight (4).
+BYTES_PER_OUTER = 4 + 8 * DX + 8 + 4 * DZ + 4
+
+# Algorithmic VALU issue slots per inner particle of the same kernel (one
+# slot: one 32-bit lane operation; 32x32->64 products and transcendentals
+# issue at quarter rate on CDNA and count 4).  A Philox4x32-10 block is ten
+# rounds of two products and four exclusive ors; a U24 uniform is shift,
+# convert, FMA; a Box-Muller pair is log, sqrt, cos, sin and three products.
+PHILOX_BLOCK = 10 * (2 * 4 + 4)
+BM_PAIR = 4 * 4 + 3
+
+
+def normals_slots(n):
+    """Issue slots for n standard normals (Philox blocks of four words)."""
+    return ((n + 3) // 4) * PHILOX_BLOCK + n * 3 + (n // 2) * BM_PAIR
+
+
+ISSUE_PER_UPDATE = {
+    # this step: NEW_Z normals, f^z (two FMAs per component), log p(y|z)
+    # (subtract and FMA per component), the inner resampling search (eight
+    # FP64 compare-and-select steps), eq:qbar and the weighted moments
+    "new_z": normals_slots(DZ),
+    "propagate_and_weigh": 2 * DZ + 2 * DY + 2 + 8 * 3 + 4 + 2 + 3 * DZ,
+    # the next step's look-ahead weight: LA_X and LA_Z normals, f^x (growth
+    # term: two products, add, reciprocal, FMAs), f^z's tanh(W x) (two FMAs,
+    # exp and reciprocal, three more), f^z, the observation residual and
+    # log p(y|x, z), ell = lam + that, and the running log-sum-exp
+    "la_normals": normals_slots(DX) + normals_slots(DZ),
+    "la_model": DX * 10 + DZ * (2 * DX + 2 * 4 + 4) + 2 * DZ + DY + 2 * DY + 2 + 1 + 4 + 4,
+}
+VALU_SLOTS_PER_UPDATE = sum(ISSUE_PER_UPDATE.values())
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one lane slot per lane per clock
+# (wave64 instructions take four clocks; packed FP32 is not used).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def kernel_source_digest():
@@ -183,19 +220,21 @@ def main():
     torch.cuda.synchronize()
     edt = time.perf_counter() - e0
 
-    # phase times: events recorded by the library between its launches
+    # phase times of the same run executed eagerly: events the library
+    # records on its stream between its launches (steps after the first:
+    # the weights and statistics phases are empty there)
     f.reset()
     events = [torch.cuda.Event(enable_timing=True) for _ in range(5 * K)]
     f.set_phase_events(events)
-    for t in range(K):
-        assert L.dpf_lookahead_step(h, yptr[t], None) == 0
+    f.run(Yk, trace=False, use_graph=False)
     torch.cuda.synchronize()
     f.set_phase_events(None)
     phases = ["weights", "resample", "newcloud", "estimate"]
     ph_ms = {p: 0.0 for p in phases}
-    for s in range(K):
+    for s in range(1, K):
         for i, p in enumerate(phases):
-            ph_ms[p] += events[5 * s + i].elapsed_time(events[5 * s + i + 1]) / K
+            ph_ms[p] += events[5 * s + i].elapsed_time(events[5 * s + i + 1]) / (K - 1)
+    first_ms = {p: round(events[i].elapsed_time(events[i + 1]), 5) for i, p in enumerate(phases)}
 
     if args.copy_mb:
         n = args.copy_mb * (1 << 20) // 4
@@ -205,14 +244,20 @@ def main():
         dst_t.copy_(src_t)
         torch.cuda.synchronize()
 
-    dom = max(("weights", "newcloud"), key=lambda p: ph_ms[p])
-    bytes_launch = updates * BYTES_PER_UPDATE[dom] + N_OUT * BYTES_PER_OUTER[dom]
-    achieved = bytes_launch / (ph_ms[dom] * 1e-3) / 1e9
-    traffic = read_traffic(dom)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_newcloud" if dom == "newcloud" else "k_la_weights",
-                "bytes_per_launch": bytes_launch, "avg_ms": round(ph_ms[dom], 5)}
+    dur = ph_ms["newcloud"] * 1e-3
+    slots_launch = updates * VALU_SLOTS_PER_UPDATE
+    achieved = slots_launch / dur / 1e12
+    bytes_launch = updates * BYTES_PER_UPDATE + N_OUT * BYTES_PER_OUTER
+    gbs = bytes_launch / dur / 1e9
+    roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(VALU_PEAK_TOPS, 2),
+                "unit": "Tops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                "traffic": read_traffic("newcloud"),
+                "kernel": "k_newcloud (run: also the next step's look-ahead weights)",
+                "op": "32-bit VALU lane issue slot (quarter-rate instructions count 4)",
+                "slots_per_update": VALU_SLOTS_PER_UPDATE, "slots_per_launch": slots_launch,
+                "avg_ms": round(ph_ms["newcloud"], 5),
+                "hbm_view": {"bytes_per_launch": bytes_launch, "achieved_gbs": round(gbs, 1),
+                             "peak_gbs": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}}
     f.close()
 
     learned = None if args.no_learned else run_learned(S, dpf, torch, np, dev, K, W)
@@ -237,6 +282,7 @@ def main():
                    "rmse_x_T200": round(rmse_x, 4)},
         "eager_value": updates * K / edt,
         "phase_ms": {p: round(v, 5) for p, v in ph_ms.items()},
+        "first_step_phase_ms": first_ms,
         "roofline": roofline,
         "learned": learned,
         "batched": batched,

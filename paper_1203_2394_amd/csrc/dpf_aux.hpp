@@ -13,10 +13,11 @@ namespace dpf {
 // t = 0, state in copy 0 (the plain DPF's initial proposals are written
 // there from the prior held in copy 1), flags and evidence cleared.
 __global__ void k_reset(int* tcur, unsigned char* cur, unsigned char* act, uint32_t* flags, double* loglik,
-                        uint32_t* lflags, int F) {
+                        uint32_t* lflags, int* fcount, int F) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
   tcur[f] = 0;
+  fcount[f] = 0;
   cur[f] = 6;  // copy 0; identity cloud slots in both copies
   act[f] = 1;
   flags[f] = 0u;

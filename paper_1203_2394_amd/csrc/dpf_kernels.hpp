@@ -118,7 +118,8 @@ struct StepArgs {
   // estimates kernel records which filters take the next step
   float* ell_next;
   float* logw_next;
-  int next_act;
+  double* gpart;  // [resampling groups][DX + DZ] partial sums of the estimates
+  int* fcount;    // [F] workgroups of the step-end kernel done (back to 0 by the last)
 };
 
 __device__ __forceinline__ int copy_of(unsigned char c) { return c & 1; }
@@ -627,6 +628,17 @@ __device__ void res_group_stat(const Src& src, int n, int g, float& mg, double& 
   qg = block_sum_256(v * v, sh.red4);
 }
 
+// The same from this thread's log-weight lw already loaded (valid: i < n),
+// with the same arithmetic as for LogSrc.
+__device__ __forceinline__ void res_group_stat_lw(float lw, bool valid, float& mg, double& sg, double& qg,
+                                                  ResScratch& sh) {
+  const float key = valid && finitef(lw) ? lw : -INFINITY;
+  mg = block_max_256(key, sh.fred4);
+  const double v = (valid && mg > -INFINITY) ? (finitef(lw) ? (double)fast_exp(lw - mg) : 0.0) : 0.0;
+  sg = block_sum_256(v, sh.red4);
+  qg = block_sum_256(v * v, sh.red4);
+}
+
 struct ResResult {
   float m;       // max log-weight (0 for linear weights or when degenerate)
   double total;  // sum of the weights exp(log w - m)
@@ -999,8 +1011,8 @@ __device__ void commit_group(const StepArgs& a, int b) {
 
 // ---------------------------------------------------------------- estimates
 // One workgroup per filter, FP64 sums in a fixed order (strided per thread,
-// then DPP and the wave results in order), so results are reproducible:
-//   look-ahead: xhat = mean_k x_t^(k), zhat = mean_k sum_j qbar z  (new copy)
+// then DPP and the wave results in order), so results are reproducible.
+// Used by the plain DPF (the look-ahead steps end with k_post):
 //   plain:      xhat = sum_i Wbar_i xt_i, zhat = sum_i Wbar_i sum_j qbar z
 //               over the proposals weighted at this step (previous copy)
 template <int DX, int DZ>
@@ -1057,11 +1069,103 @@ __global__ __launch_bounds__((fin_block<DX, DZ>())) void k_finalize(StepArgs a) 
       if (a.trace_z) a.trace_z[((long long)(t - 1) * a.n_filters + f) * DZ + q - DX] = (float)v;
     }
   }
-  // look-ahead run: whether the filter takes the next step (the weights
-  // kernel, which records it otherwise, is skipped there)
-  if (a.next_act && threadIdx.x == 0) {
-    const int lim = a.run_Tf ? min(a.run_Tf[f], a.run_T) : a.run_T;
-    a.act[f] = t < lim ? 1 : 0;
+}
+
+// ------------------------------------------------------- look-ahead step end
+// One workgroup per resampling group of every filter (the grid of
+// k_res_stats):
+//  * the estimates of the step just taken, xhat = mean_k x_t^(k) and zhat =
+//    mean_k sum_j qbar z (eq:qbar), as per-group FP64 partial sums (wave
+//    sums, then the four waves in order) that the filter's last workgroup
+//    adds up in group order -- the same order in every path, so results
+//    do not depend on how the steps were launched;
+//  * in a look-ahead run (next = 1), whose new-cloud kernel has already
+//    computed the next step's outer log-weights: what k_res_stats does
+//    before an ordinary step -- the group statistics of those weights,
+//    the non-finite check, and (last workgroup) the time advance -- plus
+//    the filter's activity for the next step.
+// The last workgroup of a filter is found with a counter it resets.
+template <int DX, int DZ>
+__global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* rgroups, int next) {
+  constexpr int NV = DX + DZ;
+  __shared__ ResScratch sh;
+  __shared__ double part[kBlock / kWave][NV];
+  __shared__ int last;
+  const int2 rg = rgroups[blockIdx.x];
+  const int f = rg.x, g = rg.y;
+  const int tf = (next && a.run_Tf != nullptr) ? a.run_Tf[f] : 0x7fffffff;
+  const int rb = a.finfo[f].rg_base;
+  asm volatile("" ::"v"(tf), "v"(rb));
+  const FilterView fv = load_filter(a, f);
+  if (!fv.act) return;
+  const int N = fv.N, oo = fv.oo;
+  const int t = fv.t;  // the step just taken
+  const unsigned char cb = (unsigned char)fv.cur;
+  const float* xs = a.x[copy_of(cb)];
+  const int i = g * kResGroup + threadIdx.x;
+  const double w = 1.0 / N;
+  // loads at a clamped index, masked afterwards (a load guarded by i < N
+  // would wait inside its own branch: one memory round per value)
+  const int ic = min(i, N - 1);
+  const bool act_next = next && t < min(tf, a.run_T);
+  float raw[NV];
+#pragma unroll
+  for (int d = 0; d < DX; ++d) raw[d] = xs[(long long)d * a.NT + oo + ic];
+#pragma unroll
+  for (int d = 0; d < DZ; ++d) raw[DX + d] = a.kpart[(long long)(oo + ic) * DZ + d];
+  const float lwn = act_next ? a.logw_next[oo + ic] : 0.f;
+  double v[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = i < N ? w * (double)raw[q] : 0.0;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    const double r = seg_reduce_wave<OpAdd, kWave>(v[q]);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave][q] = r;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < NV; q += kBlock)
+    a.gpart[(long long)(rb + g) * NV + q] = ((part[0][q] + part[1][q]) + part[2][q]) + part[3][q];
+  if (act_next) {
+    float mg;
+    double sg, qg;
+    res_group_stat_lw(lwn, i < N, mg, sg, qg, sh);
+    const float lv = i < N ? lwn : 0.f;
+    const int nonf = __syncthreads_or((!finitef(lv) && !(lv == -INFINITY)) ? 1 : 0);
+    if (threadIdx.x == 0) {
+      double* gs = a.gstat + 4LL * (rb + g);
+      gs[0] = (double)mg;
+      gs[1] = sg;
+      gs[2] = qg;
+      if (nonf) atomicOr(&a.flags[f], (uint32_t)F_NONFINITE);
+    }
+  }
+  __threadfence();
+  if (threadIdx.x == 0) last = atomicAdd(&a.fcount[f], 1) == fv.ngroup - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int q = threadIdx.x; q < NV; q += kBlock) {
+    double e = 0.0;
+    // (unrolled: the loads of several groups in flight, added in order)
+#pragma unroll 16
+    for (int gg = 0; gg < fv.ngroup; ++gg) e += a.gpart[(long long)(rb + gg) * NV + q];
+    if (q < DX) {
+      a.est_x[f * DX + q] = (float)e;
+      if (a.trace_x) a.trace_x[((long long)(t - 1) * a.n_filters + f) * DX + q] = (float)e;
+    } else {
+      a.est_z[f * DZ + q - DX] = (float)e;
+      if (a.trace_z) a.trace_z[((long long)(t - 1) * a.n_filters + f) * DZ + q - DX] = (float)e;
+    }
+  }
+  if (threadIdx.x == 0) {
+    a.fcount[f] = 0;
+    if (next) {
+      a.act[f] = act_next ? 1 : 0;
+      if (act_next) {
+        a.tcur[f] = t + 1;
+        a.cur[f] = (unsigned char)(cb ^ 1);
+      }
+    }
   }
 }
 

@@ -21,7 +21,7 @@
 //   k_newcloud_fallback    head workgroups: resample and commit the accepted
 //                          filters; the rest: look-ahead new clouds of the
 //                          filters that fell back
-//   k_finalize             estimates
+//   k_post                 estimates
 // Accepted particles are not copied: particle i's new cloud is written to
 // its own slot of the next state copy and the resampled particle k refers to
 // slot A_k through ind (lazy resampling); x and the per-particle moments are

@@ -276,6 +276,8 @@ struct Layout {
   size_t ind0, ind1, mom, mlp, mdn, xtmp, logq, kpart_tmp, mom_tmp, fb, lflags;
   // second weight buffers: a look-ahead run alternates between the two
   size_t ell1, logw1;
+  // step-end kernel: per-group partial estimates, per-filter counters
+  size_t gpart, fcount;
   int NT = 0;
   long long NMT = 0;
   int n_tiles = 0, n_rgroups = 0;
@@ -366,6 +368,8 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   L.mom_tmp = carve(cur, NT * 2 * dz * 4);
   L.fb = carve(cur, F);
   L.lflags = carve(cur, F * 4);
+  L.gpart = carve(cur, (size_t)L.n_rgroups * (dx + dz) * 8);
+  L.fcount = carve(cur, F * 4);
   L.total = cur;
   return DPF_OK;
 }
@@ -475,6 +479,8 @@ static StepArgs make_args(dpf_handle* h) {
   a.fb = nullptr;
   a.lflags = at<uint32_t>(h, h->L.lflags);
   a.ess_frac = h->ess_frac;
+  a.gpart = at<double>(h, h->L.gpart);
+  a.fcount = at<int>(h, h->L.fcount);
   return a;
 }
 
@@ -498,15 +504,11 @@ constexpr int kGatedGrid = 512;
 
 static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a) {
   const int F = h->F;
-  const bool plain = h->algo == DPF_ALGO_PLAIN;
-#define FIN(DX, DZ)                                                                                         \
-  if (h->dx == DX && h->dz == DZ) {                                                                         \
-    if (plain)                                                                                              \
-      hipLaunchKernelGGL((k_finalize<DX, DZ, true>), dim3(F), dim3(fin_block<DX, DZ>()), 0, h->stream, a);  \
-    else                                                                                                    \
-      hipLaunchKernelGGL((k_finalize<DX, DZ, false>), dim3(F), dim3(fin_block<DX, DZ>()), 0, h->stream, a); \
-    LAUNCH_CHECK("k_finalize");                                                                             \
-    return DPF_OK;                                                                                          \
+#define FIN(DX, DZ)                                                                                       \
+  if (h->dx == DX && h->dz == DZ) {                                                                       \
+    hipLaunchKernelGGL((k_finalize<DX, DZ, true>), dim3(F), dim3(fin_block<DX, DZ>()), 0, h->stream, a); \
+    LAUNCH_CHECK("k_finalize");                                                                           \
+    return DPF_OK;                                                                                        \
   }
   FIN(1, 2)
   FIN(2, 8)
@@ -515,11 +517,29 @@ static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a) {
   return fail(DPF_EUNSUPPORTED, "no finalize kernel for dims (%d,%d)", h->dx, h->dz);
 }
 
+// End of a look-ahead step: estimates; next = 1 in a look-ahead run (the
+// next step's group statistics, activity and time advance, which spare that
+// step its statistics kernel).
+static dpf_status launch_post(dpf_handle* h, const StepArgs& a, int next) {
+  const int2* rg = at<int2>(h, h->L.rgroups);
+#define POST(DX, DZ)                                                                                     \
+  if (h->dx == DX && h->dz == DZ) {                                                                      \
+    hipLaunchKernelGGL((k_post<DX, DZ>), dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a, rg, next); \
+    LAUNCH_CHECK("k_post");                                                                              \
+    return DPF_OK;                                                                                       \
+  }
+  POST(1, 2)
+  POST(2, 8)
+  POST(4, 64)
+#undef POST
+  return fail(DPF_EUNSUPPORTED, "no step-end kernel for dims (%d,%d)", h->dx, h->dz);
+}
+
 static dpf_status queue_init(dpf_handle* h) {
   const bool plain = h->algo == DPF_ALGO_PLAIN;
   hipLaunchKernelGGL(k_reset, dim3((h->F + 255) / 256), dim3(256), 0, h->stream, at<int>(h, h->L.tcur),
                      at<unsigned char>(h, h->L.cur), at<unsigned char>(h, h->L.act), at<uint32_t>(h, h->L.flags),
-                     at<double>(h, h->L.loglik), at<uint32_t>(h, h->L.lflags), h->F);
+                     at<double>(h, h->L.loglik), at<uint32_t>(h, h->L.lflags), at<int>(h, h->L.fcount), h->F);
   LAUNCH_CHECK("k_reset");
   h->mom_valid = false;
   StepArgs a = make_args(h);
@@ -692,10 +712,11 @@ extern "C" dpf_status dpf_destroy(dpf_handle* h) {
 }
 
 // fuse (look-ahead runs only): 0 a plain step; 1 the first step of a run,
-// whose new-cloud kernel also computes the next step's weights; 2 a later
-// step of the run, whose weights the previous step computed (no weights
-// kernel).  par: the weight buffers this step reads (the next step's go to
-// the other pair).
+// whose new-cloud kernel also computes the next step's weights and whose
+// step-end kernel also prepares the next step's resampling (group
+// statistics, time advance); 2 a later step of the run (no weights or
+// statistics kernel: the previous step did their work).  par: the weight
+// buffers this step reads (the next step's go to the other pair).
 static dpf_status queue_step(dpf_handle* h, const float* Y, long long y_tstride, const unsigned char* active,
                              const int* run_Tf, int run_T, float* trace_x, float* trace_z, int fuse = 0,
                              int par = 0) {
@@ -716,13 +737,12 @@ static dpf_status queue_step(dpf_handle* h, const float* Y, long long y_tstride,
     a.logw = w[par];
     a.ell_next = e[par ^ 1];
     a.logw_next = w[par ^ 1];
-    a.next_act = 1;
   }
   h->ell_sel = fuse ? par : 0;
   dpf_status s = phase_mark(h, 0);
   if (s == DPF_OK && fuse != 2) s = launch_classes(h, plain ? OP_DPF_WEIGHTS : OP_LA_WEIGHTS, a);
   if (s == DPF_OK) s = phase_mark(h, 1);
-  if (s == DPF_OK) {
+  if (s == DPF_OK && fuse != 2) {
     hipLaunchKernelGGL(k_res_stats, dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a,
                        at<int2>(h, h->L.rgroups), 1);
     LAUNCH_CHECK("k_res_stats");
@@ -730,7 +750,7 @@ static dpf_status queue_step(dpf_handle* h, const float* Y, long long y_tstride,
   if (s == DPF_OK) s = phase_mark(h, 2);
   if (s == DPF_OK) s = launch_classes(h, plain ? OP_NEWCLOUD_PLAIN : OP_NEWCLOUD_LA, a);
   if (s == DPF_OK) s = phase_mark(h, 3);
-  if (s == DPF_OK) s = launch_finalize(h, a);
+  if (s == DPF_OK) s = plain ? launch_finalize(h, a) : launch_post(h, a, fuse ? 1 : 0);
   if (s == DPF_OK) s = phase_mark(h, 4);
   h->mom_valid = a.mom != nullptr;
   return s;
@@ -792,7 +812,7 @@ static dpf_status queue_learned_step(dpf_handle* h, const float* Y, long long y_
   a.n_commit = h->L.n_rgroups;
   if (s == DPF_OK) s = launch_classes(h, OP_NEWCLOUD_FALLBACK, a, kGatedGrid);
   if (s == DPF_OK) s = phase_mark(h, 3);
-  if (s == DPF_OK) s = launch_finalize(h, a);
+  if (s == DPF_OK) s = launch_post(h, a, 0);
   if (s == DPF_OK) s = phase_mark(h, 4);
   h->mom_valid = true;
   return s;

@@ -61,9 +61,12 @@ def test_ragged_batch_matches_oracle_per_filter():
         io += n * m
 
 
-def test_graph_run_equals_step_calls_bit_for_bit():
+@pytest.mark.parametrize("N,M", [([300, 64], [256, 50]), ([5000, 40], [24, 130])])
+def test_graph_run_equals_step_calls_bit_for_bit(N, M):
+    """A run (fused steps, graph replays or eager) against step calls; N = 5000
+    has 20 resampling groups."""
     spec = S.nonlin_c2(1)
-    N, M, T = [300, 64], [256, 50], 6
+    T = 6
     Y = np.stack([S.simulate(spec, T, 9 + f)[2] for f in range(2)], axis=1).astype(np.float32)
     a = _filter(spec, N, M)
     for t in range(T):
@@ -91,6 +94,30 @@ def test_graph_run_equals_step_calls_bit_for_bit():
     b.lookahead_step(torch.from_numpy(Y[T - 1]))
     assert np.array_equal(a.export_state().cpu().numpy(), b.export_state().cpu().numpy())
     assert torch.equal(a.copy_buffer(dpf.BUF_ELL), b.copy_buffer(dpf.BUF_ELL))
+
+
+@pytest.mark.parametrize("use_run", [False, True])
+def test_step_end_kernels_agree(use_run):
+    """Filter 0 alone and next to a filter of 20 resampling groups: the same
+    bits (every reduction of a filter runs in its own fixed order)."""
+    spec = S.nonlin_c2(1)
+    T = 4
+    Y = np.stack([S.simulate(spec, T, 31 + f)[2] for f in range(2)], axis=1).astype(np.float32)
+    outs = []
+    for N, M in (([300], [256]), ([300, 5000], [256, 24])):
+        f = _filter(spec, N, M)
+        Yf = np.ascontiguousarray(Y[:, :len(N)])
+        if use_run:
+            f.run(torch.from_numpy(Yf), use_graph=False)
+        else:
+            for t in range(T):
+                f.lookahead_step(torch.from_numpy(Yf[t]))
+        st = f.unpack_state(f.export_state())
+        est = f.estimate()
+        outs.append((st["x"][0], st["z"][0], st["lam"][0], est["xhat"][0].cpu().numpy(),
+                     est["zhat"][0].cpu().numpy(), float(est["loglik"][0])))
+    for u, v in zip(outs[0], outs[1]):
+        assert np.array_equal(u, v)
 
 
 def test_per_filter_horizons_and_resume():
