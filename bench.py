@@ -158,6 +158,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ragged-filter run")
     ap.add_argument("--cpu-baseline-child", type=int, default=0)
+    ap.add_argument("--only-run", action="store_true",
+                    help="only the look-ahead runs (timed graph replays and the eager run with phase "
+                         "events): every new-cloud launch is then a run's, for profiling")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, run one device-to-device copy of this many MB "
                          "(a kernel of known traffic for calibrating hardware byte counters)")
@@ -191,15 +194,20 @@ def main():
     yptr = [ctypes.c_void_p(Y[t].data_ptr()) for t in range(n_obs)]
     updates = N_OUT * M_IN
 
-    # accuracy pass (not timed): one trajectory, RMSE of the x estimate vs truth
-    xt, _ = f.run(Y[:T_TRAJ].reshape(T_TRAJ, 1, DY), use_graph=True)
-    torch.cuda.synchronize()
-    rmse_x = float(np.sqrt(np.mean(np.sum((xt[:, 0].cpu().numpy() - xs[1:T_TRAJ + 1]) ** 2, axis=1))))
-
-    # warm-up, then the K timed steps: replays of a captured chunk of steps
-    f.reset()
-    for t in range(W):
-        assert L.dpf_lookahead_step(h, yptr[t], None) == 0
+    rmse_x = None
+    if not args.only_run:
+        # accuracy pass (not timed): one trajectory, RMSE of the x estimate vs truth
+        xt, _ = f.run(Y[:T_TRAJ].reshape(T_TRAJ, 1, DY), use_graph=True)
+        torch.cuda.synchronize()
+        rmse_x = round(float(np.sqrt(np.mean(np.sum((xt[:, 0].cpu().numpy() - xs[1:T_TRAJ + 1]) ** 2,
+                                                    axis=1)))), 4)
+        # warm-up
+        f.reset()
+        for t in range(W):
+            assert L.dpf_lookahead_step(h, yptr[t], None) == 0
+    else:
+        f.run(Y[:max(W, 2)].reshape(max(W, 2), 1, DY).contiguous(), trace=False, use_graph=False)
+    # the K timed steps: replays of a captured chunk of steps
     f.reset()
     Yk = Y[:K].reshape(K, 1, DY).contiguous()
     f.run(Yk, trace=False, use_graph=True)  # capture
@@ -211,14 +219,16 @@ def main():
     dt = time.perf_counter() - t0
 
     # the same K steps as individual calls (no graph)
-    f.reset()
-    torch.cuda.synchronize()
-    e0 = time.perf_counter()
-    for t in range(K):
-        if L.dpf_lookahead_step(h, yptr[t], None) != 0:
-            raise RuntimeError(L.dpf_last_error().decode())
-    torch.cuda.synchronize()
-    edt = time.perf_counter() - e0
+    edt = None
+    if not args.only_run:
+        f.reset()
+        torch.cuda.synchronize()
+        e0 = time.perf_counter()
+        for t in range(K):
+            if L.dpf_lookahead_step(h, yptr[t], None) != 0:
+                raise RuntimeError(L.dpf_last_error().decode())
+        torch.cuda.synchronize()
+        edt = time.perf_counter() - e0
 
     # phase times of the same run executed eagerly: events the library
     # records on its stream between its launches (steps after the first:
@@ -260,9 +270,9 @@ def main():
                              "peak_gbs": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}}
     f.close()
 
-    learned = None if args.no_learned else run_learned(S, dpf, torch, np, dev, K, W)
-    batched = None if args.no_batched else run_batched(S, dpf, torch, np, dev)
-    cpu = None if args.no_cpu_baseline else run_cpu_baseline(args.cpu_steps)
+    learned = None if (args.no_learned or args.only_run) else run_learned(S, dpf, torch, np, dev, K, W)
+    batched = None if (args.no_batched or args.only_run) else run_batched(S, dpf, torch, np, dev)
+    cpu = None if (args.no_cpu_baseline or args.only_run) else run_cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
         "value": updates * K / dt,
@@ -278,9 +288,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "look-ahead DPF step, nonlinear model dx=2 dz=8 dy=8, N=4096 outer x M=256 inner",
                    "algo": "lookahead", "N": N_OUT, "M": M_IN, "dx": DX, "dz": DZ, "dy": DY,
-                   "execution": "HIP graph replays of a captured 16-step chunk",
-                   "rmse_x_T200": round(rmse_x, 4)},
-        "eager_value": updates * K / edt,
+                   "execution": "HIP graph replays of a captured 16-step chunk (dpf_run); each step's "
+                                "new-cloud kernel also computes the next step's look-ahead weights",
+                   "rmse_x_T200": rmse_x},
+        "eager_value": updates * K / edt if edt else None,
+        "eager": "the K steps as separate dpf_lookahead_step calls (weights kernel every step, no graph)",
         "phase_ms": {p: round(v, 5) for p, v in ph_ms.items()},
         "first_step_phase_ms": first_ms,
         "roofline": roofline,

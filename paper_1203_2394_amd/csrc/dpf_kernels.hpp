@@ -921,12 +921,20 @@ __device__ void res_finish(const StepArgs& a, int f, int t, int N, const ResResu
 
 // Group statistics; with advance_time, group 0's workgroup also advances the
 // filter's time and flips its state copy (no other workgroup of this launch
-// reads them).
+// reads them).  In the learned step's second pass (fb set) a filter that
+// kept its learned proposals keeps the statistics of the first pass.
 __global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const int2* rgroups, int advance_time) {
   __shared__ ResScratch sh;
   const int2 rg = rgroups[blockIdx.x];
   const int f = rg.x;
   if (!a.act[f]) return;
+  if (a.fb != nullptr && a.fb[f] == 0) {
+    if (advance_time && rg.y == 0 && threadIdx.x == 0) {
+      a.tcur[f] = a.tcur[f] + 1;
+      a.cur[f] = (unsigned char)(a.cur[f] ^ 1);
+    }
+    return;
+  }
   const int N = a.fN[f];
   const int oo = a.ooff[f];
   float mg;
@@ -1086,7 +1094,11 @@ __global__ __launch_bounds__((fin_block<DX, DZ>())) void k_finalize(StepArgs a) 
 //    the filter's activity for the next step.
 // The last workgroup of a filter is found with a counter it resets.
 template <int DX, int DZ>
-__global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* rgroups, int next) {
+__device__ __forceinline__ void post_finish(const StepArgs& a, int f, int rb, int G, int t, unsigned char cb,
+                                            int next, bool act_next, int nthreads);
+
+template <int DX, int DZ>
+__global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* rgroups, int next, int split) {
   constexpr int NV = DX + DZ;
   __shared__ ResScratch sh;
   __shared__ double part[kBlock / kWave][NV];
@@ -1139,16 +1151,27 @@ __global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* rgroups
       if (nonf) atomicOr(&a.flags[f], (uint32_t)F_NONFINITE);
     }
   }
+  if (split) return;  // k_post_end finishes the filters
   __threadfence();
   if (threadIdx.x == 0) last = atomicAdd(&a.fcount[f], 1) == fv.ngroup - 1;
   __syncthreads();
   if (!last) return;
   __threadfence();
-  for (int q = threadIdx.x; q < NV; q += kBlock) {
+  if (threadIdx.x == 0) a.fcount[f] = 0;
+  post_finish<DX, DZ>(a, f, rb, fv.ngroup, t, cb, next, act_next, kBlock);
+}
+
+// Filter-level end of k_post: the estimates from the group partials (in
+// group order), the next step's activity and the time advance.
+template <int DX, int DZ>
+__device__ __forceinline__ void post_finish(const StepArgs& a, int f, int rb, int G, int t, unsigned char cb,
+                                            int next, bool act_next, int nthreads) {
+  constexpr int NV = DX + DZ;
+  for (int q = threadIdx.x; q < NV; q += nthreads) {
     double e = 0.0;
     // (unrolled: the loads of several groups in flight, added in order)
 #pragma unroll 16
-    for (int gg = 0; gg < fv.ngroup; ++gg) e += a.gpart[(long long)(rb + gg) * NV + q];
+    for (int gg = 0; gg < G; ++gg) e += a.gpart[(long long)(rb + gg) * NV + q];
     if (q < DX) {
       a.est_x[f * DX + q] = (float)e;
       if (a.trace_x) a.trace_x[((long long)(t - 1) * a.n_filters + f) * DX + q] = (float)e;
@@ -1157,16 +1180,29 @@ __global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* rgroups
       if (a.trace_z) a.trace_z[((long long)(t - 1) * a.n_filters + f) * DZ + q - DX] = (float)e;
     }
   }
-  if (threadIdx.x == 0) {
-    a.fcount[f] = 0;
-    if (next) {
-      a.act[f] = act_next ? 1 : 0;
-      if (act_next) {
-        a.tcur[f] = t + 1;
-        a.cur[f] = (unsigned char)(cb ^ 1);
-      }
+  if (threadIdx.x == 0 && next) {
+    a.act[f] = act_next ? 1 : 0;
+    if (act_next) {
+      a.tcur[f] = t + 1;
+      a.cur[f] = (unsigned char)(cb ^ 1);
     }
   }
+}
+
+// With many groups in a launch the cross-workgroup hand-off of k_post (a
+// device-scope fence per workgroup writes back the L2 of its XCD) costs more
+// than a kernel boundary: k_post runs split (groups only) and this kernel,
+// one 64-thread workgroup per filter, finishes the filters.
+template <int DX, int DZ>
+__global__ __launch_bounds__(kWave) void k_post_end(StepArgs a, int next) {
+  const int f = blockIdx.x;
+  const int tf = (next && a.run_Tf != nullptr) ? a.run_Tf[f] : 0x7fffffff;
+  const int rb = a.finfo[f].rg_base;
+  asm volatile("" ::"v"(tf), "v"(rb));
+  const FilterView fv = load_filter(a, f);
+  if (!fv.act) return;
+  const bool act_next = next && fv.t < min(tf, a.run_T);
+  post_finish<DX, DZ>(a, f, rb, fv.ngroup, fv.t, (unsigned char)fv.cur, next, act_next, kWave);
 }
 
 // ---------------------------------------------------------------- new cloud

@@ -519,14 +519,23 @@ static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a) {
 
 // End of a look-ahead step: estimates; next = 1 in a look-ahead run (the
 // next step's group statistics, activity and time advance, which spare that
-// step its statistics kernel).
+// step its statistics kernel).  Up to kPostFenceGroups groups in the handle:
+// one launch whose last workgroup per filter finishes it; more: the group
+// pass and a per-filter pass as two launches (same arithmetic).
+constexpr int kPostFenceGroups = 64;
+
 static dpf_status launch_post(dpf_handle* h, const StepArgs& a, int next) {
   const int2* rg = at<int2>(h, h->L.rgroups);
-#define POST(DX, DZ)                                                                                     \
-  if (h->dx == DX && h->dz == DZ) {                                                                      \
-    hipLaunchKernelGGL((k_post<DX, DZ>), dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a, rg, next); \
-    LAUNCH_CHECK("k_post");                                                                              \
-    return DPF_OK;                                                                                       \
+  const int split = h->L.n_rgroups > kPostFenceGroups ? 1 : 0;
+#define POST(DX, DZ)                                                                                           \
+  if (h->dx == DX && h->dz == DZ) {                                                                            \
+    hipLaunchKernelGGL((k_post<DX, DZ>), dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a, rg, next, split); \
+    LAUNCH_CHECK("k_post");                                                                                    \
+    if (split) {                                                                                               \
+      hipLaunchKernelGGL((k_post_end<DX, DZ>), dim3(h->F), dim3(kWave), 0, h->stream, a, next);               \
+      LAUNCH_CHECK("k_post_end");                                                                              \
+    }                                                                                                          \
+    return DPF_OK;                                                                                             \
   }
   POST(1, 2)
   POST(2, 8)

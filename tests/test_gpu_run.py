@@ -61,10 +61,11 @@ def test_ragged_batch_matches_oracle_per_filter():
         io += n * m
 
 
-@pytest.mark.parametrize("N,M", [([300, 64], [256, 50]), ([5000, 40], [24, 130])])
+@pytest.mark.parametrize("N,M", [([300, 64], [256, 50]), ([5000, 40], [24, 130]), ([16700, 40], [8, 24])])
 def test_graph_run_equals_step_calls_bit_for_bit(N, M):
     """A run (fused steps, graph replays or eager) against step calls; N = 5000
-    has 20 resampling groups."""
+    has 20 resampling groups, N = 16700 66 (more than 64 groups in a handle:
+    the step end runs as two launches)."""
     spec = S.nonlin_c2(1)
     T = 6
     Y = np.stack([S.simulate(spec, T, 9 + f)[2] for f in range(2)], axis=1).astype(np.float32)
@@ -98,13 +99,14 @@ def test_graph_run_equals_step_calls_bit_for_bit(N, M):
 
 @pytest.mark.parametrize("use_run", [False, True])
 def test_step_end_kernels_agree(use_run):
-    """Filter 0 alone and next to a filter of 20 resampling groups: the same
-    bits (every reduction of a filter runs in its own fixed order)."""
+    """Filter 0 alone (one step-end launch) and next to a filter of 66
+    resampling groups (the step end as two launches): the same bits (every
+    reduction of a filter runs in its own fixed order)."""
     spec = S.nonlin_c2(1)
     T = 4
     Y = np.stack([S.simulate(spec, T, 31 + f)[2] for f in range(2)], axis=1).astype(np.float32)
     outs = []
-    for N, M in (([300], [256]), ([300, 5000], [256, 24])):
+    for N, M in (([300], [256]), ([300, 16700], [256, 8])):
         f = _filter(spec, N, M)
         Yf = np.ascontiguousarray(Y[:, :len(N)])
         if use_run:
