@@ -154,10 +154,15 @@ dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean, float* d_
  * min(T_f, T).  d_Y: [T][F][dy] float, row t-1 holding y_t of every filter
  * (absolute time).  d_Tf: [F] int32 or NULL (all T).  d_xtrace [T][F][dx]
  * and d_ztrace [T][F][dz] (or NULL) receive the per-step estimates at row
- * t-1.  use_graph != 0 captures a chunk of 16 steps into a HIP graph once
- * and replays it (the step's launches read every per-filter time and buffer
- * choice from device memory, so replays need no host work); the T mod 16
- * remaining steps are queued directly. */
+ * t-1.  use_graph != 0 runs the first step directly, then captures a chunk
+ * of 16 steps into a HIP graph once and replays it (the step's launches read
+ * every per-filter time and buffer choice from device memory, so replays
+ * need no host work); the steps the chunks do not cover are queued directly.
+ * A look-ahead run takes Fig. 4 steps 1-2 of step t+1 (the look-ahead
+ * weights, eq:weightsMC) inside step t's new-cloud launch, from the clouds
+ * it has just built, and the outer-weight statistics of step t+1 inside step
+ * t's step-end launch: results are bit-identical to T dpf_lookahead_step
+ * calls with the same activity (per-filter horizons included). */
 dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_Tf,
                    float* d_xtrace, float* d_ztrace, int32_t use_graph);
 
@@ -173,7 +178,8 @@ dpf_status dpf_import_state(dpf_handle* h, const void* d_src, size_t bytes);
 
 /* Internal buffers of the last step, copied out for inspection:
  * DPF_BUF_ELL  float [sum N*M]: look-ahead (or measurement) log-weights ell
- * DPF_BUF_LOGW float [sum N]:   outer log-weights log w_i
+ *                               of the last step taken (also after a run)
+ * DPF_BUF_LOGW float [sum N]:   outer log-weights log w_i of that step
  * DPF_BUF_ANC  int32 [sum N]:   outer ancestors A_k
  * DPF_BUF_SEL  int32 [sum N]:   selected candidate (look-ahead) or
  *                               inner ancestor a_k (plain) per new particle;
