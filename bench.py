@@ -22,7 +22,9 @@ vector-ALU issue, so the roofline counts its algorithmic VALU issue slots
 per launch, with the algorithmic-bytes view beside it), the FP64 oracle
 timed on a bounded sample on the host, and the learned proposal (trained on
 look-ahead pairs, then run at the same N and M): its updates/s and RMSE
-beside the look-ahead step's on the same fresh sequences.
+beside the look-ahead step's on the same fresh sequences.  Beside them: the
+batched run of 1024 ragged filters and the high-dimensional inner block
+(dz = 64, N = 16384, M = 1024).
 """
 import argparse
 import hashlib
@@ -157,6 +159,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ragged-filter run")
+    ap.add_argument("--no-highdim", action="store_true", help="skip the high-dimensional inner block run")
     ap.add_argument("--cpu-baseline-child", type=int, default=0)
     ap.add_argument("--only-run", action="store_true",
                     help="only the look-ahead runs (timed graph replays and the eager run with phase "
@@ -272,6 +275,7 @@ def main():
 
     learned = None if (args.no_learned or args.only_run) else run_learned(S, dpf, torch, np, dev, K, W)
     batched = None if (args.no_batched or args.only_run) else run_batched(S, dpf, torch, np, dev)
+    highdim = None if (args.no_highdim or args.only_run) else run_highdim(S, dpf, torch, np, dev)
     cpu = None if (args.no_cpu_baseline or args.only_run) else run_cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
@@ -298,10 +302,46 @@ def main():
         "roofline": roofline,
         "learned": learned,
         "batched": batched,
+        "highdim": highdim,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
     return 0
+
+
+HD_N, HD_M, HD_T, HD_SEED = 16384, 1024, 12, 4
+
+
+def run_highdim(S, dpf, torch, np, dev):
+    """Config 4: the high-dimensional inner block (dx=4, dz=64, dy=32; banded A,
+    B sin(x), 32x64 projection, Gaussian / Student-t(3) outlier mixture
+    likelihood), N=16384 x M=1024 (16.8M inner particles, 4.3 GB per state
+    copy), one look-ahead run of HD_T steps, graph-replayed, timed after one
+    untimed run."""
+    spec = S.highdim_c4(PARAM_SEED)
+    _, _, ys = S.simulate(spec, HD_T, HD_SEED)
+    Y = torch.tensor(ys, dtype=torch.float32, device=dev).reshape(HD_T, 1, spec.dy).contiguous()
+    f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [HD_N], [HD_M], seed=FILTER_SEED,
+                   device=dev)
+    f.run(Y, trace=False, use_graph=True)
+    f.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.run(Y, trace=False, use_graph=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    updates = HD_N * HD_M
+    ms = dt * 1e3 / HD_T
+    # algorithmic bytes of a run step: z read (gathered) and written (4 dz
+    # each), lam, the parent's ell and the next ell (4 each)
+    bytes_step = updates * (8 * spec.dz + 16)
+    f.close()
+    return {"value": updates * HD_T / dt, "unit": UNIT, "ms_per_step": round(ms, 4), "steps": HD_T,
+            "config": {"workload": "look-ahead DPF, high-dimensional inner block dx=4 dz=64 dy=32 "
+                                   "(Student-t outlier mixture), N=16384 outer x M=1024 inner",
+                       "execution": "dpf_run, graph replays"},
+            "hbm_view": {"bytes_per_step": bytes_step, "achieved_gbs": round(bytes_step / (ms * 1e-3) / 1e9, 1),
+                         "frac": round(bytes_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
 def run_batched(S, dpf, torch, np, dev):
