@@ -97,6 +97,31 @@ def test_graph_run_equals_step_calls_bit_for_bit(N, M):
     assert torch.equal(a.copy_buffer(dpf.BUF_ELL), b.copy_buffer(dpf.BUF_ELL))
 
 
+@pytest.mark.parametrize("T", [17, 20, 35])
+def test_run_chunks_and_remainder_equal_step_calls(T):
+    """Look-ahead runs longer than one 16-step graph chunk: the first step
+    eager, then chunk replays, then the remainder eagerly -- the alternating
+    weight buffers must line up across every boundary.  A second run of the
+    same length replays the cached graph."""
+    spec = S.nonlin_c2(1)
+    N, M = [200, 90], [64, 40]
+    Y = np.stack([S.simulate(spec, T, 41 + f)[2] for f in range(2)], axis=1).astype(np.float32)
+    a = _filter(spec, N, M)
+    for t in range(T):
+        a.lookahead_step(torch.from_numpy(Y[t]))
+    sa = a.export_state().cpu().numpy()
+    ea = a.estimate()
+    b = _filter(spec, N, M)
+    for rep in range(2):
+        b.reset()
+        xt, _ = b.run(torch.from_numpy(Y), use_graph=True)
+        assert np.array_equal(sa, b.export_state().cpu().numpy()), rep
+        eb = b.estimate()
+        assert torch.equal(ea["xhat"], eb["xhat"]) and torch.equal(ea["loglik"], eb["loglik"])
+        for buf in (dpf.BUF_ELL, dpf.BUF_LOGW):
+            assert torch.equal(a.copy_buffer(buf), b.copy_buffer(buf)), (rep, buf)
+
+
 @pytest.mark.parametrize("use_run", [False, True])
 def test_step_end_kernels_agree(use_run):
     """Filter 0 alone (one step-end launch) and next to a filter of 66
