@@ -160,6 +160,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ragged-filter run")
     ap.add_argument("--no-highdim", action="store_true", help="skip the high-dimensional inner block run")
+    ap.add_argument("--no-fixed-rmse", action="store_true",
+                    help="skip the fixed-RMSE comparison of the look-ahead, plain and learned steps")
     ap.add_argument("--cpu-baseline-child", type=int, default=0)
     ap.add_argument("--only-run", action="store_true",
                     help="only the look-ahead runs (timed graph replays and the eager run with phase "
@@ -273,7 +275,12 @@ def main():
                              "peak_gbs": HBM_PEAK_GBS, "frac": round(gbs / HBM_PEAK_GBS, 4)}}
     f.close()
 
-    learned = None if (args.no_learned or args.only_run) else run_learned(S, dpf, torch, np, dev, K, W)
+    learned, mlp = None, None
+    if not (args.no_learned or args.only_run):
+        mlp, learned = run_learned(S, dpf, torch, np, dev, K, W)
+    fixed = None
+    if not (args.no_fixed_rmse or args.only_run):
+        fixed = run_fixed_rmse(S, dpf, torch, np, dev, K, mlp)
     batched = None if (args.no_batched or args.only_run) else run_batched(S, dpf, torch, np, dev)
     highdim = None if (args.no_highdim or args.only_run) else run_highdim(S, dpf, torch, np, dev)
     cpu = None if (args.no_cpu_baseline or args.only_run) else run_cpu_baseline(args.cpu_steps)
@@ -301,6 +308,7 @@ def main():
         "first_step_phase_ms": first_ms,
         "roofline": roofline,
         "learned": learned,
+        "fixed_rmse": fixed,
         "batched": batched,
         "highdim": highdim,
         "cpu_baseline": cpu,
@@ -311,9 +319,84 @@ def main():
 
 HD_N, HD_M, HD_T, HD_SEED = 16384, 1024, 12, 4
 
+# fixed-RMSE comparison: sequences, their length, the outer-particle grid and
+# the tolerance on the reference RMSE (the look-ahead step at N = 4096)
+FR_SEQS, FR_SEED, FR_T = 32, 9000, 200
+FR_GRID = (256, 512, 1024, 2048, 4096, 8192)
+FR_TOL = 1.05
+
+
+def run_fixed_rmse(S, dpf, torch, np, dev, K, mlp):
+    """Updates/s at a fixed RMSE (look-ahead, plain and learned steps on the
+    nonlinear model, M = 256).  The reference is the
+    look-ahead step at the bench size (N = 4096, M = 256): the RMSE of x_hat
+    against the simulated truth over FR_SEQS fresh sequences of FR_T steps
+    (run as FR_SEQS filters of one handle).  For each method the smallest N
+    on FR_GRID (M = 256) whose RMSE is within FR_TOL of the reference is
+    taken, and a single filter of that size is timed over min(K, FR_T)
+    graph-replayed steps: updates/s and particle-steps/s (N per second)."""
+    spec = S.nonlin_c2(PARAM_SEED)
+    sims = [S.simulate(spec, FR_T, FR_SEED + q) for q in range(FR_SEQS)]
+    Y = torch.tensor(np.stack([sm[2] for sm in sims], axis=1), dtype=torch.float32, device=dev).contiguous()
+    truth = np.stack([sm[0][1:FR_T + 1] for sm in sims], axis=1)  # [T][F][dx]
+    Kt = max(1, min(K, FR_T))
+
+    def make(algo, N, F):
+        f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N] * F, [M_IN] * F, seed=FILTER_SEED,
+                       device=dev, algo="plain" if algo == "plain" else "lookahead")
+        if algo == "learned":
+            f.set_proposal(mlp, ess_frac=ESS_FRAC)
+        return f
+
+    def rmse(algo, N):
+        f = make(algo, N, FR_SEQS)
+        xt, _ = f.run(Y, use_graph=True, learned=(algo == "learned"))
+        err = np.sum((xt.cpu().numpy() - truth) ** 2, axis=2)
+        f.close()
+        return float(np.sqrt(err.mean()))
+
+    def timed(algo, N):
+        Yk = Y[:Kt, :1].contiguous()
+        f = make(algo, N, 1)
+        f.run(Yk, trace=False, use_graph=True, learned=(algo == "learned"))  # capture
+        f.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.run(Yk, trace=False, use_graph=True, learned=(algo == "learned"))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        f.close()
+        return N * M_IN * Kt / dt, N * Kt / dt
+
+    ref = rmse("lookahead", N_OUT)
+    ups_plain, _ = timed("plain", N_OUT)
+    target = FR_TOL * ref
+    out = {"reference_rmse_x": round(ref, 5), "target_rmse_x": round(target, 5),
+           "rule": "smallest N in %s (M=%d) with RMSE <= %.2f x the look-ahead RMSE at N=%d; %d fresh "
+                   "sequences x T=%d; then one filter of that size timed over %d graph-replayed steps"
+                   % (list(FR_GRID), M_IN, FR_TOL, N_OUT, FR_SEQS, FR_T, Kt),
+           "plain_updates_per_s_at_N%d" % N_OUT: ups_plain,
+           "methods": {}}
+    for algo in ("lookahead", "plain", "learned"):
+        if algo == "learned" and mlp is None:
+            continue
+        tried = {}
+        chosen = None
+        for N in FR_GRID:
+            r = ref if (algo == "lookahead" and N == N_OUT) else rmse(algo, N)
+            tried[N] = round(r, 5)
+            if r <= target:
+                chosen = N
+                break
+        n_use = chosen if chosen is not None else FR_GRID[-1]
+        ups, pss = timed(algo, n_use)
+        out["methods"][algo] = {"N": n_use, "reached": chosen is not None, "rmse_by_N": tried,
+                                "updates_per_s": ups, "particle_steps_per_s": pss}
+    return out
+
 
 def run_highdim(S, dpf, torch, np, dev):
-    """Config 4: the high-dimensional inner block (dx=4, dz=64, dy=32; banded A,
+    """The high-dimensional inner block (dx=4, dz=64, dy=32; banded A,
     B sin(x), 32x64 projection, Gaussian / Student-t(3) outlier mixture
     likelihood), N=16384 x M=1024 (16.8M inner particles, 4.3 GB per state
     copy), one look-ahead run of HD_T steps, graph-replayed, timed after one
@@ -435,7 +518,7 @@ def run_learned(S, dpf, torch, np, dev, K, W):
     edt = time.perf_counter() - e0
     f.close()
     updates = N_OUT * M_IN
-    return {
+    return mlp, {
         "value": updates * K / dt,
         "ms_per_step": dt * 1e3 / K,
         "eager_value": updates * K / edt,
