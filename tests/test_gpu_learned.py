@@ -450,3 +450,29 @@ def test_learned_run_graph_equals_steps():
     assert np.array_equal(outs[0][0], outs[2][0])
     assert np.array_equal(outs[0][1], outs[1][1], equal_nan=True)
     assert np.all(np.isnan(outs[0][1][7:, 1])) and np.all(np.isfinite(outs[0][1][:7]))
+
+
+def test_trained_network_gains_over_the_untrained_one():
+    """What training buys: pairs from look-ahead runs, ten epochs on the GPU,
+    then the learned step on fresh sequences.  The trained proposal is
+    accepted (ESS >= N/10) in almost every filter-step, so the step takes its
+    one-pass form at the look-ahead step's RMSE; the same network untrained
+    is rejected in most steps, each of which then pays for the learned pass
+    and the look-ahead fallback."""
+    from paper_1203_2394_amd import proposal as PR
+    spec = _spec()
+    X, xt = PR.generate_pairs(spec, 400000, simulate=S.simulate, device="cuda")
+    trained, losses = PR.train(X, xt, epochs=10, batch=4096, lr=1e-3, seed=0)
+    untrained, _ = PR.train(X, xt, epochs=0, batch=4096, seed=0)
+    kw = dict(N=1024, M=128, T=100, n_seq=16, data_seed=7000, ess_frac=0.1, simulate=S.simulate,
+              device="cuda", timing_reps=1)
+    ev_t = PR.evaluate(spec, trained, **kw)
+    ev_u = PR.evaluate(spec, untrained, **kw)
+    for name, ev in (("trained", ev_t), ("untrained", ev_u)):
+        print("%s: RMSE learned %.4f look-ahead %.4f, fallback %.3f, ms/step learned %.4f look-ahead %.4f"
+              % (name, ev["learned"]["rmse_x"], ev["lookahead"]["rmse_x"], ev["learned"]["fallback_frac"],
+                 ev["learned"]["ms_per_step"], ev["lookahead"]["ms_per_step"]), flush=True)
+    assert losses[-1] < losses[0] - 1.0
+    assert ev_t["learned"]["fallback_frac"] < 0.05
+    assert ev_u["learned"]["fallback_frac"] > 0.5
+    assert ev_t["learned"]["rmse_x"] <= 1.10 * ev_t["lookahead"]["rmse_x"]
