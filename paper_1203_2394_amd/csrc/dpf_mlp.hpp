@@ -549,22 +549,30 @@ __global__ void k_mlp_adam(AdamArgs a) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e == 0 && a.loss) {
     double s = 0.0;
+#pragma unroll 16
     for (int g = 0; g < a.groups; ++g) s += a.loss_part[g];
     *a.loss = (float)(s / a.B);
   }
   if (e >= PL::n) return;
   float g = 0.f;
+  // (each sum unrolled: the loads of 16 partials in flight, added in order)
   if (e < PL::b1) {
+#pragma unroll 16
     for (int c = 0; c < a.chunks; ++c) g += a.wpart[0][(size_t)c * (kMlpHid * kMlpIn) + e];
   } else if (e < PL::W2) {
+#pragma unroll 16
     for (int t = 0; t < a.tiles; ++t) g += a.b1_part[(size_t)t * kMlpHid + e - PL::b1];
   } else if (e < PL::b2) {
+#pragma unroll 16
     for (int c = 0; c < a.chunks; ++c) g += a.wpart[1][(size_t)c * (kMlpHid * kMlpHid) + e - PL::W2];
   } else if (e < PL::W3) {
+#pragma unroll 16
     for (int t = 0; t < a.tiles; ++t) g += a.b2_part[(size_t)t * kMlpHid + e - PL::b2];
   } else if (e < PL::b3) {
+#pragma unroll 16
     for (int c = 0; c < a.chunks; ++c) g += a.wpart[2][(size_t)c * (kMlpOut * kMlpHid) + e - PL::W3];
   } else {
+#pragma unroll 16
     for (int t = 0; t < a.groups; ++t) g += a.b3_part[(size_t)t * kMlpOut + e - PL::b3];
   }
   if (a.grad_out) a.grad_out[e] = g;
