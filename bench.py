@@ -23,8 +23,9 @@ per launch, with the algorithmic-bytes view beside it), the FP64 oracle
 timed on a bounded sample on the host, and the learned proposal (trained on
 look-ahead pairs, then run at the same N and M): its updates/s and RMSE
 beside the look-ahead step's on the same fresh sequences.  Beside them: the
-batched run of 1024 ragged filters and the high-dimensional inner block
-(dz = 64, N = 16384, M = 1024).
+look-ahead, plain and learned steps at a fixed RMSE (32 fresh sequences as
+32 filters of one handle), the batched run of 1024 ragged filters and the
+high-dimensional inner block (dz = 64, N = 16384, M = 1024).
 """
 import argparse
 import hashlib

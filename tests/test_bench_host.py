@@ -1,0 +1,50 @@
+"""Host-side pieces of bench.py (no GPU): the single-GPU guard, the CPU
+baseline leg (the oracle on one step of the workload), the issue-slot count
+behind the roofline, and that the committed counter summary was taken on the
+current kernel sources (else the bench reports its traffic as null)."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def _run(*args, timeout=300):
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + list(args), capture_output=True,
+                          text=True, timeout=timeout)
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = _run("--gpus", "2", timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_cpu_baseline_child_times_the_oracle_on_the_workload():
+    r = _run("--cpu-baseline-child", "1")
+    assert r.returncode == 0, r.stderr
+    out = json.loads(r.stdout.strip().splitlines()[-1])
+    assert out["steps"] == 1 and out["updates"] == bench.N_OUT * bench.M_IN == 4096 * 256
+    assert out["seconds"] > 0
+
+
+def test_issue_slot_count():
+    # Philox4x32-10 block: ten rounds of two quarter-rate 32x32->64 products
+    # (4 slots each) and four exclusive ors; a Box-Muller pair: four
+    # quarter-rate transcendentals and three full-rate operations
+    assert bench.PHILOX_BLOCK == 120 and bench.BM_PAIR == 19
+    # n normals: ceil(n/4) Philox blocks, one U24 conversion of three slots
+    # per word, n/2 Box-Muller pairs
+    assert bench.normals_slots(8) == 2 * 120 + 24 + 4 * 19
+    assert bench.normals_slots(2) == 120 + 6 + 19
+    assert bench.VALU_SLOTS_PER_UPDATE == sum(bench.ISSUE_PER_UPDATE.values()) == 1112
+    assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
+
+
+def test_traffic_summary_matches_the_kernel_sources():
+    assert bench.read_traffic("newcloud") is not None
+    assert bench.read_traffic("post") is not None
