@@ -161,6 +161,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ragged-filter run")
     ap.add_argument("--no-highdim", action="store_true", help="skip the high-dimensional inner block run")
+    ap.add_argument("--no-twodim", action="store_true", help="skip the Table 1 model 1 runs")
     ap.add_argument("--no-fixed-rmse", action="store_true",
                     help="skip the fixed-RMSE comparison of the look-ahead, plain and learned steps")
     ap.add_argument("--cpu-baseline-child", type=int, default=0)
@@ -284,6 +285,7 @@ def main():
         fixed = run_fixed_rmse(S, dpf, torch, np, dev, mlp)
     batched = None if (args.no_batched or args.only_run) else run_batched(S, dpf, torch, np, dev)
     highdim = None if (args.no_highdim or args.only_run) else run_highdim(S, dpf, torch, np, dev)
+    twodim = None if (args.no_twodim or args.only_run) else run_twodim(S, dpf, torch, np, dev)
     cpu = None if (args.no_cpu_baseline or args.only_run) else run_cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
@@ -312,6 +314,7 @@ def main():
         "fixed_rmse": fixed,
         "batched": batched,
         "highdim": highdim,
+        "table1_model1": twodim,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
@@ -381,6 +384,42 @@ def run_fixed_rmse(S, dpf, torch, np, dev, mlp):
                 chosen = r
                 break
         out["at_target"][m] = chosen if chosen is not None else {"reached": False}
+    return out
+
+
+TD_SEQS, TD_T, TD_N, TD_M, TD_SEED = 32, 250, 4096, 256, 12000
+
+
+def run_twodim(S, dpf, torch, np, dev):
+    """Model 1 of Table 1 (dx = dz = dy = 1, time-varying drift, correlated
+    noises): TD_SEQS fresh sequences of TD_T steps as filters of one handle
+    (N = 4096, M = 256), look-ahead and plain runs, graph-replayed; updates/s
+    of the second run of each handle and the RMSE of x_hat and z_hat."""
+    spec = S.twodim_table1()
+    sims = [S.simulate(spec, TD_T, TD_SEED + q) for q in range(TD_SEQS)]
+    Y = torch.tensor(np.stack([sm[2] for sm in sims], axis=1), dtype=torch.float32, device=dev).contiguous()
+    tx = np.stack([sm[0][1:] for sm in sims], axis=1)
+    tz = np.stack([sm[1][1:] for sm in sims], axis=1)
+    out = {"config": {"workload": "Table 1 model 1 (dx=dz=dy=1), %d sequences x T=%d as filters of one handle, "
+                                  "N=%d, M=%d" % (TD_SEQS, TD_T, TD_N, TD_M)}}
+    for algo in ("lookahead", "plain"):
+        f = dpf.Filter(spec.kind, 1, 1, 1, spec.blob, [TD_N] * TD_SEQS, [TD_M] * TD_SEQS, seed=FILTER_SEED,
+                       device=dev, algo=algo)
+        xt, zt = f.run(Y, use_graph=True)
+        ex = np.sqrt(np.mean((xt.cpu().numpy() - tx) ** 2, axis=(0, 2)))
+        ez = np.sqrt(np.mean((zt.cpu().numpy() - tz) ** 2, axis=(0, 2)))
+        f.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.run(Y, trace=False, use_graph=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        f.close()
+        out[algo] = {"updates_per_s": TD_N * TD_M * TD_SEQS * TD_T / dt, "ms_per_step": dt * 1e3 / TD_T,
+                     "rmse_x": round(float(np.sqrt(np.mean(ex ** 2))), 4),
+                     "rmse_z": round(float(np.sqrt(np.mean(ez ** 2))), 4),
+                     "seq_rmse_x_median": round(float(np.median(ex)), 4),
+                     "seq_rmse_x_max": round(float(ex.max()), 4)}
     return out
 
 

@@ -13,13 +13,14 @@ Parameter blob layouts are those of the library interface (include/dpf.h):
 LINGAUSS: Ax[dx*dx] Cxz[dx*dz] qx Az[dz*dz] Bzx[dz*dx] qz Hx[dy*dx] Hz[dy*dz] r
 NONLIN:   a b qx W[dz*dx] rho qz c r bmode
 HIGHDIM:  a b qx Alo[dz-1] Adiag[dz] Aup[dz-1] B[dz*dx] qz C[dy*dz] r eps nu gonly
+TWODIM:   qx qz cxz rho b amp freq r
 """
 from dataclasses import dataclass, field
 from typing import List, Optional
 
 import numpy as np
 
-LINGAUSS, NONLIN, HIGHDIM = 1, 2, 3
+LINGAUSS, NONLIN, HIGHDIM, TWODIM = 1, 2, 3, 4
 
 
 @dataclass
@@ -32,7 +33,7 @@ class ModelSpec:
 
     @property
     def name(self):
-        return {LINGAUSS: "lingauss", NONLIN: "nonlin", HIGHDIM: "highdim"}[self.kind]
+        return {LINGAUSS: "lingauss", NONLIN: "nonlin", HIGHDIM: "highdim", TWODIM: "twodim"}[self.kind]
 
 
 def lingauss_c1(coupled: bool = False) -> ModelSpec:
@@ -50,6 +51,19 @@ def lingauss_c1(coupled: bool = False) -> ModelSpec:
     Hz = [1.0, 0.5]
     blob = np.array(Ax + Cxz + [0.1] + Az + Bzx + [0.1] + Hx + Hz + [0.2], dtype=np.float64)
     return ModelSpec(LINGAUSS, 1, 2, 1, blob)
+
+
+def twodim_table1(qx: float = 1.0, qz: float = 1.0, cxz: float = 0.1) -> ModelSpec:
+    """Model 1 of Table 1 (the 2-dimensional example), dx = dz = dy = 1:
+
+    x_{t+1} = x_t + z_t / (1 + z_t^2) + v^x_t
+    z_{t+1} = x_t + 0.5 z_t + 25 z_t / (1 + z_t^2) + 8 cos(1.2 t) + v^z_t
+    y_t = atan(x_t) + z_t^2 / 20 + e_t
+    (v^x, v^z) ~ N(0, [[qx, cxz], [cxz, qz]]) (Table 1: 1, 1, 0.1), e ~ N(0, 1).
+    Parameters are rounded to FP32 once, as the library stores them.
+    """
+    blob = np.array([qx, qz, cxz, 0.5, 25.0, 8.0, 1.2, 1.0], dtype=np.float32).astype(np.float64)
+    return ModelSpec(TWODIM, 1, 1, 1, blob)
 
 
 def nonlin_c2(param_seed: int = 1, dx: int = 2, dz: int = 8, bmode: int = 0) -> ModelSpec:
@@ -87,6 +101,8 @@ def highdim_c4(param_seed: int = 1, dx: int = 4, dz: int = 64, dy: int = 32,
 
 # ---------------------------------------------------------------- simulator
 def _sim_fns(spec: ModelSpec):
+    """fx(x, z, g), fz(x, xn, z, g, t), hy(x, z, g); t is the time of the
+    state the transition leaves."""
     dx, dz, dy, b = spec.dx, spec.dz, spec.dy, spec.blob
     if spec.kind == LINGAUSS:
         o = 0
@@ -100,7 +116,7 @@ def _sim_fns(spec: ModelSpec):
         Hz = b[o:o + dy * dz].reshape(dy, dz); o += dy * dz
         r = b[o]
         fx = lambda x, z, g: Ax @ x + Cxz @ z + np.sqrt(qx) * g.normal(size=dx)
-        fz = lambda x, xn, z, g: Az @ z + Bzx @ xn + np.sqrt(qz) * g.normal(size=dz)
+        fz = lambda x, xn, z, g, t: Az @ z + Bzx @ xn + np.sqrt(qz) * g.normal(size=dz)
         hy = lambda x, z, g: Hx @ x + Hz @ z + np.sqrt(r) * g.normal(size=dy)
         return fx, fz, hy
     if spec.kind == NONLIN:
@@ -108,7 +124,7 @@ def _sim_fns(spec: ModelSpec):
         W = b[3:3 + dz * dx].reshape(dz, dx)
         rho, qz, c, r, bmode = b[3 + dz * dx:3 + dz * dx + 5]
         fx = lambda x, z, g: a * x + bb * x / (1 + x * x) + np.sqrt(qx) * g.normal(size=dx)
-        fz = lambda x, xn, z, g: np.tanh(W @ xn) + rho * z + np.sqrt(qz) * g.normal(size=dz)
+        fz = lambda x, xn, z, g, t: np.tanh(W @ xn) + rho * z + np.sqrt(qz) * g.normal(size=dz)
 
         def hy(x, z, g):
             off = c * x[np.arange(dy) % dx] ** 2 if bmode == 0 else c * np.dot(x, x)
@@ -126,7 +142,7 @@ def _sim_fns(spec: ModelSpec):
         C = b[o:o + dy * dz].reshape(dy, dz); o += dy * dz
         r, eps, nu, gonly = b[o:o + 4]
         fx = lambda x, z, g: a * x + bb * x / (1 + x * x) + np.sqrt(qx) * g.normal(size=dx)
-        fz = lambda x, xn, z, g: A @ z + B @ np.sin(xn) + np.sqrt(qz) * g.normal(size=dz)
+        fz = lambda x, xn, z, g, t: A @ z + B @ np.sin(xn) + np.sqrt(qz) * g.normal(size=dz)
 
         def hy(x, z, g):
             e = np.sqrt(r) * g.normal(size=dy)
@@ -134,6 +150,17 @@ def _sim_fns(spec: ModelSpec):
                 out = g.random(size=dy) < eps
                 e = np.where(out, np.sqrt(r) * g.standard_t(nu, size=dy), e)
             return C @ z + e
+        return fx, fz, hy
+    if spec.kind == TWODIM:
+        qx, qz, cxz, rho, bb, amp, freq, r = b
+        # the noise pair drawn jointly: v^x first, then v^z given v^x
+        fx = lambda x, z, g: x + z / (1 + z * z) + np.sqrt(qx) * g.normal(size=1)
+
+        def fz(x, xn, z, g, t):
+            vx = xn - x - z / (1 + z * z)
+            vz = cxz / qx * vx + np.sqrt(qz - cxz * cxz / qx) * g.normal(size=1)
+            return x + rho * z + bb * z / (1 + z * z) + amp * np.cos(freq * t) + vz
+        hy = lambda x, z, g: np.arctan(x) + z * z / 20 + np.sqrt(r) * g.normal(size=1)
         return fx, fz, hy
     raise ValueError(spec.kind)
 
@@ -145,9 +172,9 @@ def simulate(spec: ModelSpec, T: int, data_seed: int):
     x = g.normal(size=spec.dx)
     z = g.normal(size=spec.dz)
     xs, zs, ys = [x], [z], []
-    for _ in range(T):
+    for s in range(T):
         xn = fx(x, z, g)
-        zn = fz(x, xn, z, g)
+        zn = fz(x, xn, z, g, s)
         ys.append(hy(xn, zn, g))
         x, z = xn, zn
         xs.append(x)

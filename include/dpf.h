@@ -73,12 +73,22 @@ typedef enum {
  *   x' as NONLIN ; z' = A z + B sin(x') + sqrt(qz) w, A tridiagonal ;
  *   y = C z + e, each e_k with density (1-eps) N(0,r) + eps t_nu(e/sqrt r)/sqrt r
  *   (gonly != 0: plain N(0, r)).
+ * DPF_MODEL_TWODIM -- model 1 of Table 1 (the 2-dimensional example), built
+ *   for (dx,dz,dy) = (1,1,1):
+ *   qx qz cxz rho b amp freq r
+ *   x' = x + z/(1+z^2) + v^x ;
+ *   z' = x + rho z + b z/(1+z^2) + amp cos(freq t) + v^z, t the time of the
+ *   state the transition leaves ;
+ *   (v^x, v^z) ~ N(0, [[qx, cxz], [cxz, qz]]) ; y = atan(x) + z^2/20 + e,
+ *   e ~ N(0, r).  Table 1's values: 1 1 0.1 0.5 25 8 1.2 1.  Needs qx > 0,
+ *   r > 0 and qx qz > cxz^2 (else DPF_EINVAL).
  * Every model has the prior [x_0; z_0] ~ N(0, I).
  */
 typedef enum {
   DPF_MODEL_LINGAUSS = 1,
   DPF_MODEL_NONLIN = 2,
-  DPF_MODEL_HIGHDIM = 3
+  DPF_MODEL_HIGHDIM = 3,
+  DPF_MODEL_TWODIM = 4
 } dpf_model;
 
 /* Which filter a handle runs. */

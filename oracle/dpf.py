@@ -60,7 +60,7 @@ def propose(model, x, z, lq, A, t, seed, fid):
             flags |= FLAG_NONFINITE
         binner[k] = b
         nu = P.normals(seed, fid, t, k, j, P.DPF_Z, model.dz)
-        zn[k] = model.fz(x[p], xn[k], z[p, b], nu)
+        zn[k] = model.fz(x[p], xn[k], z[p, b], nu, t)
     return xn, zn, anc, binner, flags
 
 

@@ -76,7 +76,7 @@ def lookahead(model, state, y, seed, fid):
     nu_z = P.normals(seed, fid, t, i, j, P.LA_Z, model.dz)
     xp = x[:, None, :]
     xla = model.fx(xp, z, nu_x)
-    zla = model.fz(xp, xla, z, nu_z)
+    zla = model.fz(xp, xla, z, nu_z, t - 1)
     ell = lam + model.logpy(y, xla, zla)
     logw = logsumexp(ell)
     return xla, zla, ell, logw
@@ -139,7 +139,7 @@ def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None):
             flags |= FLAG_NONFINITE
         binner[k] = b
         nu = P.normals(seed, fid, t, k, j, P.NEW_Z, model.dz)
-        znew[k] = model.fz(x[p], xnew[k], z[p, b], nu)
+        znew[k] = model.fz(x[p], xnew[k], z[p, b], nu, t - 1)
         lamnew[k], deg_l = normalise_log(model.logpy(y, xnew[k], znew[k]))
         if deg_l:
             flags |= FLAG_DEGENERATE_INNER

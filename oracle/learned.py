@@ -214,7 +214,7 @@ def step(model, state, y, seed, fid, mdn_out, ess_frac=0.1):
             flags |= FLAG_DEGENERATE_INNER
         binner[i] = b
         nu = P.normals(seed, fid, t, i, j, P.NEW_Z, model.dz)
-        zt[i] = model.fz(x[i], xt[i], z[i, b], nu)
+        zt[i] = model.fz(x[i], xt[i], z[i, b], nu, t - 1)
         ell = model.logpy(y, xt[i], zt[i])
         log_py[i] = logsumexp(ell) - math.log(M)           # eq:approx2, unit weights
         lt[i], _ = normalise_log(ell)

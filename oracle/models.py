@@ -8,7 +8,9 @@ p(x_0), p(z_0|x_0), p(x_{t+1}|x_t,z_t), p(z_{t+1}|x_{t:t+1},z_t) and
 p(y_t|x_t,z_t), with all parameters known.  Each model below provides
 
     fx(x, z, nu)        sample of x_{t+1} given standard normals nu (dx)
-    fz(x, xn, z, nu)    sample of z_{t+1} given x_t, x_{t+1}, z_t, normals (dz)
+    fz(x, xn, z, nu, t) sample of z_{t+1} given x_t, x_{t+1}, z_t, normals (dz);
+                        t is the time of the state the transition leaves
+                        (only a time-varying model uses it)
     logpx(xn, x, z)     log p(x_{t+1} | x_t, z_t)
     logpy(y, x, z)      log p(y_t | x_t, z_t)
 
@@ -33,12 +35,18 @@ HIGHDIM:
     x' as NONLIN's x (dx components),  z' = A z + B sin(x') + sqrt(qz) w with
     A tridiagonal,  y = C z + e where each e_k has density
     (1-eps) N(0, r) + eps * t_nu(e/sqrt(r))/sqrt(r)  (gonly=1: pure N(0, r)).
+TWODIM (model 1 of Table 1, dx = dz = dy = 1):
+    qx qz cxz rho b amp freq r
+    x' = x + z/(1+z^2) + v^x,  z' = x + rho z + b z/(1+z^2) + amp cos(freq t) + v^z,
+    (v^x, v^z) ~ N(0, [[qx, cxz], [cxz, qz]]),  y = atan(x) + z^2/20 + e, e ~ N(0, r).
+    In the factorisation of Eq. (1) the inner transition is conditioned on
+    x_{t+1}, i.e. on v^x: v^z | v^x ~ N(cxz/qx v^x, qz - cxz^2/qx).
 """
 import math
 
 import numpy as np
 
-LINGAUSS, NONLIN, HIGHDIM = 1, 2, 3
+LINGAUSS, NONLIN, HIGHDIM, TWODIM = 1, 2, 3, 4
 
 LOG2PI = math.log(2.0 * math.pi)
 
@@ -82,7 +90,7 @@ class LinGauss:
     def fx(self, x, z, nu):
         return self.mean_x(x, z) + math.sqrt(self.qx) * nu
 
-    def fz(self, x, xn, z, nu):
+    def fz(self, x, xn, z, nu, t=0):
         return _matvec(self.Az, z) + _matvec(self.Bzx, xn) + math.sqrt(self.qz) * nu
 
     def logpx(self, xn, x, z):
@@ -115,7 +123,7 @@ class NonLin:
     def fx(self, x, z, nu):
         return _growth(self.a, self.b, x) + math.sqrt(self.qx) * nu
 
-    def fz(self, x, xn, z, nu):
+    def fz(self, x, xn, z, nu, t=0):
         return np.tanh(_matvec(self.W, xn)) + self.rho * z + math.sqrt(self.qz) * nu
 
     def logpx(self, xn, x, z):
@@ -155,7 +163,7 @@ class HighDim:
     def fx(self, x, z, nu):
         return _growth(self.a, self.b, x) + math.sqrt(self.qx) * nu
 
-    def fz(self, x, xn, z, nu):
+    def fz(self, x, xn, z, nu, t=0):
         return _matvec(self.A, z) + _matvec(self.B, np.sin(xn)) + math.sqrt(self.qz) * nu
 
     def logpx(self, xn, x, z):
@@ -177,6 +185,43 @@ class HighDim:
         return np.sum(comp, axis=-1)
 
 
+class TwoDim:
+    """Model 1 of Table 1: a scalar outer state driven by the inner one
+    (x' depends on z), a time-varying inner drift and correlated noises."""
+    kind = TWODIM
+
+    def __init__(self, dx, dz, dy, blob):
+        if (dx, dz, dy) != (1, 1, 1):
+            raise ValueError("TWODIM is (1, 1, 1)")
+        if len(blob) != 8:
+            raise ValueError("TWODIM blob has %d values, expected 8" % len(blob))
+        self.dx = self.dz = self.dy = 1
+        self.qx, self.qz, self.cxz, self.rho, self.b, self.amp, self.freq, self.r = (float(v) for v in blob)
+        self.kz = self.cxz / self.qx                       # E[v^z | v^x] = kz v^x
+        self.qzc = self.qz - self.cxz * self.cxz / self.qx  # Var[v^z | v^x]
+
+    @staticmethod
+    def _sat(z):
+        return z / (1.0 + z * z)
+
+    def mean_x(self, x, z):
+        return x + self._sat(z)
+
+    def fx(self, x, z, nu):
+        return self.mean_x(x, z) + math.sqrt(self.qx) * nu
+
+    def fz(self, x, xn, z, nu, t=0):
+        vx = xn - self.mean_x(x, z)
+        drift = x + self.rho * z + self.b * self._sat(z) + self.amp * math.cos(self.freq * t)
+        return drift + self.kz * vx + math.sqrt(self.qzc) * nu
+
+    def logpx(self, xn, x, z):
+        return _gauss_iso_logpdf(xn - self.mean_x(x, z), self.qx)
+
+    def logpy(self, y, x, z):
+        return _gauss_iso_logpdf(y - np.arctan(x) - z * z / 20.0, self.r)
+
+
 def make_model(kind, dx, dz, dy, blob):
     blob = np.asarray(blob, dtype=np.float64)
     if kind == LINGAUSS:
@@ -185,4 +230,6 @@ def make_model(kind, dx, dz, dy, blob):
         return NonLin(dx, dz, dy, blob)
     if kind == HIGHDIM:
         return HighDim(dx, dz, dy, blob)
+    if kind == TWODIM:
+        return TwoDim(dx, dz, dy, blob)
     raise ValueError("unknown model kind %r" % (kind,))

@@ -150,20 +150,21 @@ __device__ __forceinline__ FilterView load_filter(const StepArgs& a, int f) {
 }
 __device__ __forceinline__ bool ident_slots(unsigned char c, int copy) { return (c >> (1 + copy)) & 1; }
 
-// fz_pre for a whole segment whose lanes share the outer particle: lane q of
-// each wave's part of the segment evaluates component q once, and the
-// components are broadcast (readlane within a wave, lane permutes when two
-// segments share a wave) instead of every lane evaluating all of them.
+// fz_pre (transition out of time ts) for a whole segment whose lanes share
+// the outer particle: lane q of each wave's part of the segment evaluates
+// component q once, and the components are broadcast (readlane within a
+// wave, lane permutes when two segments share a wave) instead of every lane
+// evaluating all of them.
 template <class Mdl, int SEG>
-__device__ __forceinline__ void fz_pre_seg(const float* P, const float* xp, const float* xn, float* pre) {
+__device__ __forceinline__ void fz_pre_seg(const float* P, const float* xp, const float* xn, int ts, float* pre) {
   constexpr int DZ = Mdl::DZ;
   constexpr int W = SEG < 64 ? SEG : 64;
   if constexpr (DZ > W) {
-    Mdl::fz_pre(P, xp, xn, pre);
+    Mdl::fz_pre(P, xp, xn, ts, pre);
   } else {
     const int lane = threadIdx.x & 63;
     const int q = lane % W;
-    const float mine = Mdl::fz_pre_k(P, xp, xn, q < DZ ? q : 0);
+    const float mine = Mdl::fz_pre_k(P, xp, xn, ts, q < DZ ? q : 0);
     if constexpr (W == 64) {
 #pragma unroll
       for (int k = 0; k < DZ; ++k) pre[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mine), k));
@@ -333,7 +334,7 @@ __device__ __forceinline__ float la_logpy(const StepArgs& a, const Key& key, int
   normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
   normals<Mdl::DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, nu_z);
   Mdl::fx(a.prm, x, z, nu_x, xl);
-  Mdl::fz_pre(a.prm, x, xl, pre);
+  Mdl::fz_pre(a.prm, x, xl, t - 1, pre);
   Mdl::fz_post(a.prm, pre, z, nu_z, zl);
   Mdl::obs_pre(a.prm, y, xl, r0);
   return Mdl::logpy_post(a.prm, r0, zl);
@@ -1530,7 +1531,8 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
 
   // ---- 4. gather + propagate (+ measurement update in look-ahead mode) ---
   float pre[DZ];
-  fz_pre_seg<Mdl, SEG>(a.prm, xp, xn, pre);
+  // (plain: t is the step just taken and the proposal is for t + 1)
+  fz_pre_seg<Mdl, SEG>(a.prm, xp, xn, PLAIN ? t : t - 1, pre);
   float y[DY], r0[DY];
   if (!PLAIN) {
     load_y<Mdl>(a, f, t, y);

@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
 
   // ---- 3. local resampling, propagation, measurement update --------------
   float pre[DZ];
-  fz_pre_seg<Mdl, SEG>(a.prm, xp, xn, pre);
+  fz_pre_seg<Mdl, SEG>(a.prm, xp, xn, t - 1, pre);
   float y[DY], r0[DY];
   load_y<Mdl>(a, f, t, y);
   Mdl::obs_pre(a.prm, y, xn, r0);

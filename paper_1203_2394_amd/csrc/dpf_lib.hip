@@ -240,6 +240,17 @@ static void derive_highdim(int dx, int dz, int dy, const double* p, std::vector<
   o.push_back((float)(1.0 / (nu * r)));                          // inv_nur
 }
 
+static void derive_twodim(const double* p, std::vector<float>& o) {
+  const double qx = p[0], qz = p[1], cxz = p[2], r = p[7];
+  o.push_back((float)sqrt(qx));                          // sx
+  o.push_back((float)(cxz / qx));                        // kz
+  o.push_back((float)sqrt(qz - cxz * cxz / qx));         // szc
+  o.push_back((float)(1.0 / qx));                        // inv_qx
+  o.push_back((float)(-0.5 * log(2.0 * M_PI * qx)));     // cx
+  o.push_back((float)(1.0 / r));                         // inv_r
+  o.push_back((float)(-0.5 * log(2.0 * M_PI * r)));      // cy
+}
+
 using MLG = LinGauss<1, 2, 1>;
 using MNL = NonLin<2, 8>;
 using MHD = HighDim<4, 64, 32>;
@@ -254,6 +265,9 @@ static const Engine kEngines[] = {
     {4, 64, 32, (size_t)MHD::L::n_raw, (size_t)MHD::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_highdim(4, 64, 32, p, o); },
      engine_launch<MHD>, nullptr, nullptr, has_moments<MHD>()},
+    {1, 1, 1, (size_t)TwoDim::L::n_raw, (size_t)TwoDim::L::n_total,
+     [](const double* p, std::vector<float>& o) { derive_twodim(p, o); }, engine_launch<TwoDim>, nullptr,
+     nullptr, has_moments<TwoDim>()},
 };
 
 static const Engine* find_engine(int model, int dx, int dz, int dy) {
@@ -261,6 +275,7 @@ static const Engine* find_engine(int model, int dx, int dz, int dy) {
   if (model == DPF_MODEL_LINGAUSS) idx = 0;
   if (model == DPF_MODEL_NONLIN) idx = 1;
   if (model == DPF_MODEL_HIGHDIM) idx = 2;
+  if (model == DPF_MODEL_TWODIM) idx = 3;
   if (idx < 0) return nullptr;
   const Engine* e = &kEngines[idx];
   if (e->dx != dx || e->dz != dz || e->dy != dy) return nullptr;
@@ -302,6 +317,11 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
                 c->dy);
   if (!c->params || c->n_params != eng->n_raw)
     return fail(DPF_EINVAL, "model %d needs %zu parameters, got %zu", c->model, eng->n_raw, c->n_params);
+  if (c->model == DPF_MODEL_TWODIM) {
+    const double qx = c->params[0], qz = c->params[1], cxz = c->params[2], r = c->params[7];
+    if (!(qx > 0.0 && r > 0.0 && qz * qx > cxz * cxz))
+      return fail(DPF_EINVAL, "TWODIM needs qx > 0, r > 0 and a positive definite noise covariance");
+  }
   if (c->n_filters < 1 || !c->N || !c->M) return fail(DPF_EINVAL, "need n_filters >= 1 and N, M arrays");
   const int F = c->n_filters;
   L.NT = 0;
@@ -513,6 +533,7 @@ static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a) {
   FIN(1, 2)
   FIN(2, 8)
   FIN(4, 64)
+  FIN(1, 1)
 #undef FIN
   return fail(DPF_EUNSUPPORTED, "no finalize kernel for dims (%d,%d)", h->dx, h->dz);
 }
@@ -540,6 +561,7 @@ static dpf_status launch_post(dpf_handle* h, const StepArgs& a, int next) {
   POST(1, 2)
   POST(2, 8)
   POST(4, 64)
+  POST(1, 1)
 #undef POST
   return fail(DPF_EUNSUPPORTED, "no step-end kernel for dims (%d,%d)", h->dx, h->dz);
 }

@@ -5,7 +5,8 @@
 // done once per segment when it is uniform there:
 //
 //   fx(P, x, z, nu, xn)           x_{t+1} = f^x(x_t, z_t, v^x)    (nu: DX normals)
-//   fz_pre(P, x, xn, pre)         the part of f^z that depends only on x_{t:t+1}
+//   fz_pre(P, x, xn, t, pre)      the part of f^z that depends only on x_{t:t+1}
+//                                 (and on t, for a time-varying model)
 //   fz_post(P, pre, z, nu, zn)    z_{t+1} = f^z(x_{t:t+1}, z_t, v^z) (nu: DZ normals)
 //   obs_pre(P, y, x, r0)          the part of y - h(x, z) that depends only on x
 //   logpy_post(P, r0, z)          log p(y_t | x_t, z_t)
@@ -68,11 +69,11 @@ struct LinGauss {
       xn[a] = s + P[L::sx] * nu[a];
     }
   }
-  __device__ static void fz_pre(const float* P, const float* x, const float* xn, float* pre) {
+  __device__ static void fz_pre(const float* P, const float* x, const float* xn, int t, float* pre) {
 #pragma unroll
-    for (int a = 0; a < DZ; ++a) pre[a] = fz_pre_k(P, x, xn, a);
+    for (int a = 0; a < DZ; ++a) pre[a] = fz_pre_k(P, x, xn, t, a);
   }
-  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int a) {
+  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int, int a) {
     float s = 0.f;
 #pragma unroll
     for (int b = 0; b < DX; ++b) s += P[L::Bzx + a * DX + b] * xn[b];
@@ -150,11 +151,11 @@ struct NonLin {
 #pragma unroll
     for (int d = 0; d < DX; ++d) xn[d] = growth(a, b, x[d]) + s * nu[d];
   }
-  __device__ static void fz_pre(const float* P, const float* x, const float* xn, float* pre) {
+  __device__ static void fz_pre(const float* P, const float* x, const float* xn, int t, float* pre) {
 #pragma unroll
-    for (int k = 0; k < DZ; ++k) pre[k] = fz_pre_k(P, x, xn, k);
+    for (int k = 0; k < DZ; ++k) pre[k] = fz_pre_k(P, x, xn, t, k);
   }
-  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int k) {
+  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int, int k) {
     float s = 0.f;
 #pragma unroll
     for (int d = 0; d < DX; ++d) s += P[L::W + k * DX + d] * xn[d];
@@ -227,7 +228,7 @@ struct HighDim {
 #pragma unroll
     for (int d = 0; d < DX; ++d) xn[d] = growth(a, b, x[d]) + s * nu[d];
   }
-  __device__ static void fz_pre(const float* P, const float*, const float* xn, float* pre) {
+  __device__ static void fz_pre(const float* P, const float*, const float* xn, int, float* pre) {
     float sn[DX];
 #pragma unroll
     for (int d = 0; d < DX; ++d) sn[d] = __builtin_amdgcn_sinf(xn[d] * kInv2Pi);
@@ -239,7 +240,7 @@ struct HighDim {
       pre[k] = s;
     }
   }
-  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int k) {
+  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int, int k) {
     float s = 0.f;
 #pragma unroll
     for (int d = 0; d < DX; ++d) s += P[L::B + k * DX + d] * __builtin_amdgcn_sinf(xn[d] * kInv2Pi);
@@ -288,6 +289,56 @@ struct HighDim {
       q += e * e;
     }
     return P[L::cx] - 0.5f * P[L::inv_qx] * q;
+  }
+};
+
+// ------------------------------------------------------------------ TWODIM
+// Model 1 of Table 1 (the 2-dimensional example), dx = dz = dy = 1:
+//   x' = x + z / (1 + z^2) + v^x ,
+//   z' = x + rho z + b z / (1 + z^2) + amp cos(freq t) + v^z ,
+//   y  = atan(x) + z^2 / 20 + e ,
+// (v^x, v^z) ~ N(0, [[qx, cxz], [cxz, qz]]), e ~ N(0, r); t is the time of
+// the state the transition leaves.  The outer transition depends on z
+// (kXdepZ); given x' the inner noise is v^z | v^x ~ N(kz v^x, qz|x) with
+// kz = cxz / qx, qz|x = qz - cxz^2 / qx, v^x = x' - x - z / (1 + z^2).
+struct TwoDim {
+  static constexpr int DX = 1, DZ = 1, DY = 1;
+  static constexpr bool kXdepZ = true;
+  struct Layout {
+    static constexpr int qx = 0, qz = 1, cxz = 2, rho = 3, b = 4, amp = 5, freq = 6, r = 7, n_raw = 8;
+    static constexpr int sx = n_raw, kz = sx + 1, szc = kz + 1, inv_qx = szc + 1, cx = inv_qx + 1,
+                         inv_r = cx + 1, cy = inv_r + 1, n_total = cy + 1;
+  };
+  using L = Layout;
+
+  __device__ static float sat(float z) { return z / (1.0f + z * z); }
+  __device__ static void fx(const float* P, const float* x, const float* z, const float* nu, float* xn) {
+    xn[0] = x[0] + sat(z[0]) + P[L::sx] * nu[0];
+  }
+  // x + amp cos(freq t) + kz (x' - x); the angle in double (t runs to
+  // thousands of radians)
+  __device__ static float fz_pre_k(const float* P, const float* x, const float* xn, int t, int) {
+    const float cyc = (float)((double)P[L::amp] * cos((double)P[L::freq] * (double)t));
+    return x[0] + cyc + P[L::kz] * (xn[0] - x[0]);
+  }
+  __device__ static void fz_pre(const float* P, const float* x, const float* xn, int t, float* pre) {
+    pre[0] = fz_pre_k(P, x, xn, t, 0);
+  }
+  // pre + rho z + b z/(1+z^2) - kz z/(1+z^2) + sqrt(qz|x) nu
+  __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu, float* zn) {
+    const float g = sat(z[0]);
+    zn[0] = pre[0] + P[L::rho] * z[0] + P[L::b] * g - P[L::kz] * g + P[L::szc] * nu[0];
+  }
+  __device__ static void obs_pre(const float*, const float* y, const float* x, float* r0) {
+    r0[0] = y[0] - atanf(x[0]);
+  }
+  __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
+    const float e = r0[0] - 0.05f * z[0] * z[0];
+    return P[L::cy] - 0.5f * P[L::inv_r] * e * e;
+  }
+  __device__ static float logpx(const float* P, const float* xn, const float* x, const float* z) {
+    const float e = xn[0] - x[0] - sat(z[0]);
+    return P[L::cx] - 0.5f * P[L::inv_qx] * e * e;
   }
 };
 

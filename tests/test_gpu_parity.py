@@ -37,6 +37,7 @@ SPECS = {
     "nonlin_bmode1": lambda: S.nonlin_c2(2, bmode=1),
     "highdim": lambda: S.highdim_c4(1),
     "highdim_gauss": lambda: S.highdim_c4(1, gaussian_only=True),
+    "twodim": lambda: S.twodim_table1(),
 }
 
 
@@ -82,6 +83,9 @@ def _la_case(name, N, M, warm, steps, seed=4242, data_seed=3):
     ("nonlin_bmode1", 64, 128, 1, 1),
     ("highdim", 8, 1024, 1, 1),
     ("highdim_gauss", 12, 100, 1, 1),
+    ("twodim", 130, 64, 3, 3),
+    ("twodim", 37, 300, 6, 2),
+    ("twodim", 500, 19, 2, 2),
 ])
 def test_lookahead_step_parity(name, N, M, warm, steps):
     for r, info, est in _la_case(name, N, M, warm, steps):
@@ -131,6 +135,8 @@ def _plain_case(name, N, M, warm, steps, seed=777, data_seed=5):
     ("lingauss_coupled", 64, 37, 2, 2),
     ("nonlin", 300, 200, 1, 2),
     ("highdim", 8, 1024, 1, 1),
+    ("twodim", 130, 64, 3, 2),
+    ("twodim", 300, 19, 5, 2),
 ])
 def test_plain_step_parity(name, N, M, warm, steps):
     for r, info, est in _plain_case(name, N, M, warm, steps):
@@ -184,7 +190,8 @@ def _tiling_start_cached(name, algo, N, M, seed):
     ("nonlin", 3, 40, 150), ("nonlin", 2, 7, 150), ("nonlin", 9, 256, 150), ("nonlin", 9, 130, 150),
     ("nonlin", 10, 200, 150), ("nonlin", 10, 256, 150),
     ("lingauss_coupled", 9, 200, 90), ("lingauss_coupled", 10, 150, 90), ("lingauss_coupled", 3, 100, 90),
-    ("nonlin", 9, 8, 16700), ("nonlin", 3, 8, 16700), ("nonlin", 0, 8, 16700)])
+    ("nonlin", 9, 8, 16700), ("nonlin", 3, 8, 16700), ("nonlin", 0, 8, 16700),
+    ("twodim", 9, 200, 90), ("twodim", 7, 100, 90)])
 @pytest.mark.parametrize("algo", ["lookahead", "plain"])
 def test_step_parity_under_every_tiling(name, cls, M, N, algo):
     """The same step under a non-default tile class (SEG, JPT) matches the

@@ -122,6 +122,30 @@ def test_run_chunks_and_remainder_equal_step_calls(T):
             assert torch.equal(a.copy_buffer(buf), b.copy_buffer(buf)), (rep, buf)
 
 
+@pytest.mark.parametrize("algo", ["lookahead", "plain"])
+def test_time_varying_model_run_equals_step_calls(algo):
+    """Model 1 of Table 1 has a drift that depends on t: a run (fused
+    steps across a chunk boundary) and step calls must agree bit for bit."""
+    spec = S.twodim_table1()
+    N, M, T = [300, 77], [64, 130], 19
+    Y = np.stack([S.simulate(spec, T, 61 + f)[2] for f in range(2)], axis=1).astype(np.float32)
+    a = _filter(spec, N, M, algo=algo)
+    step = a.lookahead_step if algo == "lookahead" else a.step
+    for t in range(T):
+        step(torch.from_numpy(Y[t]))
+    b = _filter(spec, N, M, algo=algo)
+    xt, _ = b.run(torch.from_numpy(Y), use_graph=True)
+    # (the plain DPF's state is the proposals x, z; its lam block is unused)
+    sa, sb = a.unpack_state(a.export_state()), b.unpack_state(b.export_state())
+    keys = ("t", "x", "z", "lam") if algo == "lookahead" else ("t", "x", "z")
+    for k in keys:
+        for u, v in zip(sa[k], sb[k]):
+            assert np.array_equal(u, v), k
+    assert torch.equal(a.estimate()["xhat"], b.estimate()["xhat"])
+    assert torch.equal(a.estimate()["zhat"], b.estimate()["zhat"])
+    assert np.all(np.isfinite(xt.cpu().numpy()))
+
+
 @pytest.mark.parametrize("use_run", [False, True])
 def test_step_end_kernels_agree(use_run):
     """Filter 0 alone (one step-end launch) and next to a filter of 66

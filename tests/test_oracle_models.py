@@ -89,3 +89,89 @@ def test_broadcasting_shapes():
     nu = np.zeros((5, 7, 2))
     assert m.fx(x, z, nu).shape == (5, 7, 2)
     assert m.logpy(np.zeros(8), m.fx(x, z, nu), z).shape == (5, 7)
+
+
+def test_twodim_transition_is_the_joint_gaussian_of_table1():
+    """Model 1 of Table 1.  The factorised transition p(x'|x,z) p(z'|x,x',z)
+    of the oracle must be the joint law of Table 1: the pair of noises
+    (x' - mean_x, z' - mean_z) is N(0, [[1, .1], [.1, 1]]).  Both densities
+    are checked against SciPy's bivariate normal: log p(x'|.) from logpx, and
+    the inner conditional from the sampler (affine in its normal), so a wrong
+    conditional mean (a dropped v^x term, a wrong sign) or variance fails."""
+    spec = S.twodim_table1()
+    m = _model(spec)
+    # (the library stores parameters in FP32; the spec rounds them once)
+    cov = np.array([[1.0, 0.1], [0.1, 1.0]], dtype=np.float32).astype(np.float64)
+    f12 = float(np.float32(1.2))
+    g = np.random.default_rng(5)
+    for _ in range(50):
+        x, z, t = g.normal(size=1) * 3, g.normal(size=1) * 3, int(g.integers(0, 400))
+        mean_x = x[0] + z[0] / (1 + z[0] ** 2)
+        mean_z = x[0] + 0.5 * z[0] + 25 * z[0] / (1 + z[0] ** 2) + 8 * math.cos(f12 * t)
+        vx, vz = g.normal(size=2) * 1.3
+        xn = np.array([mean_x + vx])
+        # z' = a + c * nu for the sampler: recover a and c, then the density
+        a = m.fz(x, xn, z, np.zeros(1), t)[0]
+        c = m.fz(x, xn, z, np.ones(1), t)[0] - a
+        log_cond = stats.norm.logpdf(mean_z + vz, a, abs(c))
+        joint = stats.multivariate_normal(mean=[0.0, 0.0], cov=cov).logpdf([vx, vz])
+        assert np.isclose(float(m.logpx(xn, x, z)) + log_cond, joint, rtol=0, atol=1e-9)
+    # the time-varying drift: 8 cos(1.2 t) with t the time the transition leaves
+    x, z, xn = np.array([0.3]), np.array([-1.2]), np.array([0.1])
+    d = m.fz(x, xn, z, np.zeros(1), 7)[0] - m.fz(x, xn, z, np.zeros(1), 2)[0]
+    assert np.isclose(d, 8 * (math.cos(1.2 * 7) - math.cos(1.2 * 2)), atol=1e-5)
+
+
+def test_twodim_likelihood_matches_scipy_and_integrates_to_one():
+    spec = S.twodim_table1()
+    m = _model(spec)
+    g = np.random.default_rng(6)
+    for _ in range(20):
+        x, z, y = g.normal(size=1) * 4, g.normal(size=1) * 4, g.normal(size=1) * 3
+        want = stats.norm.logpdf(y[0], math.atan(x[0]) + z[0] ** 2 / 20, 1.0)
+        assert np.isclose(m.logpy(y, x, z), want)
+    ys = np.linspace(-15, 25, 40001)[:, None]
+    dens = np.exp(m.logpy(ys, np.array([0.7]), np.array([2.0])))
+    assert abs(np.trapezoid(dens, ys[:, 0]) - 1.0) < 1e-6
+
+
+def test_twodim_simulator_noise_covariance():
+    """The simulator's own restatement of Table 1 (a separate module) draws
+    noise pairs with the stated covariance."""
+    spec = S.twodim_table1()
+    xs, zs, _ = S.simulate(spec, 40000, 11)
+    x, z = xs[:-1, 0], zs[:-1, 0]
+    t = np.arange(len(x))
+    vx = xs[1:, 0] - x - z / (1 + z * z)
+    vz = zs[1:, 0] - (x + 0.5 * z + 25 * z / (1 + z * z) + 8 * np.cos(float(np.float32(1.2)) * t))
+    c = np.cov(np.stack([vx, vz]))
+    assert np.allclose(c, [[1.0, 0.1], [0.1, 1.0]], atol=0.03)
+
+
+def test_twodim_time_convention_in_the_filters():
+    """Table 1 writes z_{t+1} with 8 cos(1.2 t): the step that consumes y_t
+    propagates out of time t - 1 (look-ahead draws and new clouds), the plain
+    DPF's step t proposes t + 1 out of time t."""
+    from oracle import dpf as odpf
+    from oracle import ladpf
+    from oracle import philox as P
+    spec = S.twodim_table1()
+    m = _model(spec)
+    f12 = float(np.float32(1.2))
+    st = ladpf.init_state(m, 3, 4, 9, 0)
+    st["t"] = 4                                   # the step consumes y_5
+    xla, zla, _, _ = ladpf.lookahead(m, st, np.array([0.2]), 9, 0)
+    nu_z = P.normals(9, 0, 5, np.arange(3)[:, None], np.arange(4)[None, :], P.LA_Z, 1)
+    x, z = st["x"][:, None, :], st["z"]
+    vx = xla - x - z / (1 + z * z)
+    want = x + 0.5 * z + 25 * z / (1 + z * z) + 8 * math.cos(f12 * 4) + 0.1 * vx + math.sqrt(0.99) * nu_z
+    assert np.allclose(zla, want, atol=1e-6)
+    # plain: step t = 5 proposes z_6 out of time 5
+    xs, zs = st["x"], st["z"]
+    xn, zn, anc, b, _ = odpf.propose(m, xs, zs, np.full((3, 4), -math.log(4)), np.arange(3), 5, 9, 0)
+    nu = np.stack([P.normals(9, 0, 5, k, np.arange(4), P.DPF_Z, 1) for k in range(3)])
+    zp = np.stack([zs[k, b[k]] for k in range(3)])
+    vx = xn[:, None, :] - xs[:, None, :] - zp / (1 + zp * zp)
+    want = xs[:, None, :] + 0.5 * zp + 25 * zp / (1 + zp * zp) + 8 * math.cos(f12 * 5) + 0.1 * vx \
+        + math.sqrt(0.99) * nu
+    assert np.allclose(zn, want, atol=1e-6)
