@@ -161,7 +161,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched ragged-filter run")
     ap.add_argument("--no-highdim", action="store_true", help="skip the high-dimensional inner block run")
-    ap.add_argument("--no-twodim", action="store_true", help="skip the Table 1 model 1 runs")
+    ap.add_argument("--no-table1", action="store_true", help="skip the runs of the models of Table 1")
     ap.add_argument("--no-fixed-rmse", action="store_true",
                     help="skip the fixed-RMSE comparison of the look-ahead, plain and learned steps")
     ap.add_argument("--cpu-baseline-child", type=int, default=0)
@@ -285,7 +285,10 @@ def main():
         fixed = run_fixed_rmse(S, dpf, torch, np, dev, mlp)
     batched = None if (args.no_batched or args.only_run) else run_batched(S, dpf, torch, np, dev)
     highdim = None if (args.no_highdim or args.only_run) else run_highdim(S, dpf, torch, np, dev)
-    twodim = None if (args.no_twodim or args.only_run) else run_twodim(S, dpf, torch, np, dev)
+    table1 = None
+    if not (args.no_table1 or args.only_run):
+        table1 = {"model1": run_table1(S, dpf, torch, np, dev, S.twodim_table1(), "Table 1 model 1"),
+                  "model2": run_table1(S, dpf, torch, np, dev, S.fourdim_table1(), "Table 1 model 2")}
     cpu = None if (args.no_cpu_baseline or args.only_run) else run_cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
@@ -314,7 +317,7 @@ def main():
         "fixed_rmse": fixed,
         "batched": batched,
         "highdim": highdim,
-        "table1_model1": twodim,
+        "table1": table1,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
@@ -390,21 +393,20 @@ def run_fixed_rmse(S, dpf, torch, np, dev, mlp):
 TD_SEQS, TD_T, TD_N, TD_M, TD_SEED = 32, 250, 4096, 256, 12000
 
 
-def run_twodim(S, dpf, torch, np, dev):
-    """Model 1 of Table 1 (dx = dz = dy = 1, time-varying drift, correlated
-    noises): TD_SEQS fresh sequences of TD_T steps as filters of one handle
-    (N = 4096, M = 256), look-ahead and plain runs, graph-replayed; updates/s
-    of the second run of each handle and the RMSE of x_hat and z_hat."""
-    spec = S.twodim_table1()
+def run_table1(S, dpf, torch, np, dev, spec, name):
+    """A model of Table 1 (time-varying drifts): TD_SEQS fresh sequences of
+    TD_T steps as filters of one handle (N = 4096, M = 256), look-ahead and
+    plain runs, graph-replayed; updates/s of the second run of each handle
+    and the RMSE of x_hat and z_hat."""
     sims = [S.simulate(spec, TD_T, TD_SEED + q) for q in range(TD_SEQS)]
     Y = torch.tensor(np.stack([sm[2] for sm in sims], axis=1), dtype=torch.float32, device=dev).contiguous()
     tx = np.stack([sm[0][1:] for sm in sims], axis=1)
     tz = np.stack([sm[1][1:] for sm in sims], axis=1)
-    out = {"config": {"workload": "Table 1 model 1 (dx=dz=dy=1), %d sequences x T=%d as filters of one handle, "
-                                  "N=%d, M=%d" % (TD_SEQS, TD_T, TD_N, TD_M)}}
+    out = {"config": {"workload": "%s (dx=%d dz=%d dy=%d), %d sequences x T=%d as filters of one handle, "
+                                  "N=%d, M=%d" % (name, spec.dx, spec.dz, spec.dy, TD_SEQS, TD_T, TD_N, TD_M)}}
     for algo in ("lookahead", "plain"):
-        f = dpf.Filter(spec.kind, 1, 1, 1, spec.blob, [TD_N] * TD_SEQS, [TD_M] * TD_SEQS, seed=FILTER_SEED,
-                       device=dev, algo=algo)
+        f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [TD_N] * TD_SEQS, [TD_M] * TD_SEQS,
+                       seed=FILTER_SEED, device=dev, algo=algo)
         xt, zt = f.run(Y, use_graph=True)
         ex = np.sqrt(np.mean((xt.cpu().numpy() - tx) ** 2, axis=(0, 2)))
         ez = np.sqrt(np.mean((zt.cpu().numpy() - tz) ** 2, axis=(0, 2)))

@@ -14,13 +14,14 @@ LINGAUSS: Ax[dx*dx] Cxz[dx*dz] qx Az[dz*dz] Bzx[dz*dx] qz Hx[dy*dx] Hz[dy*dz] r
 NONLIN:   a b qx W[dz*dx] rho qz c r bmode
 HIGHDIM:  a b qx Alo[dz-1] Adiag[dz] Aup[dz-1] B[dz*dx] qz C[dy*dz] r eps nu gonly
 TWODIM:   qx qz cxz rho b amp freq r
+FOURDIM:  a1 bs c21 a2 qx1 qx2 qz1 qz2 cz rho b amp freq r
 """
 from dataclasses import dataclass, field
 from typing import List, Optional
 
 import numpy as np
 
-LINGAUSS, NONLIN, HIGHDIM, TWODIM = 1, 2, 3, 4
+LINGAUSS, NONLIN, HIGHDIM, TWODIM, FOURDIM = 1, 2, 3, 4, 5
 
 
 @dataclass
@@ -33,7 +34,8 @@ class ModelSpec:
 
     @property
     def name(self):
-        return {LINGAUSS: "lingauss", NONLIN: "nonlin", HIGHDIM: "highdim", TWODIM: "twodim"}[self.kind]
+        return {LINGAUSS: "lingauss", NONLIN: "nonlin", HIGHDIM: "highdim", TWODIM: "twodim",
+                FOURDIM: "fourdim"}[self.kind]
 
 
 def lingauss_c1(coupled: bool = False) -> ModelSpec:
@@ -64,6 +66,20 @@ def twodim_table1(qx: float = 1.0, qz: float = 1.0, cxz: float = 0.1) -> ModelSp
     """
     blob = np.array([qx, qz, cxz, 0.5, 25.0, 8.0, 1.2, 1.0], dtype=np.float32).astype(np.float64)
     return ModelSpec(TWODIM, 1, 1, 1, blob)
+
+
+def fourdim_table1() -> ModelSpec:
+    """Model 2 of Table 1 (the 4-dimensional example), dx = dz = 2, dy = 1:
+
+    x1' = 0.5 x1 + 8 sin t + v1,  x2' = 0.4 x1 + 0.5 x2 + v2
+    z1' = z1 + z2 / (1 + z2^2) + w1
+    z2' = z1' + 0.5 z2 + 25 z2 / (1 + z2^2) + 8 cos(1.2 t) + w2
+    y = (x1 + x2) / (1 + x1^2) + atan(z1) + z2^2 / 20 + e
+    v ~ N(0, I), (w1, w2) ~ N(0, [[1, 0.1], [0.1, 10]]), e ~ N(0, 1).
+    """
+    blob = np.array([0.5, 8.0, 0.4, 0.5, 1.0, 1.0, 1.0, 10.0, 0.1, 0.5, 25.0, 8.0, 1.2, 1.0],
+                    dtype=np.float32).astype(np.float64)
+    return ModelSpec(FOURDIM, 2, 2, 1, blob)
 
 
 def nonlin_c2(param_seed: int = 1, dx: int = 2, dz: int = 8, bmode: int = 0) -> ModelSpec:
@@ -115,7 +131,7 @@ def _sim_fns(spec: ModelSpec):
         Hx = b[o:o + dy * dx].reshape(dy, dx); o += dy * dx
         Hz = b[o:o + dy * dz].reshape(dy, dz); o += dy * dz
         r = b[o]
-        fx = lambda x, z, g: Ax @ x + Cxz @ z + np.sqrt(qx) * g.normal(size=dx)
+        fx = lambda x, z, g, t: Ax @ x + Cxz @ z + np.sqrt(qx) * g.normal(size=dx)
         fz = lambda x, xn, z, g, t: Az @ z + Bzx @ xn + np.sqrt(qz) * g.normal(size=dz)
         hy = lambda x, z, g: Hx @ x + Hz @ z + np.sqrt(r) * g.normal(size=dy)
         return fx, fz, hy
@@ -123,7 +139,7 @@ def _sim_fns(spec: ModelSpec):
         a, bb, qx = b[0], b[1], b[2]
         W = b[3:3 + dz * dx].reshape(dz, dx)
         rho, qz, c, r, bmode = b[3 + dz * dx:3 + dz * dx + 5]
-        fx = lambda x, z, g: a * x + bb * x / (1 + x * x) + np.sqrt(qx) * g.normal(size=dx)
+        fx = lambda x, z, g, t: a * x + bb * x / (1 + x * x) + np.sqrt(qx) * g.normal(size=dx)
         fz = lambda x, xn, z, g, t: np.tanh(W @ xn) + rho * z + np.sqrt(qz) * g.normal(size=dz)
 
         def hy(x, z, g):
@@ -141,7 +157,7 @@ def _sim_fns(spec: ModelSpec):
         qz = b[o]; o += 1
         C = b[o:o + dy * dz].reshape(dy, dz); o += dy * dz
         r, eps, nu, gonly = b[o:o + 4]
-        fx = lambda x, z, g: a * x + bb * x / (1 + x * x) + np.sqrt(qx) * g.normal(size=dx)
+        fx = lambda x, z, g, t: a * x + bb * x / (1 + x * x) + np.sqrt(qx) * g.normal(size=dx)
         fz = lambda x, xn, z, g, t: A @ z + B @ np.sin(xn) + np.sqrt(qz) * g.normal(size=dz)
 
         def hy(x, z, g):
@@ -154,13 +170,27 @@ def _sim_fns(spec: ModelSpec):
     if spec.kind == TWODIM:
         qx, qz, cxz, rho, bb, amp, freq, r = b
         # the noise pair drawn jointly: v^x first, then v^z given v^x
-        fx = lambda x, z, g: x + z / (1 + z * z) + np.sqrt(qx) * g.normal(size=1)
+        fx = lambda x, z, g, t: x + z / (1 + z * z) + np.sqrt(qx) * g.normal(size=1)
 
         def fz(x, xn, z, g, t):
             vx = xn - x - z / (1 + z * z)
             vz = cxz / qx * vx + np.sqrt(qz - cxz * cxz / qx) * g.normal(size=1)
             return x + rho * z + bb * z / (1 + z * z) + amp * np.cos(freq * t) + vz
         hy = lambda x, z, g: np.arctan(x) + z * z / 20 + np.sqrt(r) * g.normal(size=1)
+        return fx, fz, hy
+    if spec.kind == FOURDIM:
+        a1, bs, c21, a2, qx1, qx2, qz1, qz2, cz, rho, bb, amp, freq, r = b
+
+        def fx(x, z, g, t):
+            v = g.normal(size=2) * np.sqrt([qx1, qx2])
+            return np.array([a1 * x[0] + bs * np.sin(t), c21 * x[0] + a2 * x[1]]) + v
+
+        def fz(x, xn, z, g, t):
+            w = g.multivariate_normal([0.0, 0.0], [[qz1, cz], [cz, qz2]])
+            z1 = z[0] + z[1] / (1 + z[1] ** 2) + w[0]
+            return np.array([z1, z1 + rho * z[1] + bb * z[1] / (1 + z[1] ** 2) + amp * np.cos(freq * t) + w[1]])
+        hy = lambda x, z, g: (np.array([(x[0] + x[1]) / (1 + x[0] ** 2) + np.arctan(z[0]) + z[1] ** 2 / 20])
+                              + np.sqrt(r) * g.normal(size=1))
         return fx, fz, hy
     raise ValueError(spec.kind)
 
@@ -173,7 +203,7 @@ def simulate(spec: ModelSpec, T: int, data_seed: int):
     z = g.normal(size=spec.dz)
     xs, zs, ys = [x], [z], []
     for s in range(T):
-        xn = fx(x, z, g)
+        xn = fx(x, z, g, s)
         zn = fz(x, xn, z, g, s)
         ys.append(hy(xn, zn, g))
         x, z = xn, zn

@@ -82,13 +82,24 @@ typedef enum {
  *   (v^x, v^z) ~ N(0, [[qx, cxz], [cxz, qz]]) ; y = atan(x) + z^2/20 + e,
  *   e ~ N(0, r).  Table 1's values: 1 1 0.1 0.5 25 8 1.2 1.  Needs qx > 0,
  *   r > 0 and qx qz > cxz^2 (else DPF_EINVAL).
+ * DPF_MODEL_FOURDIM -- model 2 of Table 1 (the 4-dimensional example), built
+ *   for (dx,dz,dy) = (2,2,1):
+ *   a1 bs c21 a2 qx1 qx2 qz1 qz2 cz rho b amp freq r
+ *   x1' = a1 x1 + bs sin t + v1 ; x2' = c21 x1 + a2 x2 + v2 ;
+ *   z1' = z1 + z2/(1+z2^2) + w1 ; z2' = z1' + rho z2 + b z2/(1+z2^2) +
+ *   amp cos(freq t) + w2, t the time of the state the transition leaves ;
+ *   v ~ N(0, diag(qx1, qx2)), (w1, w2) ~ N(0, [[qz1, cz], [cz, qz2]]) ;
+ *   y = (x1 + x2)/(1 + x1^2) + atan(z1) + z2^2/20 + e, e ~ N(0, r).
+ *   Table 1's values: 0.5 8 0.4 0.5 1 1 1 10 0.1 0.5 25 8 1.2 1.  Needs
+ *   positive variances and qz1 qz2 > cz^2 (else DPF_EINVAL).
  * Every model has the prior [x_0; z_0] ~ N(0, I).
  */
 typedef enum {
   DPF_MODEL_LINGAUSS = 1,
   DPF_MODEL_NONLIN = 2,
   DPF_MODEL_HIGHDIM = 3,
-  DPF_MODEL_TWODIM = 4
+  DPF_MODEL_TWODIM = 4,
+  DPF_MODEL_FOURDIM = 5
 } dpf_model;
 
 /* Which filter a handle runs. */

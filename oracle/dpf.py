@@ -51,8 +51,8 @@ def propose(model, x, z, lq, A, t, seed, fid):
         p = A[k]
         a, _, _ = systematic_log(lq[p], 1, float(u_anc[k]))
         anc[k] = a[0]
-        xn[k] = model.fx(x[p], z[p, anc[k]], nu_x[k])
-        kappa = lq[p] + model.logpx(xn[k], x[p], z[p])
+        xn[k] = model.fx(x[p], z[p, anc[k]], nu_x[k], t)
+        kappa = lq[p] + model.logpx(xn[k], x[p], z[p], t)
         b, deg_i, nonf_i = systematic_log(kappa, M, float(u_inner[k]))
         if deg_i:
             flags |= FLAG_DEGENERATE_INNER

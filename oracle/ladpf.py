@@ -75,7 +75,7 @@ def lookahead(model, state, y, seed, fid):
     nu_x = P.normals(seed, fid, t, i, j, P.LA_X, model.dx)
     nu_z = P.normals(seed, fid, t, i, j, P.LA_Z, model.dz)
     xp = x[:, None, :]
-    xla = model.fx(xp, z, nu_x)
+    xla = model.fx(xp, z, nu_x, t - 1)
     zla = model.fz(xp, xla, z, nu_z, t - 1)
     ell = lam + model.logpy(y, xla, zla)
     logw = logsumexp(ell)
@@ -131,7 +131,7 @@ def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None):
         c, deg_c, _ = systematic_log(ell[p], 1, float(u_cand[k]))
         cand[k] = c[0]
         xnew[k] = xla[p, cand[k]]
-        kappa = lam[p] + model.logpx(xnew[k], x[p], z[p])
+        kappa = lam[p] + model.logpx(xnew[k], x[p], z[p], t - 1)
         b, deg_i, nonf_i = systematic_log(kappa, M, float(u_inner[k]))
         if deg_i:
             flags |= FLAG_DEGENERATE_INNER

@@ -207,7 +207,7 @@ def step(model, state, y, seed, fid, mdn_out, ess_frac=0.1):
     j = np.arange(M)
     flags = 0
     for i in range(N):
-        kappa = lam[i] + model.logpx(xt[i], x[i], z[i])
+        kappa = lam[i] + model.logpx(xt[i], x[i], z[i], t - 1)
         log_px[i] = logsumexp(kappa)                       # eq:approx1 at xt_i
         b, deg_i, _ = systematic_log(kappa, M, float(u_in[i]))
         if deg_i:

@@ -7,11 +7,11 @@ z_{t+1} = f^z(x_{t:t+1}, z_t, v^z), y_t = h(x_t, z_t, e_t), equivalently as
 p(x_0), p(z_0|x_0), p(x_{t+1}|x_t,z_t), p(z_{t+1}|x_{t:t+1},z_t) and
 p(y_t|x_t,z_t), with all parameters known.  Each model below provides
 
-    fx(x, z, nu)        sample of x_{t+1} given standard normals nu (dx)
-    fz(x, xn, z, nu, t) sample of z_{t+1} given x_t, x_{t+1}, z_t, normals (dz);
-                        t is the time of the state the transition leaves
-                        (only a time-varying model uses it)
-    logpx(xn, x, z)     log p(x_{t+1} | x_t, z_t)
+    fx(x, z, nu, t)     sample of x_{t+1} given standard normals nu (dx)
+    fz(x, xn, z, nu, t) sample of z_{t+1} given x_t, x_{t+1}, z_t, normals (dz)
+    logpx(xn, x, z, t)  log p(x_{t+1} | x_t, z_t)
+    (t is the time of the state the transition leaves; only the models of
+    Table 1 use it)
     logpy(y, x, z)      log p(y_t | x_t, z_t)
 
 on arrays whose last axis is the state dimension (leading axes broadcast).
@@ -41,12 +41,18 @@ TWODIM (model 1 of Table 1, dx = dz = dy = 1):
     (v^x, v^z) ~ N(0, [[qx, cxz], [cxz, qz]]),  y = atan(x) + z^2/20 + e, e ~ N(0, r).
     In the factorisation of Eq. (1) the inner transition is conditioned on
     x_{t+1}, i.e. on v^x: v^z | v^x ~ N(cxz/qx v^x, qz - cxz^2/qx).
+FOURDIM (model 2 of Table 1, dx = dz = 2, dy = 1):
+    a1 bs c21 a2 qx1 qx2 qz1 qz2 cz rho b amp freq r
+    x1' = a1 x1 + bs sin t + v1,  x2' = c21 x1 + a2 x2 + v2,
+    z1' = z1 + z2/(1+z2^2) + w1,  z2' = z1' + rho z2 + b z2/(1+z2^2) + amp cos(freq t) + w2,
+    (v1, v2) ~ N(0, diag(qx1, qx2)), (w1, w2) ~ N(0, [[qz1, cz], [cz, qz2]]),
+    y = (x1 + x2)/(1 + x1^2) + atan(z1) + z2^2/20 + e, e ~ N(0, r).
 """
 import math
 
 import numpy as np
 
-LINGAUSS, NONLIN, HIGHDIM, TWODIM = 1, 2, 3, 4
+LINGAUSS, NONLIN, HIGHDIM, TWODIM, FOURDIM = 1, 2, 3, 4, 5
 
 LOG2PI = math.log(2.0 * math.pi)
 
@@ -87,13 +93,13 @@ class LinGauss:
     def mean_x(self, x, z):
         return _matvec(self.Ax, x) + _matvec(self.Cxz, z)
 
-    def fx(self, x, z, nu):
+    def fx(self, x, z, nu, t=0):
         return self.mean_x(x, z) + math.sqrt(self.qx) * nu
 
     def fz(self, x, xn, z, nu, t=0):
         return _matvec(self.Az, z) + _matvec(self.Bzx, xn) + math.sqrt(self.qz) * nu
 
-    def logpx(self, xn, x, z):
+    def logpx(self, xn, x, z, t=0):
         return _gauss_iso_logpdf(xn - self.mean_x(x, z), self.qx)
 
     def logpy(self, y, x, z):
@@ -120,13 +126,13 @@ class NonLin:
         if p != len(blob):
             raise ValueError("NONLIN blob has %d values, expected %d" % (len(blob), p))
 
-    def fx(self, x, z, nu):
+    def fx(self, x, z, nu, t=0):
         return _growth(self.a, self.b, x) + math.sqrt(self.qx) * nu
 
     def fz(self, x, xn, z, nu, t=0):
         return np.tanh(_matvec(self.W, xn)) + self.rho * z + math.sqrt(self.qz) * nu
 
-    def logpx(self, xn, x, z):
+    def logpx(self, xn, x, z, t=0):
         return _gauss_iso_logpdf(xn - _growth(self.a, self.b, x), self.qx)
 
     def obs_offset(self, x):
@@ -160,13 +166,13 @@ class HighDim:
         if p != len(blob):
             raise ValueError("HIGHDIM blob has %d values, expected %d" % (len(blob), p))
 
-    def fx(self, x, z, nu):
+    def fx(self, x, z, nu, t=0):
         return _growth(self.a, self.b, x) + math.sqrt(self.qx) * nu
 
     def fz(self, x, xn, z, nu, t=0):
         return _matvec(self.A, z) + _matvec(self.B, np.sin(xn)) + math.sqrt(self.qz) * nu
 
-    def logpx(self, xn, x, z):
+    def logpx(self, xn, x, z, t=0):
         return _gauss_iso_logpdf(xn - _growth(self.a, self.b, x), self.qx)
 
     def logpy(self, y, x, z):
@@ -207,7 +213,7 @@ class TwoDim:
     def mean_x(self, x, z):
         return x + self._sat(z)
 
-    def fx(self, x, z, nu):
+    def fx(self, x, z, nu, t=0):
         return self.mean_x(x, z) + math.sqrt(self.qx) * nu
 
     def fz(self, x, xn, z, nu, t=0):
@@ -215,11 +221,53 @@ class TwoDim:
         drift = x + self.rho * z + self.b * self._sat(z) + self.amp * math.cos(self.freq * t)
         return drift + self.kz * vx + math.sqrt(self.qzc) * nu
 
-    def logpx(self, xn, x, z):
+    def logpx(self, xn, x, z, t=0):
         return _gauss_iso_logpdf(xn - self.mean_x(x, z), self.qx)
 
     def logpy(self, y, x, z):
         return _gauss_iso_logpdf(y - np.arctan(x) - z * z / 20.0, self.r)
+
+
+class FourDim:
+    """Model 2 of Table 1: two outer and two inner components coupled only
+    through the observation; a sin t drift in x1, a cos(1.2 t) drift in z2,
+    correlated inner noises, z2' driven by the new z1'."""
+    kind = FOURDIM
+
+    def __init__(self, dx, dz, dy, blob):
+        if (dx, dz, dy) != (2, 2, 1):
+            raise ValueError("FOURDIM is (2, 2, 1)")
+        if len(blob) != 14:
+            raise ValueError("FOURDIM blob has %d values, expected 14" % len(blob))
+        self.dx, self.dz, self.dy = 2, 2, 1
+        (self.a1, self.bs, self.c21, self.a2, self.qx1, self.qx2, self.qz1, self.qz2, self.cz, self.rho,
+         self.b, self.amp, self.freq, self.r) = (float(v) for v in blob)
+        # (w1, w2) = L (nu1, nu2) with L L^T the inner noise covariance
+        self.L = np.linalg.cholesky(np.array([[self.qz1, self.cz], [self.cz, self.qz2]]))
+
+    def mean_x(self, x, t):
+        m1 = self.a1 * x[..., 0] + self.bs * math.sin(t)
+        m2 = self.c21 * x[..., 0] + self.a2 * x[..., 1]
+        return np.stack([m1, m2], axis=-1)
+
+    def fx(self, x, z, nu, t=0):
+        return self.mean_x(x, t) + np.sqrt([self.qx1, self.qx2]) * nu
+
+    def fz(self, x, xn, z, nu, t=0):
+        w = _matvec(self.L, nu)
+        z1 = z[..., 0] + z[..., 1] / (1.0 + z[..., 1] ** 2) + w[..., 0]
+        z2 = (z1 + self.rho * z[..., 1] + self.b * z[..., 1] / (1.0 + z[..., 1] ** 2)
+              + self.amp * math.cos(self.freq * t) + w[..., 1])
+        return np.stack([z1, z2], axis=-1)
+
+    def logpx(self, xn, x, z, t=0):
+        e = xn - self.mean_x(x, t)
+        return (-0.5 * e[..., 0] ** 2 / self.qx1 - 0.5 * e[..., 1] ** 2 / self.qx2
+                - 0.5 * (2 * LOG2PI + math.log(self.qx1) + math.log(self.qx2)))
+
+    def logpy(self, y, x, z):
+        h = (x[..., 0] + x[..., 1]) / (1.0 + x[..., 0] ** 2) + np.arctan(z[..., 0]) + z[..., 1] ** 2 / 20.0
+        return _gauss_iso_logpdf(y - h[..., None], self.r)
 
 
 def make_model(kind, dx, dz, dy, blob):
@@ -232,4 +280,6 @@ def make_model(kind, dx, dz, dy, blob):
         return HighDim(dx, dz, dy, blob)
     if kind == TWODIM:
         return TwoDim(dx, dz, dy, blob)
+    if kind == FOURDIM:
+        return FourDim(dx, dz, dy, blob)
     raise ValueError("unknown model kind %r" % (kind,))

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdpf.so")
 
 DPF_ABI_VERSION = 1
-MODEL_LINGAUSS, MODEL_NONLIN, MODEL_HIGHDIM, MODEL_TWODIM = 1, 2, 3, 4
+MODEL_LINGAUSS, MODEL_NONLIN, MODEL_HIGHDIM, MODEL_TWODIM, MODEL_FOURDIM = 1, 2, 3, 4, 5
 ALGO_LOOKAHEAD, ALGO_PLAIN = 0, 1
 FLAG_DEGENERATE_OUTER, FLAG_DEGENERATE_INNER, FLAG_NONFINITE, FLAG_FALLBACK = 1, 2, 4, 8
 BUF_ELL, BUF_LOGW, BUF_ANC, BUF_SEL, BUF_MDN, BUF_X, BUF_FALLBACK = range(7)

@@ -333,7 +333,7 @@ __device__ __forceinline__ float la_logpy(const StepArgs& a, const Key& key, int
   float nu_x[Mdl::DX], nu_z[Mdl::DZ], xl[Mdl::DX], pre[Mdl::DZ], zl[Mdl::DZ], r0[Mdl::DY];
   normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
   normals<Mdl::DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, nu_z);
-  Mdl::fx(a.prm, x, z, nu_x, xl);
+  Mdl::fx(a.prm, x, z, nu_x, t - 1, xl);
   Mdl::fz_pre(a.prm, x, xl, t - 1, pre);
   Mdl::fz_post(a.prm, pre, z, nu_z, zl);
   Mdl::obs_pre(a.prm, y, xl, r0);
@@ -1363,7 +1363,7 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
         normals<DX>(key, (uint32_t)t, (uint32_t)k, 0u, P_DPF_X, nu);
       else
         normals<DX>(key, (uint32_t)t, (uint32_t)pw, (uint32_t)cw, P_LA_X, nu);
-      Mdl::fx(a.prm, xpw, zc, nu, xw);
+      Mdl::fx(a.prm, xpw, zc, nu, PLAIN ? t : t - 1, xw);
       if (ls == 0) {
         if (!a.anc_ready) a.anc[oo + k] = pw;
         a.sel[oo + k] = cw;
@@ -1470,7 +1470,7 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
     else
       normals<DX>(key, (uint32_t)t, (uint32_t)p, (uint32_t)c, P_LA_X, nu);
     float xw[DX];
-    Mdl::fx(a.prm, xp, zc, nu, xw);
+    Mdl::fx(a.prm, xp, zc, nu, PLAIN ? t : t - 1, xw);
 #pragma unroll
     for (int d = 0; d < DX; ++d) xs_sh[s][d] = xw[d];
     if (vk) {
@@ -1504,7 +1504,7 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
         float zj[DZ];
 #pragma unroll
         for (int d = 0; d < DZ; ++d) zj[d] = kPreZ ? zpre[kPreZ ? r : 0][kPreZ ? d : 0] : zp[d * M + j];
-        kap += Mdl::logpx(a.prm, xn, xp, zj);
+        kap += Mdl::logpx(a.prm, xn, xp, zj, PLAIN ? t : t - 1);
       }
       ev[r] = kap;
       if (finitef(kap)) mk = fmaxf(mk, kap);

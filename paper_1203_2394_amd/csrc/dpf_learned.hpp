@@ -221,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
   float zd[DZ];
 #pragma unroll
   for (int d = 0; d < DZ; ++d) zd[d] = 0.f;
-  const float lpx0 = Mdl::kXdepZ ? 0.f : Mdl::logpx(a.prm, xn, xp, zd);
+  const float lpx0 = Mdl::kXdepZ ? 0.f : Mdl::logpx(a.prm, xn, xp, zd, t - 1);
   float ev[JPT];
   float mk = -INFINITY;
 #pragma unroll
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
         float zj[DZ];
 #pragma unroll
         for (int d = 0; d < DZ; ++d) zj[d] = zp[d * M + j];
-        kap += Mdl::logpx(a.prm, xn, xp, zj);
+        kap += Mdl::logpx(a.prm, xn, xp, zj, t - 1);
       } else {
         kap += lpx0;
       }

@@ -251,6 +251,20 @@ static void derive_twodim(const double* p, std::vector<float>& o) {
   o.push_back((float)(-0.5 * log(2.0 * M_PI * r)));      // cy
 }
 
+static void derive_fourdim(const double* p, std::vector<float>& o) {
+  const double qx1 = p[4], qx2 = p[5], qz1 = p[6], qz2 = p[7], cz = p[8], r = p[13];
+  o.push_back((float)sqrt(qx1));                                          // sx1
+  o.push_back((float)sqrt(qx2));                                          // sx2
+  o.push_back((float)sqrt(qz1));                                          // sz1
+  o.push_back((float)(cz / qz1));                                         // kz
+  o.push_back((float)sqrt(qz2 - cz * cz / qz1));                          // szc
+  o.push_back((float)(1.0 / qx1));                                        // inv_qx1
+  o.push_back((float)(1.0 / qx2));                                        // inv_qx2
+  o.push_back((float)(-0.5 * (log(2.0 * M_PI * qx1) + log(2.0 * M_PI * qx2))));  // cx
+  o.push_back((float)(1.0 / r));                                          // inv_r
+  o.push_back((float)(-0.5 * log(2.0 * M_PI * r)));                       // cy
+}
+
 using MLG = LinGauss<1, 2, 1>;
 using MNL = NonLin<2, 8>;
 using MHD = HighDim<4, 64, 32>;
@@ -268,6 +282,9 @@ static const Engine kEngines[] = {
     {1, 1, 1, (size_t)TwoDim::L::n_raw, (size_t)TwoDim::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_twodim(p, o); }, engine_launch<TwoDim>, nullptr,
      nullptr, has_moments<TwoDim>()},
+    {2, 2, 1, (size_t)FourDim::L::n_raw, (size_t)FourDim::L::n_total,
+     [](const double* p, std::vector<float>& o) { derive_fourdim(p, o); }, engine_launch<FourDim>, nullptr,
+     nullptr, has_moments<FourDim>()},
 };
 
 static const Engine* find_engine(int model, int dx, int dz, int dy) {
@@ -276,6 +293,7 @@ static const Engine* find_engine(int model, int dx, int dz, int dy) {
   if (model == DPF_MODEL_NONLIN) idx = 1;
   if (model == DPF_MODEL_HIGHDIM) idx = 2;
   if (model == DPF_MODEL_TWODIM) idx = 3;
+  if (model == DPF_MODEL_FOURDIM) idx = 4;
   if (idx < 0) return nullptr;
   const Engine* e = &kEngines[idx];
   if (e->dx != dx || e->dz != dz || e->dy != dy) return nullptr;
@@ -321,6 +339,11 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
     const double qx = c->params[0], qz = c->params[1], cxz = c->params[2], r = c->params[7];
     if (!(qx > 0.0 && r > 0.0 && qz * qx > cxz * cxz))
       return fail(DPF_EINVAL, "TWODIM needs qx > 0, r > 0 and a positive definite noise covariance");
+  }
+  if (c->model == DPF_MODEL_FOURDIM) {
+    const double* q = c->params;
+    if (!(q[4] > 0.0 && q[5] > 0.0 && q[6] > 0.0 && q[13] > 0.0 && q[6] * q[7] > q[8] * q[8]))
+      return fail(DPF_EINVAL, "FOURDIM needs positive variances and a positive definite inner noise covariance");
   }
   if (c->n_filters < 1 || !c->N || !c->M) return fail(DPF_EINVAL, "need n_filters >= 1 and N, M arrays");
   const int F = c->n_filters;
@@ -534,6 +557,7 @@ static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a) {
   FIN(2, 8)
   FIN(4, 64)
   FIN(1, 1)
+  FIN(2, 2)
 #undef FIN
   return fail(DPF_EUNSUPPORTED, "no finalize kernel for dims (%d,%d)", h->dx, h->dz);
 }
@@ -562,6 +586,7 @@ static dpf_status launch_post(dpf_handle* h, const StepArgs& a, int next) {
   POST(2, 8)
   POST(4, 64)
   POST(1, 1)
+  POST(2, 2)
 #undef POST
   return fail(DPF_EUNSUPPORTED, "no step-end kernel for dims (%d,%d)", h->dx, h->dz);
 }

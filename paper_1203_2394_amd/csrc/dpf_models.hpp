@@ -4,13 +4,16 @@
 // arrays, split so that the work that depends only on the outer state is
 // done once per segment when it is uniform there:
 //
-//   fx(P, x, z, nu, xn)           x_{t+1} = f^x(x_t, z_t, v^x)    (nu: DX normals)
+//   fx(P, x, z, nu, t, xn)        x_{t+1} = f^x(x_t, z_t, v^x)    (nu: DX normals)
 //   fz_pre(P, x, xn, t, pre)      the part of f^z that depends only on x_{t:t+1}
 //                                 (and on t, for a time-varying model)
 //   fz_post(P, pre, z, nu, zn)    z_{t+1} = f^z(x_{t:t+1}, z_t, v^z) (nu: DZ normals)
 //   obs_pre(P, y, x, r0)          the part of y - h(x, z) that depends only on x
 //   logpy_post(P, r0, z)          log p(y_t | x_t, z_t)
-//   logpx(P, xn, x, z)            log p(x_{t+1} | x_t, z_t)
+//   logpx(P, xn, x, z, t)         log p(x_{t+1} | x_t, z_t)
+//
+// t is the time of the state the transition leaves (used only by a
+// time-varying model).
 //
 // kXdepZ says whether p(x_{t+1} | x_t, z_t) depends on z_t; when it does
 // not, the x-conditioning factor of eq:qnobar is constant over the inner
@@ -57,7 +60,7 @@ struct LinGauss {
   };
   using L = Layout;
 
-  __device__ static void fx(const float* P, const float* x, const float* z, const float* nu,
+  __device__ static void fx(const float* P, const float* x, const float* z, const float* nu, int,
                             float* xn) {
 #pragma unroll
     for (int a = 0; a < DX; ++a) {
@@ -109,7 +112,7 @@ struct LinGauss {
     }
     return P[L::cy] - 0.5f * P[L::inv_r] * q;
   }
-  __device__ static float logpx(const float* P, const float* xn, const float* x, const float* z) {
+  __device__ static float logpx(const float* P, const float* xn, const float* x, const float* z, int) {
     float q = 0.f;
 #pragma unroll
     for (int a = 0; a < DX; ++a) {
@@ -145,7 +148,7 @@ struct NonLin {
   };
   using L = Layout;
 
-  __device__ static void fx(const float* P, const float* x, const float*, const float* nu,
+  __device__ static void fx(const float* P, const float* x, const float*, const float* nu, int,
                             float* xn) {
     const float a = P[L::a], b = P[L::b], s = P[L::sx];
 #pragma unroll
@@ -189,7 +192,7 @@ struct NonLin {
     }
     return P[L::cy] - 0.5f * P[L::inv_r] * q;
   }
-  __device__ static float logpx(const float* P, const float* xn, const float* x, const float*) {
+  __device__ static float logpx(const float* P, const float* xn, const float* x, const float*, int) {
     const float a = P[L::a], b = P[L::b];
     float q = 0.f;
 #pragma unroll
@@ -222,7 +225,7 @@ struct HighDim {
   };
   using L = Layout;
 
-  __device__ static void fx(const float* P, const float* x, const float*, const float* nu,
+  __device__ static void fx(const float* P, const float* x, const float*, const float* nu, int,
                             float* xn) {
     const float a = P[L::a], b = P[L::b], s = P[L::sx];
 #pragma unroll
@@ -280,7 +283,7 @@ struct HighDim {
     }
     return gonly ? P[L::cy] - 0.5f * P[L::inv_r] * q : acc;
   }
-  __device__ static float logpx(const float* P, const float* xn, const float* x, const float*) {
+  __device__ static float logpx(const float* P, const float* xn, const float* x, const float*, int) {
     const float a = P[L::a], b = P[L::b];
     float q = 0.f;
 #pragma unroll
@@ -312,7 +315,7 @@ struct TwoDim {
   using L = Layout;
 
   __device__ static float sat(float z) { return z / (1.0f + z * z); }
-  __device__ static void fx(const float* P, const float* x, const float* z, const float* nu, float* xn) {
+  __device__ static void fx(const float* P, const float* x, const float* z, const float* nu, int, float* xn) {
     xn[0] = x[0] + sat(z[0]) + P[L::sx] * nu[0];
   }
   // x + amp cos(freq t) + kz (x' - x); the angle in double (t runs to
@@ -336,9 +339,65 @@ struct TwoDim {
     const float e = r0[0] - 0.05f * z[0] * z[0];
     return P[L::cy] - 0.5f * P[L::inv_r] * e * e;
   }
-  __device__ static float logpx(const float* P, const float* xn, const float* x, const float* z) {
+  __device__ static float logpx(const float* P, const float* xn, const float* x, const float* z, int) {
     const float e = xn[0] - x[0] - sat(z[0]);
     return P[L::cx] - 0.5f * P[L::inv_qx] * e * e;
+  }
+};
+
+// ----------------------------------------------------------------- FOURDIM
+// Model 2 of Table 1 (the 4-dimensional example), dx = dz = 2, dy = 1:
+//   x1' = a1 x1 + bs sin t + v1 ,  x2' = c21 x1 + a2 x2 + v2 ,
+//   z1' = z1 + z2 / (1 + z2^2) + w1 ,
+//   z2' = z1' + rho z2 + b z2 / (1 + z2^2) + amp cos(freq t) + w2 ,
+//   y   = (x1 + x2) / (1 + x1^2) + atan(z1) + z2^2 / 20 + e ,
+// v ~ N(0, diag(qx1, qx2)), (w1, w2) ~ N(0, [[qz1, cz], [cz, qz2]]) drawn as
+// w1 = sqrt(qz1) nu1, w2 = (cz / qz1) w1 + sqrt(qz2 - cz^2 / qz1) nu2, e ~ N(0, r);
+// t is the time of the state the transition leaves.  The blocks are coupled
+// only through y (p(x' | x, z) does not depend on z).
+struct FourDim {
+  static constexpr int DX = 2, DZ = 2, DY = 1;
+  static constexpr bool kXdepZ = false;
+  struct Layout {
+    static constexpr int a1 = 0, bs = 1, c21 = 2, a2 = 3, qx1 = 4, qx2 = 5, qz1 = 6, qz2 = 7, cz = 8, rho = 9,
+                         b = 10, amp = 11, freq = 12, r = 13, n_raw = 14;
+    static constexpr int sx1 = n_raw, sx2 = sx1 + 1, sz1 = sx2 + 1, kz = sz1 + 1, szc = kz + 1,
+                         inv_qx1 = szc + 1, inv_qx2 = inv_qx1 + 1, cx = inv_qx2 + 1, inv_r = cx + 1,
+                         cy = inv_r + 1, n_total = cy + 1;
+  };
+  using L = Layout;
+
+  // the time-dependent drift in double (t runs to thousands of radians)
+  __device__ static float drift_x(const float* P, int t) { return (float)((double)P[L::bs] * sin((double)t)); }
+  __device__ static void fx(const float* P, const float* x, const float*, const float* nu, int t, float* xn) {
+    xn[0] = P[L::a1] * x[0] + drift_x(P, t) + P[L::sx1] * nu[0];
+    xn[1] = P[L::c21] * x[0] + P[L::a2] * x[1] + P[L::sx2] * nu[1];
+  }
+  __device__ static float fz_pre_k(const float* P, const float*, const float*, int t, int k) {
+    return k == 1 ? (float)((double)P[L::amp] * cos((double)P[L::freq] * (double)t)) : 0.0f;
+  }
+  __device__ static void fz_pre(const float* P, const float* x, const float* xn, int t, float* pre) {
+    pre[0] = 0.0f;
+    pre[1] = fz_pre_k(P, x, xn, t, 1);
+  }
+  __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu, float* zn) {
+    const float g = z[1] / (1.0f + z[1] * z[1]);
+    const float w1 = P[L::sz1] * nu[0];
+    const float z1 = z[0] + g + w1;
+    zn[0] = z1;
+    zn[1] = z1 + P[L::rho] * z[1] + P[L::b] * g + pre[1] + P[L::kz] * w1 + P[L::szc] * nu[1];
+  }
+  __device__ static void obs_pre(const float*, const float* y, const float* x, float* r0) {
+    r0[0] = y[0] - (x[0] + x[1]) / (1.0f + x[0] * x[0]);
+  }
+  __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
+    const float e = r0[0] - atanf(z[0]) - 0.05f * z[1] * z[1];
+    return P[L::cy] - 0.5f * P[L::inv_r] * e * e;
+  }
+  __device__ static float logpx(const float* P, const float* xn, const float* x, const float*, int t) {
+    const float e0 = xn[0] - (P[L::a1] * x[0] + drift_x(P, t));
+    const float e1 = xn[1] - (P[L::c21] * x[0] + P[L::a2] * x[1]);
+    return P[L::cx] - 0.5f * (P[L::inv_qx1] * e0 * e0 + P[L::inv_qx2] * e1 * e1);
   }
 };
 

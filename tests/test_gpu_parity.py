@@ -38,6 +38,7 @@ SPECS = {
     "highdim": lambda: S.highdim_c4(1),
     "highdim_gauss": lambda: S.highdim_c4(1, gaussian_only=True),
     "twodim": lambda: S.twodim_table1(),
+    "fourdim": lambda: S.fourdim_table1(),
 }
 
 
@@ -86,6 +87,8 @@ def _la_case(name, N, M, warm, steps, seed=4242, data_seed=3):
     ("twodim", 130, 64, 3, 3),
     ("twodim", 37, 300, 6, 2),
     ("twodim", 500, 19, 2, 2),
+    ("fourdim", 120, 64, 3, 3),
+    ("fourdim", 33, 200, 7, 2),
 ])
 def test_lookahead_step_parity(name, N, M, warm, steps):
     for r, info, est in _la_case(name, N, M, warm, steps):
@@ -137,6 +140,8 @@ def _plain_case(name, N, M, warm, steps, seed=777, data_seed=5):
     ("highdim", 8, 1024, 1, 1),
     ("twodim", 130, 64, 3, 2),
     ("twodim", 300, 19, 5, 2),
+    ("fourdim", 120, 64, 3, 2),
+    ("fourdim", 260, 25, 6, 2),
 ])
 def test_plain_step_parity(name, N, M, warm, steps):
     for r, info, est in _plain_case(name, N, M, warm, steps):
@@ -191,7 +196,7 @@ def _tiling_start_cached(name, algo, N, M, seed):
     ("nonlin", 10, 200, 150), ("nonlin", 10, 256, 150),
     ("lingauss_coupled", 9, 200, 90), ("lingauss_coupled", 10, 150, 90), ("lingauss_coupled", 3, 100, 90),
     ("nonlin", 9, 8, 16700), ("nonlin", 3, 8, 16700), ("nonlin", 0, 8, 16700),
-    ("twodim", 9, 200, 90), ("twodim", 7, 100, 90)])
+    ("twodim", 9, 200, 90), ("twodim", 7, 100, 90), ("fourdim", 8, 100, 90), ("fourdim", 10, 256, 90)])
 @pytest.mark.parametrize("algo", ["lookahead", "plain"])
 def test_step_parity_under_every_tiling(name, cls, M, N, algo):
     """The same step under a non-default tile class (SEG, JPT) matches the

@@ -122,11 +122,12 @@ def test_run_chunks_and_remainder_equal_step_calls(T):
             assert torch.equal(a.copy_buffer(buf), b.copy_buffer(buf)), (rep, buf)
 
 
+@pytest.mark.parametrize("model", ["twodim", "fourdim"])
 @pytest.mark.parametrize("algo", ["lookahead", "plain"])
-def test_time_varying_model_run_equals_step_calls(algo):
-    """Model 1 of Table 1 has a drift that depends on t: a run (fused
+def test_time_varying_model_run_equals_step_calls(algo, model):
+    """Models 1 and 2 of Table 1 have drifts that depend on t: a run (fused
     steps across a chunk boundary) and step calls must agree bit for bit."""
-    spec = S.twodim_table1()
+    spec = S.twodim_table1() if model == "twodim" else S.fourdim_table1()
     N, M, T = [300, 77], [64, 130], 19
     Y = np.stack([S.simulate(spec, T, 61 + f)[2] for f in range(2)], axis=1).astype(np.float32)
     a = _filter(spec, N, M, algo=algo)

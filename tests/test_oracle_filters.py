@@ -104,7 +104,7 @@ def test_inner_kalman_pin_detects_missing_x_conditioning():
     M = 40000
     state = ladpf.init_state(m, 1, M, 77, 0)
     real = m.logpx
-    m.logpx = lambda xn, x, z: np.zeros(np.broadcast(xn[..., 0], z[..., 0]).shape)
+    m.logpx = lambda xn, x, z, t=0: np.zeros(np.broadcast(xn[..., 0], z[..., 0]).shape)
     mu_c, P_c = np.zeros(2), np.eye(2)
     worst = 0.0
     for y in ys:

@@ -175,3 +175,49 @@ def test_twodim_time_convention_in_the_filters():
     want = xs[:, None, :] + 0.5 * zp + 25 * zp / (1 + zp * zp) + 8 * math.cos(f12 * 5) + 0.1 * vx \
         + math.sqrt(0.99) * nu
     assert np.allclose(zn, want, atol=1e-6)
+
+
+def test_fourdim_transition_and_likelihood_match_table1_laws():
+    """Model 2 of Table 1.  log p(x'|x) against SciPy with the sin t drift;
+    the inner sampler is affine in its normals, z' = a + C nu: the noise pair
+    (w1, w2) it implies (w2 taken from z2' minus z1' and the drift, as Table
+    1 writes z2' in terms of the new z1') must have covariance
+    [[1, 0.1], [0.1, 10]] and zero mean; the likelihood against SciPy."""
+    spec = S.fourdim_table1()
+    m = _model(spec)
+    f12 = float(np.float32(1.2))
+    g = np.random.default_rng(8)
+    for _ in range(30):
+        x, z, t = g.normal(size=2) * 3, g.normal(size=2) * 3, int(g.integers(0, 400))
+        xn = g.normal(size=2) * 4
+        want = (stats.norm.logpdf(xn[0], 0.5 * x[0] + 8 * math.sin(t), 1.0)
+                + stats.norm.logpdf(xn[1], 0.4 * x[0] + 0.5 * x[1], 1.0))
+        assert np.isclose(m.logpx(xn, x, z, t), want)
+        base = m.fz(x, xn, z, np.zeros(2), t)
+
+        def noise(zn):
+            w1 = zn[0] - (z[0] + z[1] / (1 + z[1] ** 2))
+            w2 = zn[1] - (zn[0] + 0.5 * z[1] + 25 * z[1] / (1 + z[1] ** 2) + 8 * math.cos(f12 * t))
+            return np.array([w1, w2])
+        assert np.allclose(noise(base), 0.0, atol=1e-9)
+        C = np.stack([noise(m.fz(x, xn, z, np.eye(2)[k], t)) for k in range(2)], axis=1)
+        cov = np.array([[1.0, 0.1], [0.1, 10.0]], dtype=np.float32).astype(np.float64)
+        assert np.allclose(C @ C.T, cov, atol=1e-9)
+        y = g.normal(size=1) * 3
+        h = (x[0] + x[1]) / (1 + x[0] ** 2) + math.atan(z[0]) + z[1] ** 2 / 20
+        assert np.isclose(m.logpy(y, x, z), stats.norm.logpdf(y[0], h, 1.0))
+
+
+def test_fourdim_simulator_noise_covariance():
+    spec = S.fourdim_table1()
+    xs, zs, _ = S.simulate(spec, 40000, 12)
+    t = np.arange(len(xs) - 1)
+    x, z = xs[:-1], zs[:-1]
+    v1 = xs[1:, 0] - 0.5 * x[:, 0] - 8 * np.sin(t)
+    v2 = xs[1:, 1] - 0.4 * x[:, 0] - 0.5 * x[:, 1]
+    w1 = zs[1:, 0] - z[:, 0] - z[:, 1] / (1 + z[:, 1] ** 2)
+    w2 = zs[1:, 1] - zs[1:, 0] - 0.5 * z[:, 1] - 25 * z[:, 1] / (1 + z[:, 1] ** 2) \
+        - 8 * np.cos(float(np.float32(1.2)) * t)
+    c = np.cov(np.stack([v1, v2, w1, w2]))
+    want = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0.1], [0, 0, 0.1, 10]])
+    assert np.all(np.abs(c - want) <= 0.05 * np.sqrt(np.outer(np.diag(want), np.diag(want))))
