@@ -289,6 +289,7 @@ def main():
     if not (args.no_table1 or args.only_run):
         table1 = {"model1": run_table1(S, dpf, torch, np, dev, S.twodim_table1(), "Table 1 model 1"),
                   "model2": run_table1(S, dpf, torch, np, dev, S.fourdim_table1(), "Table 1 model 2")}
+        table1["grid"] = run_table1_grid(S, dpf, torch, np, dev, table1)
     cpu = None if (args.no_cpu_baseline or args.only_run) else run_cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
@@ -422,6 +423,48 @@ def run_table1(S, dpf, torch, np, dev, spec, name):
                      "rmse_z": round(float(np.sqrt(np.mean(ez ** 2))), 4),
                      "seq_rmse_x_median": round(float(np.median(ex)), 4),
                      "seq_rmse_x_max": round(float(ex.max()), 4)}
+    return out
+
+
+GRID_SEQS, GRID_N, GRID_M, GRID_SEED = 256, (20, 50, 100, 200), (10, 20), 20000
+
+
+def run_table1_grid(S, dpf, torch, np, dev, ref):
+    """Section 4.1's study on the models of Table 1: RMSE of x_hat and z_hat
+    and the fraction of diverged runs against (N, M) for the look-ahead and
+    plain steps, GRID_SEQS fresh 250-step sequences per point run as filters
+    of one handle.  A run diverges when an estimate is non-finite or its RMSE
+    of x exceeds 3x the reference (the look-ahead run at N = 4096, M = 256 of
+    `ref`)."""
+    out = {}
+    for key, spec in (("model1", S.twodim_table1()), ("model2", S.fourdim_table1())):
+        sims = [S.simulate(spec, TD_T, GRID_SEED + q) for q in range(GRID_SEQS)]
+        Y = torch.tensor(np.stack([sm[2] for sm in sims], axis=1), dtype=torch.float32, device=dev).contiguous()
+        tx = np.stack([sm[0][1:] for sm in sims], axis=1)
+        tz = np.stack([sm[1][1:] for sm in sims], axis=1)
+        lim = 3.0 * ref[key]["lookahead"]["rmse_x"]
+        rows = []
+        for N in GRID_N:
+            for M in GRID_M:
+                row = {"N": N, "M": M}
+                for algo in ("lookahead", "plain"):
+                    f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N] * GRID_SEQS,
+                                   [M] * GRID_SEQS, seed=FILTER_SEED, device=dev, algo=algo)
+                    xt, zt = f.run(Y, use_graph=True)
+                    f.close()
+                    xt, zt = xt.cpu().numpy(), zt.cpu().numpy()
+                    ex = np.sqrt(np.mean((xt - tx) ** 2, axis=(0, 2)))
+                    ez = np.sqrt(np.mean((zt - tz) ** 2, axis=(0, 2)))
+                    div = ~np.isfinite(ex) | ~np.isfinite(ez) | (ex > lim)
+                    ok = ~div
+                    row[algo] = {"rmse_x": round(float(np.sqrt(np.mean(ex[ok] ** 2))), 4) if ok.any() else None,
+                                 "rmse_z": round(float(np.sqrt(np.mean(ez[ok] ** 2))), 4) if ok.any() else None,
+                                 "diverged": round(float(div.mean()), 4)}
+                rows.append(row)
+        out[key] = {"divergence_limit_rmse_x": round(lim, 4), "points": rows}
+    out["config"] = {"workload": "models 1 and 2 of Table 1, %d fresh sequences x T=%d per point as filters of "
+                                 "one handle, N in %s, M in %s" % (GRID_SEQS, TD_T, list(GRID_N), list(GRID_M)),
+                     "rmse": "over the sequences that did not diverge"}
     return out
 
 
