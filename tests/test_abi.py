@@ -129,3 +129,20 @@ def test_tile_class_table():
     assert set(classes[6:]) == {(32, 2), (32, 4), (64, 2), (256, 1), (128, 2)}
     assert all(256 % seg == 0 for seg, _ in classes)
     assert _lib().dpf_set_tiling(None, None) == 1
+
+
+def test_table1_models_are_built_and_their_noise_covariances_checked():
+    L = _lib()
+    for spec in (S.twodim_table1(), S.fourdim_table1()):
+        c, keep = _cfg(spec, [100], [20])
+        assert L.dpf_workspace_bytes(ctypes.byref(c)) > 0, L.dpf_last_error()
+    # a cross covariance as large as the variances is not positive definite
+    c, keep = _cfg(S.twodim_table1(qx=1.0, qz=1.0, cxz=1.0), [100], [20])
+    assert L.dpf_workspace_bytes(ctypes.byref(c)) == 0
+    assert b"positive definite" in L.dpf_last_error()
+    spec = S.fourdim_table1()
+    blob = spec.blob.copy()
+    blob[8] = 4.0                                     # cz^2 > qz1 qz2 = 10
+    c, keep = _cfg(S.ModelSpec(spec.kind, 2, 2, 1, blob), [100], [20])
+    assert L.dpf_workspace_bytes(ctypes.byref(c)) == 0
+    assert b"positive definite" in L.dpf_last_error()
