@@ -187,6 +187,18 @@ dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean, float* d_
 dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_Tf,
                    float* d_xtrace, float* d_ztrace, int32_t use_graph);
 
+/* Rao-Blackwellised estimate of the new outer state of the look-ahead step
+ * just taken: xhat_rb = sum_i Wbar_i sum_j pi_ij xla^{(i,j)}, Wbar the
+ * normalised look-ahead weights (eq:weightsMC), pi_i. = softmax_j ell_ij the
+ * candidate probabilities of eq:approx3's sampling-importance-resampling,
+ * xla the look-ahead candidates (regenerated from their random streams) --
+ * the expectation of the particle that outer resampling and the candidate
+ * draw produce, without their sampling noise.  d_xrb: device float
+ * [F][dx], written on the handle's stream; NaN for filters that sat the
+ * step out.  Valid only directly after dpf_lookahead_step (DPF_ESTATE after
+ * any other state change: a run, a learned step, an import, a reset). */
+dpf_status dpf_estimate_rb(dpf_handle* h, float* d_xrb);
+
 /* State import / export (checkpoint, and step-level comparisons).  Layout,
  * all little-endian: int32 t[F] padded to a multiple of 16 bytes, then
  * float x[dx][sum N], float z[sum_f N_f*dz*M_f] (filter blocks in order,

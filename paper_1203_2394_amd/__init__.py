@@ -33,6 +33,7 @@ EXPORTS = [
     "dpf_set_proposal", "dpf_learned_step", "dpf_learned_step_given", "dpf_features",
     "dpf_mlp_blob_bytes", "dpf_mlp_param_count", "dpf_mlp_forward", "dpf_mlp_train_workspace_bytes",
     "dpf_mlp_pack", "dpf_mlp_train_step", "dpf_learned_run", "dpf_tile_classes", "dpf_set_tiling",
+    "dpf_estimate_rb",
 ]
 
 
@@ -80,6 +81,7 @@ def lib():
         "dpf_lookahead_step": (_i32, [_vp, _vp, _vp]),
         "dpf_step": (_i32, [_vp, _vp, _vp]),
         "dpf_estimate": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "dpf_estimate_rb": (_i32, [_vp, _vp]),
         "dpf_run": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _i32]),
         "dpf_state_bytes": (_sz, [_vp]),
         "dpf_export_state": (_i32, [_vp, _vp, _sz]),
@@ -258,6 +260,14 @@ class Filter:
         }
         _check(lib().dpf_estimate(self._h, _ptr(out["xhat"]), _ptr(out["zhat"]), _ptr(out["ess"]),
                                   _ptr(out["loglik"]), _ptr(out["flags"])))
+        return out
+
+    def estimate_rb(self):
+        """Rao-Blackwellised x estimate [F][dx] of the look-ahead step just
+        taken (dpf_estimate_rb)."""
+        torch = _torch()
+        out = torch.empty(self.F, self.dx, dtype=torch.float32, device=self.device)
+        _check(lib().dpf_estimate_rb(self._h, _ptr(out)))
         return out
 
     def run(self, Y, Tf=None, trace=True, use_graph=True, learned=False):

@@ -21,6 +21,7 @@
 #include "dpf_kernels.hpp"
 #include "dpf_learned.hpp"
 #include "dpf_mlp.hpp"
+#include "dpf_rb.hpp"
 
 using namespace dpf;
 
@@ -85,6 +86,7 @@ struct Engine {
   dpf_status (*mlp_state)(const StepArgs& a, hipStream_t s);  // null: no learned proposal
   dpf_status (*mdn_draw)(const StepArgs& a, hipStream_t s);
   bool moments;
+  dpf_status (*rb)(const StepArgs& a, double* tmp, float* out, hipStream_t s);
 };
 
 enum Op {
@@ -265,6 +267,16 @@ static void derive_fourdim(const double* p, std::vector<float>& o) {
   o.push_back((float)(-0.5 * log(2.0 * M_PI * r)));                       // cy
 }
 
+template <class Mdl>
+static dpf_status engine_rb(const StepArgs& a, double* tmp, float* out, hipStream_t s) {
+  constexpr int per = kBlock / kWave;  // outer particles per workgroup
+  hipLaunchKernelGGL(k_rb_outer<Mdl>, dim3((a.NT + per - 1) / per), dim3(kBlock), 0, s, a, tmp);
+  LAUNCH_CHECK("k_rb_outer");
+  hipLaunchKernelGGL(k_rb_finish<Mdl::DX>, dim3(a.n_filters), dim3(kBlock), 0, s, a, (const double*)tmp, out);
+  LAUNCH_CHECK("k_rb_finish");
+  return DPF_OK;
+}
+
 using MLG = LinGauss<1, 2, 1>;
 using MNL = NonLin<2, 8>;
 using MHD = HighDim<4, 64, 32>;
@@ -272,19 +284,19 @@ using MHD = HighDim<4, 64, 32>;
 static const Engine kEngines[] = {
     {1, 2, 1, (size_t)MLG::L::n_raw, (size_t)MLG::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_lingauss(1, 2, 1, p, o); },
-     engine_launch<MLG>, nullptr, nullptr, has_moments<MLG>()},
+     engine_launch<MLG>, nullptr, nullptr, has_moments<MLG>(), engine_rb<MLG>},
     {2, 8, 8, (size_t)MNL::L::n_raw, (size_t)MNL::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_nonlin(2, 8, p, o); }, engine_launch<MNL>,
-     engine_mlp_state<MNL>, engine_mdn_draw<MNL>, has_moments<MNL>()},
+     engine_mlp_state<MNL>, engine_mdn_draw<MNL>, has_moments<MNL>(), engine_rb<MNL>},
     {4, 64, 32, (size_t)MHD::L::n_raw, (size_t)MHD::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_highdim(4, 64, 32, p, o); },
-     engine_launch<MHD>, nullptr, nullptr, has_moments<MHD>()},
+     engine_launch<MHD>, nullptr, nullptr, has_moments<MHD>(), engine_rb<MHD>},
     {1, 1, 1, (size_t)TwoDim::L::n_raw, (size_t)TwoDim::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_twodim(p, o); }, engine_launch<TwoDim>, nullptr,
-     nullptr, has_moments<TwoDim>()},
+     nullptr, has_moments<TwoDim>(), engine_rb<TwoDim>},
     {2, 2, 1, (size_t)FourDim::L::n_raw, (size_t)FourDim::L::n_total,
      [](const double* p, std::vector<float>& o) { derive_fourdim(p, o); }, engine_launch<FourDim>, nullptr,
-     nullptr, has_moments<FourDim>()},
+     nullptr, has_moments<FourDim>(), engine_rb<FourDim>},
 };
 
 static const Engine* find_engine(int model, int dx, int dz, int dy) {
@@ -311,6 +323,8 @@ struct Layout {
   size_t ell1, logw1;
   // step-end kernel: per-group partial estimates, per-filter counters
   size_t gpart, fcount;
+  // Rao-Blackwellised estimate: per-outer partial sums
+  size_t xrb;
   int NT = 0;
   long long NMT = 0;
   int n_tiles = 0, n_rgroups = 0;
@@ -413,6 +427,7 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   L.lflags = carve(cur, F * 4);
   L.gpart = carve(cur, (size_t)L.n_rgroups * (dx + dz) * 8);
   L.fcount = carve(cur, F * 4);
+  L.xrb = carve(cur, (size_t)L.NT * dx * 8);
   L.total = cur;
   return DPF_OK;
 }
@@ -451,6 +466,9 @@ struct dpf_handle {
   // which weight buffers (0: ell/logw, 1: ell1/logw1) hold the weights of
   // the last step taken
   int ell_sel = 0;
+  // the last call that changed the state was dpf_lookahead_step (what
+  // dpf_estimate_rb needs)
+  bool rb_ready = false;
 };
 
 constexpr int kPhaseEvents = 5;
@@ -592,6 +610,7 @@ static dpf_status launch_post(dpf_handle* h, const StepArgs& a, int next) {
 }
 
 static dpf_status queue_init(dpf_handle* h) {
+  h->rb_ready = false;
   const bool plain = h->algo == DPF_ALGO_PLAIN;
   hipLaunchKernelGGL(k_reset, dim3((h->F + 255) / 256), dim3(256), 0, h->stream, at<int>(h, h->L.tcur),
                      at<unsigned char>(h, h->L.cur), at<unsigned char>(h, h->L.act), at<uint32_t>(h, h->L.flags),
@@ -830,6 +849,7 @@ static dpf_status queue_moments(dpf_handle* h, const float* y, float* feat) {
 static dpf_status queue_learned_step(dpf_handle* h, const float* Y, long long y_tstride,
                                      const unsigned char* active, const int* run_Tf, int run_T, float* trace_x,
                                      float* trace_z, const float* mdn_given) {
+  h->rb_ready = false;
   dpf_status s = DPF_OK;
   if (!h->mom_valid && !mdn_given) s = queue_moments(h, nullptr, nullptr);
   if (s != DPF_OK) return s;
@@ -886,7 +906,19 @@ extern "C" dpf_status dpf_set_phase_events(dpf_handle* h, void* const* hip_event
 extern "C" dpf_status dpf_lookahead_step(dpf_handle* h, const float* d_y, const uint8_t* d_active) {
   if (!h || !d_y) return fail(DPF_EINVAL, "handle and d_y are required");
   if (h->algo != DPF_ALGO_LOOKAHEAD) return fail(DPF_ESTATE, "handle was created for the plain DPF");
-  return queue_step(h, d_y, 0, d_active, nullptr, INT_MAX, nullptr, nullptr);
+  h->rb_ready = false;
+  const dpf_status s = queue_step(h, d_y, 0, d_active, nullptr, INT_MAX, nullptr, nullptr);
+  h->rb_ready = s == DPF_OK;
+  return s;
+}
+
+extern "C" dpf_status dpf_estimate_rb(dpf_handle* h, float* d_xrb) {
+  if (!h || !d_xrb) return fail(DPF_EINVAL, "handle and d_xrb are required");
+  if (!h->rb_ready) return fail(DPF_ESTATE, "dpf_estimate_rb follows a dpf_lookahead_step call");
+  StepArgs a = make_args(h);
+  a.ell = at<float>(h, h->ell_sel ? h->L.ell1 : h->L.ell);
+  a.logw = at<float>(h, h->ell_sel ? h->L.logw1 : h->L.logw);
+  return h->eng->rb(a, at<double>(h, h->L.xrb), d_xrb, h->stream);
 }
 
 extern "C" dpf_status dpf_step(dpf_handle* h, const float* d_y, const uint8_t* d_active) {
@@ -980,6 +1012,7 @@ constexpr int kGraphChunk = 16;
 
 static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T, const int32_t* d_Tf,
                             float* d_xtrace, float* d_ztrace, int32_t use_graph) {
+  h->rb_ready = false;
   if (!h || !d_Y) return fail(DPF_EINVAL, "handle and d_Y are required");
   if (T < 0) return fail(DPF_EINVAL, "T = %d", T);
   if (T == 0) return DPF_OK;
@@ -1067,6 +1100,7 @@ extern "C" size_t dpf_state_bytes(const dpf_handle* h) {
 }
 
 static dpf_status state_io(dpf_handle* h, char* ext, int dir) {
+  if (dir == 1) h->rb_ready = false;
   const int F = h->F;
   const size_t tb = state_time_bytes(F);
   float* ex = (float*)(ext + tb);

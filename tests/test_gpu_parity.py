@@ -67,9 +67,11 @@ def _la_case(name, N, M, warm, steps, seed=4242, data_seed=3):
         sel = f.copy_buffer(dpf.BUF_SEL).cpu().numpy()
         gs = {"x": g["x"][0], "z": g["z"][0], "lam": g["lam"][0]}
         assert int(g["t"][0]) == st32["t"] + 1
+        est = f.estimate()
+        est["xhat_rb"] = f.estimate_rb()
         r, st, info = compare_la(model, st32, ys[t], seed, 0, gs, ell, logw, anc, sel)
         print("LA %s N=%d M=%d t=%d: %s" % (name, N, M, t + 1, r.line()), flush=True)
-        reports.append((r, info, f.estimate()))
+        reports.append((r, info, est))
     return reports
 
 
@@ -93,6 +95,11 @@ def _la_case(name, N, M, warm, steps, seed=4242, data_seed=3):
 def test_lookahead_step_parity(name, N, M, warm, steps):
     for r, info, est in _la_case(name, N, M, warm, steps):
         assert_clean(r, n=N)
+        # the Rao-Blackwellised estimate involves no sampled index: compared
+        # always; its weights come from FP32 ell (absolute error ~3e-5 at
+        # |ell| ~ 100) applied to candidates up to ~20 apart
+        xrb = est["xhat_rb"][0].cpu().numpy()
+        assert np.allclose(xrb, info["xhat_rb"], rtol=1e-4, atol=1e-3), (xrb, info["xhat_rb"])
         if r["clean_frac"] == 1.0 and r["anc_flips"] == 0:
             xg = est["xhat"][0].cpu().numpy()
             assert np.allclose(xg, info["xhat"], rtol=1e-4, atol=1e-4), (xg, info["xhat"])

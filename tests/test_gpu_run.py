@@ -122,6 +122,24 @@ def test_run_chunks_and_remainder_equal_step_calls(T):
             assert torch.equal(a.copy_buffer(buf), b.copy_buffer(buf)), (rep, buf)
 
 
+def test_rb_estimate_follows_step_calls_only():
+    """dpf_estimate_rb after a look-ahead step; NaN for a filter that sat the
+    step out; refused after a run (the estimate needs the step's own buffers
+    and state copies)."""
+    spec = S.nonlin_c2(1)
+    Y = np.stack([S.simulate(spec, 3, 71 + f)[2] for f in range(2)], axis=1).astype(np.float32)
+    f = _filter(spec, [300, 90], [64, 40])
+    f.lookahead_step(torch.from_numpy(Y[0]))
+    rb = f.estimate_rb().cpu().numpy()
+    assert np.all(np.isfinite(rb))
+    f.lookahead_step(torch.from_numpy(Y[1]), active=np.array([1, 0], dtype=np.uint8))
+    rb = f.estimate_rb().cpu().numpy()
+    assert np.all(np.isfinite(rb[0])) and np.all(np.isnan(rb[1]))
+    f.run(torch.from_numpy(Y), use_graph=False)
+    with pytest.raises(dpf.DPFError):
+        f.estimate_rb()
+
+
 @pytest.mark.parametrize("model", ["twodim", "fourdim"])
 @pytest.mark.parametrize("algo", ["lookahead", "plain"])
 def test_time_varying_model_run_equals_step_calls(algo, model):
