@@ -44,6 +44,7 @@ def test_ragged_batch_matches_oracle_per_filter():
     g.import_state(torch.from_numpy(g.pack_state([s["t"] for s in states], [s["x"] for s in states],
                                                  [s["z"] for s in states], [s["lam"] for s in states])))
     g.lookahead_step(torch.tensor(ys[1], dtype=torch.float32))
+    rb = g.estimate_rb().cpu().numpy()
     out = g.unpack_state(g.export_state())
     ell = g.copy_buffer(dpf.BUF_ELL).cpu().numpy()
     logw = g.copy_buffer(dpf.BUF_LOGW).cpu().numpy()
@@ -53,10 +54,12 @@ def test_ragged_batch_matches_oracle_per_filter():
     for f in range(F):
         n, m = N[f], M[f]
         gs = {"x": out["x"][f], "z": out["z"][f], "lam": out["lam"][f]}
-        r, _, _ = compare_la(model, states[f], ys[1, f], seed, f, gs, ell[io:io + n * m].reshape(n, m),
-                             logw[oo:oo + n], anc[oo:oo + n], sel[oo:oo + n])
+        r, _, info = compare_la(model, states[f], ys[1, f], seed, f, gs, ell[io:io + n * m].reshape(n, m),
+                                logw[oo:oo + n], anc[oo:oo + n], sel[oo:oo + n])
         print("filter %d N=%d M=%d: %s" % (f, n, m, r.line()), flush=True)
         assert_clean(r, max_flip_frac=0.05)
+        # the Rao-Blackwellised estimate of each filter of the ragged handle
+        assert np.allclose(rb[f], info["xhat_rb"], rtol=1e-4, atol=1e-3), (f, rb[f], info["xhat_rb"])
         oo += n
         io += n * m
 
