@@ -47,16 +47,6 @@ __device__ __forceinline__ int filter_of_outer(const int* off, int F, int g) {
   return lo;
 }
 
-// Raw features of outer particle g of filter f (column c < DX + DY + 2 DZ):
-// [x_{t-1} (DX), y_t (DY), cloud mean (DZ), cloud variance (DZ)].
-template <class Mdl>
-__device__ __forceinline__ float raw_feature(const StepArgs& a, int f, int g, int c) {
-  constexpr int DX = Mdl::DX, DY = Mdl::DY, DZ = Mdl::DZ;
-  if (c < DX) return a.x[copy_of(a.cur[f])][(long long)c * a.NT + g];
-  if (c < DX + DY) return a.Y[(long long)a.tcur[f] * a.y_tstride + (long long)f * DY + (c - DX)];
-  return a.mom[(long long)g * 2 * DZ + (c - DX - DY)];
-}
-
 // Draw from the mixture of output row o: component by one inverse-CDF draw
 // over softmax(logits) with U53 MDN_U at (t, i), then mean + sd * normals
 // (MDN_X at (t, i, 0)); returns log q of the draw.
@@ -135,15 +125,40 @@ __global__ __launch_bounds__(kBlock) void k_mlp_fwd_state(StepArgs a) {
   const int nrows = min(kMlpRows, a.NT - row0);
   const float* fmean = reinterpret_cast<const float*>(a.mlp + MlpBlobLayout::fmean);
   const float* fstd = reinterpret_cast<const float*>(a.mlp + MlpBlobLayout::fstd);
-  for (int e = threadIdx.x; e < kMlpRows * kMlpIn; e += kBlock) {
+  // The tile's features, two per thread: column c of row g is
+  // [x_{t-1} (DX), y_t (DY), cloud mean (DZ), cloud variance (DZ)][c],
+  // standardised.  Every load is issued at a clamped (in-range) index before
+  // any value is used and the results are masked afterwards: a load guarded
+  // by a branch would wait inside it, one memory round per guard.
+  static_assert(kMlpRows * kMlpIn == 2 * kBlock, "two features per thread");
+  constexpr int DX = Mdl::DX, DY = Mdl::DY, DZ = Mdl::DZ;
+  float fv[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int e = threadIdx.x + q * kBlock;
     const int r = e / kMlpIn, c = e % kMlpIn;
-    float v = 0.f;
-    if (r < nrows && c < NF) {
-      const int g = row0 + r;
-      const int f = filter_of_outer(a.ooff, a.n_filters, g);
-      if (step_active(a, f)) v = (raw_feature<Mdl>(a, f, g, c) - fmean[c]) / fstd[c];
-    }
-    sh.x0[r][c] = f2bf(v);
+    const int g = row0 + min(r, nrows - 1);
+    const int f = filter_of_outer(a.ooff, a.n_filters, g);
+    const int cc = min(c, NF - 1);
+    const int am = a.active != nullptr ? a.active[f] : 1;
+    const int tf = a.run_Tf != nullptr ? a.run_Tf[f] : 0x7fffffff;
+    const int tc = a.tcur[f];
+    const unsigned char cu = a.cur[f];
+    const float mu = fmean[cc], sd = fstd[cc];
+    const float* px = a.x[copy_of(cu)] + (long long)min(cc, DX - 1) * a.NT + g;
+    // (a run's observation row, clamped: a filter past its horizon reads row
+    // run_T - 1 and masks it)
+    const int ty = a.y_tstride != 0 ? min(tc, a.run_T - 1) : 0;
+    const float* py = a.Y + (long long)ty * a.y_tstride + (long long)f * DY + min(max(cc - DX, 0), DY - 1);
+    const float* pm = a.mom + (long long)g * 2 * DZ + min(max(cc - DX - DY, 0), 2 * DZ - 1);
+    const float raw = *(cc < DX ? px : (cc < DX + DY ? py : pm));
+    const bool act = am != 0 && tc < min(tf, a.run_T);
+    fv[q] = (r < nrows && c < NF && act) ? (raw - mu) / sd : 0.f;
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int e = threadIdx.x + q * kBlock;
+    sh.x0[e / kMlpIn][e % kMlpIn] = f2bf(fv[q]);
   }
   __syncthreads();
   mlp_rows<false>(fr, sh, row0, nrows, a.mdn, MlpTrainOut{});
