@@ -592,14 +592,17 @@ __device__ bool learned_rejected(const StepArgs& a, int f, int N, float* fred4, 
   const int th = threadIdx.x;
   const int G = a.finfo[f].ngroup;
   const double* gs = a.gstat + 4LL * a.finfo[f].rg_base;
-  const float gm = th < G ? (float)gs[4 * th] : -INFINITY;
+  // the three statistics of a group in one memory round (clamped, masked)
+  const int thc = min(th, G - 1);
+  const double g0 = gs[4 * thc], g1 = gs[4 * thc + 1], g2 = gs[4 * thc + 2];
+  const float gm = th < G ? (float)g0 : -INFINITY;
   const float m = block_max_256(gm, fred4);
   if (!(m > -INFINITY)) return true;
   double T = 0.0, Q = 0.0;
   if (th < G) {
     const double c = group_scale<LogSrc>(gm, m);
-    T = c * gs[4 * th + 1];
-    Q = (c * c) * gs[4 * th + 2];
+    T = c * g1;
+    Q = (c * c) * g2;
   }
   const double total = block_sum_256(T, red4);
   const double sumsq = block_sum_256(Q, red4);
@@ -928,16 +931,20 @@ __global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const int2* rg
   __shared__ ResScratch sh;
   const int2 rg = rgroups[blockIdx.x];
   const int f = rg.x;
-  if (!a.act[f]) return;
-  if (a.fb != nullptr && a.fb[f] == 0) {
+  // the filter's values in one memory round (a load under a branch would
+  // wait inside it)
+  const int ac = a.act[f];
+  const int fbv = a.fb != nullptr ? a.fb[f] : 1;
+  const int tc = a.tcur[f], cu = a.cur[f], N = a.fN[f], oo = a.ooff[f], rb = a.finfo[f].rg_base;
+  asm volatile("" ::"v"(ac), "v"(fbv), "v"(tc), "v"(cu), "v"(N), "v"(oo), "v"(rb));
+  if (!ac) return;
+  if (fbv == 0) {
     if (advance_time && rg.y == 0 && threadIdx.x == 0) {
-      a.tcur[f] = a.tcur[f] + 1;
-      a.cur[f] = (unsigned char)(a.cur[f] ^ 1);
+      a.tcur[f] = tc + 1;
+      a.cur[f] = (unsigned char)(cu ^ 1);
     }
     return;
   }
-  const int N = a.fN[f];
-  const int oo = a.ooff[f];
   float mg;
   double sg, qg;
   res_group_stat(LogSrc{a.logw + oo}, N, rg.y, mg, sg, qg, sh);
@@ -945,14 +952,14 @@ __global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const int2* rg
   const float v = i < N ? a.logw[oo + i] : 0.f;
   const int nonf = __syncthreads_or((!finitef(v) && !(v == -INFINITY)) ? 1 : 0);
   if (threadIdx.x == 0) {
-    double* gs = a.gstat + 4LL * (a.finfo[f].rg_base + rg.y);
+    double* gs = a.gstat + 4LL * (rb + rg.y);
     gs[0] = (double)mg;
     gs[1] = sg;
     gs[2] = qg;
     if (nonf) atomicOr(&a.flags[f], (uint32_t)F_NONFINITE);
     if (advance_time && rg.y == 0) {
-      a.tcur[f] = a.tcur[f] + 1;
-      a.cur[f] = (unsigned char)(a.cur[f] ^ 1);
+      a.tcur[f] = tc + 1;
+      a.cur[f] = (unsigned char)(cu ^ 1);
     }
   }
 }
