@@ -984,19 +984,21 @@ __device__ void commit_group(const StepArgs& a, int b) {
   __shared__ int res[kBlock];
   const int2 rg = a.rgroups[b];
   const int f = rg.x;
-  if (!a.act[f] || a.fb[f]) return;
-  const int N = a.fN[f];
-  const int oo = a.ooff[f];
-  const int t = a.tcur[f];
+  // the filter's values in one memory round (a load under a branch would
+  // wait inside it)
+  const int ac = a.act[f], fbv = a.fb[f], N = a.fN[f], oo = a.ooff[f], t = a.tcur[f], cu = a.cur[f];
+  const int rb = a.finfo[f].rg_base, G = a.finfo[f].ngroup;
+  asm volatile("" ::"v"(ac), "v"(fbv), "v"(N), "v"(oo), "v"(t), "v"(cu), "v"(rb), "v"(G));
+  if (!ac || fbv) return;
   const int k0 = rg.y * kResGroup;
   const int np = min(kResGroup, N - k0);
   const Key key = make_key(a.seed, (uint32_t)f);
   const double u = uniform53(key, (uint32_t)t, 0u, P_OUTER_U);
-  const ResResult rr = resolve_points(LogSrc{a.logw + oo}, N, N, u, k0, np, a.gstat + 4LL * a.finfo[f].rg_base,
-                                      a.finfo[f].ngroup, res, rsh, rg.y == 0);
+  const ResResult rr = resolve_points(LogSrc{a.logw + oo}, N, N, u, k0, np, a.gstat + 4LL * rb, G, res, rsh,
+                                      rg.y == 0);
   if (rg.y == 0 && threadIdx.x == 0) res_finish(a, f, t, N, rr);
   const int th = threadIdx.x;
-  const int dst = copy_of(a.cur[f]);
+  const int dst = copy_of((unsigned char)cu);
   if (th < np) {
     const long long gk = oo + k0 + th, gp = oo + res[th];
     float xv[DX], kv[DZ], mv[2 * DZ];
@@ -1016,7 +1018,7 @@ __device__ void commit_group(const StepArgs& a, int b) {
 #pragma unroll
       for (int d = 0; d < 2 * DZ; ++d) a.mom[gk * 2 * DZ + d] = mv[d];
     }
-    if (k0 == 0 && th == 0) a.cur[f] = (unsigned char)(a.cur[f] & ~(2 << dst));
+    if (k0 == 0 && th == 0) a.cur[f] = (unsigned char)(cu & ~(2 << dst));
   }
   if (rg.y == 0 && th == 0) {
     const uint32_t lf = a.lflags[f];
@@ -1677,11 +1679,10 @@ __global__ __launch_bounds__(kBlock) void k_newcloud_fallback(StepArgs a) {
   __shared__ int todo[kBlock], wcnt[kBlock / kWave];
   for (int base = bid; base < a.n_tiles; base += kBlock * nb) {
     const int mine = base + threadIdx.x * nb;
-    bool need = false;
-    if (mine < a.n_tiles) {
-      const int f = a.tiles[mine].x;
-      need = a.act[f] && a.fb[f];
-    }
+    // tile, then both of its filter's bytes in one round (clamped, masked)
+    const int f = a.tiles[min(mine, a.n_tiles - 1)].x;
+    const int ac = a.act[f], fbv = a.fb[f];
+    const bool need = mine < a.n_tiles && ac && fbv;
     const int nt = block_compact(need, mine, todo, wcnt, nullptr);
     for (int q = 0; q < nt; ++q) {
       newcloud_tile<Mdl, SEG, JPT, PLAIN>(a, todo[q]);
