@@ -146,3 +146,12 @@ def test_table1_models_are_built_and_their_noise_covariances_checked():
     c, keep = _cfg(S.ModelSpec(spec.kind, 2, 2, 1, blob), [100], [20])
     assert L.dpf_workspace_bytes(ctypes.byref(c)) == 0
     assert b"positive definite" in L.dpf_last_error()
+
+
+def test_model_ids_agree_across_header_binding_and_inputs():
+    txt = open(HEADER).read()
+    ids = {k: int(v) for k, v in re.findall(r"DPF_MODEL_([A-Z]+)\s*=\s*(\d+)", txt)}
+    assert ids == {"LINGAUSS": 1, "NONLIN": 2, "HIGHDIM": 3, "TWODIM": 4, "FOURDIM": 5}
+    for name, v in ids.items():
+        assert getattr(dpf, "MODEL_" + name) == v
+        assert getattr(S, name) == v
