@@ -12,7 +12,7 @@ namespace dpf {
 
 // t = 0, state in copy 0 (the plain DPF's initial proposals are written
 // there from the prior held in copy 1), flags and evidence cleared.
-__global__ void k_reset(int* tcur, unsigned char* cur, unsigned char* act, uint32_t* flags, double* loglik,
+static __global__ void k_reset(int* tcur, unsigned char* cur, unsigned char* act, uint32_t* flags, double* loglik,
                         uint32_t* lflags, int* fcount, int F) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
@@ -41,7 +41,7 @@ __device__ __forceinline__ int filter_of(const long long* off, int F, long long 
 
 // Export (dir = 0) or import (dir = 1) one per-particle array whose filter
 // blocks start at `off[f] * width` (width = elements per unit of off).
-__global__ void k_state_copy(float* ext, float* buf0, float* buf1, const unsigned char* cur,
+static __global__ void k_state_copy(float* ext, float* buf0, float* buf1, const unsigned char* cur,
                              const long long* off, int F, long long n_units, int width, int dir) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_units * width) return;
@@ -58,7 +58,7 @@ __global__ void k_state_copy(float* ext, float* buf0, float* buf1, const unsigne
 // lam per outer particle): export reads particle i's cloud from slot
 // ind[copy][oo + i]; import writes slot order (the caller sets ind to the
 // identity).
-__global__ void k_state_copy_cloud(float* ext, float* buf0, float* buf1, const int* ind0, const int* ind1,
+static __global__ void k_state_copy_cloud(float* ext, float* buf0, float* buf1, const int* ind0, const int* ind1,
                                    const unsigned char* cur,
                                    const long long* ioff, const int* ooff, const int* fM, int F, long long n_units,
                                    int width, int dir) {
@@ -80,7 +80,7 @@ __global__ void k_state_copy_cloud(float* ext, float* buf0, float* buf1, const i
 }
 
 // x is [DX][NT]: element e = d * NT + g, filter by g.
-__global__ void k_state_copy_x(float* ext, float* buf0, float* buf1, const unsigned char* cur,
+static __global__ void k_state_copy_x(float* ext, float* buf0, float* buf1, const unsigned char* cur,
                                const long long* ooff64, int F, int NT, int DX, int dir) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)NT * DX) return;
@@ -93,13 +93,13 @@ __global__ void k_state_copy_x(float* ext, float* buf0, float* buf1, const unsig
 }
 
 // Export of the time header: t[f] for f < F, zeros in the padding up to n_words.
-__global__ void k_export_time(const int* tcur, int* ext_t, int F, int n_words) {
+static __global__ void k_export_time(const int* tcur, int* ext_t, int F, int n_words) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n_words) return;
   ext_t[q] = q < F ? tcur[q] : 0;
 }
 
-__global__ void k_import_time(const int* ext_t, int* tcur, unsigned char* cur, uint32_t* flags,
+static __global__ void k_import_time(const int* ext_t, int* tcur, unsigned char* cur, uint32_t* flags,
                               double* loglik, int F) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
@@ -110,7 +110,7 @@ __global__ void k_import_time(const int* ext_t, int* tcur, unsigned char* cur, u
 }
 
 // ---------------------------------------------------------------- primitives
-__global__ void k_philox_words(Key key, const uint32_t* ctr, long long n, uint32_t* out) {
+static __global__ void k_philox_words(Key key, const uint32_t* ctr, long long n, uint32_t* out) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const Words w = philox(key, ctr[4 * e], ctr[4 * e + 1], ctr[4 * e + 2], ctr[4 * e + 3]);
@@ -119,7 +119,7 @@ __global__ void k_philox_words(Key key, const uint32_t* ctr, long long n, uint32
 }
 
 template <int D>
-__global__ void k_normals_grid(Key key, uint32_t t, uint32_t purpose, int na, int nb, float* out) {
+static __global__ void k_normals_grid(Key key, uint32_t t, uint32_t purpose, int na, int nb, float* out) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)na * nb) return;
   const int a = (int)(e / nb), b = (int)(e % nb);
@@ -132,7 +132,7 @@ __global__ void k_normals_grid(Key key, uint32_t t, uint32_t purpose, int na, in
 // Systematic resampling of one FP64 weight vector by the outer-resampling
 // code of the step (group statistics, then points resolved 256 per
 // workgroup by the same device function the new-cloud kernel uses).
-__global__ __launch_bounds__(kBlock) void k_prim_res_stats(const double* w, int n, double* gstat) {
+static __global__ __launch_bounds__(kBlock) void k_prim_res_stats(const double* w, int n, double* gstat) {
   __shared__ ResScratch sh;
   float mg;
   double sg, qg;
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_prim_res_stats(const double* w, int 
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_prim_res_select(const double* w, int n, int n_out, double u,
+static __global__ __launch_bounds__(kBlock) void k_prim_res_select(const double* w, int n, int n_out, double u,
                                                             const double* gstat, int* out) {
   __shared__ ResScratch sh;
   __shared__ int res[kBlock];
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_prim_res_select(const double* w, int
 
 // One segment per (S index); the cdf build and search are those of k_newcloud.
 template <int SEG, int JPT>
-__global__ __launch_bounds__(kBlock) void k_seg_systematic_prim(const double* w, int S, int n,
+static __global__ __launch_bounds__(kBlock) void k_seg_systematic_prim(const double* w, int S, int n,
                                                                  int n_out, const double* u,
                                                                  int* out) {
   constexpr int NSEG = kBlock / SEG;

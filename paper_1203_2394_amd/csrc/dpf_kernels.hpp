@@ -264,7 +264,7 @@ __device__ __forceinline__ int block_compact(bool pred, int value, int* out, int
 // goes to copy 1 with ell = 0 and anc = identity, after which the proposal
 // kernel runs with t = 0 (no y_0 is consumed).
 template <class Mdl, int SEG, int JPT, bool PLAIN>
-__global__ __launch_bounds__(kBlock) void k_init(StepArgs a) {
+static __global__ __launch_bounds__(kBlock) void k_init(StepArgs a) {
   const int4 tile = a.tiles[blockIdx.x];
   const int f = tile.x;
   const int N = a.fN[f], M = a.fM[f];
@@ -396,13 +396,13 @@ __device__ __forceinline__ void la_weights_tile(const StepArgs& a, int ti, bool 
   if (vi && ls == 0) a.logw[oo + i] = lw;
 }
 
-__device__ bool learned_rejected(const StepArgs& a, int f, int N, float* fred4, double* red4);
+static __device__ bool learned_rejected(const StepArgs& a, int f, int N, float* fred4, double* red4);
 
 // One workgroup per tile.  (A kernel that loops over tiles compiles to
 // markedly slower code for the single-tile case, so the learned step's
 // fallback has kernels of its own.)
 template <class Mdl, int SEG, int JPT>
-__global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
+static __global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
   la_weights_tile<Mdl, SEG, JPT>(a, blockIdx.x, false);
 }
 
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
 // tile records the decision and the fallback flag), and runs the look-ahead
 // weights only for the tiles of rejecting filters.
 template <class Mdl, int SEG, int JPT>
-__global__ __launch_bounds__(kBlock) void k_la_weights_fallback(StepArgs a) {
+static __global__ __launch_bounds__(kBlock) void k_la_weights_fallback(StepArgs a) {
   __shared__ int tfl[kBlock], runs[kBlock], todo[kBlock], wcnt[kBlock / kWave];
   __shared__ unsigned char rejr[kBlock];
   __shared__ float fred4[kBlock / kWave];
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_la_weights_fallback(StepArgs a) {
 // log w_i = logsumexp_j ell - log M, and the per-particle partial
 // sum_j qbar_ij zt_ij (qbar = softmax_j ell, step 3) for the estimate.
 template <class Mdl, int SEG, int JPT>
-__global__ __launch_bounds__(kBlock) void k_dpf_weights(StepArgs a) {
+static __global__ __launch_bounds__(kBlock) void k_dpf_weights(StepArgs a) {
   __shared__ SegScratch sh;
   __shared__ float vred[kBlock / kWave][Mdl::DZ];
   const int4 tile = a.tiles[blockIdx.x];
@@ -588,7 +588,7 @@ __device__ __forceinline__ double group_scale(float mg, float m) {
 // log-weight, or ESS = (sum w)^2 / sum w^2 below ess_frac * N -- from the
 // group statistics of the learned log-weights.  All 256 threads take part;
 // every workgroup gets the same answer.
-__device__ bool learned_rejected(const StepArgs& a, int f, int N, float* fred4, double* red4) {
+static __device__ bool learned_rejected(const StepArgs& a, int f, int N, float* fred4, double* red4) {
   const int th = threadIdx.x;
   const int G = a.finfo[f].ngroup;
   const double* gs = a.gstat + 4LL * a.finfo[f].rg_base;
@@ -905,7 +905,7 @@ __device__ int select_w0(const float* e, int M, double u, bool& deg_out) {
 }
 
 // Filter-level bookkeeping of the outer resampling (one thread per filter).
-__device__ void res_finish(const StepArgs& a, int f, int t, int N, const ResResult& r) {
+static __device__ void res_finish(const StepArgs& a, int f, int t, int N, const ResResult& r) {
   a.fstat[4 * f + 0] = r.deg ? 0.0 : (double)r.m;
   a.fstat[4 * f + 1] = r.total;
   a.fstat[4 * f + 2] = r.sumsq;
@@ -927,7 +927,7 @@ __device__ void res_finish(const StepArgs& a, int f, int t, int N, const ResResu
 // filter's time and flips its state copy (no other workgroup of this launch
 // reads them).  In the learned step's second pass (fb set) a filter that
 // kept its learned proposals keeps the statistics of the first pass.
-__global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const int2* rgroups, int advance_time) {
+static __global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const int2* rgroups, int advance_time) {
   __shared__ ResScratch sh;
   const int2 rg = rgroups[blockIdx.x];
   const int f = rg.x;
@@ -1037,7 +1037,7 @@ template <int DX, int DZ>
 constexpr int fin_block() { return DX + DZ > 16 ? 256 : 1024; }
 
 template <int DX, int DZ, bool PLAIN>
-__global__ __launch_bounds__((fin_block<DX, DZ>())) void k_finalize(StepArgs a) {
+static __global__ __launch_bounds__((fin_block<DX, DZ>())) void k_finalize(StepArgs a) {
   constexpr int NV = DX + DZ;
   constexpr int BS = fin_block<DX, DZ>();
   __shared__ double red[NV][BS / kWave];
@@ -1108,7 +1108,7 @@ __device__ __forceinline__ void post_finish(const StepArgs& a, int f, int rb, in
                                             int next, bool act_next, int nthreads);
 
 template <int DX, int DZ>
-__global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* rgroups, int next, int split) {
+static __global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* rgroups, int next, int split) {
   constexpr int NV = DX + DZ;
   __shared__ ResScratch sh;
   __shared__ double part[kBlock / kWave][NV];
@@ -1204,7 +1204,7 @@ __device__ __forceinline__ void post_finish(const StepArgs& a, int f, int rb, in
 // than a kernel boundary: k_post runs split (groups only) and this kernel,
 // one 64-thread workgroup per filter, finishes the filters.
 template <int DX, int DZ>
-__global__ __launch_bounds__(kWave) void k_post_end(StepArgs a, int next) {
+static __global__ __launch_bounds__(kWave) void k_post_end(StepArgs a, int next) {
   const int f = blockIdx.x;
   const int tf = (next && a.run_Tf != nullptr) ? a.run_Tf[f] : 0x7fffffff;
   const int rb = a.finfo[f].rg_base;
@@ -1660,14 +1660,14 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
 }
 
 template <class Mdl, int SEG, int JPT, bool PLAIN>
-__global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
+static __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
   newcloud_tile<Mdl, SEG, JPT, PLAIN>(a, blockIdx.x);
 }
 
 // Learned step: the new clouds of the filters that fell back only (smaller
 // grid looping over the tiles, tiles checked at once).
 template <class Mdl, int SEG, int JPT>
-__global__ __launch_bounds__(kBlock) void k_newcloud_fallback(StepArgs a) {
+static __global__ __launch_bounds__(kBlock) void k_newcloud_fallback(StepArgs a) {
   constexpr bool PLAIN = false;
   // the first n_commit workgroups commit the filters that kept their
   // learned proposals

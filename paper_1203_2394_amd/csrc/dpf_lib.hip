@@ -18,16 +18,17 @@
 
 #include "../../include/dpf.h"
 #include "dpf_aux.hpp"
+#include "dpf_engine.hpp"
 #include "dpf_kernels.hpp"
 #include "dpf_learned.hpp"
 #include "dpf_mlp.hpp"
-#include "dpf_rb.hpp"
 
 using namespace dpf;
 
 static thread_local std::string g_err;
+thread_local MomArgs dpf::g_mom_args = {nullptr, nullptr};
 
-static dpf_status fail(dpf_status s, const char* fmt, ...) {
+dpf_status dpf::fail(dpf_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -37,32 +38,7 @@ static dpf_status fail(dpf_status s, const char* fmt, ...) {
   return s;
 }
 
-#define HIP_TRY(expr)                                                                      \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess) return fail(DPF_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
-
-#define LAUNCH_CHECK(what)                                                                 \
-  do {                                                                                     \
-    hipError_t e_ = hipGetLastError();                                                     \
-    if (e_ != hipSuccess) return fail(DPF_EDEVICE, "launch of %s failed: %s", what, hipGetErrorString(e_)); \
-  } while (0)
-
 extern "C" const char* dpf_last_error(void) { return g_err.c_str(); }
-
-// ------------------------------------------------------------ tile classes
-struct ClassShape {
-  int seg, jpt;
-};
-// The first six are the defaults (the first that holds M); the others are
-// chosen only by dpf_set_tiling (an autotuner).  For 129..256 inner particles
-// the default is one wave per outer particle with four inner particles per
-// lane, which measured faster than a 256-lane workgroup per particle.
-static const ClassShape kClasses[] = {{32, 1}, {64, 1}, {128, 1}, {64, 4},  {256, 4}, {256, 16},
-                                      {32, 2}, {32, 4}, {64, 2},  {256, 1}, {128, 2}};
-constexpr int kNumClasses = 11;
-constexpr int kNumDefaultClasses = 6;
 
 static int class_of(int M) {
   for (int c = 0; c < kNumDefaultClasses; ++c)
@@ -70,245 +46,14 @@ static int class_of(int M) {
   return -1;
 }
 
-struct TileClass {
-  int cls;
-  int n_tiles;
-  int4* d_tiles;
-};
-
-// ------------------------------------------------------------ model engines
-struct Engine {
-  int dx, dz, dy;
-  size_t n_raw;
-  size_t n_total;
-  void (*derive)(const double* raw, std::vector<float>& out);
-  dpf_status (*launch)(int op, const StepArgs& a, const TileClass& tc, hipStream_t s);
-  dpf_status (*mlp_state)(const StepArgs& a, hipStream_t s);  // null: no learned proposal
-  dpf_status (*mdn_draw)(const StepArgs& a, hipStream_t s);
-  bool moments;
-  dpf_status (*rb)(const StepArgs& a, double* tmp, float* out, hipStream_t s);
-};
-
-enum Op {
-  OP_INIT_LA,
-  OP_INIT_PLAIN,
-  OP_LA_WEIGHTS,
-  OP_DPF_WEIGHTS,
-  OP_NEWCLOUD_LA,
-  OP_NEWCLOUD_PLAIN,
-  OP_LEARNED_INNER,
-  OP_MOMENTS,
-  OP_LA_WEIGHTS_FALLBACK,
-  OP_NEWCLOUD_FALLBACK
-};
-
-// Models served by the learned proposal (the network's mixture is over a
-// two-dimensional x; the features must fit its input).
-template <class Mdl>
-constexpr bool learned_model() { return Mdl::DX == 2 && has_moments<Mdl>(); }
-
-// Extra arguments of OP_MOMENTS (feature rows for dpf_features).
-struct MomArgs {
-  const float* y;
-  float* feat;
-};
-static thread_local MomArgs g_mom_args = {nullptr, nullptr};
-
-template <class Mdl, int SEG, int JPT>
-static void launch_op(int op, const StepArgs& a, int n, hipStream_t s) {
-  switch (op) {
-    case OP_INIT_LA:
-      hipLaunchKernelGGL((k_init<Mdl, SEG, JPT, false>), dim3(n), dim3(kBlock), 0, s, a);
-      break;
-    case OP_INIT_PLAIN:
-      hipLaunchKernelGGL((k_init<Mdl, SEG, JPT, true>), dim3(n), dim3(kBlock), 0, s, a);
-      break;
-    case OP_LA_WEIGHTS:
-      hipLaunchKernelGGL((k_la_weights<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
-      break;
-    case OP_DPF_WEIGHTS:
-      hipLaunchKernelGGL((k_dpf_weights<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
-      break;
-    case OP_NEWCLOUD_LA:
-      hipLaunchKernelGGL((k_newcloud<Mdl, SEG, JPT, false>), dim3(n), dim3(kBlock), 0, s, a);
-      break;
-    case OP_NEWCLOUD_PLAIN:
-      hipLaunchKernelGGL((k_newcloud<Mdl, SEG, JPT, true>), dim3(n), dim3(kBlock), 0, s, a);
-      break;
-    case OP_LEARNED_INNER:
-      if constexpr (learned_model<Mdl>())
-        hipLaunchKernelGGL((k_learned_inner<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
-      break;
-    case OP_LA_WEIGHTS_FALLBACK:
-      if constexpr (learned_model<Mdl>())
-        hipLaunchKernelGGL((k_la_weights_fallback<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
-      break;
-    case OP_NEWCLOUD_FALLBACK:
-      if constexpr (learned_model<Mdl>())
-        hipLaunchKernelGGL((k_newcloud_fallback<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
-      break;
-    case OP_MOMENTS:
-      if constexpr (has_moments<Mdl>())
-        hipLaunchKernelGGL((k_moments<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a, g_mom_args.y,
-                           g_mom_args.feat);
-      break;
-  }
-}
-
-template <class Mdl>
-static dpf_status engine_mlp_state(const StepArgs& a, hipStream_t s) {
-  if constexpr (learned_model<Mdl>()) {
-    hipLaunchKernelGGL(k_mlp_fwd_state<Mdl>, dim3((a.NT + kMlpRows - 1) / kMlpRows), dim3(kBlock), 0, s, a);
-    LAUNCH_CHECK("k_mlp_fwd_state");
-    return DPF_OK;
-  } else {
-    return fail(DPF_EUNSUPPORTED, "no learned proposal for this model");
-  }
-}
-
-template <class Mdl>
-static dpf_status engine_mdn_draw(const StepArgs& a, hipStream_t s) {
-  if constexpr (learned_model<Mdl>()) {
-    hipLaunchKernelGGL(k_mdn_draw<Mdl>, dim3((a.NT + kBlock - 1) / kBlock), dim3(kBlock), 0, s, a);
-    LAUNCH_CHECK("k_mdn_draw");
-    return DPF_OK;
-  } else {
-    return fail(DPF_EUNSUPPORTED, "no learned proposal for this model");
-  }
-}
-
-template <class Mdl>
-static dpf_status engine_launch(int op, const StepArgs& a, const TileClass& tc, hipStream_t s) {
-  const int n = tc.n_tiles;
-  switch (tc.cls) {
-    case 0: launch_op<Mdl, 32, 1>(op, a, n, s); break;
-    case 1: launch_op<Mdl, 64, 1>(op, a, n, s); break;
-    case 2: launch_op<Mdl, 128, 1>(op, a, n, s); break;
-    case 3: launch_op<Mdl, 64, 4>(op, a, n, s); break;
-    case 4: launch_op<Mdl, 256, 4>(op, a, n, s); break;
-    case 5: launch_op<Mdl, 256, 16>(op, a, n, s); break;
-    case 6: launch_op<Mdl, 32, 2>(op, a, n, s); break;
-    case 7: launch_op<Mdl, 32, 4>(op, a, n, s); break;
-    case 8: launch_op<Mdl, 64, 2>(op, a, n, s); break;
-    case 9: launch_op<Mdl, 256, 1>(op, a, n, s); break;
-    case 10: launch_op<Mdl, 128, 2>(op, a, n, s); break;
-    default: return fail(DPF_EUNSUPPORTED, "no kernel class %d", tc.cls);
-  }
-  LAUNCH_CHECK("step kernel");
-  return DPF_OK;
-}
-
-// Derived constants (computed in double, stored as float after the raw values).
-static void derive_lingauss(int dx, int dz, int dy, const double* p, std::vector<float>& o) {
-  const size_t iqx = dx * dx + dx * dz, iqz = iqx + 1 + dz * dz + dz * dx,
-               ir = iqz + 1 + dy * dx + dy * dz;
-  const double qx = p[iqx], qz = p[iqz], r = p[ir];
-  o.push_back((float)sqrt(qx));
-  o.push_back((float)sqrt(qz));
-  o.push_back((float)(1.0 / qx));
-  o.push_back((float)(1.0 / r));
-  o.push_back((float)(-0.5 * dx * log(2.0 * M_PI * qx)));
-  o.push_back((float)(-0.5 * dy * log(2.0 * M_PI * r)));
-}
-
-static void derive_nonlin(int dx, int dz, const double* p, std::vector<float>& o) {
-  const double qx = p[2];
-  const size_t irho = 3 + (size_t)dz * dx;
-  const double qz = p[irho + 1], r = p[irho + 3];
-  o.push_back((float)sqrt(qx));
-  o.push_back((float)sqrt(qz));
-  o.push_back((float)(1.0 / qx));
-  o.push_back((float)(1.0 / r));
-  o.push_back((float)(-0.5 * dx * log(2.0 * M_PI * qx)));
-  o.push_back((float)(-0.5 * dz * log(2.0 * M_PI * r)));
-}
-
-static void derive_highdim(int dx, int dz, int dy, const double* p, std::vector<float>& o) {
-  const double qx = p[2];
-  const size_t iqz = 3 + (size_t)(dz - 1) + dz + (dz - 1) + (size_t)dz * dx;
-  const double qz = p[iqz];
-  const size_t ir = iqz + 1 + (size_t)dy * dz;
-  const double r = p[ir], eps = p[ir + 1], nu = p[ir + 2];
-  o.push_back((float)sqrt(qx));                                  // sx
-  o.push_back((float)sqrt(qz));                                  // sz
-  o.push_back((float)(1.0 / qx));                                // inv_qx
-  o.push_back((float)(-0.5 * dx * log(2.0 * M_PI * qx)));        // cx
-  o.push_back((float)(1.0 / r));                                 // inv_r
-  o.push_back((float)(-0.5 * dy * log(2.0 * M_PI * r)));         // cy
-  o.push_back((float)(log1p(-eps) - 0.5 * log(2.0 * M_PI * r))); // lg0
-  o.push_back((float)(log(eps) + lgamma(0.5 * (nu + 1.0)) - lgamma(0.5 * nu) -
-                      0.5 * log(nu * M_PI * r)));                // lt0
-  o.push_back((float)(0.5 * (nu + 1.0)));                        // tnu
-  o.push_back((float)(1.0 / (nu * r)));                          // inv_nur
-}
-
-static void derive_twodim(const double* p, std::vector<float>& o) {
-  const double qx = p[0], qz = p[1], cxz = p[2], r = p[7];
-  o.push_back((float)sqrt(qx));                          // sx
-  o.push_back((float)(cxz / qx));                        // kz
-  o.push_back((float)sqrt(qz - cxz * cxz / qx));         // szc
-  o.push_back((float)(1.0 / qx));                        // inv_qx
-  o.push_back((float)(-0.5 * log(2.0 * M_PI * qx)));     // cx
-  o.push_back((float)(1.0 / r));                         // inv_r
-  o.push_back((float)(-0.5 * log(2.0 * M_PI * r)));      // cy
-}
-
-static void derive_fourdim(const double* p, std::vector<float>& o) {
-  const double qx1 = p[4], qx2 = p[5], qz1 = p[6], qz2 = p[7], cz = p[8], r = p[13];
-  o.push_back((float)sqrt(qx1));                                          // sx1
-  o.push_back((float)sqrt(qx2));                                          // sx2
-  o.push_back((float)sqrt(qz1));                                          // sz1
-  o.push_back((float)(cz / qz1));                                         // kz
-  o.push_back((float)sqrt(qz2 - cz * cz / qz1));                          // szc
-  o.push_back((float)(1.0 / qx1));                                        // inv_qx1
-  o.push_back((float)(1.0 / qx2));                                        // inv_qx2
-  o.push_back((float)(-0.5 * (log(2.0 * M_PI * qx1) + log(2.0 * M_PI * qx2))));  // cx
-  o.push_back((float)(1.0 / r));                                          // inv_r
-  o.push_back((float)(-0.5 * log(2.0 * M_PI * r)));                       // cy
-}
-
-template <class Mdl>
-static dpf_status engine_rb(const StepArgs& a, double* tmp, float* out, hipStream_t s) {
-  constexpr int per = kBlock / kWave;  // outer particles per workgroup
-  hipLaunchKernelGGL(k_rb_outer<Mdl>, dim3((a.NT + per - 1) / per), dim3(kBlock), 0, s, a, tmp);
-  LAUNCH_CHECK("k_rb_outer");
-  hipLaunchKernelGGL(k_rb_finish<Mdl::DX>, dim3(a.n_filters), dim3(kBlock), 0, s, a, (const double*)tmp, out);
-  LAUNCH_CHECK("k_rb_finish");
-  return DPF_OK;
-}
-
-using MLG = LinGauss<1, 2, 1>;
-using MNL = NonLin<2, 8>;
-using MHD = HighDim<4, 64, 32>;
-
-static const Engine kEngines[] = {
-    {1, 2, 1, (size_t)MLG::L::n_raw, (size_t)MLG::L::n_total,
-     [](const double* p, std::vector<float>& o) { derive_lingauss(1, 2, 1, p, o); },
-     engine_launch<MLG>, nullptr, nullptr, has_moments<MLG>(), engine_rb<MLG>},
-    {2, 8, 8, (size_t)MNL::L::n_raw, (size_t)MNL::L::n_total,
-     [](const double* p, std::vector<float>& o) { derive_nonlin(2, 8, p, o); }, engine_launch<MNL>,
-     engine_mlp_state<MNL>, engine_mdn_draw<MNL>, has_moments<MNL>(), engine_rb<MNL>},
-    {4, 64, 32, (size_t)MHD::L::n_raw, (size_t)MHD::L::n_total,
-     [](const double* p, std::vector<float>& o) { derive_highdim(4, 64, 32, p, o); },
-     engine_launch<MHD>, nullptr, nullptr, has_moments<MHD>(), engine_rb<MHD>},
-    {1, 1, 1, (size_t)TwoDim::L::n_raw, (size_t)TwoDim::L::n_total,
-     [](const double* p, std::vector<float>& o) { derive_twodim(p, o); }, engine_launch<TwoDim>, nullptr,
-     nullptr, has_moments<TwoDim>(), engine_rb<TwoDim>},
-    {2, 2, 1, (size_t)FourDim::L::n_raw, (size_t)FourDim::L::n_total,
-     [](const double* p, std::vector<float>& o) { derive_fourdim(p, o); }, engine_launch<FourDim>, nullptr,
-     nullptr, has_moments<FourDim>(), engine_rb<FourDim>},
-};
-
 static const Engine* find_engine(int model, int dx, int dz, int dy) {
-  int idx = -1;
-  if (model == DPF_MODEL_LINGAUSS) idx = 0;
-  if (model == DPF_MODEL_NONLIN) idx = 1;
-  if (model == DPF_MODEL_HIGHDIM) idx = 2;
-  if (model == DPF_MODEL_TWODIM) idx = 3;
-  if (model == DPF_MODEL_FOURDIM) idx = 4;
-  if (idx < 0) return nullptr;
-  const Engine* e = &kEngines[idx];
-  if (e->dx != dx || e->dz != dz || e->dy != dy) return nullptr;
+  const Engine* e = nullptr;
+  if (model == DPF_MODEL_LINGAUSS) e = &kEngLinGauss;
+  if (model == DPF_MODEL_NONLIN) e = &kEngNonLin;
+  if (model == DPF_MODEL_HIGHDIM) e = &kEngHighDim;
+  if (model == DPF_MODEL_TWODIM) e = &kEngTwoDim;
+  if (model == DPF_MODEL_FOURDIM) e = &kEngFourDim;
+  if (!e || e->dx != dx || e->dz != dz || e->dy != dy) return nullptr;
   return e;
 }
 
@@ -454,7 +199,7 @@ struct dpf_handle {
   // multi-step graph cache
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
-  const void* g_key[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const void* g_key[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int g_T = -1;
   // phase timing: caller-owned events consumed kPhaseEvents per step
   std::vector<hipEvent_t> prof_events;
@@ -564,20 +309,7 @@ static dpf_status launch_classes(dpf_handle* h, int op, StepArgs a, int grid_cap
 constexpr int kGatedGrid = 512;
 
 static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a) {
-  const int F = h->F;
-#define FIN(DX, DZ)                                                                                       \
-  if (h->dx == DX && h->dz == DZ) {                                                                       \
-    hipLaunchKernelGGL((k_finalize<DX, DZ, true>), dim3(F), dim3(fin_block<DX, DZ>()), 0, h->stream, a); \
-    LAUNCH_CHECK("k_finalize");                                                                           \
-    return DPF_OK;                                                                                        \
-  }
-  FIN(1, 2)
-  FIN(2, 8)
-  FIN(4, 64)
-  FIN(1, 1)
-  FIN(2, 2)
-#undef FIN
-  return fail(DPF_EUNSUPPORTED, "no finalize kernel for dims (%d,%d)", h->dx, h->dz);
+  return h->eng->finalize(a, h->F, h->stream);
 }
 
 // End of a look-ahead step: estimates; next = 1 in a look-ahead run (the
@@ -588,25 +320,8 @@ static dpf_status launch_finalize(dpf_handle* h, const StepArgs& a) {
 constexpr int kPostFenceGroups = 64;
 
 static dpf_status launch_post(dpf_handle* h, const StepArgs& a, int next) {
-  const int2* rg = at<int2>(h, h->L.rgroups);
   const int split = h->L.n_rgroups > kPostFenceGroups ? 1 : 0;
-#define POST(DX, DZ)                                                                                           \
-  if (h->dx == DX && h->dz == DZ) {                                                                            \
-    hipLaunchKernelGGL((k_post<DX, DZ>), dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a, rg, next, split); \
-    LAUNCH_CHECK("k_post");                                                                                    \
-    if (split) {                                                                                               \
-      hipLaunchKernelGGL((k_post_end<DX, DZ>), dim3(h->F), dim3(kWave), 0, h->stream, a, next);               \
-      LAUNCH_CHECK("k_post_end");                                                                              \
-    }                                                                                                          \
-    return DPF_OK;                                                                                             \
-  }
-  POST(1, 2)
-  POST(2, 8)
-  POST(4, 64)
-  POST(1, 1)
-  POST(2, 2)
-#undef POST
-  return fail(DPF_EUNSUPPORTED, "no step-end kernel for dims (%d,%d)", h->dx, h->dz);
+  return h->eng->post(a, at<int2>(h, h->L.rgroups), h->L.n_rgroups, h->F, next, split, h->stream);
 }
 
 static dpf_status queue_init(dpf_handle* h) {
@@ -1012,9 +727,9 @@ constexpr int kGraphChunk = 16;
 
 static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T, const int32_t* d_Tf,
                             float* d_xtrace, float* d_ztrace, int32_t use_graph) {
-  h->rb_ready = false;
   if (!h || !d_Y) return fail(DPF_EINVAL, "handle and d_Y are required");
   if (T < 0) return fail(DPF_EINVAL, "T = %d", T);
+  h->rb_ready = false;
   if (T == 0) return DPF_OK;
   if (mode == 1 && !h->mom_valid) {
     // moments of the starting state, outside any captured step
@@ -1033,7 +748,13 @@ static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T
     if (st != DPF_OK || T == 1) return st;
   }
   const int S = T - 1 < kGraphChunk ? T - 1 : kGraphChunk;
-  const void* key[6] = {d_Y, d_Tf, d_xtrace, d_ztrace, (const void*)h->stream, (const void*)(intptr_t)mode};
+  // every value make_args copies into the captured kernel arguments that can
+  // change between runs is part of the key: the buffers, the stream, the
+  // mode, whether cloud moments are maintained, and the fallback threshold
+  uint64_t ess_bits;
+  memcpy(&ess_bits, &h->ess_frac, sizeof(ess_bits));
+  const void* key[8] = {d_Y, d_Tf, d_xtrace, d_ztrace, (const void*)h->stream, (const void*)(intptr_t)mode,
+                        (const void*)(intptr_t)(h->has_proposal ? 1 : 0), (const void*)(uintptr_t)ess_bits};
   const bool cached = h->gexec && h->g_T == T && memcmp(key, h->g_key, sizeof(key)) == 0;
   if (!cached) {
     if (h->gexec) {

@@ -225,7 +225,7 @@ __device__ void mlp_rows(const MlpFrags& fr, MlpShared& sh, int row0, int nrows,
 // Standardised FP32 features X [B][32] -> outputs [B][32] (TRAIN: also the
 // activations the backward pass needs).
 template <bool TRAIN>
-__global__ __launch_bounds__(kBlock) void k_mlp_fwd_x(const unsigned char* blob, const float* X, int B,
+static __global__ __launch_bounds__(kBlock) void k_mlp_fwd_x(const unsigned char* blob, const float* X, int B,
                                                       float* out, MlpTrainOut tr) {
   __shared__ MlpShared sh;
   MlpFrags fr;
@@ -289,7 +289,7 @@ __device__ float mdn_logpdf(const float* o, const float* x) {
 // batch-contiguous [32][B], per-workgroup column sums (FP32, bias of the
 // output layer) and the FP64 sum of the row NLLs.
 template <int DX>
-__global__ __launch_bounds__(kBlock) void k_mdn_grad(const float* out, const float* xt, int B, bf16_t* gb,
+static __global__ __launch_bounds__(kBlock) void k_mdn_grad(const float* out, const float* xt, int B, bf16_t* gb,
                                                      bf16_t* gt, float* b3_part, double* loss_part) {
   using Q = Mdn<DX>;
   __shared__ float red[kBlock / kWave][kMlpOut];
@@ -431,7 +431,7 @@ __device__ __forceinline__ void mlp_back_layer(const bf16_t (*in)[SIN], const bf
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_mlp_bwd(MlpBwdArgs p) {
+static __global__ __launch_bounds__(kBlock) void k_mlp_bwd(MlpBwdArgs p) {
   __shared__ alignas(16) bf16_t g_sh[kMlpRows][kInStride];
   __shared__ alignas(16) bf16_t da2_sh[kMlpRows][kHidStride];
   const int row0 = blockIdx.x * kMlpRows;
@@ -467,7 +467,7 @@ struct WgArgs {
   int B, chunks;
 };
 
-__global__ __launch_bounds__(kBlock) void k_mlp_wgrad(WgArgs p) {
+static __global__ __launch_bounds__(kBlock) void k_mlp_wgrad(WgArgs p) {
   int blk = blockIdx.x;
   const int chunk = blockIdx.y;
   int j = 0;
@@ -544,7 +544,7 @@ __device__ __forceinline__ void mlp_store_param(int e, float val, unsigned char*
   }
 }
 
-__global__ void k_mlp_adam(AdamArgs a) {
+static __global__ void k_mlp_adam(AdamArgs a) {
   using PL = MlpParamLayout;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e == 0 && a.loss) {
@@ -589,7 +589,7 @@ __global__ void k_mlp_adam(AdamArgs a) {
 
 // Masters -> blob (and transposed copies when W2t / W3t are given), plus the
 // feature standardisation.
-__global__ void k_mlp_pack(const float* params, const float* fmean, const float* fstd, unsigned char* blob,
+static __global__ void k_mlp_pack(const float* params, const float* fmean, const float* fstd, unsigned char* blob,
                            bf16_t* W2t, bf16_t* W3t) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < MlpParamLayout::n) mlp_store_param(e, params[e], blob, W2t, W3t);

@@ -155,3 +155,12 @@ def test_model_ids_agree_across_header_binding_and_inputs():
     for name, v in ids.items():
         assert getattr(dpf, "MODEL_" + name) == v
         assert getattr(S, name) == v
+
+
+def test_run_calls_reject_null_handles():
+    # both runs check their handle before touching it
+    L = _lib()
+    for fn in (L.dpf_run, L.dpf_learned_run):
+        assert fn(None, ctypes.c_void_p(256), 4, None, None, None, 1) == 1
+        assert len(L.dpf_last_error()) > 0
+        assert fn(None, None, 4, None, None, None, 0) == 1
