@@ -197,3 +197,46 @@ def test_features_are_cloud_moments():
     mean = (q[:, None] * st["z"][3]).sum(0)
     var = (q[:, None] * (st["z"][3] - mean) ** 2).sum(0)
     assert np.allclose(f[3], np.r_[st["x"][3], np.arange(8.0), mean, var])
+
+
+@pytest.mark.parametrize("M", [4, 16])
+def test_learned_weight_at_several_inner_particles(M):
+    """M > 1, non-uniform inner weights, q = p(x_t | x_{t-1}) on a model whose
+    f^x ignores z: eq:approx1 at x_t is the transition density itself (the
+    inner weights sum to one), so the step-1 weight of Fig. 2 reduces to
+    eq:approx2, log w = logsumexp_j log p(y | x_t, z_t^j) - log M.  Dropping
+    the inner weights from eq:approx1, or the -log M of eq:approx2, shifts
+    every weight by log M."""
+    spec, m = _nonlin()
+    g = np.random.default_rng(100 + M)
+    N = 30
+    lam = g.normal(size=(N, M)) * 1.5
+    lam -= np.log(np.exp(lam).sum(axis=1, keepdims=True))
+    st = {"x": g.normal(size=(N, 2)) * 2, "z": g.normal(size=(N, M, 8)), "lam": lam, "t": 3}
+    out = np.zeros((N, Lr.D_OUT))
+    out[:, 1:4] = -80.0                      # one live component
+    gx = 0.5 * st["x"] + 25 * st["x"] / (1 + st["x"] ** 2)
+    out[:, 4:6] = gx                         # the transition mean
+    out[:, 12:14] = 0.0                      # log sd = log sqrt(qx) = 0
+    y = g.normal(size=8)
+    _, info = Lr.step(m, st, y, 9, 0, out, ess_frac=0.0)
+    assert not info["fallback"]
+    # eq:approx1 at x_t: the transition density (SciPy), whatever the inner weights
+    ref_px = stats.norm.logpdf(info["xt"], gx, 1.0).sum(axis=1)
+    assert np.allclose(info["log_px"], ref_px, rtol=1e-10, atol=1e-10)
+    assert np.allclose(info["logq"], ref_px, rtol=1e-10, atol=1e-10)
+    # the local resampling follows the inner weights: counts within floor/ceil of M qbar
+    q = np.exp(lam)
+    for i in range(N):
+        cnt = np.bincount(info["binner"][i], minlength=M)
+        assert np.all(cnt >= np.floor(M * q[i] - 1e-9)) and np.all(cnt <= np.ceil(M * q[i] + 1e-9))
+    # z_t from the resampled components and the NEW_Z normals, then eq:approx2
+    from oracle import philox as P
+    ref = np.empty(N)
+    for i in range(N):
+        nu = P.normals(9, 0, 4, i, np.arange(M), P.NEW_Z, 8)
+        zt = m.fz(st["x"][i], info["xt"][i], st["z"][i, info["binner"][i]], nu)
+        ell = stats.norm.logpdf(y[None, :], zt + 0.05 * np.tile(info["xt"][i] ** 2, 4)[None, :],
+                                np.sqrt(0.5)).sum(axis=1)
+        ref[i] = np.log(np.mean(np.exp(ell - ell.max()))) + ell.max()
+    assert np.allclose(info["logw"], ref, rtol=1e-10, atol=1e-9)
