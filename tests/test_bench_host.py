@@ -48,3 +48,29 @@ def test_issue_slot_count():
 def test_traffic_summary_matches_the_kernel_sources():
     assert bench.read_traffic("newcloud") is not None
     assert bench.read_traffic("post") is not None
+
+
+def test_cpu_baseline_reports_all_cores_and_one():
+    r = bench.run_cpu_baseline(1)
+    assert r is not None and r["kind"] == "oracle"
+    assert r["cores"] == max(1, min(16, bench.cpu_cores()))
+    assert r["value"] > 0 and r["single_core_value"] > 0
+    assert "processes" in r["sample"]
+
+
+def test_bench_kalman_posterior_equals_the_oracle_kalman_filter():
+    """The accuracy target the bench measures against is the exact posterior:
+    its x marginal must equal the oracle's joint Kalman filter."""
+    import numpy as np
+
+    import dpf_synth as S
+    from oracle.kalman import kalman_filter
+    from oracle.models import make_model
+
+    spec = S.lingauss_c1(False)
+    _, _, ys = S.simulate(spec, 40, 3)
+    mu, var = bench.kalman_x_posterior(spec.blob, ys[:, 0])
+    m = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
+    means, covs, _ = kalman_filter(m, ys)
+    assert np.allclose(mu, means[:, 0], rtol=1e-12, atol=1e-12)
+    assert np.allclose(var, covs[:, 0, 0], rtol=1e-12, atol=1e-12)

@@ -8,6 +8,7 @@ Sizes span several tiles with ragged tails in N and M.
 """
 import copy
 import functools
+import math
 
 import numpy as np
 import pytest
@@ -71,8 +72,47 @@ def _la_case(name, N, M, warm, steps, seed=4242, data_seed=3):
         est["xhat_rb"] = f.estimate_rb()
         r, st, info = compare_la(model, st32, ys[t], seed, 0, gs, ell, logw, anc, sel)
         print("LA %s N=%d M=%d t=%d: %s" % (name, N, M, t + 1, r.line()), flush=True)
-        reports.append((r, info, est))
+        reports.append((r, info, est, gs, logw))
     return reports
+
+
+def _check_evidence(est, info, logw_g, what):
+    """The evidence and ESS of a step depend only on the outer log-weights,
+    which involve no sampled index: compared with the oracle in every case.
+    After an import the cumulative evidence is this step's increment
+    logsumexp_i log w_i - log N.  Bounds: the stated 1e-4 relative target,
+    and the propagation of the log-weights' own difference d = max|dlog w|
+    (logsumexp moves by at most d, log ESS = 2 LSE(lw) - LSE(2 lw) by 4d)."""
+    d = float(np.max(np.abs(logw_g.astype(np.float64) - info["logw"])))
+    ll = float(est["loglik"][0])
+    ref = float(info["dlogz"])
+    assert abs(ll - ref) <= 1e-4 * max(1.0, abs(ref)), (what, ll, ref)
+    assert abs(ll - ref) <= d + 1e-9 * max(1.0, abs(ref)), (what, ll, ref, d)
+    ess = float(est["ess"][0])
+    assert abs(math.log(ess) - math.log(info["ess"])) <= 4 * d + 1e-6, (what, ess, info["ess"], d)
+
+
+def _check_self_estimates(est, gs, logw_g):
+    """Estimates of a look-ahead step against FP64 values recomputed from the
+    GPU's own new state and outer log-weights (no dependence on index flips):
+    xhat = mean_k x_k, zhat = mean_k sum_j exp(lam_kj) z_kj, ESS and the
+    evidence increment from log w."""
+    x = gs["x"].astype(np.float64)
+    z = gs["z"].astype(np.float64)
+    lam = gs["lam"].astype(np.float64)
+    N = x.shape[0]
+    xh = x.mean(axis=0)
+    zh = np.einsum("nm,nmd->d", np.exp(lam), z) / N
+    lw = logw_g.astype(np.float64)
+    w = np.exp(lw - lw.max())
+    ess = w.sum() ** 2 / np.sum(w * w)
+    dlogz = lw.max() + math.log(w.sum()) - math.log(N)
+    xs = max(1.0, float(np.abs(x).mean()))
+    zs = max(1.0, float(np.abs(z).mean()))
+    assert np.allclose(est["xhat"][0].cpu().numpy(), xh, rtol=1e-5, atol=1e-5 * xs), (est["xhat"], xh)
+    assert np.allclose(est["zhat"][0].cpu().numpy(), zh, rtol=1e-5, atol=1e-5 * zs), (est["zhat"], zh)
+    assert abs(float(est["ess"][0]) - ess) <= 1e-5 * ess, (float(est["ess"][0]), ess)
+    assert abs(float(est["loglik"][0]) - dlogz) <= 1e-6 * max(1.0, abs(dlogz)), (float(est["loglik"][0]), dlogz)
 
 
 @pytest.mark.parametrize("name,N,M,warm,steps", [
@@ -93,8 +133,10 @@ def _la_case(name, N, M, warm, steps, seed=4242, data_seed=3):
     ("fourdim", 33, 200, 7, 2),
 ])
 def test_lookahead_step_parity(name, N, M, warm, steps):
-    for r, info, est in _la_case(name, N, M, warm, steps):
+    for r, info, est, gs, logw in _la_case(name, N, M, warm, steps):
         assert_clean(r, n=N)
+        _check_evidence(est, info, logw, name)
+        _check_self_estimates(est, gs, logw)
         # the Rao-Blackwellised estimate involves no sampled index: compared
         # always; its weights come from FP32 ell (absolute error ~3e-5 at
         # |ell| ~ 100) applied to candidates up to ~20 apart
@@ -108,10 +150,18 @@ def test_lookahead_step_parity(name, N, M, warm, steps):
             assert abs(float(est["ess"][0]) - info["ess"]) <= 1e-3 * info["ess"]
 
 
-def test_lookahead_step_parity_full_size_nonlin():
-    """The benchmark's configuration (N=4096, M=256, dz=8), one step."""
-    for r, info, est in _la_case("nonlin", 4096, 256, 1, 1):
+@pytest.mark.parametrize("N,M", [(4096, 256), (16700, 8)])
+def test_lookahead_step_parity_full_size_nonlin(N, M):
+    """The benchmark's configuration (N=4096, M=256, dz=8), one step; and
+    N = 16700 (66 groups of outer weights: the step end as a group pass and a
+    per-filter pass).  Estimates, ESS and evidence are compared even where
+    indices flipped: against the oracle where they depend on the weights only,
+    against FP64 sums of the GPU's own new state where they depend on the
+    resampled particles."""
+    for r, info, est, gs, logw in _la_case("nonlin", N, M, 1, 1):
         assert_clean(r)
+        _check_evidence(est, info, logw, "full size")
+        _check_self_estimates(est, gs, logw)
 
 
 def _plain_case(name, N, M, warm, steps, seed=777, data_seed=5):
@@ -136,7 +186,7 @@ def _plain_case(name, N, M, warm, steps, seed=777, data_seed=5):
         gs = {"x": g["x"][0], "z": g["z"][0]}
         r, st, info = compare_plain(model, st32, ys[t], seed, 0, gs, ell, logw, anc, sel)
         print("DPF %s N=%d M=%d t=%d: %s" % (name, N, M, t + 1, r.line()), flush=True)
-        out.append((r, info, f.estimate()))
+        out.append((r, info, f.estimate(), logw))
     return out
 
 
@@ -151,8 +201,9 @@ def _plain_case(name, N, M, warm, steps, seed=777, data_seed=5):
     ("fourdim", 260, 25, 6, 2),
 ])
 def test_plain_step_parity(name, N, M, warm, steps):
-    for r, info, est in _plain_case(name, N, M, warm, steps):
+    for r, info, est, logw in _plain_case(name, N, M, warm, steps):
         assert_clean(r, n=N)
+        _check_evidence(est, info, logw, name)
         # plain estimates are formed before resampling: they depend only on ell
         xg = est["xhat"][0].cpu().numpy()
         assert np.allclose(xg, info["xhat"], rtol=1e-4, atol=1e-4)

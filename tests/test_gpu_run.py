@@ -277,3 +277,103 @@ def test_autotuner_picks_a_measured_class_and_round_trips(tmp_path):
     ys = np.stack([S.simulate(spec, 20, 70 + q)[2] for q in range(3)], axis=1)
     xt, _ = f.run(torch.tensor(ys, dtype=torch.float32), use_graph=True)
     assert np.all(np.isfinite(xt.cpu().numpy()))
+
+
+def _lingauss_tuned_handle(seed):
+    """Three linear-Gaussian filters under the batched run's tuned classes:
+    (32, 1), (32, 2) and (32, 4) for M = 32, 64 and 128."""
+    spec = S.lingauss_c1(False)
+    N, M, cls = [300, 200, 150], [32, 64, 128], [0, 6, 7]
+    f = _filter(spec, N, M, seed=seed)
+    f.set_tiling(cls)
+    return spec, N, M, f
+
+
+def test_tuned_batched_classes_match_oracle():
+    """The tile classes the autotuner picks for the batched linear-Gaussian
+    run, in one ragged handle, two consecutive steps each compared with the
+    oracle per filter (every step starts from the oracle's state, rounded)."""
+    seed = 4040
+    spec, N, M, g = _lingauss_tuned_handle(seed)
+    model = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
+    F = len(N)
+    ys = np.stack([S.simulate(spec, 4, 90 + f)[2] for f in range(F)], axis=1)  # [T][F][1]
+    ys = ys.astype(np.float32).astype(np.float64)
+    states = []
+    for f in range(F):
+        st = ladpf.init_state(model, N[f], M[f], seed, f)
+        st, _ = ladpf.step(model, st, ys[0, f], seed, f)
+        states.append(to_state32(st))
+    for t in (1, 2):
+        g.import_state(torch.from_numpy(g.pack_state([s["t"] for s in states], [s["x"] for s in states],
+                                                     [s["z"] for s in states], [s["lam"] for s in states])))
+        g.lookahead_step(torch.tensor(ys[t], dtype=torch.float32))
+        out = g.unpack_state(g.export_state())
+        ell = g.copy_buffer(dpf.BUF_ELL).cpu().numpy()
+        logw = g.copy_buffer(dpf.BUF_LOGW).cpu().numpy()
+        anc = g.copy_buffer(dpf.BUF_ANC).cpu().numpy()
+        sel = g.copy_buffer(dpf.BUF_SEL).cpu().numpy()
+        est = g.estimate()
+        oo = io = 0
+        nxt = []
+        for f in range(F):
+            n, m = N[f], M[f]
+            gs = {"x": out["x"][f], "z": out["z"][f], "lam": out["lam"][f]}
+            r, new_o, info = compare_la(model, states[f], ys[t, f], seed, f, gs,
+                                        ell[io:io + n * m].reshape(n, m), logw[oo:oo + n], anc[oo:oo + n],
+                                        sel[oo:oo + n])
+            print("tuned class step %d filter %d N=%d M=%d: %s" % (t, f, n, m, r.line()), flush=True)
+            assert_clean(r, n=n)
+            ll = float(est["loglik"][f])
+            assert abs(ll - info["dlogz"]) <= 1e-4 * max(1.0, abs(info["dlogz"])), (f, ll, info["dlogz"])
+            nxt.append(to_state32(new_o))
+            oo += n
+            io += n * m
+        states = nxt
+
+
+def test_tuned_batched_classes_run_equals_step_calls():
+    """Under the same classes, a graph-replayed run (fused steps: each step's
+    look-ahead weights inside the previous new-cloud launch) equals step
+    calls bit for bit, with per-filter horizons across a chunk boundary."""
+    T = 21
+    spec, N, M, a = _lingauss_tuned_handle(77)
+    Y = np.stack([S.simulate(spec, T, 130 + f)[2] for f in range(len(N))], axis=1).astype(np.float32)
+    Tf = [21, 18, 9]
+    for t in range(T):
+        act = np.array([t < Tf[f] for f in range(len(N))], dtype=np.uint8)
+        a.lookahead_step(torch.from_numpy(Y[t]), active=act)
+    _, _, _, b = _lingauss_tuned_handle(77)
+    b.run(torch.from_numpy(Y), Tf=Tf, use_graph=True)
+    assert np.array_equal(a.export_state().cpu().numpy(), b.export_state().cpu().numpy())
+    ea, eb = a.estimate(), b.estimate()
+    for k in ("xhat", "zhat", "ess", "loglik"):
+        assert torch.equal(ea[k], eb[k]), k
+
+
+def test_cumulative_evidence_over_steps():
+    """The cumulative evidence sums the per-step increments: two steps on the
+    GPU from an imported state against the oracle's increments, the second
+    taken by the oracle from the GPU's own state after the first (so index
+    flips in the first step do not matter)."""
+    spec = S.nonlin_c2(1)
+    model = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
+    N, M, seed = 700, 64, 31
+    _, _, ys = S.simulate(spec, 3, 12)
+    ys = ys.astype(np.float32).astype(np.float64)
+    st = ladpf.init_state(model, N, M, seed, 0)
+    st, _ = ladpf.step(model, st, ys[0], seed, 0)
+    st32 = to_state32(st)
+    f = _filter(spec, [N], [M], seed=seed)
+    f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["x"], st32["z"], st32["lam"])))
+    f.lookahead_step(torch.tensor(ys[1], dtype=torch.float32))
+    g1 = f.unpack_state(f.export_state())
+    _, info1 = ladpf.step(model, st32, ys[1], seed, 0)
+    f.lookahead_step(torch.tensor(ys[2], dtype=torch.float32))
+    st_g = {"x": g1["x"][0].astype(np.float64), "z": g1["z"][0].astype(np.float64),
+            "lam": g1["lam"][0].astype(np.float64), "t": int(g1["t"][0])}
+    _, info2 = ladpf.step(model, st_g, ys[2], seed, 0)
+    ll = float(f.estimate()["loglik"][0])
+    ref = info1["dlogz"] + info2["dlogz"]
+    print("cumulative evidence gpu %.9g oracle %.9g" % (ll, ref), flush=True)
+    assert abs(ll - ref) <= 1e-4 * max(1.0, abs(ref))
