@@ -33,6 +33,23 @@ Step t, given y_t, in the order of Fig. 4:
    finally the inner measurement update eq:qbar gives
    lam_t^{(k,j)} = log p(y_t | x_t^{(k)}, z_t^{(k,j)}) - logsumexp_j(.).
 
+Nested look-ahead estimator (optional, n_comp = K >= 1).  Fig. 4 step 1
+draws N_x' candidates and, for each, N_z' companions from the inner
+predictive given that candidate; eq:weightsMC averages p(y_t | .) over all
+of them.  With K companions per candidate (N_x' = M stratified candidates as
+above, N_z' = K): the companions of candidate xla^{(i,m)} take ancestors
+b_1..b_K by systematic resampling (U53 LA_B at (t, i, m)) of the inner
+weights conditioned on the candidate as in eq:qnobar,
+kappa_j = lam^{(i,j)} + log p(xla^{(i,m)} | x_{t-1}^{(i)}, z_{t-1}^{(i,j)}),
+and are propagated with the inner prior, zla^{(i,m,k)} ~
+p(z_t | x_{t-1}^{(i)}, xla^{(i,m)}, z_{t-1}^{(i,b_k)}) (LA_Z normals k dz ..
+k dz + dz - 1 of the draw at (t, i, m)); then
+ell^{(i,m)} = lam^{(i,m)} + log (1/K) sum_k p(y_t | xla^{(i,m)}, zla^{(i,m,k)})
+and log w^{(i)} = logsumexp_m ell^{(i,m)} as before.  Steps 3-4 are
+unchanged (the SIR of step 4 uses these ell).  Cost K M^2 model
+evaluations per outer particle where p(x_t | x_{t-1}, z_{t-1}) depends on z,
+K M otherwise (kappa is then lam up to a constant).
+
 Estimates: xhat = mean_k x_t^{(k)}, zhat = mean_k sum_j qbar_t z_t,
 ESS of the look-ahead weights, dlogZ = logsumexp_i log w - log N, and the
 Rao-Blackwellised xhat_rb = sum_i Wbar_i sum_j pi_ij xla^{(i,j)} (the exact
@@ -82,19 +99,56 @@ def lookahead(model, state, y, seed, fid):
     return xla, zla, ell, logw
 
 
-def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None):
+def lookahead_nested(model, state, y, seed, fid, K, u_comp=None):
+    """Fig. 4 steps 1-2 with K companions per candidate (the nested estimator
+    of eq:weightsMC, see the module text); returns (xla, ell, logw, comp),
+    comp[i, m] the K companion ancestors of candidate (i, m).  u_comp
+    replaces the LA_B offsets (test hook)."""
+    x, z, lam = state["x"], state["z"], state["lam"]
+    t = state["t"] + 1
+    N, M = lam.shape
+    dz = model.dz
+    i_ = np.arange(N)[:, None]
+    j_ = np.arange(M)[None, :]
+    nu_x = P.normals(seed, fid, t, i_, j_, P.LA_X, model.dx)
+    xla = model.fx(x[:, None, :], z, nu_x, t - 1)
+    nu_z = P.normals(seed, fid, t, i_, j_, P.LA_Z, K * dz).reshape(N, M, K, dz)
+    if u_comp is None:
+        u_comp = P.uniform53_ab(seed, fid, t, i_, j_, P.LA_B)
+    ell = np.empty((N, M))
+    comp = np.empty((N, M, K), dtype=np.int64)
+    for i in range(N):
+        for m in range(M):
+            # inner weights conditioned on the candidate (eq:qnobar)
+            kappa = lam[i] + model.logpx(xla[i, m], x[i], z[i], t - 1)
+            b, _, _ = systematic_log(kappa, K, float(u_comp[i, m]))
+            comp[i, m] = b
+            zc = model.fz(x[i], xla[i, m], z[i, b], nu_z[i, m], t - 1)
+            ell[i, m] = lam[i, m] + logsumexp(model.logpy(y, xla[i, m], zc)) - math.log(K)
+    logw = logsumexp(ell)
+    return xla, ell, logw, comp
+
+
+def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None, n_comp=0):
     """One look-ahead DPF step consuming y_t.  Returns (new_state, info).
 
     The ``u_*`` arguments replace the Philox offsets (test hooks for
     enumerating resampling outcomes); by default they come from the
-    random-number contract.
+    random-number contract.  n_comp >= 1: the nested look-ahead estimator
+    with that many companions per candidate; 0: one companion drawn with
+    the candidate from the same inner component.
     """
     x, z, lam = state["x"], state["z"], state["lam"]
     t = state["t"] + 1
     N, M = lam.shape
     flags = 0
 
-    xla, zla, ell, logw = lookahead(model, state, y, seed, fid)
+    comp = None
+    if n_comp:
+        xla, ell, logw, comp = lookahead_nested(model, state, y, seed, fid, n_comp)
+        zla = None
+    else:
+        xla, zla, ell, logw = lookahead(model, state, y, seed, fid)
 
     # Step 3: outer resampling with the look-ahead weights.
     if u_outer is None:
@@ -148,7 +202,7 @@ def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None):
     zhat = np.einsum("nm,nmd->d", np.exp(lamnew), znew) / N
     new_state = {"x": xnew, "z": znew, "lam": lamnew, "t": t}
     info = {
-        "xla": xla, "zla": zla, "ell": ell, "logw": logw, "A": A, "cand": cand,
+        "xla": xla, "zla": zla, "comp": comp, "ell": ell, "logw": logw, "A": A, "cand": cand,
         "binner": binner, "u_outer": u_outer, "u_cand": np.asarray(u_cand),
         "u_inner": np.asarray(u_inner),
         "xhat": xhat, "zhat": zhat, "ess": ess, "dlogz": dlogz, "xhat_rb": xhat_rb,
@@ -176,12 +230,12 @@ def state_x_new(info):
     return xla[A, cand]
 
 
-def run(model, N, M, ys, seed, fid):
+def run(model, N, M, ys, seed, fid, n_comp=0):
     """Run the look-ahead DPF over observations y_1..y_T; returns per-step estimates."""
     state = init_state(model, N, M, seed, fid)
     out = {"xhat": [], "zhat": [], "ess": [], "dlogz": [], "xhat_rb": [], "flags": 0}
     for y in ys:
-        state, info = step(model, state, y, seed, fid)
+        state, info = step(model, state, y, seed, fid, n_comp=n_comp)
         for key in ("xhat", "zhat", "ess", "dlogz", "xhat_rb"):
             out[key].append(info[key])
         out["flags"] |= info["flags"]

@@ -36,6 +36,8 @@ MASK32 = np.uint64(0xFFFFFFFF)
 # Purpose tags of the counter's top byte.
 INIT_X, INIT_Z, LA_X, LA_Z, OUTER_U, CAND_U, INNER_U, NEW_Z = range(8)
 DPF_ANC_U, DPF_X, DPF_Z, MDN_U, MDN_X = range(8, 13)
+# companion ancestors of the nested look-ahead estimator (one U53 per candidate)
+LA_B = 13
 
 
 def philox4x32_10(ctr, key):
@@ -103,6 +105,12 @@ def u53(w0, w1):
 def uniform53(seed, filter_id, t, a, purpose):
     """The single U53 offset of a resampling / selection draw at (t, a, 0)."""
     w = words(seed, filter_id, t, a, 0, purpose, 0)
+    return u53(w[..., 0], w[..., 1])
+
+
+def uniform53_ab(seed, filter_id, t, a, b, purpose):
+    """U53 offset of a draw at counter (t, a, b) (block 0)."""
+    w = words(seed, filter_id, t, a, b, purpose, 0)
     return u53(w[..., 0], w[..., 1])
 
 

@@ -257,3 +257,87 @@ def test_plain_dpf_with_one_inner_particle_is_bootstrap_pf():
         A = _textbook_systematic(w, float(P.uniform53(seed, fid, t, 0, P.OUTER_U)))
         x, z = propagate(x[A], z[A], t)
     assert np.allclose(x, out["state"]["xt"], rtol=1e-12)
+
+
+# ---- nested look-ahead estimator (K companions per candidate)
+# Linear-Gaussian pieces written out from the model statement of the
+# workload (c = [1, 0.5], A = [[0.8, 0.1], [0, 0.7]], coupling 0.2 z1 into x
+# for the coupled variant): given x_{t-1} = x and one inner component z_j,
+#   y_t ~ N(1.575 x + (0.8 + 1.75 g) z1 + 0.45 z2, 0.63125), g the coupling;
+# given also the candidate x_t = xc,
+#   y_t ~ N(1.75 xc + 0.8 z1 + 0.45 z2, 0.325)   (c.(A z + 0.5 xc 1) + xc,
+#   variance c.c 0.1 + 0.2), and x_t | x, z_j ~ N(0.9 x + g z1, 0.1).
+def _y_given_parent(x, z, g):
+    return 1.575 * x + (0.8 + 1.75 * g) * z[..., 0] + 0.45 * z[..., 1], 0.63125
+
+
+@pytest.mark.parametrize("coupled,K", [(False, 1), (False, 4), (True, 1), (True, 3)])
+def test_nested_lookahead_weight_expectation_closed_form(coupled, K):
+    """For any number of companions the nested weight is unbiased for the
+    predictive likelihood of eq:weightsopt under the inner cloud:
+    E[w_i] = sum_j qbar_j p(y_t | x_{t-1}^i, z_{t-1}^{ij}).  On the coupled
+    model this needs the companions' ancestors drawn from the inner weights
+    conditioned on the candidate (eq:qnobar)."""
+    spec = S.lingauss_c1(coupled)
+    m = _model(spec)
+    g = np.random.default_rng(15 + K + 10 * coupled)
+    st = _random_state(m, 3, 4, g)
+    st["z"] *= 2.0                        # spread clouds: the conditioning matters
+    y = np.array([0.9])
+    R = 3000
+    W = np.empty((R, 3))
+    for r in range(R):
+        _, _, logw, _ = ladpf.lookahead_nested(m, st, y, 99, r, K)
+        W[r] = np.exp(logw)
+    qbar = np.exp(st["lam"])
+    mj, v = _y_given_parent(st["x"][:, :1], st["z"], 0.2 if coupled else 0.0)
+    expect = np.sum(qbar * stats.norm.pdf(y[0], mj, math.sqrt(v)), axis=1)
+    se = W.std(axis=0) / math.sqrt(R)
+    assert np.all(np.abs(W.mean(axis=0) - expect) < 5 * se), (W.mean(axis=0), expect, se)
+
+
+@pytest.mark.parametrize("coupled", [False, True])
+def test_nested_candidate_score_with_many_companions(coupled):
+    """With many companions ell^{(i,m)} - lam^{(i,m)} approaches the inner
+    predictive likelihood at the candidate, log sum_j q_j N(y; 1.75 xc +
+    0.8 z1_j + 0.45 z2_j, 0.325), q_j proportional to qbar_j p(xc | x, z_j)
+    (eq:approx3's first factor with the x-conditioned inner weights)."""
+    spec = S.lingauss_c1(coupled)
+    m = _model(spec)
+    gc = 0.2 if coupled else 0.0
+    rng = np.random.default_rng(21)
+    st = _random_state(m, 2, 3, rng)
+    st["z"] *= 2.0
+    y = np.array([0.5])
+    K = 200000
+    xla, ell, _, comp = ladpf.lookahead_nested(m, st, y, 5, 0, K)
+    for i in range(2):
+        for j in range(3):
+            xc = xla[i, j, 0]
+            px = stats.norm.pdf(xc, 0.9 * st["x"][i, 0] + gc * st["z"][i, :, 0], math.sqrt(0.1))
+            q = np.exp(st["lam"][i]) * px
+            q /= q.sum()
+            mu = 1.75 * xc + 0.8 * st["z"][i, :, 0] + 0.45 * st["z"][i, :, 1]
+            ref = np.sum(q * stats.norm.pdf(y[0], mu, math.sqrt(0.325)))
+            # Monte Carlo error of the mean of K likelihood values: with
+            # s = c.w ~ N(0, 0.125), E_s[N(y; mu + s, 0.2)^2] =
+            # N(y; mu, 0.1 + 0.125) / sqrt(0.8 pi) bounds each term's variance
+            se = math.sqrt(np.sum(q * stats.norm.pdf(y[0], mu, math.sqrt(0.225))) / math.sqrt(0.8 * math.pi) / K)
+            got = math.exp(ell[i, j] - st["lam"][i, j])
+            assert abs(got - ref) <= 6 * se, (i, j, got, ref, se)
+            # the companions' ancestors follow the conditioned weights
+            cnt = np.bincount(comp[i, j], minlength=3)
+            assert np.all(np.abs(cnt - K * q) <= 1.0 + 1e-9)
+
+
+def test_nested_step_resamples_and_proposes_as_the_paired_step():
+    """Steps 3-4 do not depend on how the weights were formed: a nested step
+    on the plain linear-Gaussian model keeps the step's invariants and its
+    x estimate tracks the Kalman filter like the paired reading's."""
+    spec = S.lingauss_c1(False)
+    m = _model(spec)
+    _, _, ys = S.simulate(spec, 12, 8)
+    mu, _, _ = kalman.kalman_filter(m, ys)
+    out = ladpf.run(m, 60, 12, ys, 3, 0, n_comp=3)
+    assert np.all(np.isfinite(out["xhat"]))
+    assert np.mean(np.abs(out["xhat"][:, 0] - mu[:, 0])) < 0.15
