@@ -85,12 +85,33 @@ def _assert_elementwise(got, ref, what, rel=1e-2):
 
 
 def _oracle_grads(p, X, xt):
-    """Loss and gradients with the BF16-rounded forward of the GPU, FP64 backward."""
+    """Loss and gradients with the BF16-rounded forward of the GPU, FP64
+    backward; and an element-wise bound on the GPU's deviation from them."""
     out, cache = Lr.forward(p, X, bf16_mode=True)
     L, gout = Lr.mdn_nll_grad(out, xt)
     pq = dict(p)
     pq["W2"], pq["W3"] = Lr.bf16(p["W2"]), Lr.bf16(p["W3"])
-    return L, Lr.backward(pq, cache, gout)
+    return L, Lr.backward(pq, cache, gout), _grad_bounds(pq, cache, gout)
+
+
+def _grad_bounds(pq, cache, gout):
+    """Forward-error bound of every gradient element.  The GPU rounds the
+    output gradient and the two hidden-layer gradients to BF16 (relative
+    error u = 2^-9 each), its BF16 layer inputs may sit one BF16 unit (2u)
+    from the oracle's (their FP32 pre-activations differ from FP64 ones by
+    rounding), and it accumulates in FP32.  A product term of a weight
+    gradient thus carries at most (roundings on its chain) * u of its own
+    magnitude; the magnitudes are the same backward chain on absolute
+    values: |g|, then (|g| |W3|) |gelu'(a2)|, then (. |W2|) |gelu'(a1)|."""
+    u = 2.0 ** -9
+    ag = np.abs(gout)
+    m2 = (ag @ np.abs(pq["W3"])) * np.abs(Lr.gelu_grad(cache["a2"]))
+    m1 = (m2 @ np.abs(pq["W2"])) * np.abs(Lr.gelu_grad(cache["a1"]))
+    b = {"W3": 3 * u * (ag.T @ np.abs(cache["h2"])), "b3": 2 * u * ag.sum(axis=0),
+         "W2": 5 * u * (m2.T @ np.abs(cache["h1"])), "b2": 4 * u * m2.sum(axis=0),
+         "W1": 7 * u * (m1.T @ np.abs(cache["x0"])), "b1": 6 * u * m1.sum(axis=0)}
+    # FP32 accumulation and storage: a floor of 2^-20 of each tensor's largest magnitude
+    return {k: v + 2.0 ** -20 * float(np.max(v)) / u for k, v in b.items()}
 
 
 @pytest.mark.parametrize("B", [32, 1056])
@@ -101,7 +122,7 @@ def test_loss_gradient_matches_oracle(B):
     X[:, :26] = g.normal(size=(B, 26))
     X = X.astype(np.float32).astype(np.float64)
     xt = (g.normal(size=(B, 2)) * 2).astype(np.float32).astype(np.float64)
-    L, grads = _oracle_grads(p, X, xt)
+    L, grads, bounds = _oracle_grads(p, X, xt)
     m = _mlp(p, batch=B)
     loss, gvec = m.loss_and_grad(torch.tensor(X, dtype=torch.float32), torch.tensor(xt, dtype=torch.float32))
     gg = dpf.unflatten_params(gvec.cpu().numpy())
@@ -111,7 +132,9 @@ def test_loss_gradient_matches_oracle(B):
         e = _rel_l2(gg[k][kk], grads[k])
         print("grad %s B=%d rel_l2=%.3g" % (k, B, e), flush=True)
         assert e < 1e-2, k
-        _assert_elementwise(gg[k][kk], grads[k], "grad %s B=%d" % (k, B))
+        d = np.abs(gg[k][kk] - grads[k])
+        print("grad %s B=%d: worst |d| / bound = %.3g" % (k, B, float(np.max(d / bounds[k]))), flush=True)
+        assert np.all(d <= bounds[k]), k
     assert np.all(gg["W3"][20:] == 0.0) and np.all(gg["b3"][20:] == 0.0)
     assert np.all(gg["W1"][:, 26:] == 0.0)
     # no update: parameters unchanged
