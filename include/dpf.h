@@ -19,8 +19,10 @@
  *  - "d_" pointers are device memory of the GPU current when the handle was
  *    created; "h_" or unprefixed pointers in dpf_config are host memory.
  *  - The caller owns all device memory (workspace, inputs, outputs); the
- *    library never allocates device memory.  Buffers must stay valid until
- *    the work queued on the handle's stream has finished.
+ *    library never allocates device memory (its one device array, the 8 KiB
+ *    of dpf_systematic_noalloc, is part of the loaded code object).  Buffers
+ *    must stay valid until the work queued on the handle's stream has
+ *    finished.
  *  - All calls are asynchronous on the handle's HIP stream and return after
  *    queueing.  Argument and launch errors return synchronously with a
  *    non-zero dpf_status and a message from dpf_last_error(); conditions
@@ -375,6 +377,18 @@ dpf_status dpf_normals(uint64_t seed, uint32_t filter_id, uint32_t t, uint32_t p
  * (per-group statistics). */
 dpf_status dpf_systematic(const double* d_w, int32_t n, int32_t n_out, double u, double* d_scratch,
                           int32_t* d_out, void* hip_stream);
+
+/* dpf_systematic without a scratch argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, rule and results as
+ * dpf_systematic; the group statistics live in a library-owned device array
+ * of 4 * 256 doubles (8 KiB) per GPU, held until the process ends, so n is at
+ * most 65536 (larger n: DPF_EUNSUPPORTED).  Allocates nothing.  Every call
+ * on a GPU uses that GPU's one array: calls that may overlap on one GPU
+ * (different streams, host threads) race and must be serialised by the
+ * caller; calls queued on one stream are ordered. */
+dpf_status dpf_systematic_noalloc(const double* d_w, int32_t n, int32_t n_out, double u, int32_t* d_out,
+                                  void* hip_stream);
 
 /* The same rule per segment by the inner-resampling code: d_w [S][n]
  * doubles, d_u [S], n_out = n (local resampling) or 1 (single draw);

@@ -33,7 +33,7 @@ EXPORTS = [
     "dpf_set_proposal", "dpf_learned_step", "dpf_learned_step_given", "dpf_features",
     "dpf_mlp_blob_bytes", "dpf_mlp_param_count", "dpf_mlp_forward", "dpf_mlp_train_workspace_bytes",
     "dpf_mlp_pack", "dpf_mlp_train_step", "dpf_learned_run", "dpf_tile_classes", "dpf_set_tiling",
-    "dpf_estimate_rb",
+    "dpf_estimate_rb", "dpf_systematic_noalloc",
 ]
 
 
@@ -92,6 +92,7 @@ def lib():
         "dpf_normals": (_i32, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                _i32, _i32, _i32, _vp, _vp]),
         "dpf_systematic": (_i32, [_vp, _i32, _i32, ctypes.c_double, _vp, _vp, _vp]),
+        "dpf_systematic_noalloc": (_i32, [_vp, _i32, _i32, ctypes.c_double, _vp, _vp]),
         "dpf_segmented_systematic": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp]),
         "dpf_set_phase_events": (_i32, [_vp, _vp, _i32]),
         "dpf_set_proposal": (_i32, [_vp, _vp, _sz, ctypes.c_double]),

@@ -13,6 +13,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -949,6 +950,56 @@ extern "C" dpf_status dpf_systematic(const double* d_w, int32_t n, int32_t n_out
   LAUNCH_CHECK("k_prim_res_stats");
   hipLaunchKernelGGL(k_prim_res_select, dim3((n_out + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d_w, n, n_out, u,
                      d_scratch, (int*)d_out);
+  LAUNCH_CHECK("k_prim_res_select");
+  return DPF_OK;
+}
+
+// ------------------------------------------------ systematic, no allocation
+// dpf_systematic_noalloc keeps the per-group statistics in this file-scope
+// device array instead of a caller-supplied scratch buffer.  In host code
+// the name is only a stand-in: kernels get the address that
+// hipGetSymbolAddress returns for the current device (each device holds its
+// own copy), looked up once per device on the first call there.
+constexpr int kNoAllocMaxN = 65536;
+constexpr int kNoAllocGroups = kNoAllocMaxN / kResGroup;
+static __device__ __align__(256) double scratch[4 * kNoAllocGroups];
+constexpr int kMaxDevices = 64;
+static double* g_scratch_dev[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static dpf_status scratch_for_current_device(double** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(DPF_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    double* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DPF_EDEVICE, "hipGetSymbolAddress of the scratch array failed: %s", hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_systematic_noalloc(const double* d_w, int32_t n, int32_t n_out, double u, int32_t* d_out,
+                                             void* hip_stream) {
+  if (!d_w || !d_out || n < 1 || n_out < 1) return fail(DPF_EINVAL, "bad arguments");
+  if (n > kNoAllocMaxN)
+    return fail(DPF_EUNSUPPORTED, "n = %d exceeds the %d weights the library's own scratch holds", n, kNoAllocMaxN);
+  if (!(u >= 0.0 && u < 1.0)) return fail(DPF_EINVAL, "u must be in [0, 1)");
+  double* ws = nullptr;
+  const dpf_status st = scratch_for_current_device(&ws);
+  if (st != DPF_OK) return st;
+  // every group entry the kernels read is written by the statistics launch
+  // of this call first, so nothing needs clearing
+  const int G = (n + kResGroup - 1) / kResGroup;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipLaunchKernelGGL(k_prim_res_stats, dim3(G), dim3(kBlock), 0, s, d_w, n, ws);
+  LAUNCH_CHECK("k_prim_res_stats");
+  hipLaunchKernelGGL(k_prim_res_select, dim3((n_out + kBlock - 1) / kBlock), dim3(kBlock), 0, s, d_w, n, n_out, u,
+                     (const double*)ws, (int*)d_out);
   LAUNCH_CHECK("k_prim_res_select");
   return DPF_OK;
 }
