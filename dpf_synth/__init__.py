@@ -13,7 +13,7 @@ Parameter blob layouts are those of the library interface (include/dpf.h):
 LINGAUSS: Ax[dx*dx] Cxz[dx*dz] qx Az[dz*dz] Bzx[dz*dx] qz Hx[dy*dx] Hz[dy*dz] r
 NONLIN:   a b qx W[dz*dx] rho qz c r bmode
 HIGHDIM:  a b qx Alo[dz-1] Adiag[dz] Aup[dz-1] B[dz*dx] qz C[dy*dz] r eps nu gonly
-TWODIM:   qx qz cxz rho b amp freq r
+TWODIM:   qx qz cxz rho b amp freq r tswap   (TWODIM_ZFIRST: the same blob)
 FOURDIM:  a1 bs c21 a2 qx1 qx2 qz1 qz2 cz rho b amp freq r
 """
 from dataclasses import dataclass, field
@@ -21,7 +21,7 @@ from typing import List, Optional
 
 import numpy as np
 
-LINGAUSS, NONLIN, HIGHDIM, TWODIM, FOURDIM = 1, 2, 3, 4, 5
+LINGAUSS, NONLIN, HIGHDIM, TWODIM, FOURDIM, TWODIM_ZFIRST = 1, 2, 3, 4, 5, 6
 
 
 @dataclass
@@ -35,7 +35,7 @@ class ModelSpec:
     @property
     def name(self):
         return {LINGAUSS: "lingauss", NONLIN: "nonlin", HIGHDIM: "highdim", TWODIM: "twodim",
-                FOURDIM: "fourdim"}[self.kind]
+                FOURDIM: "fourdim", TWODIM_ZFIRST: "twodim_zfirst"}[self.kind]
 
 
 def lingauss_c1(coupled: bool = False) -> ModelSpec:
@@ -55,17 +55,22 @@ def lingauss_c1(coupled: bool = False) -> ModelSpec:
     return ModelSpec(LINGAUSS, 1, 2, 1, blob)
 
 
-def twodim_table1(qx: float = 1.0, qz: float = 1.0, cxz: float = 0.1) -> ModelSpec:
+def twodim_table1(qx: float = 1.0, qz: float = 1.0, cxz: float = 0.1, tswap: float = np.inf,
+                  zfirst: bool = False) -> ModelSpec:
     """Model 1 of Table 1 (the 2-dimensional example), dx = dz = dy = 1:
 
     x_{t+1} = x_t + z_t / (1 + z_t^2) + v^x_t
     z_{t+1} = x_t + 0.5 z_t + 25 z_t / (1 + z_t^2) + 8 cos(1.2 t) + v^z_t
     y_t = atan(x_t) + z_t^2 / 20 + e_t
     (v^x, v^z) ~ N(0, [[qx, cxz], [cxz, qz]]) (Table 1: 1, 1, 0.1), e ~ N(0, 1).
-    Parameters are rounded to FP32 once, as the library stores them.
+    From t >= tswap on the two transition laws are swapped (x' = z + 0.5 x +
+    25 x / (1 + x^2) + 8 cos(1.2 t) + v^x, z' = z + x / (1 + x^2) + v^z).
+    zfirst: the decomposition that samples z first (outer z, inner x); the
+    simulated truth and observations are the same.  Parameters are rounded
+    to FP32 once, as the library stores them.
     """
-    blob = np.array([qx, qz, cxz, 0.5, 25.0, 8.0, 1.2, 1.0], dtype=np.float32).astype(np.float64)
-    return ModelSpec(TWODIM, 1, 1, 1, blob)
+    blob = np.array([qx, qz, cxz, 0.5, 25.0, 8.0, 1.2, 1.0, tswap], dtype=np.float32).astype(np.float64)
+    return ModelSpec(TWODIM_ZFIRST if zfirst else TWODIM, 1, 1, 1, blob)
 
 
 def fourdim_table1() -> ModelSpec:
@@ -167,15 +172,19 @@ def _sim_fns(spec: ModelSpec):
                 e = np.where(out, np.sqrt(r) * g.standard_t(nu, size=dy), e)
             return C @ z + e
         return fx, fz, hy
-    if spec.kind == TWODIM:
-        qx, qz, cxz, rho, bb, amp, freq, r = b
+    if spec.kind in (TWODIM, TWODIM_ZFIRST):
+        qx, qz, cxz, rho, bb, amp, freq, r, tswap = b
+        slow = lambda s_, o_: s_ + o_ / (1 + o_ * o_)
+        grow = lambda g_, o_, t: o_ + rho * g_ + bb * g_ / (1 + g_ * g_) + amp * np.cos(freq * t)
+        mx = lambda x, z, t: grow(x, z, t) if t >= tswap else slow(x, z)
+        mz = lambda x, z, t: slow(z, x) if t >= tswap else grow(z, x, t)
         # the noise pair drawn jointly: v^x first, then v^z given v^x
-        fx = lambda x, z, g, t: x + z / (1 + z * z) + np.sqrt(qx) * g.normal(size=1)
+        fx = lambda x, z, g, t: mx(x, z, t) + np.sqrt(qx) * g.normal(size=1)
 
         def fz(x, xn, z, g, t):
-            vx = xn - x - z / (1 + z * z)
+            vx = xn - mx(x, z, t)
             vz = cxz / qx * vx + np.sqrt(qz - cxz * cxz / qx) * g.normal(size=1)
-            return x + rho * z + bb * z / (1 + z * z) + amp * np.cos(freq * t) + vz
+            return mz(x, z, t) + vz
         hy = lambda x, z, g: np.arctan(x) + z * z / 20 + np.sqrt(r) * g.normal(size=1)
         return fx, fz, hy
     if spec.kind == FOURDIM:

@@ -77,13 +77,19 @@ typedef enum {
  *   (gonly != 0: plain N(0, r)).
  * DPF_MODEL_TWODIM -- model 1 of Table 1 (the 2-dimensional example), built
  *   for (dx,dz,dy) = (1,1,1):
- *   qx qz cxz rho b amp freq r
+ *   qx qz cxz rho b amp freq r tswap
  *   x' = x + z/(1+z^2) + v^x ;
  *   z' = x + rho z + b z/(1+z^2) + amp cos(freq t) + v^z, t the time of the
  *   state the transition leaves ;
  *   (v^x, v^z) ~ N(0, [[qx, cxz], [cxz, qz]]) ; y = atan(x) + z^2/20 + e,
- *   e ~ N(0, r).  Table 1's values: 1 1 0.1 0.5 25 8 1.2 1.  Needs qx > 0,
- *   r > 0 and qx qz > cxz^2 (else DPF_EINVAL).
+ *   e ~ N(0, r).  Table 1's values: 1 1 0.1 0.5 25 8 1.2 1.  From t >= tswap
+ *   on the two transition laws are swapped (the change point of Section
+ *   4.3): x' = z + rho x + b x/(1+x^2) + amp cos(freq t) + v^x,
+ *   z' = z + x/(1+x^2) + v^z (tswap = +inf: never).  Needs qx, qz, r > 0
+ *   and qx qz > cxz^2 (else DPF_EINVAL).  x is sampled first (outer).
+ * DPF_MODEL_TWODIM_ZFIRST -- the same model and parameter blob, z sampled
+ *   first (the other decomposition of Section 3 / 4.3): the outer state is
+ *   z, the inner state x, so xmean estimates z and zmean estimates x.
  * DPF_MODEL_FOURDIM -- model 2 of Table 1 (the 4-dimensional example), built
  *   for (dx,dz,dy) = (2,2,1):
  *   a1 bs c21 a2 qx1 qx2 qz1 qz2 cz rho b amp freq r
@@ -101,7 +107,8 @@ typedef enum {
   DPF_MODEL_NONLIN = 2,
   DPF_MODEL_HIGHDIM = 3,
   DPF_MODEL_TWODIM = 4,
-  DPF_MODEL_FOURDIM = 5
+  DPF_MODEL_FOURDIM = 5,
+  DPF_MODEL_TWODIM_ZFIRST = 6
 } dpf_model;
 
 /* Which filter a handle runs. */
@@ -188,6 +195,24 @@ dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean, float* d_
  * calls with the same activity (per-filter horizons included). */
 dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_Tf,
                    float* d_xtrace, float* d_ztrace, int32_t use_graph);
+
+/* Nested look-ahead estimator (Section 2.1 after eq:approx3; Fig. 4 step 1
+ * with N_z' > 1 companions per candidate, eq:weightsMC).  n_comp = K >= 1:
+ * the look-ahead weight of every candidate x^{(i,m)} (drawn from inner
+ * component m, LA_X at (t, i, m)) averages p(y_t | x^{(i,m)}, z) over K
+ * companions z drawn from the inner predictive given the candidate -- their
+ * ancestors by systematic resampling (U53 of purpose LA_B = 13 at (t, i, m))
+ * of the inner weights conditioned on the candidate as in eq:qnobar, their
+ * propagation with LA_Z normals k dz .. k dz + dz - 1 at (t, i, m):
+ *   ell^{(i,m)} = log qbar^{(i,m)} + log (1/K) sum_k p(y_t | x^{(i,m)}, z^{(i,m,k)}).
+ * n_comp = 0 (the default): one companion drawn together with the candidate
+ * from the same inner component.  1 <= K <= 1024; DPF_ESTATE for a plain
+ * handle.  Takes effect from the next dpf_lookahead_step / dpf_run (a run
+ * with K >= 1 takes each step whole instead of computing the next step's
+ * weights inside the new-cloud launch; results still equal step calls).  Cost
+ * per outer particle: K M model evaluations, K M^2 where p(x' | x, z) depends
+ * on z.  The learned step's fallback keeps the paired form. */
+dpf_status dpf_set_lookahead_companions(dpf_handle* h, int32_t n_comp);
 
 /* Rao-Blackwellised estimate of the new outer state of the look-ahead step
  * just taken: xhat_rb = sum_i Wbar_i sum_j pi_ij xla^{(i,j)}, Wbar the

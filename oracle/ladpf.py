@@ -129,14 +129,16 @@ def lookahead_nested(model, state, y, seed, fid, K, u_comp=None):
     return xla, ell, logw, comp
 
 
-def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None, n_comp=0):
+def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None, n_comp=0, ell_given=None):
     """One look-ahead DPF step consuming y_t.  Returns (new_state, info).
 
     The ``u_*`` arguments replace the Philox offsets (test hooks for
     enumerating resampling outcomes); by default they come from the
     random-number contract.  n_comp >= 1: the nested look-ahead estimator
     with that many companions per candidate; 0: one companion drawn with
-    the candidate from the same inner component.
+    the candidate from the same inner component.  ell_given (N, M): take
+    these look-ahead log-weights instead of computing them (test hook for
+    checking steps 3-4 on given weights); the candidates are still drawn.
     """
     x, z, lam = state["x"], state["z"], state["lam"]
     t = state["t"] + 1
@@ -144,11 +146,14 @@ def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None, n_
     flags = 0
 
     comp = None
-    if n_comp:
+    if n_comp and ell_given is None:
         xla, ell, logw, comp = lookahead_nested(model, state, y, seed, fid, n_comp)
         zla = None
     else:
         xla, zla, ell, logw = lookahead(model, state, y, seed, fid)
+    if ell_given is not None:
+        ell = np.asarray(ell_given, dtype=np.float64)
+        logw = logsumexp(ell)
 
     # Step 3: outer resampling with the look-ahead weights.
     if u_outer is None:

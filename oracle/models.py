@@ -35,8 +35,9 @@ HIGHDIM:
     x' as NONLIN's x (dx components),  z' = A z + B sin(x') + sqrt(qz) w with
     A tridiagonal,  y = C z + e where each e_k has density
     (1-eps) N(0, r) + eps * t_nu(e/sqrt(r))/sqrt(r)  (gonly=1: pure N(0, r)).
-TWODIM (model 1 of Table 1, dx = dz = dy = 1):
-    qx qz cxz rho b amp freq r
+TWODIM (model 1 of Table 1, dx = dz = dy = 1; TWODIM_ZFIRST: the same
+model with z sampled first, outer z and inner x):
+    qx qz cxz rho b amp freq r tswap
     x' = x + z/(1+z^2) + v^x,  z' = x + rho z + b z/(1+z^2) + amp cos(freq t) + v^z,
     (v^x, v^z) ~ N(0, [[qx, cxz], [cxz, qz]]),  y = atan(x) + z^2/20 + e, e ~ N(0, r).
     In the factorisation of Eq. (1) the inner transition is conditioned on
@@ -52,7 +53,7 @@ import math
 
 import numpy as np
 
-LINGAUSS, NONLIN, HIGHDIM, TWODIM, FOURDIM = 1, 2, 3, 4, 5
+LINGAUSS, NONLIN, HIGHDIM, TWODIM, FOURDIM, TWODIM_ZFIRST = 1, 2, 3, 4, 5, 6
 
 LOG2PI = math.log(2.0 * math.pi)
 
@@ -101,6 +102,10 @@ class LinGauss:
 
     def logpx(self, xn, x, z, t=0):
         return _gauss_iso_logpdf(xn - self.mean_x(x, z), self.qx)
+
+    def obs_mean(self, x, z):
+        """Noise-free observation Hx x + Hz z."""
+        return _matvec(self.Hx, x) + _matvec(self.Hz, z)
 
     def logpy(self, y, x, z):
         return _gauss_iso_logpdf(y - _matvec(self.Hx, x) - _matvec(self.Hz, z), self.r)
@@ -193,39 +198,83 @@ class HighDim:
 
 class TwoDim:
     """Model 1 of Table 1: a scalar outer state driven by the inner one
-    (x' depends on z), a time-varying inner drift and correlated noises."""
+    (x' depends on z), a time-varying inner drift and correlated noises.
+
+    From t >= tswap on the two transition laws are swapped (x follows the
+    law z had and z the law x had; each keeps its own noise): the change
+    point of Section 4.3.  zfirst: the decomposition that samples z first,
+    i.e. the outer state is z and the inner one x (the other action of
+    Section 4.3); the arrays passed in are then (outer z, inner x).
+    """
     kind = TWODIM
 
-    def __init__(self, dx, dz, dy, blob):
+    def __init__(self, dx, dz, dy, blob, zfirst=False):
         if (dx, dz, dy) != (1, 1, 1):
             raise ValueError("TWODIM is (1, 1, 1)")
-        if len(blob) != 8:
-            raise ValueError("TWODIM blob has %d values, expected 8" % len(blob))
+        if len(blob) != 9:
+            raise ValueError("TWODIM blob has %d values, expected 9" % len(blob))
         self.dx = self.dz = self.dy = 1
-        self.qx, self.qz, self.cxz, self.rho, self.b, self.amp, self.freq, self.r = (float(v) for v in blob)
-        self.kz = self.cxz / self.qx                       # E[v^z | v^x] = kz v^x
-        self.qzc = self.qz - self.cxz * self.cxz / self.qx  # Var[v^z | v^x]
+        (self.qx, self.qz, self.cxz, self.rho, self.b, self.amp, self.freq, self.r,
+         self.tswap) = (float(v) for v in blob)
+        self.zfirst = bool(zfirst)
+        if zfirst:
+            self.kind = TWODIM_ZFIRST
 
     @staticmethod
-    def _sat(z):
-        return z / (1.0 + z * z)
+    def _sat(v):
+        return v / (1.0 + v * v)
 
-    def mean_x(self, x, z):
-        return x + self._sat(z)
+    # the two laws in the paper's variables (x, z)
+    def _slow(self, s, other):
+        return s + self._sat(other)
+
+    def _grow(self, g, other, t):
+        return other + self.rho * g + self.b * self._sat(g) + self.amp * math.cos(self.freq * t)
+
+    def _mean_x(self, x, z, t):
+        return self._grow(x, z, t) if t >= self.tswap else self._slow(x, z)
+
+    def _mean_z(self, x, z, t):
+        return self._slow(z, x) if t >= self.tswap else self._grow(z, x, t)
+
+    def _roles(self):
+        """(variance of the outer noise, of the inner one) and the regression
+        of the inner noise on the outer one."""
+        qo, qi = (self.qz, self.qx) if self.zfirst else (self.qx, self.qz)
+        return qo, qi, self.cxz / qo, qi - self.cxz * self.cxz / qo
+
+    def _xz(self, o, i):
+        return (i, o) if self.zfirst else (o, i)
+
+    def _mean_o(self, o, i, t):
+        x, z = self._xz(o, i)
+        return self._mean_z(x, z, t) if self.zfirst else self._mean_x(x, z, t)
+
+    def _mean_i(self, o, i, t):
+        x, z = self._xz(o, i)
+        return self._mean_x(x, z, t) if self.zfirst else self._mean_z(x, z, t)
 
     def fx(self, x, z, nu, t=0):
-        return self.mean_x(x, z) + math.sqrt(self.qx) * nu
+        qo, _, _, _ = self._roles()
+        return self._mean_o(x, z, t) + math.sqrt(qo) * nu
 
     def fz(self, x, xn, z, nu, t=0):
-        vx = xn - self.mean_x(x, z)
-        drift = x + self.rho * z + self.b * self._sat(z) + self.amp * math.cos(self.freq * t)
-        return drift + self.kz * vx + math.sqrt(self.qzc) * nu
+        """Inner transition given the outer one: v_i | v_o ~ N(k v_o, q_i|o)."""
+        _, _, k, qc = self._roles()
+        vo = xn - self._mean_o(x, z, t)
+        return self._mean_i(x, z, t) + k * vo + math.sqrt(qc) * nu
 
     def logpx(self, xn, x, z, t=0):
-        return _gauss_iso_logpdf(xn - self.mean_x(x, z), self.qx)
+        qo, _, _, _ = self._roles()
+        return _gauss_iso_logpdf(xn - self._mean_o(x, z, t), qo)
+
+    def obs_mean(self, x, z):
+        """Noise-free observation atan(x) + z^2 / 20 (paper variables)."""
+        xx, zz = self._xz(x, z)
+        return np.arctan(xx) + zz * zz / 20.0
 
     def logpy(self, y, x, z):
-        return _gauss_iso_logpdf(y - np.arctan(x) - z * z / 20.0, self.r)
+        return _gauss_iso_logpdf(y - self.obs_mean(x, z), self.r)
 
 
 class FourDim:
@@ -265,6 +314,11 @@ class FourDim:
         return (-0.5 * e[..., 0] ** 2 / self.qx1 - 0.5 * e[..., 1] ** 2 / self.qx2
                 - 0.5 * (2 * LOG2PI + math.log(self.qx1) + math.log(self.qx2)))
 
+    def obs_mean(self, x, z):
+        """Noise-free observation (x1 + x2)/(1 + x1^2) + atan(z1) + z2^2/20."""
+        h = (x[..., 0] + x[..., 1]) / (1.0 + x[..., 0] ** 2) + np.arctan(z[..., 0]) + z[..., 1] ** 2 / 20.0
+        return h[..., None]
+
     def logpy(self, y, x, z):
         h = (x[..., 0] + x[..., 1]) / (1.0 + x[..., 0] ** 2) + np.arctan(z[..., 0]) + z[..., 1] ** 2 / 20.0
         return _gauss_iso_logpdf(y - h[..., None], self.r)
@@ -280,6 +334,8 @@ def make_model(kind, dx, dz, dy, blob):
         return HighDim(dx, dz, dy, blob)
     if kind == TWODIM:
         return TwoDim(dx, dz, dy, blob)
+    if kind == TWODIM_ZFIRST:
+        return TwoDim(dx, dz, dy, blob, zfirst=True)
     if kind == FOURDIM:
         return FourDim(dx, dz, dy, blob)
     raise ValueError("unknown model kind %r" % (kind,))

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdpf.so")
 
 DPF_ABI_VERSION = 1
-MODEL_LINGAUSS, MODEL_NONLIN, MODEL_HIGHDIM, MODEL_TWODIM, MODEL_FOURDIM = 1, 2, 3, 4, 5
+MODEL_LINGAUSS, MODEL_NONLIN, MODEL_HIGHDIM, MODEL_TWODIM, MODEL_FOURDIM, MODEL_TWODIM_ZFIRST = 1, 2, 3, 4, 5, 6
 ALGO_LOOKAHEAD, ALGO_PLAIN = 0, 1
 FLAG_DEGENERATE_OUTER, FLAG_DEGENERATE_INNER, FLAG_NONFINITE, FLAG_FALLBACK = 1, 2, 4, 8
 BUF_ELL, BUF_LOGW, BUF_ANC, BUF_SEL, BUF_MDN, BUF_X, BUF_FALLBACK = range(7)
@@ -33,7 +33,7 @@ EXPORTS = [
     "dpf_set_proposal", "dpf_learned_step", "dpf_learned_step_given", "dpf_features",
     "dpf_mlp_blob_bytes", "dpf_mlp_param_count", "dpf_mlp_forward", "dpf_mlp_train_workspace_bytes",
     "dpf_mlp_pack", "dpf_mlp_train_step", "dpf_learned_run", "dpf_tile_classes", "dpf_set_tiling",
-    "dpf_estimate_rb", "dpf_systematic_noalloc",
+    "dpf_estimate_rb", "dpf_systematic_noalloc", "dpf_set_lookahead_companions",
 ]
 
 
@@ -102,6 +102,7 @@ def lib():
         "dpf_learned_run": (_i32, [_vp, _vp, _i32, _vp, _vp, _vp, _i32]),
         "dpf_tile_classes": (_i32, [_vp, _vp, _i32]),
         "dpf_set_tiling": (_i32, [_vp, _vp]),
+        "dpf_set_lookahead_companions": (_i32, [_vp, _i32]),
         "dpf_mlp_blob_bytes": (_sz, []),
         "dpf_mlp_param_count": (_sz, []),
         "dpf_mlp_forward": (_i32, [_vp, _vp, _i32, _vp, _vp]),
@@ -218,6 +219,11 @@ class Filter:
         """Tile class per filter (index into tile_classes(), or -1 = default)."""
         c = np.ascontiguousarray(np.broadcast_to(np.asarray(classes, dtype=np.int32), (self.F,)))
         _check(lib().dpf_set_tiling(self._h, c.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_companions(self, n_comp):
+        """Companions per look-ahead candidate: K >= 1 the nested estimator,
+        0 the paired form (default)."""
+        _check(lib().dpf_set_lookahead_companions(self._h, int(n_comp)))
 
     # -------------------------------------------------------------- learned proposal
     def set_proposal(self, mlp, ess_frac=0.1):

@@ -57,7 +57,8 @@ enum Op {
   OP_LEARNED_INNER,
   OP_MOMENTS,
   OP_LA_WEIGHTS_FALLBACK,
-  OP_NEWCLOUD_FALLBACK
+  OP_NEWCLOUD_FALLBACK,
+  OP_LA_WEIGHTS_NESTED
 };
 
 // Extra arguments of OP_MOMENTS (feature rows for dpf_features).
@@ -86,6 +87,6 @@ struct Engine {
                      hipStream_t s);
 };
 
-extern const Engine kEngLinGauss, kEngNonLin, kEngHighDim, kEngTwoDim, kEngFourDim;
+extern const Engine kEngLinGauss, kEngNonLin, kEngHighDim, kEngTwoDim, kEngFourDim, kEngTwoDimZ;
 
 }  // namespace dpf

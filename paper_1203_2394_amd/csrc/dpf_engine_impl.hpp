@@ -30,6 +30,9 @@ static void launch_op(int op, const StepArgs& a, int n, hipStream_t s) {
     case OP_LA_WEIGHTS:
       hipLaunchKernelGGL((k_la_weights<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
       break;
+    case OP_LA_WEIGHTS_NESTED:
+      hipLaunchKernelGGL((k_la_weights_nested<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
+      break;
     case OP_DPF_WEIGHTS:
       hipLaunchKernelGGL((k_dpf_weights<Mdl, SEG, JPT>), dim3(n), dim3(kBlock), 0, s, a);
       break;

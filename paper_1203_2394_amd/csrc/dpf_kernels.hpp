@@ -98,6 +98,7 @@ struct StepArgs {
   int anc_ready;  // outer ancestors already in anc
   const int2* rgroups;  // (filter, group) of each resampling workgroup
   int n_commit;         // learned-step commit workgroups at the head of the launch
+  int n_comp;           // companions per look-ahead candidate (nested estimator; 0: paired)
   // look-ahead state: cloud slot of each outer particle, per copy.  A step
   // that resamples by copying writes the identity; the learned step writes
   // its outer ancestors instead of moving the clouds.
@@ -159,7 +160,7 @@ template <class Mdl, int SEG>
 __device__ __forceinline__ void fz_pre_seg(const float* P, const float* xp, const float* xn, int ts, float* pre) {
   constexpr int DZ = Mdl::DZ;
   constexpr int W = SEG < 64 ? SEG : 64;
-  if constexpr (DZ > W) {
+  if constexpr (DZ > W || Mdl::NPRE != DZ) {
     Mdl::fz_pre(P, xp, xn, ts, pre);
   } else {
     const int lane = threadIdx.x & 63;
@@ -330,7 +331,7 @@ __device__ __forceinline__ float la_logpy(const StepArgs& a, const Key& key, int
     y[d] = yi[d];
     asm volatile("" : "+v"(y[d]));
   }
-  float nu_x[Mdl::DX], nu_z[Mdl::DZ], xl[Mdl::DX], pre[Mdl::DZ], zl[Mdl::DZ], r0[Mdl::DY];
+  float nu_x[Mdl::DX], nu_z[Mdl::DZ], xl[Mdl::DX], pre[Mdl::NPRE], zl[Mdl::DZ], r0[Mdl::DY];
   normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
   normals<Mdl::DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, nu_z);
   Mdl::fx(a.prm, x, z, nu_x, t - 1, xl);
@@ -394,6 +395,210 @@ __device__ __forceinline__ void la_weights_tile(const StepArgs& a, int ti, bool 
   }
   const float lw = seg_lse<SEG>(acc, sh);
   if (vi && ls == 0) a.logw[oo + i] = lw;
+}
+
+// Nested look-ahead weights (Fig. 4 step 1 with N_z' = K companions per
+// candidate, eq:weightsMC): candidate m of outer particle i is drawn from
+// inner component m as in the paired form (LA_X at (t, i, m)); its K
+// companions take ancestors by systematic resampling (U53 LA_B at
+// (t, i, m)) of the inner weights conditioned on the candidate,
+// kappa_j = lam_j + log p(xla_m | x_i, z_j) (eq:qnobar), and are propagated
+// with the inner prior (LA_Z normals k dz .. k dz + dz - 1 at (t, i, m));
+// ell_m = lam_m + log (1/K) sum_k p(y_t | xla_m, zla_mk).  When p(x' | x, z)
+// does not depend on z the conditioned weights are lam itself: one
+// cumulative sum serves every candidate and each lane scores its own
+// candidates.  Otherwise the segment walks the candidates in order, forming
+// each one's conditioned cumulative sum together and spreading its
+// companions over the lanes.
+template <class Mdl, int SEG, int JPT>
+__device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti) {
+  constexpr int DX = Mdl::DX, DZ = Mdl::DZ, DY = Mdl::DY;
+  constexpr int NSEG = kBlock / SEG, CAP = SEG * JPT;
+  constexpr bool kCond = Mdl::kXdepZ;
+  constexpr bool kHoldZ = kCond && JPT * DZ <= 64;  // the lane's cloud stays in registers
+  __shared__ SegScratch sh;
+  __shared__ double cdf[NSEG][CAP];
+  __shared__ float xs[NSEG][kCond ? CAP : 1][DX];
+  const int4 tile = a.tiles[ti];
+  const int f = tile.x;
+  const int am = a.active != nullptr ? a.active[f] : 1;
+  const int tf = a.run_Tf != nullptr ? a.run_Tf[f] : 0x7fffffff;
+  asm volatile("" ::"v"(am), "v"(tf));
+  const FilterView fv = load_filter(a, f);
+  const bool act = am != 0 && fv.t < min(tf, a.run_T);  // step_active
+  if (tile.z == 0 && threadIdx.x == 0) a.act[f] = act ? 1 : 0;
+  if (!act) return;
+  const int N = fv.N, M = fv.M, K = a.n_comp;
+  const int s = threadIdx.x / SEG;
+  const int i = tile.y + s;
+  const int ls = threadIdx.x % SEG;
+  const bool vi = i < N;
+  const int oo = fv.oo;
+  const long long io = fv.io;
+  const int t = fv.t + 1;
+  const unsigned char cb = (unsigned char)fv.cur;
+  const int src = copy_of(cb);
+  const Key key = make_key(a.seed, (uint32_t)f);
+  const int ci = vi ? (ident_slots(cb, src) ? i : a.ind[src][oo + i]) : 0;
+  const float logK = fast_log((float)K);
+
+  float y[DY], x[DX];
+  load_y<Mdl>(a, f, t, y);
+#pragma unroll
+  for (int d = 0; d < DX; ++d) x[d] = vi ? a.x[src][(long long)d * a.NT + oo + i] : 0.f;
+  const float* zrow = a.z[src] + (io + (long long)ci * M) * DZ;
+  const float* lrow = a.lam[src] + io + (long long)ci * M;
+  float* erow = a.ell + io + (long long)(vi ? i : 0) * M;
+
+  // candidates (as in the paired form) and the lanes' inner weights
+  float lamv[JPT], xl[JPT][DX];
+  float zh[kHoldZ ? JPT : 1][kHoldZ ? DZ : 1];
+#pragma unroll
+  for (int r = 0; r < JPT; ++r) {
+    const int j = ls + r * SEG;
+    lamv[r] = -INFINITY;
+#pragma unroll
+    for (int d = 0; d < DX; ++d) xl[r][d] = 0.f;
+    if (vi && j < M) {
+      float z[DZ], nu[DX];
+#pragma unroll
+      for (int d = 0; d < DZ; ++d) z[d] = zrow[d * M + j];
+      if constexpr (kHoldZ) {
+#pragma unroll
+        for (int d = 0; d < DZ; ++d) zh[kHoldZ ? r : 0][kHoldZ ? d : 0] = z[d];
+      }
+      lamv[r] = lrow[j];
+      normals<DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu);
+      Mdl::fx(a.prm, x, z, nu, t - 1, xl[r]);
+      if constexpr (kCond) {
+#pragma unroll
+        for (int d = 0; d < DX; ++d) xs[s][kCond ? j : 0][d] = xl[r][d];
+      }
+    }
+  }
+  float ev[JPT];
+#pragma unroll
+  for (int r = 0; r < JPT; ++r) ev[r] = -INFINITY;
+
+  if constexpr (!kCond) {
+    // ---- one cumulative sum of the inner weights for every candidate
+    float mloc = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < JPT; ++r)
+      if (finitef(lamv[r])) mloc = fmaxf(mloc, lamv[r]);
+    const float m0 = seg_max<SEG>(mloc, sh);
+    const bool deg = !(m0 > -INFINITY);
+    double carry = 0.0;
+#pragma unroll
+    for (int r = 0; r < JPT; ++r) {
+      const int j = ls + r * SEG;
+      double w = 0.0;
+      if (j < M) w = deg ? 1.0 : (finitef(lamv[r]) ? (double)fast_exp(lamv[r] - m0) : 0.0);
+      double tot;
+      const double c = seg_scan_incl<SEG>(w, sh, tot);
+      cdf[s][r * SEG + ls] = carry + c;
+      carry += tot;
+    }
+    seg_lds_sync<SEG>();
+    const double total = cdf[s][M - 1];
+#pragma unroll
+    for (int r = 0; r < JPT; ++r) {
+      const int j = ls + r * SEG;
+      if (vi && j < M) {
+        float pre[Mdl::NPRE], r0[DY];
+        Mdl::fz_pre(a.prm, x, xl[r], t - 1, pre);
+        Mdl::obs_pre(a.prm, y, xl[r], r0);
+        const double u = uniform53_ab(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_B);
+        Lse acck;
+        for (int k = 0; k < K; ++k) {
+          const int b = cdf_search(cdf[s], M, sys_point(k, u, total, K));
+          float zg[DZ], nu[DZ], zc[DZ];
+#pragma unroll
+          for (int d = 0; d < DZ; ++d) zg[d] = zrow[d * M + b];
+          normals_k<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, k, nu);
+          Mdl::fz_post(a.prm, pre, zg, nu, zc);
+          acck.add(Mdl::logpy_post(a.prm, r0, zc));
+        }
+        const float g = (acck.m == -INFINITY) ? -INFINITY : acck.m + fast_log(acck.s) - logK;
+        ev[r] = la_ell(lamv[r], g);
+      }
+    }
+  } else {
+    // ---- candidates in order, each with its own conditioned weights
+    seg_lds_sync<SEG>();
+    for (int m = 0; m < M; ++m) {
+      float xm[DX];
+#pragma unroll
+      for (int d = 0; d < DX; ++d) xm[d] = xs[s][m][d];
+      float kv[JPT];
+      float mloc = -INFINITY;
+#pragma unroll
+      for (int r = 0; r < JPT; ++r) {
+        const int j = ls + r * SEG;
+        kv[r] = -INFINITY;
+        if (vi && j < M && finitef(lamv[r])) {
+          float zj[DZ];
+#pragma unroll
+          for (int d = 0; d < DZ; ++d) zj[d] = kHoldZ ? zh[kHoldZ ? r : 0][kHoldZ ? d : 0] : zrow[d * M + j];
+          kv[r] = lamv[r] + Mdl::logpx(a.prm, xm, x, zj, t - 1);
+          if (finitef(kv[r])) mloc = fmaxf(mloc, kv[r]);
+        }
+      }
+      const float m2 = seg_max<SEG>(mloc, sh);
+      const bool deg = !(m2 > -INFINITY);
+      double carry = 0.0;
+#pragma unroll
+      for (int r = 0; r < JPT; ++r) {
+        const int j = ls + r * SEG;
+        double w = 0.0;
+        if (j < M) w = deg ? 1.0 : (finitef(kv[r]) ? (double)fast_exp(kv[r] - m2) : 0.0);
+        double tot;
+        const double c = seg_scan_incl<SEG>(w, sh, tot);
+        cdf[s][r * SEG + ls] = carry + c;
+        carry += tot;
+      }
+      seg_lds_sync<SEG>();
+      Lse acck;
+      if (vi) {
+        const double total = cdf[s][M - 1];
+        const double u = uniform53_ab(key, (uint32_t)t, (uint32_t)i, (uint32_t)m, P_LA_B);
+        float pre[Mdl::NPRE], r0[DY];
+        Mdl::fz_pre(a.prm, x, xm, t - 1, pre);
+        Mdl::obs_pre(a.prm, y, xm, r0);
+        for (int k = ls; k < K; k += SEG) {
+          const int b = cdf_search(cdf[s], M, sys_point(k, u, total, K));
+          float zg[DZ], nu[DZ], zc[DZ];
+#pragma unroll
+          for (int d = 0; d < DZ; ++d) zg[d] = zrow[d * M + b];
+          normals_k<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)m, P_LA_Z, k, nu);
+          Mdl::fz_post(a.prm, pre, zg, nu, zc);
+          acck.add(Mdl::logpy_post(a.prm, r0, zc));
+        }
+      }
+      const float lse = seg_lse<SEG>(acck, sh);
+      // the lane holding candidate m keeps its score
+#pragma unroll
+      for (int r = 0; r < JPT; ++r)
+        if (vi && m == ls + r * SEG) ev[r] = la_ell(lamv[r], lse == -INFINITY ? -INFINITY : lse - logK);
+      seg_lds_sync<SEG>();
+    }
+  }
+  Lse acc;
+#pragma unroll
+  for (int r = 0; r < JPT; ++r) {
+    const int j = ls + r * SEG;
+    if (vi && j < M) {
+      erow[j] = ev[r];
+      acc.add(ev[r]);
+    }
+  }
+  const float lw = seg_lse<SEG>(acc, sh);
+  if (vi && ls == 0) a.logw[oo + i] = lw;
+}
+
+template <class Mdl, int SEG, int JPT>
+__global__ __launch_bounds__(kBlock) void k_la_weights_nested(StepArgs a) {
+  la_weights_nested_tile<Mdl, SEG, JPT>(a, blockIdx.x);
 }
 
 static __device__ bool learned_rejected(const StepArgs& a, int f, int N, float* fred4, double* red4);
@@ -1539,7 +1744,7 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
   const double tot2 = cdf[s][M - 1];
 
   // ---- 4. gather + propagate (+ measurement update in look-ahead mode) ---
-  float pre[DZ];
+  float pre[Mdl::NPRE];
   // (plain: t is the step just taken and the proposal is for t + 1)
   fz_pre_seg<Mdl, SEG>(a.prm, xp, xn, PLAIN ? t : t - 1, pre);
   float y[DY], r0[DY];

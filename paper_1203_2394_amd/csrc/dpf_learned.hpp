@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
   const double u_in = uniform53(key, (uint32_t)t, (uint32_t)i, P_INNER_U);
 
   // ---- 3. local resampling, propagation, measurement update --------------
-  float pre[DZ];
+  float pre[Mdl::NPRE];
   fz_pre_seg<Mdl, SEG>(a.prm, xp, xn, t - 1, pre);
   float y[DY], r0[DY];
   load_y<Mdl>(a, f, t, y);

@@ -54,6 +54,7 @@ static const Engine* find_engine(int model, int dx, int dz, int dy) {
   if (model == DPF_MODEL_HIGHDIM) e = &kEngHighDim;
   if (model == DPF_MODEL_TWODIM) e = &kEngTwoDim;
   if (model == DPF_MODEL_FOURDIM) e = &kEngFourDim;
+  if (model == DPF_MODEL_TWODIM_ZFIRST) e = &kEngTwoDimZ;
   if (!e || e->dx != dx || e->dz != dz || e->dy != dy) return nullptr;
   return e;
 }
@@ -95,10 +96,10 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
                 c->dy);
   if (!c->params || c->n_params != eng->n_raw)
     return fail(DPF_EINVAL, "model %d needs %zu parameters, got %zu", c->model, eng->n_raw, c->n_params);
-  if (c->model == DPF_MODEL_TWODIM) {
+  if (c->model == DPF_MODEL_TWODIM || c->model == DPF_MODEL_TWODIM_ZFIRST) {
     const double qx = c->params[0], qz = c->params[1], cxz = c->params[2], r = c->params[7];
-    if (!(qx > 0.0 && r > 0.0 && qz * qx > cxz * cxz))
-      return fail(DPF_EINVAL, "TWODIM needs qx > 0, r > 0 and a positive definite noise covariance");
+    if (!(qx > 0.0 && qz > 0.0 && r > 0.0 && qz * qx > cxz * cxz))
+      return fail(DPF_EINVAL, "TWODIM needs qx, qz, r > 0 and a positive definite noise covariance");
   }
   if (c->model == DPF_MODEL_FOURDIM) {
     const double* q = c->params;
@@ -200,7 +201,7 @@ struct dpf_handle {
   // multi-step graph cache
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
-  const void* g_key[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const void* g_key[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int g_T = -1;
   // phase timing: caller-owned events consumed kPhaseEvents per step
   std::vector<hipEvent_t> prof_events;
@@ -215,9 +216,12 @@ struct dpf_handle {
   // the last call that changed the state was dpf_lookahead_step (what
   // dpf_estimate_rb needs)
   bool rb_ready = false;
+  // companions per look-ahead candidate (nested estimator); 0: paired
+  int n_comp = 0;
 };
 
 constexpr int kPhaseEvents = 5;
+constexpr int kMaxCompanions = 1024;
 
 static dpf_status phase_mark(dpf_handle* h, int phase) {
   if (h->prof_next + (size_t)(kPhaseEvents - phase) > h->prof_events.size()) return DPF_OK;
@@ -288,6 +292,7 @@ static StepArgs make_args(dpf_handle* h) {
   a.ess_frac = h->ess_frac;
   a.gpart = at<double>(h, h->L.gpart);
   a.fcount = at<int>(h, h->L.fcount);
+  a.n_comp = h->n_comp;
   return a;
 }
 
@@ -531,7 +536,8 @@ static dpf_status queue_step(dpf_handle* h, const float* Y, long long y_tstride,
   }
   h->ell_sel = fuse ? par : 0;
   dpf_status s = phase_mark(h, 0);
-  if (s == DPF_OK && fuse != 2) s = launch_classes(h, plain ? OP_DPF_WEIGHTS : OP_LA_WEIGHTS, a);
+  const int wop = plain ? OP_DPF_WEIGHTS : (h->n_comp > 0 ? OP_LA_WEIGHTS_NESTED : OP_LA_WEIGHTS);
+  if (s == DPF_OK && fuse != 2) s = launch_classes(h, wop, a);
   if (s == DPF_OK) s = phase_mark(h, 1);
   if (s == DPF_OK && fuse != 2) {
     hipLaunchKernelGGL(k_res_stats, dim3(h->L.n_rgroups), dim3(kBlock), 0, h->stream, a,
@@ -628,6 +634,15 @@ extern "C" dpf_status dpf_lookahead_step(dpf_handle* h, const float* d_y, const 
   return s;
 }
 
+extern "C" dpf_status dpf_set_lookahead_companions(dpf_handle* h, int32_t n_comp) {
+  if (!h) return fail(DPF_EINVAL, "handle is NULL");
+  if (h->algo != DPF_ALGO_LOOKAHEAD) return fail(DPF_ESTATE, "companions belong to the look-ahead DPF");
+  if (n_comp < 0 || n_comp > kMaxCompanions)
+    return fail(DPF_EINVAL, "n_comp = %d outside 0..%d", n_comp, kMaxCompanions);
+  h->n_comp = n_comp;
+  return DPF_OK;
+}
+
 extern "C" dpf_status dpf_estimate_rb(dpf_handle* h, float* d_xrb) {
   if (!h || !d_xrb) return fail(DPF_EINVAL, "handle and d_xrb are required");
   if (!h->rb_ready) return fail(DPF_ESTATE, "dpf_estimate_rb follows a dpf_lookahead_step call");
@@ -712,7 +727,9 @@ static dpf_status queue_run_step(dpf_handle* h, int mode, const float* d_Y, int 
                                  float* xt, float* zt, int q) {
   const long long stride = (long long)h->F * h->dy;
   if (mode == 1) return queue_learned_step(h, d_Y, stride, nullptr, (const int*)d_Tf, T, xt, zt, nullptr);
-  if (h->algo == DPF_ALGO_LOOKAHEAD && T > 1)
+  // (the fused next-step weights are the paired form: a nested run takes
+  // every step whole)
+  if (h->algo == DPF_ALGO_LOOKAHEAD && T > 1 && h->n_comp == 0)
     return queue_step(h, d_Y, stride, nullptr, (const int*)d_Tf, T, xt, zt, q == 0 ? 1 : 2, q & 1);
   return queue_step(h, d_Y, stride, nullptr, (const int*)d_Tf, T, xt, zt);
 }
@@ -754,8 +771,9 @@ static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T
   // mode, whether cloud moments are maintained, and the fallback threshold
   uint64_t ess_bits;
   memcpy(&ess_bits, &h->ess_frac, sizeof(ess_bits));
-  const void* key[8] = {d_Y, d_Tf, d_xtrace, d_ztrace, (const void*)h->stream, (const void*)(intptr_t)mode,
-                        (const void*)(intptr_t)(h->has_proposal ? 1 : 0), (const void*)(uintptr_t)ess_bits};
+  const void* key[9] = {d_Y, d_Tf, d_xtrace, d_ztrace, (const void*)h->stream, (const void*)(intptr_t)mode,
+                        (const void*)(intptr_t)(h->has_proposal ? 1 : 0), (const void*)(uintptr_t)ess_bits,
+                        (const void*)(intptr_t)h->n_comp};
   const bool cached = h->gexec && h->g_T == T && memcmp(key, h->g_key, sizeof(key)) == 0;
   if (!cached) {
     if (h->gexec) {
@@ -794,7 +812,7 @@ static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T
     if (st != DPF_OK) return st;
   }
   // (the captured steps do not update the host's record of the buffers)
-  if (mode == 0 && h->algo == DPF_ALGO_LOOKAHEAD) h->ell_sel = (T - 1) & 1;
+  if (mode == 0 && h->algo == DPF_ALGO_LOOKAHEAD && h->n_comp == 0) h->ell_sel = (T - 1) & 1;
   return DPF_OK;
 }
 

@@ -6,11 +6,14 @@
 //
 //   fx(P, x, z, nu, t, xn)        x_{t+1} = f^x(x_t, z_t, v^x)    (nu: DX normals)
 //   fz_pre(P, x, xn, t, pre)      the part of f^z that depends only on x_{t:t+1}
-//                                 (and on t, for a time-varying model)
+//                                 (and on t, for a time-varying model): NPRE
+//                                 values (DZ unless the model says otherwise)
 //   fz_post(P, pre, z, nu, zn)    z_{t+1} = f^z(x_{t:t+1}, z_t, v^z) (nu: DZ normals)
 //   obs_pre(P, y, x, r0)          the part of y - h(x, z) that depends only on x
 //   logpy_post(P, r0, z)          log p(y_t | x_t, z_t)
 //   logpx(P, xn, x, z, t)         log p(x_{t+1} | x_t, z_t)
+//   obs_mean(P, x, z, h)          the noise-free observation h(x, z) (models with
+//                                 a one-dimensional y: the predicted observation)
 //
 // t is the time of the state the transition leaves (used only by a
 // time-varying model).
@@ -48,7 +51,7 @@ __device__ __forceinline__ float tanh_f(float a) {
 // y = Hx x + Hz z + sqrt(r) e.
 template <int DX_, int DZ_, int DY_>
 struct LinGauss {
-  static constexpr int DX = DX_, DZ = DZ_, DY = DY_;
+  static constexpr int DX = DX_, DZ = DZ_, DY = DY_, NPRE = DZ_;
   static constexpr bool kXdepZ = true;
   struct Layout {
     static constexpr int Ax = 0, Cxz = Ax + DX * DX, qx = Cxz + DX * DZ, Az = qx + 1,
@@ -112,6 +115,18 @@ struct LinGauss {
     }
     return P[L::cy] - 0.5f * P[L::inv_r] * q;
   }
+  // noise-free observation h(x, z) = Hx x + Hz z
+  __device__ static void obs_mean(const float* P, const float* x, const float* z, float* h) {
+#pragma unroll
+    for (int a = 0; a < DY; ++a) {
+      float s = 0.f;
+#pragma unroll
+      for (int b = 0; b < DX; ++b) s += P[L::Hx + a * DX + b] * x[b];
+#pragma unroll
+      for (int b = 0; b < DZ; ++b) s += P[L::Hz + a * DZ + b] * z[b];
+      h[a] = s;
+    }
+  }
   __device__ static float logpx(const float* P, const float* xn, const float* x, const float* z, int) {
     float q = 0.f;
 #pragma unroll
@@ -138,7 +153,7 @@ __device__ __forceinline__ float growth(float a, float b, float x) {
 // with g_k = x_{k mod DX}^2 (bmode 0) or |x|^2 (bmode 1).
 template <int DX_, int DZ_>
 struct NonLin {
-  static constexpr int DX = DX_, DZ = DZ_, DY = DZ_;
+  static constexpr int DX = DX_, DZ = DZ_, DY = DZ_, NPRE = DZ;
   static constexpr bool kXdepZ = false;
   struct Layout {
     static constexpr int a = 0, b = 1, qx = 2, W = 3, rho = W + DZ * DX, qz = rho + 1, c = qz + 1,
@@ -209,7 +224,7 @@ struct NonLin {
 // per-component density (1-eps) N(0, r) + eps t_nu(e/sqrt r)/sqrt r.
 template <int DX_, int DZ_, int DY_>
 struct HighDim {
-  static constexpr int DX = DX_, DZ = DZ_, DY = DY_;
+  static constexpr int DX = DX_, DZ = DZ_, DY = DY_, NPRE = DZ;
   static constexpr bool kXdepZ = false;
   struct Layout {
     static constexpr int a = 0, b = 1, qx = 2, Alo = 3, Adg = Alo + DZ - 1, Aup = Adg + DZ,
@@ -296,54 +311,87 @@ struct HighDim {
 };
 
 // ------------------------------------------------------------------ TWODIM
-// Model 1 of Table 1 (the 2-dimensional example), dx = dz = dy = 1:
+// Model 1 of Table 1 (the 2-dimensional example), dx = dz = dy = 1, in
+// either sampling order, with an optional change point.  In the paper's
+// variables (x, z):
 //   x' = x + z / (1 + z^2) + v^x ,
 //   z' = x + rho z + b z / (1 + z^2) + amp cos(freq t) + v^z ,
 //   y  = atan(x) + z^2 / 20 + e ,
 // (v^x, v^z) ~ N(0, [[qx, cxz], [cxz, qz]]), e ~ N(0, r); t is the time of
-// the state the transition leaves.  The outer transition depends on z
-// (kXdepZ); given x' the inner noise is v^z | v^x ~ N(kz v^x, qz|x) with
-// kz = cxz / qx, qz|x = qz - cxz^2 / qx, v^x = x' - x - z / (1 + z^2).
-struct TwoDim {
-  static constexpr int DX = 1, DZ = 1, DY = 1;
+// the state the transition leaves.  From t >= tswap on the two transition
+// models are swapped (x' = z + rho x + b x / (1 + x^2) + amp cos(freq t) + v^x,
+// z' = z + x / (1 + x^2) + v^z; the noises stay with their variables): the
+// change point of the decomposition experiment of Section 4.3.
+// ZF = false samples x first (outer x, inner z, DPF_MODEL_TWODIM); ZF = true
+// samples z first (outer z, inner x, DPF_MODEL_TWODIM_ZFIRST), the other
+// action of Section 4.3.  With outer o and inner i, one of them follows the
+// "slow" law s' = s + g / (1 + g^2) and the other the "growth" law
+// g' = s + rho g + b g / (1 + g^2) + amp cos(freq t); the outer transition
+// depends on the inner variable (kXdepZ), and given o' the inner noise is
+// v_i | v_o ~ N(k v_o, q_i - cxz^2 / q_o), k = cxz / q_o.  Every form of the
+// inner transition is c1 i + c2 i / (1 + i^2) + (terms of o, o', t) + noise,
+// so fz_pre passes (terms, c1, c2) and NPRE = 3.
+template <bool ZF>
+struct Table1M1 {
+  static constexpr int DX = 1, DZ = 1, DY = 1, NPRE = 3;
   static constexpr bool kXdepZ = true;
   struct Layout {
-    static constexpr int qx = 0, qz = 1, cxz = 2, rho = 3, b = 4, amp = 5, freq = 6, r = 7, n_raw = 8;
-    static constexpr int sx = n_raw, kz = sx + 1, szc = kz + 1, inv_qx = szc + 1, cx = inv_qx + 1,
-                         inv_r = cx + 1, cy = inv_r + 1, n_total = cy + 1;
+    static constexpr int qx = 0, qz = 1, cxz = 2, rho = 3, b = 4, amp = 5, freq = 6, r = 7, tswap = 8,
+                         n_raw = 9;
+    // so = sqrt(q_o), k = cxz / q_o, sic = sqrt(q_i - cxz^2 / q_o)
+    static constexpr int so = n_raw, k = so + 1, sic = k + 1, inv_qo = sic + 1, co = inv_qo + 1,
+                         inv_r = co + 1, cy = inv_r + 1, n_total = cy + 1;
   };
   using L = Layout;
 
-  __device__ static float sat(float z) { return z / (1.0f + z * z); }
-  __device__ static void fx(const float* P, const float* x, const float* z, const float* nu, int, float* xn) {
-    xn[0] = x[0] + sat(z[0]) + P[L::sx] * nu[0];
+  __device__ static float sat(float v) { return v / (1.0f + v * v); }
+  // the angle in double (t runs to thousands of radians)
+  __device__ static float cyc(const float* P, int t) {
+    return (float)((double)P[L::amp] * cos((double)P[L::freq] * (double)t));
   }
-  // x + amp cos(freq t) + kz (x' - x); the angle in double (t runs to
-  // thousands of radians)
-  __device__ static float fz_pre_k(const float* P, const float* x, const float* xn, int t, int) {
-    const float cyc = (float)((double)P[L::amp] * cos((double)P[L::freq] * (double)t));
-    return x[0] + cyc + P[L::kz] * (xn[0] - x[0]);
+  // whether the outer variable follows the slow law at t
+  __device__ static bool outer_slow(const float* P, int t) { return ((float)t >= P[L::tswap]) == ZF; }
+  __device__ static float mean_o(const float* P, float o, float i, int t) {
+    return outer_slow(P, t) ? o + sat(i) : i + P[L::rho] * o + P[L::b] * sat(o) + cyc(P, t);
+  }
+  __device__ static void fx(const float* P, const float* x, const float* z, const float* nu, int t, float* xn) {
+    xn[0] = mean_o(P, x[0], z[0], t) + P[L::so] * nu[0];
   }
   __device__ static void fz_pre(const float* P, const float* x, const float* xn, int t, float* pre) {
-    pre[0] = fz_pre_k(P, x, xn, t, 0);
+    const float o = x[0], on = xn[0], k = P[L::k];
+    if (outer_slow(P, t)) {
+      // inner growth: o + A + k (o' - o) + rho i + (b - k) sat(i)
+      pre[0] = o + cyc(P, t) + k * (on - o);
+      pre[1] = P[L::rho];
+      pre[2] = P[L::b] - k;
+    } else {
+      // inner slow: sat(o) + k (o' - rho o - b sat(o) - A) + (1 - k) i
+      pre[0] = sat(o) + k * (on - P[L::rho] * o - P[L::b] * sat(o) - cyc(P, t));
+      pre[1] = 1.0f - k;
+      pre[2] = 0.0f;
+    }
   }
-  // pre + rho z + b z/(1+z^2) - kz z/(1+z^2) + sqrt(qz|x) nu
   __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu, float* zn) {
-    const float g = sat(z[0]);
-    zn[0] = pre[0] + P[L::rho] * z[0] + P[L::b] * g - P[L::kz] * g + P[L::szc] * nu[0];
+    zn[0] = pre[1] * z[0] + pre[2] * sat(z[0]) + pre[0] + P[L::sic] * nu[0];
   }
   __device__ static void obs_pre(const float*, const float* y, const float* x, float* r0) {
-    r0[0] = y[0] - atanf(x[0]);
+    r0[0] = ZF ? y[0] - 0.05f * x[0] * x[0] : y[0] - atanf(x[0]);
   }
   __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
-    const float e = r0[0] - 0.05f * z[0] * z[0];
+    const float e = ZF ? r0[0] - atanf(z[0]) : r0[0] - 0.05f * z[0] * z[0];
     return P[L::cy] - 0.5f * P[L::inv_r] * e * e;
   }
-  __device__ static float logpx(const float* P, const float* xn, const float* x, const float* z, int) {
-    const float e = xn[0] - x[0] - sat(z[0]);
-    return P[L::cx] - 0.5f * P[L::inv_qx] * e * e;
+  __device__ static float logpx(const float* P, const float* xn, const float* x, const float* z, int t) {
+    const float e = xn[0] - mean_o(P, x[0], z[0], t);
+    return P[L::co] - 0.5f * P[L::inv_qo] * e * e;
+  }
+  // noise-free observation h(x, z) = atan(x) + z^2 / 20
+  __device__ static void obs_mean(const float*, const float* x, const float* z, float* h) {
+    h[0] = ZF ? atanf(z[0]) + 0.05f * x[0] * x[0] : atanf(x[0]) + 0.05f * z[0] * z[0];
   }
 };
+using TwoDim = Table1M1<false>;
+using TwoDimZ = Table1M1<true>;
 
 // ----------------------------------------------------------------- FOURDIM
 // Model 2 of Table 1 (the 4-dimensional example), dx = dz = 2, dy = 1:
@@ -356,7 +404,7 @@ struct TwoDim {
 // t is the time of the state the transition leaves.  The blocks are coupled
 // only through y (p(x' | x, z) does not depend on z).
 struct FourDim {
-  static constexpr int DX = 2, DZ = 2, DY = 1;
+  static constexpr int DX = 2, DZ = 2, DY = 1, NPRE = 2;
   static constexpr bool kXdepZ = false;
   struct Layout {
     static constexpr int a1 = 0, bs = 1, c21 = 2, a2 = 3, qx1 = 4, qx2 = 5, qz1 = 6, qz2 = 7, cz = 8, rho = 9,
@@ -393,6 +441,10 @@ struct FourDim {
   __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
     const float e = r0[0] - atanf(z[0]) - 0.05f * z[1] * z[1];
     return P[L::cy] - 0.5f * P[L::inv_r] * e * e;
+  }
+  // noise-free observation h(x, z) = (x1 + x2) / (1 + x1^2) + atan(z1) + z2^2 / 20
+  __device__ static void obs_mean(const float*, const float* x, const float* z, float* h) {
+    h[0] = (x[0] + x[1]) / (1.0f + x[0] * x[0]) + atanf(z[0]) + 0.05f * z[1] * z[1];
   }
   __device__ static float logpx(const float* P, const float* xn, const float* x, const float*, int t) {
     const float e0 = xn[0] - (P[L::a1] * x[0] + drift_x(P, t));

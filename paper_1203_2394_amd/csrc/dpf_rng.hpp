@@ -25,7 +25,7 @@ namespace dpf {
 enum Purpose : uint32_t {
   P_INIT_X = 0, P_INIT_Z = 1, P_LA_X = 2, P_LA_Z = 3, P_OUTER_U = 4, P_CAND_U = 5,
   P_INNER_U = 6, P_NEW_Z = 7, P_DPF_ANC_U = 8, P_DPF_X = 9, P_DPF_Z = 10,
-  P_MDN_U = 11, P_MDN_X = 12
+  P_MDN_U = 11, P_MDN_X = 12, P_LA_B = 13
 };
 
 struct Key {
@@ -96,6 +96,12 @@ __device__ __forceinline__ double uniform53(Key key, uint32_t t, uint32_t a, uin
   return u53(w.w[0], w.w[1]);
 }
 
+// The U53 offset of a draw at counter (t, a, b).
+__device__ __forceinline__ double uniform53_ab(Key key, uint32_t t, uint32_t a, uint32_t b, uint32_t purpose) {
+  const Words w = draw(key, t, a, b, purpose, 0u);
+  return u53(w.w[0], w.w[1]);
+}
+
 // Box-Muller pair in FP32 from two words.
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& n0, float& n1) {
   constexpr float kMinus2Ln2 = -1.3862943611198906f;  // -2 ln 2
@@ -123,6 +129,34 @@ __device__ __forceinline__ void normals(Key key, uint32_t t, uint32_t a, uint32_
         if (d0 + 1 < D) out[d0 + 1] = n1;
       }
     }
+  }
+}
+
+// Normals k D .. k D + D - 1 of the draw at counter (t, a, b): the k-th
+// group of D (normal n from block n / 4, slots as above), so that k = 0 is
+// normals<D>.
+template <int D>
+__device__ __forceinline__ void normals_k(Key key, uint32_t t, uint32_t a, uint32_t b, uint32_t purpose, int k,
+                                          float* out) {
+  static_assert(D % 4 == 0 || D == 2 || D == 1, "normals_k: D must be 1, 2 or a multiple of 4");
+  if constexpr (D % 4 == 0) {
+    const uint32_t b0 = (uint32_t)k * (uint32_t)(D / 4);
+#pragma unroll
+    for (int blk = 0; blk < D / 4; ++blk) {
+      const Words w = draw(key, t, a, b, purpose, b0 + (uint32_t)blk);
+      box_muller(w.w[0], w.w[1], out[4 * blk], out[4 * blk + 1]);
+      box_muller(w.w[2], w.w[3], out[4 * blk + 2], out[4 * blk + 3]);
+    }
+  } else if constexpr (D == 2) {
+    const Words w = draw(key, t, a, b, purpose, (uint32_t)(k >> 1));
+    const bool hi = (k & 1) != 0;
+    box_muller(hi ? w.w[2] : w.w[0], hi ? w.w[3] : w.w[1], out[0], out[1]);
+  } else {
+    const Words w = draw(key, t, a, b, purpose, (uint32_t)(k >> 2));
+    const bool hi = (k & 2) != 0;
+    float n0, n1;
+    box_muller(hi ? w.w[2] : w.w[0], hi ? w.w[3] : w.w[1], n0, n1);
+    out[0] = (k & 1) ? n1 : n0;
   }
 }
 

@@ -57,10 +57,11 @@ class Report(dict):
         return ", ".join("%s=%s" % (k, ("%.3g" % v) if isinstance(v, float) else v) for k, v in self.items())
 
 
-def compare_la(model, st32, y32, seed, fid, g_state, g_ell, g_logw, g_anc, g_sel):
+def compare_la(model, st32, y32, seed, fid, g_state, g_ell, g_logw, g_anc, g_sel, **step_kw):
     """Compare one look-ahead step.  g_* are the GPU's results as numpy
-    arrays in oracle layout.  Returns (report, oracle_new_state, info)."""
-    new_o, info = ladpf.step(model, st32, y32, seed, fid)
+    arrays in oracle layout; step_kw go to the oracle's step.  Returns
+    (report, oracle_new_state, info)."""
+    new_o, info = ladpf.step(model, st32, y32, seed, fid, **step_kw)
     N, M = st32["lam"].shape
     r = Report()
     r["err_ell"] = rel_err(g_ell, info["ell"])
@@ -249,3 +250,35 @@ def assert_clean_learned(r, n=None, max_flip_frac=0.02):
         assert r[key] <= TOL, r.line()
     floor = 1.0 / n if n else 0.0
     assert r["clean_frac"] >= 1.0 - max(max_flip_frac, floor), r.line()
+
+
+def compare_nested_weights(model, st32, y32, seed, fid, K, g_ell):
+    """Compare the nested look-ahead weights of one step (K companions per
+    candidate) with the oracle's.  A companion ancestor may flip where its
+    systematic point lies within DELTA of a boundary of the candidate's
+    conditioned cumulative weights; an ell mismatch must be explained by such
+    a near tie.  Returns (report, oracle ell, rows with an explained flip)."""
+    xla, ell_o, logw_o, comp = ladpf.lookahead_nested(model, st32, y32, seed, fid, K)
+    N, M = st32["lam"].shape
+    t = st32["t"] + 1
+    u = P.uniform53_ab(seed, fid, t, np.arange(N)[:, None], np.arange(M)[None, :], P.LA_B)
+    r = Report()
+    both_inf = np.isinf(g_ell) & np.isinf(ell_o) & (np.sign(g_ell) == np.sign(ell_o))
+    d = np.where(both_inf, 0.0, np.abs(g_ell - ell_o) / np.maximum(1.0, np.abs(ell_o)))
+    bad = np.argwhere(d > TOL)
+    r["ell_off"] = len(bad)
+    unexpl = 0
+    tainted = np.zeros(N, dtype=bool)
+    for i, m in bad:
+        kap = st32["lam"][i] + model.logpx(xla[i, m], st32["x"][i], st32["z"][i], t - 1)
+        wk, _, _ = weights_from_log(kap)
+        C = np.cumsum(wk)
+        Pk = ((np.arange(K) + u[i, m]) * C[-1]) / K
+        near = np.min(np.abs(Pk[:, None] - C[None, :])) <= DELTA * C[-1]
+        unexpl += not near
+        tainted[i] = True
+    r["ell_unexplained"] = int(unexpl)
+    ok = ~both_inf & (d <= TOL)
+    r["err_ell"] = float(np.max(d[ok])) if ok.any() else 0.0
+    r["tainted_rows"] = int(tainted.sum())
+    return r, ell_o, tainted

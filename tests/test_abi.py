@@ -150,8 +150,8 @@ def test_table1_models_are_built_and_their_noise_covariances_checked():
 
 def test_model_ids_agree_across_header_binding_and_inputs():
     txt = open(HEADER).read()
-    ids = {k: int(v) for k, v in re.findall(r"DPF_MODEL_([A-Z]+)\s*=\s*(\d+)", txt)}
-    assert ids == {"LINGAUSS": 1, "NONLIN": 2, "HIGHDIM": 3, "TWODIM": 4, "FOURDIM": 5}
+    ids = {k: int(v) for k, v in re.findall(r"DPF_MODEL_([A-Z_]+)\s*=\s*(\d+)", txt)}
+    assert ids == {"LINGAUSS": 1, "NONLIN": 2, "HIGHDIM": 3, "TWODIM": 4, "FOURDIM": 5, "TWODIM_ZFIRST": 6}
     for name, v in ids.items():
         assert getattr(dpf, "MODEL_" + name) == v
         assert getattr(S, name) == v

@@ -7,6 +7,7 @@ mean; fed unit noise it must move by the noise standard deviation.
 import math
 
 import numpy as np
+import pytest
 from scipy import stats
 
 import dpf_synth as S
@@ -221,3 +222,67 @@ def test_fourdim_simulator_noise_covariance():
     c = np.cov(np.stack([v1, v2, w1, w2]))
     want = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0.1], [0, 0, 0.1, 10]])
     assert np.all(np.abs(c - want) <= 0.05 * np.sqrt(np.outer(np.diag(want), np.diag(want))))
+
+
+@pytest.mark.parametrize("zfirst,after,q", [(False, True, (1.0, 1.0, 0.1)), (True, False, (1.0, 1.0, 0.1)),
+                                             (True, True, (1.0, 1.0, 0.1)), (False, False, (1.3, 0.7, 0.2)),
+                                             (True, False, (1.3, 0.7, 0.2)), (True, True, (1.3, 0.7, 0.2))])
+def test_twodim_orders_and_change_point_are_the_joint_gaussian(zfirst, after, q):
+    """Both sampling orders of model 1 factorise the same joint transition:
+    log p(o'|o, i) + log p(i'|o, i, o') must equal SciPy's bivariate normal
+    of the noise pair (v^x, v^z) ~ N(0, [[1, .1], [.1, 1]]) around the means
+    of Table 1 (and around the same means with other noise covariances) --
+    before the change point x' = x + z/(1+z^2) and
+    z' = x + .5 z + 25 z/(1+z^2) + 8 cos(1.2 t); from tswap on the two laws
+    swapped (x' = z + .5 x + 25 x/(1+x^2) + 8 cos(1.2 t), z' = z + x/(1+x^2)).
+    With z first the outer state is z and the inner one x."""
+    tswap = 300
+    spec = S.twodim_table1(qx=q[0], qz=q[1], cxz=q[2], tswap=tswap, zfirst=zfirst)
+    m = _model(spec)
+    cov = np.array([[q[0], q[2]], [q[2], q[1]]], dtype=np.float32).astype(np.float64)
+    f12 = float(np.float32(1.2))
+    g = np.random.default_rng(7 + 2 * zfirst + after)
+    for _ in range(50):
+        x, z = g.normal() * 3, g.normal() * 3
+        t = int(g.integers(tswap, tswap + 200)) if after else int(g.integers(0, tswap))
+        if after:
+            mean_x = z + 0.5 * x + 25 * x / (1 + x * x) + 8 * math.cos(f12 * t)
+            mean_z = z + x / (1 + x * x)
+        else:
+            mean_x = x + z / (1 + z * z)
+            mean_z = x + 0.5 * z + 25 * z / (1 + z * z) + 8 * math.cos(f12 * t)
+        vx, vz = g.normal(size=2) * 1.3
+        xn, zn = mean_x + vx, mean_z + vz
+        o, i, on, inn = (z, x, zn, xn) if zfirst else (x, z, xn, zn)
+        o, i, on = np.array([o]), np.array([i]), np.array([on])
+        a = m.fz(o, on, i, np.zeros(1), t)[0]
+        c = m.fz(o, on, i, np.ones(1), t)[0] - a
+        log_cond = stats.norm.logpdf(inn, a, abs(c))
+        joint = stats.multivariate_normal(mean=[0.0, 0.0], cov=cov).logpdf([vx, vz])
+        assert np.isclose(float(m.logpx(on, o, i, t)) + log_cond, joint, rtol=0, atol=1e-9)
+        # the outer sampler is its density's mean plus its scale times the normal
+        assert np.isclose(m.fx(o, i, np.zeros(1), t)[0], mean_z if zfirst else mean_x, atol=1e-12)
+    # the observation, whichever block is outer
+    yv = np.array([0.4])
+    o, i = (np.array([1.5]), np.array([-0.7])) if zfirst else (np.array([-0.7]), np.array([1.5]))
+    assert np.isclose(m.logpy(yv, o, i), stats.norm.logpdf(0.4, math.atan(-0.7) + 1.5 ** 2 / 20, 1.0))
+
+
+def test_twodim_simulator_swaps_the_laws_at_the_change_point():
+    spec = S.twodim_table1(tswap=500)
+    xs, zs, _ = S.simulate(spec, 20000, 12)
+    f12 = float(np.float32(1.2))
+    x, z = xs[:-1, 0], zs[:-1, 0]
+    t = np.arange(len(x))
+    a = t >= 500
+    vx = np.where(a, xs[1:, 0] - (z + 0.5 * x + 25 * x / (1 + x * x) + 8 * np.cos(f12 * t)),
+                  xs[1:, 0] - x - z / (1 + z * z))
+    vz = np.where(a, zs[1:, 0] - z - x / (1 + x * x),
+                  zs[1:, 0] - (x + 0.5 * z + 25 * z / (1 + z * z) + 8 * np.cos(f12 * t)))
+    c = np.cov(np.stack([vx[a], vz[a]]))
+    assert np.allclose(c, [[1.0, 0.1], [0.1, 1.0]], atol=0.04)
+    assert np.max(np.abs(vx[~a])) < 6 and np.max(np.abs(vz[~a])) < 6
+    # the z-first spec simulates the same truth and observations
+    xs2, zs2, ys2 = S.simulate(S.twodim_table1(tswap=500, zfirst=True), 300, 12)
+    _, _, ys = S.simulate(spec, 300, 12)
+    assert np.array_equal(ys, ys2) and np.array_equal(xs[:301], xs2) and np.array_equal(zs[:301], zs2)
