@@ -50,6 +50,13 @@ unchanged (the SIR of step 4 uses these ell).  Cost K M^2 model
 evaluations per outer particle where p(x_t | x_{t-1}, z_{t-1}) depends on z,
 K M otherwise (kappa is then lam up to a constant).
 
+Predicted observation (models with a noise-free observation mean h): the
+look-ahead draws are draws from the one-step predictive p(x_t, z_t | y_{0:t-1})
+with weights qbar^{(i,j)} / N, so yhat_{t|t-1} = (1/N) sum_i sum_j
+qbar^{(i,j)} h(xla^{(i,j)}, zla^{(i,j)}) (nested: the mean over each
+candidate's companions).  Its error y_t - yhat is the reward signal of the
+decomposition choice of Section 3.
+
 Estimates: xhat = mean_k x_t^{(k)}, zhat = mean_k sum_j qbar_t z_t,
 ESS of the look-ahead weights, dlogZ = logsumexp_i log w - log N, and the
 Rao-Blackwellised xhat_rb = sum_i Wbar_i sum_j pi_ij xla^{(i,j)} (the exact
@@ -117,6 +124,7 @@ def lookahead_nested(model, state, y, seed, fid, K, u_comp=None):
         u_comp = P.uniform53_ab(seed, fid, t, i_, j_, P.LA_B)
     ell = np.empty((N, M))
     comp = np.empty((N, M, K), dtype=np.int64)
+    hmean = np.zeros((N, M, model.dy)) if hasattr(model, "obs_mean") else None
     for i in range(N):
         for m in range(M):
             # inner weights conditioned on the candidate (eq:qnobar)
@@ -125,8 +133,17 @@ def lookahead_nested(model, state, y, seed, fid, K, u_comp=None):
             comp[i, m] = b
             zc = model.fz(x[i], xla[i, m], z[i, b], nu_z[i, m], t - 1)
             ell[i, m] = lam[i, m] + logsumexp(model.logpy(y, xla[i, m], zc)) - math.log(K)
+            if hmean is not None:
+                hmean[i, m] = np.mean(model.obs_mean(xla[i, m], zc), axis=0)
     logw = logsumexp(ell)
-    return xla, ell, logw, comp
+    return xla, ell, logw, comp, hmean
+
+
+def predicted_observation(lam, hmean):
+    """yhat_{t|t-1} = (1/N) sum_i sum_j qbar^{(i,j)} h^{(i,j)}: the look-ahead
+    draws weighted as draws from the one-step predictive."""
+    N = lam.shape[0]
+    return np.einsum("nm,nmd->d", np.exp(lam), hmean) / N
 
 
 def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None, n_comp=0, ell_given=None):
@@ -146,11 +163,15 @@ def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None, n_
     flags = 0
 
     comp = None
-    if n_comp and ell_given is None:
-        xla, ell, logw, comp = lookahead_nested(model, state, y, seed, fid, n_comp)
+    yhat = None
+    if n_comp:
+        xla, ell, logw, comp, hmean = lookahead_nested(model, state, y, seed, fid, n_comp)
         zla = None
     else:
         xla, zla, ell, logw = lookahead(model, state, y, seed, fid)
+        hmean = model.obs_mean(xla, zla) if hasattr(model, "obs_mean") else None
+    if hmean is not None:
+        yhat = predicted_observation(lam, hmean)
     if ell_given is not None:
         ell = np.asarray(ell_given, dtype=np.float64)
         logw = logsumexp(ell)
@@ -211,7 +232,7 @@ def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None, n_
         "binner": binner, "u_outer": u_outer, "u_cand": np.asarray(u_cand),
         "u_inner": np.asarray(u_inner),
         "xhat": xhat, "zhat": zhat, "ess": ess, "dlogz": dlogz, "xhat_rb": xhat_rb,
-        "flags": flags,
+        "yhat": yhat, "flags": flags,
     }
     return new_state, info
 

@@ -258,7 +258,7 @@ def compare_nested_weights(model, st32, y32, seed, fid, K, g_ell):
     systematic point lies within DELTA of a boundary of the candidate's
     conditioned cumulative weights; an ell mismatch must be explained by such
     a near tie.  Returns (report, oracle ell, rows with an explained flip)."""
-    xla, ell_o, logw_o, comp = ladpf.lookahead_nested(model, st32, y32, seed, fid, K)
+    xla, ell_o, logw_o, comp, _ = ladpf.lookahead_nested(model, st32, y32, seed, fid, K)
     N, M = st32["lam"].shape
     t = st32["t"] + 1
     u = P.uniform53_ab(seed, fid, t, np.arange(N)[:, None], np.arange(M)[None, :], P.LA_B)

@@ -287,7 +287,7 @@ def test_nested_lookahead_weight_expectation_closed_form(coupled, K):
     R = 3000
     W = np.empty((R, 3))
     for r in range(R):
-        _, _, logw, _ = ladpf.lookahead_nested(m, st, y, 99, r, K)
+        _, _, logw, _, _ = ladpf.lookahead_nested(m, st, y, 99, r, K)
         W[r] = np.exp(logw)
     qbar = np.exp(st["lam"])
     mj, v = _y_given_parent(st["x"][:, :1], st["z"], 0.2 if coupled else 0.0)
@@ -310,7 +310,7 @@ def test_nested_candidate_score_with_many_companions(coupled):
     st["z"] *= 2.0
     y = np.array([0.5])
     K = 200000
-    xla, ell, _, comp = ladpf.lookahead_nested(m, st, y, 5, 0, K)
+    xla, ell, _, comp, _ = ladpf.lookahead_nested(m, st, y, 5, 0, K)
     for i in range(2):
         for j in range(3):
             xc = xla[i, j, 0]
@@ -341,3 +341,43 @@ def test_nested_step_resamples_and_proposes_as_the_paired_step():
     out = ladpf.run(m, 60, 12, ys, 3, 0, n_comp=3)
     assert np.all(np.isfinite(out["xhat"]))
     assert np.mean(np.abs(out["xhat"][:, 0] - mu[:, 0])) < 0.15
+
+
+@pytest.mark.parametrize("K", [0, 3])
+def test_predicted_observation_expectation_closed_form(K):
+    """The predicted observation weighs the look-ahead draws as draws from
+    the one-step predictive: on the linear-Gaussian model its expectation
+    over the draws is (1/N) sum_i sum_j qbar_ij (1.575 x_i + 0.8 z1_ij +
+    0.45 z2_ij) (y = x + [1, .5] z with x_t = .9 x + v, z_t = A z + .5 x_t 1 + w),
+    for the paired draws and for K companions per candidate."""
+    spec = S.lingauss_c1(False)
+    m = _model(spec)
+    g = np.random.default_rng(33 + K)
+    st = _random_state(m, 4, 5, g)
+    y = np.array([0.3])
+    R = 1500
+    Y = np.empty(R)
+    for r in range(R):
+        _, info = ladpf.step(m, st, y, 17, r, n_comp=K)
+        Y[r] = info["yhat"][0]
+    mj, _ = _y_given_parent(st["x"][:, :1], st["z"], 0.0)
+    expect = np.sum(np.exp(st["lam"]) * mj) / 4
+    se = Y.std() / math.sqrt(R)
+    assert abs(Y.mean() - expect) < 5 * se, (Y.mean(), expect, se)
+
+
+def test_predicted_observation_approaches_the_kalman_prediction():
+    """With many particles yhat_{t|t-1} approaches the Kalman filter's
+    one-step prediction H F mu_{t-1}."""
+    spec = S.lingauss_c1(False)
+    m = _model(spec)
+    _, _, ys = S.simulate(spec, 6, 4)
+    F, Q, H, R_ = kalman.joint_matrices(m)
+    mu, _, _ = kalman.kalman_filter(m, ys)
+    st = ladpf.init_state(m, 3000, 40, 8, 0)
+    errs = []
+    for t in range(6):
+        st, info = ladpf.step(m, st, ys[t], 8, 0)
+        pred = (H @ F @ mu[t - 1])[0] if t > 0 else 0.0
+        errs.append(abs(info["yhat"][0] - pred))
+    assert max(errs) < 0.05, errs
