@@ -221,6 +221,9 @@ def main():
                          "network kernels)")
     ap.add_argument("--no-kalman", action="store_true",
                     help="skip the linear-Gaussian model at the Kalman filter's accuracy")
+    ap.add_argument("--no-bandit", action="store_true",
+                    help="skip the automatic decomposition experiment (Hedge / Exp3)")
+    ap.add_argument("--only-bandit", action="store_true", help="only the automatic decomposition experiment")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, run one device-to-device copy of this many MB "
                          "(a kernel of known traffic for calibrating hardware byte counters)")
@@ -248,6 +251,9 @@ def main():
         return 0
     if args.only_mlp:
         print(json.dumps({"mlp_profile": run_mlp_profile(S, dpf, torch, np, dev)}))
+        return 0
+    if args.only_bandit:
+        print(json.dumps({"bandit": run_bandit(S, dpf, torch, np, dev)}))
         return 0
     spec = S.nonlin_c2(PARAM_SEED)
     n_obs = max(T_TRAJ, K, W)
@@ -354,6 +360,7 @@ def main():
                   "model2": run_table1(S, dpf, torch, np, dev, S.fourdim_table1(), "Table 1 model 2")}
         table1["grid"] = run_table1_grid(S, dpf, torch, np, dev, table1)
     kalman = None if (args.no_kalman or args.only_run) else run_kalman_target(S, dpf, torch, np, dev)
+    bandit = None if (args.no_bandit or args.only_run) else run_bandit(S, dpf, torch, np, dev)
     cpu = None if (args.no_cpu_baseline or args.only_run) else run_cpu_baseline(args.cpu_steps)
     out = {
         "metric": METRIC,
@@ -387,6 +394,7 @@ def main():
         "highdim": highdim,
         "table1": table1,
         "kalman_target": kalman,
+        "bandit": bandit,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
@@ -515,6 +523,91 @@ def run_mlp_profile(S, dpf, torch, np, dev):
     return {"learned_steps": 8, "training_steps": 2, "batch": B}
 
 
+# the decomposition experiment of Section 4.3: sequences, horizon, change
+# point, filter sizes, reward and bandit parameters, the RMSE window
+BD_SEQS, BD_T, BD_TC, BD_N, BD_M, BD_SEED = 16, 4000, 600, 200, 20, 50000
+BD_ALPHA, BD_GAMMA, BD_ETA, BD_WINDOW = 1e-3, 0.2, 0.5, (3000, 4000)
+BD_CHECKPOINTS = (1, 100, 300, 600, 700, 1000, 1500, 2000, 3000, 4000)
+
+
+def run_bandit(S, dpf, torch, np, dev):
+    """Automatic decomposition (Section 3, Section 4.3): model 1 of Table 1
+    with its transition laws swapped from t = BD_TC on, BD_SEQS fresh
+    sequences of BD_T steps.  Action 1 samples x first, action 2 z first:
+    each is a look-ahead DPF over all sequences (one handle, filters =
+    sequences, N x M particles, graph-replayed run) that forms the predicted
+    observation of every step.  Rewards r = alpha / (alpha + (y - yhat)^2);
+    Hedge (every action's reward) and Exp3 (the chosen action's only) pick
+    at each step which filter's estimate is reported, with a seeded stream
+    per sequence.  Reports the action probabilities over time (means over
+    the sequences) and the RMSE of x and z over the window for each fixed
+    action, Hedge and Exp3."""
+    from paper_1203_2394_amd import bandit as BB
+
+    T = BD_T
+    specs = [S.twodim_table1(tswap=BD_TC), S.twodim_table1(tswap=BD_TC, zfirst=True)]
+    sims = [S.simulate(specs[0], T, BD_SEED + q) for q in range(BD_SEQS)]
+    Y = torch.tensor(np.stack([sm[2] for sm in sims], axis=1), dtype=torch.float32, device=dev).contiguous()
+    tx = np.stack([sm[0][1:, 0] for sm in sims], axis=1)  # [T][F]
+    tz = np.stack([sm[1][1:, 0] for sm in sims], axis=1)
+    y = Y[:, :, 0].cpu().numpy().astype(np.float64)
+    est, yhat, timing = [], [], []
+    for a, spec in enumerate(specs):
+        f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [BD_N] * BD_SEQS, [BD_M] * BD_SEQS,
+                       seed=FILTER_SEED + a, device=dev)
+        tr = f.set_prediction(True, trace_T=T)
+        xt, zt = f.run(Y, use_graph=True)
+        o, i = xt[:, :, 0].cpu().numpy(), zt[:, :, 0].cpu().numpy()
+        est.append((o, i) if a == 0 else (i, o))          # (x_hat, z_hat) in the paper's variables
+        yhat.append(tr.cpu().numpy().astype(np.float64))
+        f.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.run(Y, trace=False, use_graph=True)
+        torch.cuda.synchronize()
+        timing.append(time.perf_counter() - t0)
+        f.close()
+    R = np.stack([BB.reward(y - yh, BD_ALPHA) for yh in yhat], axis=2)   # [T][F][2]
+    R = np.where(np.isfinite(R), R, 0.0)
+    lo, hi = BD_WINDOW
+    w = slice(lo, hi)  # rows t-1 for lo < t <= hi
+
+    def rmse(xh, zh):
+        ex = (xh[w] - tx[w]) ** 2
+        ez = (zh[w] - tz[w]) ** 2
+        return {"x": round(float(np.sqrt(np.nanmean(ex))), 4), "z": round(float(np.sqrt(np.nanmean(ez))), 4)}
+
+    out = {"action1_x_first": rmse(*est[0]), "action2_z_first": rmse(*est[1])}
+    probs = {}
+    for name in ("hedge", "exp3"):
+        acts = np.empty((T, BD_SEQS), dtype=np.int64)
+        p2 = np.empty((T, BD_SEQS))
+        for q in range(BD_SEQS):
+            u = BB.uniforms(BD_SEED + 7 * q + (1 if name == "exp3" else 0), T)
+            if name == "hedge":
+                a_, P = BB.run_hedge(R[:, q], BD_ETA, u)
+                p2[:, q] = P[:, 1]
+            else:
+                a_, P, Ph = BB.run_exp3(R[:, q], BD_ETA, BD_GAMMA, u)
+                p2[:, q] = Ph[:, 1]
+            acts[:, q] = a_
+        xh = np.where(acts == 0, est[0][0], est[1][0])
+        zh = np.where(acts == 0, est[0][1], est[1][1])
+        out[name] = rmse(xh, zh)
+        out[name]["last100_action2_frac"] = round(float(np.mean(acts[-100:] == 1)), 4)
+        probs[name] = {str(c): round(float(np.mean(p2[c - 1])), 4) for c in BD_CHECKPOINTS}
+    upd = BD_N * BD_M * BD_SEQS * T
+    return {"rmse_window": "%d < t <= %d" % (lo, hi), "rmse": out,
+            "p_action2_mean": probs,
+            "updates_per_s": {"action1_x_first": upd / timing[0], "action2_z_first": upd / timing[1]},
+            "config": {"workload": "model 1 of Table 1 with its transitions swapped from t=%d, %d sequences x "
+                                   "T=%d as filters of one handle per decomposition, N=%d, M=%d" % (
+                                       BD_TC, BD_SEQS, T, BD_N, BD_M),
+                       "reward": "alpha/(alpha+eps^2), alpha=%g" % BD_ALPHA, "gamma": BD_GAMMA, "eta": BD_ETA,
+                       "execution": "both decompositions run every step (graph-replayed runs); the bandit "
+                                    "chooses which filter's estimate is reported"}}
+
+
 HD_N, HD_M, HD_T, HD_SEED = 16384, 1024, 12, 4
 
 # fixed-RMSE comparison: sequences, their length, the outer-particle grid and
@@ -617,15 +710,18 @@ def run_table1(S, dpf, torch, np, dev, spec, name):
 
 
 GRID_SEQS, GRID_N, GRID_M, GRID_SEED = 256, (20, 50, 100, 200), (10, 20), 20000
+GRID_K = (1, 4, 8)  # companions per look-ahead candidate (nested estimator)
 
 
 def run_table1_grid(S, dpf, torch, np, dev, ref):
     """Section 4.1's study on the models of Table 1: RMSE of x_hat and z_hat
     and the fraction of diverged runs against (N, M) for the look-ahead step
-    (with its plain and its Rao-Blackwellised x estimate) and the plain step, GRID_SEQS fresh 250-step sequences per point run as filters
-    of one handle.  A run diverges when an estimate is non-finite or its RMSE
-    of x exceeds 3x the reference (the look-ahead run at N = 4096, M = 256 of
-    `ref`)."""
+    (with its plain and its Rao-Blackwellised x estimate), the look-ahead
+    step with the nested estimator (K companions per candidate, K in
+    GRID_K) and the plain step, GRID_SEQS fresh 250-step sequences per point
+    run as filters of one handle.  A run diverges when an estimate is
+    non-finite or its RMSE of x exceeds 3x the reference (the look-ahead run
+    at N = 4096, M = 256 of `ref`)."""
     out = {}
     for key, spec in (("model1", S.twodim_table1()), ("model2", S.fourdim_table1())):
         sims = [S.simulate(spec, TD_T, GRID_SEED + q) for q in range(GRID_SEQS)]
@@ -637,13 +733,18 @@ def run_table1_grid(S, dpf, torch, np, dev, ref):
         for N in GRID_N:
             for M in GRID_M:
                 row = {"N": N, "M": M}
-                for algo in ("lookahead", "plain"):
+                for algo in ("lookahead", "plain") + tuple("K%d" % k for k in GRID_K):
                     f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N] * GRID_SEQS,
-                                   [M] * GRID_SEQS, seed=FILTER_SEED, device=dev, algo=algo)
+                                   [M] * GRID_SEQS, seed=FILTER_SEED, device=dev,
+                                   algo="plain" if algo == "plain" else "lookahead")
                     arms = {}
                     if algo == "plain":
                         xt, zt = f.run(Y, use_graph=True)
                         arms["plain"] = (xt, zt)
+                    elif algo.startswith("K"):
+                        f.set_companions(int(algo[1:]))
+                        xt, zt = f.run(Y, use_graph=True)
+                        arms["lookahead_" + algo] = (xt, zt)
                     else:
                         # step calls (a run gives the same bits) so that the
                         # Rao-Blackwellised estimate can follow every step
@@ -671,7 +772,10 @@ def run_table1_grid(S, dpf, torch, np, dev, ref):
         out[key] = {"divergence_limit_rmse_x": round(lim, 4), "points": rows}
     out["config"] = {"workload": "models 1 and 2 of Table 1, %d fresh sequences x T=%d per point as filters of "
                                  "one handle, N in %s, M in %s" % (GRID_SEQS, TD_T, list(GRID_N), list(GRID_M)),
-                     "rmse": "over the sequences that did not diverge"}
+                     "rmse": "over the sequences that did not diverge",
+                     "arms": "lookahead (one companion per candidate, paired), lookahead_rb (its "
+                             "Rao-Blackwellised x estimate), lookahead_K<k> (nested estimator, k companions per "
+                             "candidate), plain"}
     return out
 
 

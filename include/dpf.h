@@ -214,6 +214,23 @@ dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_
  * on z.  The learned step's fallback keeps the paired form. */
 dpf_status dpf_set_lookahead_companions(dpf_handle* h, int32_t n_comp);
 
+/* Predicted observation (the one-step-ahead prediction whose error is the
+ * reward of the decomposition choice, Section 3 and Section 4.3):
+ *   yhat_{t|t-1} = (1/N) sum_i sum_j qbar^{(i,j)} h(x^{(i,j)}, z^{(i,j)}),
+ * the look-ahead draws of Fig. 4 step 1 weighted as draws from the one-step
+ * predictive p(x_t, z_t | y_{0:t-1}) (nested estimator: h averaged over each
+ * candidate's companions); h the noise-free observation.  enable != 0: every
+ * following look-ahead step (dpf_lookahead_step, dpf_run) forms it from
+ * its own look-ahead draws; d_ytrace [T][F] float (or NULL) receives it at
+ * row t-1 as y_t is consumed.  Built for models with a one-dimensional y
+ * (LINGAUSS, TWODIM, TWODIM_ZFIRST, FOURDIM; else DPF_EUNSUPPORTED); look-ahead
+ * handles only (DPF_ESTATE); not formed by the learned step. */
+dpf_status dpf_set_prediction(dpf_handle* h, int32_t enable, float* d_ytrace);
+
+/* Copy the predicted observation of each filter's last look-ahead step:
+ * d_yhat [F] float (DPF_ESTATE unless dpf_set_prediction enabled it). */
+dpf_status dpf_predicted_observation(dpf_handle* h, float* d_yhat);
+
 /* Rao-Blackwellised estimate of the new outer state of the look-ahead step
  * just taken: xhat_rb = sum_i Wbar_i sum_j pi_ij xla^{(i,j)}, Wbar the
  * normalised look-ahead weights (eq:weightsMC), pi_i. = softmax_j ell_ij the

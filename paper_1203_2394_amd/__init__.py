@@ -33,7 +33,8 @@ EXPORTS = [
     "dpf_set_proposal", "dpf_learned_step", "dpf_learned_step_given", "dpf_features",
     "dpf_mlp_blob_bytes", "dpf_mlp_param_count", "dpf_mlp_forward", "dpf_mlp_train_workspace_bytes",
     "dpf_mlp_pack", "dpf_mlp_train_step", "dpf_learned_run", "dpf_tile_classes", "dpf_set_tiling",
-    "dpf_estimate_rb", "dpf_systematic_noalloc", "dpf_set_lookahead_companions",
+    "dpf_estimate_rb", "dpf_systematic_noalloc", "dpf_set_lookahead_companions", "dpf_set_prediction",
+    "dpf_predicted_observation",
 ]
 
 
@@ -103,6 +104,8 @@ def lib():
         "dpf_tile_classes": (_i32, [_vp, _vp, _i32]),
         "dpf_set_tiling": (_i32, [_vp, _vp]),
         "dpf_set_lookahead_companions": (_i32, [_vp, _i32]),
+        "dpf_set_prediction": (_i32, [_vp, _i32, _vp]),
+        "dpf_predicted_observation": (_i32, [_vp, _vp]),
         "dpf_mlp_blob_bytes": (_sz, []),
         "dpf_mlp_param_count": (_sz, []),
         "dpf_mlp_forward": (_i32, [_vp, _vp, _i32, _vp, _vp]),
@@ -219,6 +222,24 @@ class Filter:
         """Tile class per filter (index into tile_classes(), or -1 = default)."""
         c = np.ascontiguousarray(np.broadcast_to(np.asarray(classes, dtype=np.int32), (self.F,)))
         _check(lib().dpf_set_tiling(self._h, c.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_prediction(self, enable=True, trace_T=0):
+        """Form the predicted observation in every look-ahead step; with
+        trace_T > 0 also record it per step in a [trace_T][F] tensor
+        (returned; rows indexed by absolute time - 1)."""
+        torch = _torch()
+        tr = None
+        if enable and trace_T > 0:
+            tr = torch.full((int(trace_T), self.F), float("nan"), dtype=torch.float32, device=self.device)
+        _check(lib().dpf_set_prediction(self._h, int(bool(enable)), _ptr(tr)))
+        self._ytrace = tr
+        return tr
+
+    def predicted_observation(self):
+        torch = _torch()
+        out = torch.empty(self.F, dtype=torch.float32, device=self.device)
+        _check(lib().dpf_predicted_observation(self._h, _ptr(out)))
+        return out
 
     def set_companions(self, n_comp):
         """Companions per look-ahead candidate: K >= 1 the nested estimator,

@@ -85,6 +85,7 @@ struct Engine {
   // and a per-filter pass as two launches
   dpf_status (*post)(const StepArgs& a, const int2* rgroups, int n_rgroups, int F, int next, int split,
                      hipStream_t s);
+  bool yhat;  // the look-ahead pass can form the predicted observation
 };
 
 extern const Engine kEngLinGauss, kEngNonLin, kEngHighDim, kEngTwoDim, kEngFourDim, kEngTwoDimZ;

@@ -123,17 +123,27 @@ static dpf_status engine_finalize(const StepArgs& a, int F, hipStream_t s) {
   return DPF_OK;
 }
 
-template <class Mdl>
-static dpf_status engine_post(const StepArgs& a, const int2* rg, int n_rgroups, int F, int next, int split,
-                              hipStream_t s) {
+template <class Mdl, bool YH>
+static dpf_status engine_post_y(const StepArgs& a, const int2* rg, int n_rgroups, int F, int next, int split,
+                                hipStream_t s) {
   constexpr int DX = Mdl::DX, DZ = Mdl::DZ;
-  hipLaunchKernelGGL((k_post<DX, DZ>), dim3(n_rgroups), dim3(kBlock), 0, s, a, rg, next, split);
+  hipLaunchKernelGGL((k_post<DX, DZ, YH>), dim3(n_rgroups), dim3(kBlock), 0, s, a, rg, next, split);
   LAUNCH_CHECK("k_post");
   if (split) {
-    hipLaunchKernelGGL((k_post_end<DX, DZ>), dim3(F), dim3(kWave), 0, s, a, next);
+    hipLaunchKernelGGL((k_post_end<DX, DZ, YH>), dim3(F), dim3(kWave), 0, s, a, next);
     LAUNCH_CHECK("k_post_end");
   }
   return DPF_OK;
+}
+
+// (the predicted observation's partial sums when the step formed them)
+template <class Mdl>
+static dpf_status engine_post(const StepArgs& a, const int2* rg, int n_rgroups, int F, int next, int split,
+                              hipStream_t s) {
+  if constexpr (has_yhat<Mdl>()) {
+    if (a.yp != nullptr) return engine_post_y<Mdl, true>(a, rg, n_rgroups, F, next, split, s);
+  }
+  return engine_post_y<Mdl, false>(a, rg, n_rgroups, F, next, split, s);
 }
 
 // The engine table entry of model Mdl with parameter derivation DERIVE.
@@ -151,7 +161,8 @@ static Engine make_engine(void (*derive)(const double*, std::vector<float>&)) {
                 has_moments<Mdl>(),
                 engine_rb<Mdl>,
                 engine_finalize<Mdl>,
-                engine_post<Mdl>};
+                engine_post<Mdl>,
+                has_yhat<Mdl>()};
 }
 
 }  // namespace dpf

@@ -46,6 +46,11 @@ constexpr int kFeatMax = 32;    // input width of the learned-proposal network
 template <class Mdl>
 constexpr bool has_moments() { return Mdl::DX + Mdl::DY + 2 * Mdl::DZ <= kFeatMax; }
 
+// Models whose predicted observation the look-ahead pass can form (they
+// provide obs_mean).
+template <class Mdl>
+constexpr bool has_yhat() { return Mdl::DY == 1; }
+
 // Per-filter bookkeeping for the resampling groups.
 struct FilterInfo {
   int rg_base;  // first resampling group of the filter
@@ -99,6 +104,14 @@ struct StepArgs {
   const int2* rgroups;  // (filter, group) of each resampling workgroup
   int n_commit;         // learned-step commit workgroups at the head of the launch
   int n_comp;           // companions per look-ahead candidate (nested estimator; 0: paired)
+  // predicted observation (models with a one-dimensional y), or null: per
+  // outer particle sum_j qbar h(xla, zla) of this step's look-ahead draws
+  // (yp) and of the next step's (yp_next, written by a fused new-cloud
+  // launch); the filter's yhat and its trace
+  float* yp;
+  float* yp_next;
+  float* est_y;    // [F]
+  float* trace_y;  // [T][F] or null
   // look-ahead state: cloud slot of each outer particle, per copy.  A step
   // that resamples by copying writes the identity; the learned step writes
   // its outer ancestors instead of moving the clouds.
@@ -312,9 +325,9 @@ static __global__ __launch_bounds__(kBlock) void k_init(StepArgs a) {
 // arithmetic with the caller's on the same values, so the weights kernel and
 // the new-cloud kernel (a look-ahead run) compile it alike and get the same
 // bits.
-template <class Mdl>
+template <class Mdl, bool H = false>
 __device__ __forceinline__ float la_logpy(const StepArgs& a, const Key& key, int t, int i, int j, const float* xi,
-                                          const float* zi, const float* yi) {
+                                          const float* zi, const float* yi, float* hout = nullptr) {
   float x[Mdl::DX], z[Mdl::DZ], y[Mdl::DY];
 #pragma unroll
   for (int d = 0; d < Mdl::DX; ++d) {
@@ -338,6 +351,22 @@ __device__ __forceinline__ float la_logpy(const StepArgs& a, const Key& key, int
   Mdl::fz_pre(a.prm, x, xl, t - 1, pre);
   Mdl::fz_post(a.prm, pre, z, nu_z, zl);
   Mdl::obs_pre(a.prm, y, xl, r0);
+  if constexpr (H) {
+    // the noise-free observation of the draw, on opaque copies (no sharing
+    // with the likelihood's arithmetic)
+    float xh[Mdl::DX], zh[Mdl::DZ];
+#pragma unroll
+    for (int d = 0; d < Mdl::DX; ++d) {
+      xh[d] = xl[d];
+      asm volatile("" : "+v"(xh[d]));
+    }
+#pragma unroll
+    for (int d = 0; d < Mdl::DZ; ++d) {
+      zh[d] = zl[d];
+      asm volatile("" : "+v"(zh[d]));
+    }
+    Mdl::obs_mean(a.prm, xh, zh, hout);
+  }
   return Mdl::logpy_post(a.prm, r0, zl);
 }
 
@@ -381,6 +410,9 @@ __device__ __forceinline__ void la_weights_tile(const StepArgs& a, int ti, bool 
   const float* lrow = a.lam[src] + io + (long long)ci * M;
   float* erow = a.ell + io + (long long)(vi ? i : 0) * M;
   Lse acc;
+  constexpr bool kH = has_yhat<Mdl>();
+  const bool want_h = kH && a.yp != nullptr && !fallback;
+  float hv = 0.f;  // sum over the lane's draws of qbar h(xla, zla)
 #pragma unroll
   for (int r = 0; r < JPT; ++r) {
     const int j = ls + r * SEG;
@@ -388,13 +420,26 @@ __device__ __forceinline__ void la_weights_tile(const StepArgs& a, int ti, bool 
       float z[Mdl::DZ];
 #pragma unroll
       for (int d = 0; d < Mdl::DZ; ++d) z[d] = zrow[d * M + j];
-      const float e = la_ell(lrow[j], la_logpy<Mdl>(a, key, t, i, j, x, z, y));
+      const float lj = lrow[j];
+      float g;
+      if (want_h) {
+        float h[1];
+        g = la_logpy<Mdl, kH>(a, key, t, i, j, x, z, y, h);
+        hv += fast_exp(lj) * h[0];
+      } else {
+        g = la_logpy<Mdl>(a, key, t, i, j, x, z, y);
+      }
+      const float e = la_ell(lj, g);
       erow[j] = e;
       acc.add(e);
     }
   }
   const float lw = seg_lse<SEG>(acc, sh);
   if (vi && ls == 0) a.logw[oo + i] = lw;
+  if (want_h) {
+    const float hs = seg_sum<SEG>(hv, sh);
+    if (vi && ls == 0) a.yp[oo + i] = hs;
+  }
 }
 
 // Nested look-ahead weights (Fig. 4 step 1 with N_z' = K companions per
@@ -419,6 +464,8 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
   __shared__ SegScratch sh;
   __shared__ double cdf[NSEG][CAP];
   __shared__ float xs[NSEG][kCond ? CAP : 1][DX];
+  __shared__ float lms[NSEG][kCond ? CAP : 1];
+  constexpr bool kH = has_yhat<Mdl>();
   const int4 tile = a.tiles[ti];
   const int f = tile.x;
   const int am = a.active != nullptr ? a.active[f] : 1;
@@ -473,9 +520,15 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
       if constexpr (kCond) {
 #pragma unroll
         for (int d = 0; d < DX; ++d) xs[s][kCond ? j : 0][d] = xl[r][d];
+        lms[s][kCond ? j : 0] = lamv[r];
       }
     }
   }
+  // predicted observation: sum over the lane's candidates of qbar times the
+  // mean of h over their companions
+  const bool want_h = kH && a.yp != nullptr;
+  const float invK = 1.0f / (float)K;
+  float hv = 0.f;
   float ev[JPT];
 #pragma unroll
   for (int r = 0; r < JPT; ++r) ev[r] = -INFINITY;
@@ -510,6 +563,7 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
         Mdl::obs_pre(a.prm, y, xl[r], r0);
         const double u = uniform53_ab(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_B);
         Lse acck;
+        float hk = 0.f;
         for (int k = 0; k < K; ++k) {
           const int b = cdf_search(cdf[s], M, sys_point(k, u, total, K));
           float zg[DZ], nu[DZ], zc[DZ];
@@ -518,9 +572,17 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
           normals_k<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, k, nu);
           Mdl::fz_post(a.prm, pre, zg, nu, zc);
           acck.add(Mdl::logpy_post(a.prm, r0, zc));
+          if constexpr (kH) {
+            if (want_h) {
+              float h[1];
+              Mdl::obs_mean(a.prm, xl[r], zc, h);
+              hk += h[0];
+            }
+          }
         }
         const float g = (acck.m == -INFINITY) ? -INFINITY : acck.m + fast_log(acck.s) - logK;
         ev[r] = la_ell(lamv[r], g);
+        if (want_h) hv += fast_exp(lamv[r]) * (hk * invK);
       }
     }
   } else {
@@ -565,6 +627,7 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
         float pre[Mdl::NPRE], r0[DY];
         Mdl::fz_pre(a.prm, x, xm, t - 1, pre);
         Mdl::obs_pre(a.prm, y, xm, r0);
+        const float wm = want_h ? fast_exp(lms[s][kCond ? m : 0]) * invK : 0.f;
         for (int k = ls; k < K; k += SEG) {
           const int b = cdf_search(cdf[s], M, sys_point(k, u, total, K));
           float zg[DZ], nu[DZ], zc[DZ];
@@ -573,6 +636,13 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
           normals_k<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)m, P_LA_Z, k, nu);
           Mdl::fz_post(a.prm, pre, zg, nu, zc);
           acck.add(Mdl::logpy_post(a.prm, r0, zc));
+          if constexpr (kH) {
+            if (want_h) {
+              float h[1];
+              Mdl::obs_mean(a.prm, xm, zc, h);
+              hv += wm * h[0];
+            }
+          }
         }
       }
       const float lse = seg_lse<SEG>(acck, sh);
@@ -594,6 +664,10 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
   }
   const float lw = seg_lse<SEG>(acc, sh);
   if (vi && ls == 0) a.logw[oo + i] = lw;
+  if (want_h) {
+    const float hs = seg_sum<SEG>(hv, sh);
+    if (vi && ls == 0) a.yp[oo + i] = hs;
+  }
 }
 
 template <class Mdl, int SEG, int JPT>
@@ -1308,13 +1382,15 @@ static __global__ __launch_bounds__((fin_block<DX, DZ>())) void k_finalize(StepA
 //    the non-finite check, and (last workgroup) the time advance -- plus
 //    the filter's activity for the next step.
 // The last workgroup of a filter is found with a counter it resets.
-template <int DX, int DZ>
+// YH: also the predicted observation yhat = (1/N) sum_i yp_i (one more
+// partial sum per group).
+template <int DX, int DZ, bool YH>
 __device__ __forceinline__ void post_finish(const StepArgs& a, int f, int rb, int G, int t, unsigned char cb,
                                             int next, bool act_next, int nthreads);
 
-template <int DX, int DZ>
+template <int DX, int DZ, bool YH>
 static __global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* rgroups, int next, int split) {
-  constexpr int NV = DX + DZ;
+  constexpr int NV = DX + DZ + (YH ? 1 : 0);
   __shared__ ResScratch sh;
   __shared__ double part[kBlock / kWave][NV];
   __shared__ int last;
@@ -1340,6 +1416,7 @@ static __global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* 
   for (int d = 0; d < DX; ++d) raw[d] = xs[(long long)d * a.NT + oo + ic];
 #pragma unroll
   for (int d = 0; d < DZ; ++d) raw[DX + d] = a.kpart[(long long)(oo + ic) * DZ + d];
+  if constexpr (YH) raw[NV - 1] = a.yp[oo + ic];
   const float lwn = act_next ? a.logw_next[oo + ic] : 0.f;
   double v[NV];
 #pragma unroll
@@ -1373,15 +1450,15 @@ static __global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* 
   if (!last) return;
   __threadfence();
   if (threadIdx.x == 0) a.fcount[f] = 0;
-  post_finish<DX, DZ>(a, f, rb, fv.ngroup, t, cb, next, act_next, kBlock);
+  post_finish<DX, DZ, YH>(a, f, rb, fv.ngroup, t, cb, next, act_next, kBlock);
 }
 
 // Filter-level end of k_post: the estimates from the group partials (in
 // group order), the next step's activity and the time advance.
-template <int DX, int DZ>
+template <int DX, int DZ, bool YH>
 __device__ __forceinline__ void post_finish(const StepArgs& a, int f, int rb, int G, int t, unsigned char cb,
                                             int next, bool act_next, int nthreads) {
-  constexpr int NV = DX + DZ;
+  constexpr int NV = DX + DZ + (YH ? 1 : 0);
   for (int q = threadIdx.x; q < NV; q += nthreads) {
     double e = 0.0;
     // (unrolled: the loads of several groups in flight, added in order)
@@ -1390,9 +1467,12 @@ __device__ __forceinline__ void post_finish(const StepArgs& a, int f, int rb, in
     if (q < DX) {
       a.est_x[f * DX + q] = (float)e;
       if (a.trace_x) a.trace_x[((long long)(t - 1) * a.n_filters + f) * DX + q] = (float)e;
-    } else {
+    } else if (q < DX + DZ) {
       a.est_z[f * DZ + q - DX] = (float)e;
       if (a.trace_z) a.trace_z[((long long)(t - 1) * a.n_filters + f) * DZ + q - DX] = (float)e;
+    } else {
+      a.est_y[f] = (float)e;
+      if (a.trace_y) a.trace_y[(long long)(t - 1) * a.n_filters + f] = (float)e;
     }
   }
   if (threadIdx.x == 0 && next) {
@@ -1408,7 +1488,7 @@ __device__ __forceinline__ void post_finish(const StepArgs& a, int f, int rb, in
 // device-scope fence per workgroup writes back the L2 of its XCD) costs more
 // than a kernel boundary: k_post runs split (groups only) and this kernel,
 // one 64-thread workgroup per filter, finishes the filters.
-template <int DX, int DZ>
+template <int DX, int DZ, bool YH>
 static __global__ __launch_bounds__(kWave) void k_post_end(StepArgs a, int next) {
   const int f = blockIdx.x;
   const int tf = (next && a.run_Tf != nullptr) ? a.run_Tf[f] : 0x7fffffff;
@@ -1417,7 +1497,7 @@ static __global__ __launch_bounds__(kWave) void k_post_end(StepArgs a, int next)
   const FilterView fv = load_filter(a, f);
   if (!fv.act) return;
   const bool act_next = next && fv.t < min(tf, a.run_T);
-  post_finish<DX, DZ>(a, f, rb, fv.ngroup, fv.t, (unsigned char)fv.cur, next, act_next, kWave);
+  post_finish<DX, DZ, YH>(a, f, rb, fv.ngroup, fv.t, (unsigned char)fv.cur, next, act_next, kWave);
 }
 
 // ---------------------------------------------------------------- new cloud
@@ -1755,6 +1835,10 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
   float* zdst = a.z[dst] + (io + (long long)k * M) * DZ;
   float llv[JPT], gn[JPT];
   float zkeep[kKeepZ ? JPT : 1][DZ];
+  // predicted observation of the next step (fused run, when requested)
+  constexpr bool kH = !PLAIN && has_yhat<Mdl>();
+  const bool want_h = kH && fuse && a.yp_next != nullptr;
+  float hn[kH ? JPT : 1];
   Lse acc;
 #pragma unroll
   for (int r = 0; r < JPT; ++r) {
@@ -1783,7 +1867,13 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
         acc.add(llv[r]);
         // the next step's look-ahead likelihood of this new inner particle
         // (ALU work that overlaps the gathers of the others)
-        if (fuse) gn[r] = la_logpy<Mdl>(a, key, t + 1, k, jj, xn, zn, yn);
+        if (want_h) {
+          float h[1];
+          gn[r] = la_logpy<Mdl, kH>(a, key, t + 1, k, jj, xn, zn, yn, h);
+          hn[kH ? r : 0] = h[0];
+        } else if (fuse) {
+          gn[r] = la_logpy<Mdl>(a, key, t + 1, k, jj, xn, zn, yn);
+        }
       }
     }
   }
@@ -1848,6 +1938,7 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
     if (fuse) {
       float* en = a.ell_next + io + (long long)(vk ? k : 0) * M;
       Lse acc2;
+      float hv = 0.f;
 #pragma unroll
       for (int r = 0; r < JPT; ++r) {
         const int jj = ls + r * SEG;
@@ -1855,10 +1946,15 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
           const float e = la_ell(lamv[r], gn[r]);
           en[jj] = e;
           acc2.add(e);
+          if (want_h) hv += fast_exp(lamv[r]) * hn[kH ? r : 0];
         }
       }
       const float lw = seg_lse<SEG>(acc2, sh);
       if (vk && ls == 0) a.logw_next[oo + k] = lw;
+      if (want_h) {
+        const float hs = seg_sum<SEG>(hv, sh);
+        if (vk && ls == 0) a.yp_next[oo + k] = hs;
+      }
     }
   }
   if (vk && ls == 0 && fl) atomicOr(&a.flags[f], fl);

@@ -72,6 +72,8 @@ struct Layout {
   size_t gpart, fcount;
   // Rao-Blackwellised estimate: per-outer partial sums
   size_t xrb;
+  // predicted observation: per-outer partial sums (two, like ell) and [F]
+  size_t yp0, yp1, est_y;
   int NT = 0;
   long long NMT = 0;
   int n_tiles = 0, n_rgroups = 0;
@@ -172,9 +174,12 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   L.mom_tmp = carve(cur, NT * 2 * dz * 4);
   L.fb = carve(cur, F);
   L.lflags = carve(cur, F * 4);
-  L.gpart = carve(cur, (size_t)L.n_rgroups * (dx + dz) * 8);
+  L.gpart = carve(cur, (size_t)L.n_rgroups * (dx + dz + 1) * 8);
   L.fcount = carve(cur, F * 4);
   L.xrb = carve(cur, (size_t)L.NT * dx * 8);
+  L.yp0 = carve(cur, NT * 4);
+  L.yp1 = carve(cur, NT * 4);
+  L.est_y = carve(cur, F * 4);
   L.total = cur;
   return DPF_OK;
 }
@@ -201,7 +206,8 @@ struct dpf_handle {
   // multi-step graph cache
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
-  const void* g_key[9] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const void* g_key[11] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, nullptr, nullptr};
   int g_T = -1;
   // phase timing: caller-owned events consumed kPhaseEvents per step
   std::vector<hipEvent_t> prof_events;
@@ -218,6 +224,9 @@ struct dpf_handle {
   bool rb_ready = false;
   // companions per look-ahead candidate (nested estimator); 0: paired
   int n_comp = 0;
+  // look-ahead steps form the predicted observation (and record it in ytrace)
+  bool predict = false;
+  float* ytrace = nullptr;
 };
 
 constexpr int kPhaseEvents = 5;
@@ -293,6 +302,7 @@ static StepArgs make_args(dpf_handle* h) {
   a.gpart = at<double>(h, h->L.gpart);
   a.fcount = at<int>(h, h->L.fcount);
   a.n_comp = h->n_comp;
+  a.est_y = at<float>(h, h->L.est_y);
   return a;
 }
 
@@ -535,6 +545,12 @@ static dpf_status queue_step(dpf_handle* h, const float* Y, long long y_tstride,
     a.logw_next = w[par ^ 1];
   }
   h->ell_sel = fuse ? par : 0;
+  if (h->predict && !plain) {
+    float* yb[2] = {at<float>(h, h->L.yp0), at<float>(h, h->L.yp1)};
+    a.yp = yb[fuse ? par : 0];
+    a.yp_next = fuse ? yb[par ^ 1] : nullptr;
+    a.trace_y = h->ytrace;
+  }
   dpf_status s = phase_mark(h, 0);
   const int wop = plain ? OP_DPF_WEIGHTS : (h->n_comp > 0 ? OP_LA_WEIGHTS_NESTED : OP_LA_WEIGHTS);
   if (s == DPF_OK && fuse != 2) s = launch_classes(h, wop, a);
@@ -640,6 +656,23 @@ extern "C" dpf_status dpf_set_lookahead_companions(dpf_handle* h, int32_t n_comp
   if (n_comp < 0 || n_comp > kMaxCompanions)
     return fail(DPF_EINVAL, "n_comp = %d outside 0..%d", n_comp, kMaxCompanions);
   h->n_comp = n_comp;
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_set_prediction(dpf_handle* h, int32_t enable, float* d_ytrace) {
+  if (!h) return fail(DPF_EINVAL, "handle is NULL");
+  if (h->algo != DPF_ALGO_LOOKAHEAD) return fail(DPF_ESTATE, "the prediction is formed by the look-ahead pass");
+  if (enable && !h->eng->yhat)
+    return fail(DPF_EUNSUPPORTED, "model %d has no built predicted observation (one-dimensional y only)", h->model);
+  h->predict = enable != 0;
+  h->ytrace = enable ? d_ytrace : nullptr;
+  return DPF_OK;
+}
+
+extern "C" dpf_status dpf_predicted_observation(dpf_handle* h, float* d_yhat) {
+  if (!h || !d_yhat) return fail(DPF_EINVAL, "handle and d_yhat are required");
+  if (!h->predict) return fail(DPF_ESTATE, "prediction is not enabled (dpf_set_prediction)");
+  HIP_TRY(hipMemcpyAsync(d_yhat, h->ws + h->L.est_y, (size_t)h->F * 4, hipMemcpyDeviceToDevice, h->stream));
   return DPF_OK;
 }
 
@@ -771,9 +804,10 @@ static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T
   // mode, whether cloud moments are maintained, and the fallback threshold
   uint64_t ess_bits;
   memcpy(&ess_bits, &h->ess_frac, sizeof(ess_bits));
-  const void* key[9] = {d_Y, d_Tf, d_xtrace, d_ztrace, (const void*)h->stream, (const void*)(intptr_t)mode,
-                        (const void*)(intptr_t)(h->has_proposal ? 1 : 0), (const void*)(uintptr_t)ess_bits,
-                        (const void*)(intptr_t)h->n_comp};
+  const void* key[11] = {d_Y, d_Tf, d_xtrace, d_ztrace, (const void*)h->stream, (const void*)(intptr_t)mode,
+                         (const void*)(intptr_t)(h->has_proposal ? 1 : 0), (const void*)(uintptr_t)ess_bits,
+                         (const void*)(intptr_t)h->n_comp, (const void*)(intptr_t)(h->predict ? 1 : 0),
+                         (const void*)h->ytrace};
   const bool cached = h->gexec && h->g_T == T && memcmp(key, h->g_key, sizeof(key)) == 0;
   if (!cached) {
     if (h->gexec) {

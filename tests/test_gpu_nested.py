@@ -60,6 +60,9 @@ def test_nested_step_parity(name, N, M, K, warm, steps):
         st, _ = ladpf.step(model, st, ys[t], seed, 0, n_comp=K)
     f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N], [M], seed=seed)
     f.set_companions(K)
+    predict = spec.dy == 1
+    if predict:
+        f.set_prediction(True)
     for t in range(warm, warm + steps):
         st32 = to_state32(st)
         f.import_state(torch.from_numpy(f.pack_state(st32["t"], st32["x"], st32["z"], st32["lam"])))
@@ -85,6 +88,12 @@ def test_nested_step_parity(name, N, M, K, warm, steps):
         assert abs(ll - info["dlogz"]) <= 1e-4 * max(1.0, abs(info["dlogz"])), (ll, info["dlogz"])
         ess = float(est["ess"][0])
         assert abs(ess - info["ess"]) <= 1e-4 * info["ess"], (ess, info["ess"])
+        if predict and rw["tainted_rows"] == 0:
+            # the predicted observation over the companions
+            _, _, _, _, hmean = ladpf.lookahead_nested(model, st32, ys[t], seed, 0, K)
+            yo = float(ladpf.predicted_observation(st32["lam"], hmean)[0])
+            yg = float(f.predicted_observation()[0])
+            assert abs(yg - yo) <= 1e-4 * max(1.0, abs(yo)), (yg, yo)
 
 
 @pytest.mark.parametrize("name,N,M,K", [("nonlin", [300, 90], [64, 40], 3), ("twodim", [200, 50], [20, 10], 4)])

@@ -40,7 +40,14 @@ SPECS = {
     "highdim_gauss": lambda: S.highdim_c4(1, gaussian_only=True),
     "twodim": lambda: S.twodim_table1(),
     "fourdim": lambda: S.fourdim_table1(),
+    # the other sampling order, and both orders across the change point at t = 5
+    "twodim_z": lambda: S.twodim_table1(zfirst=True),
+    "twodim_swap": lambda: S.twodim_table1(tswap=5),
+    "twodim_z_swap": lambda: S.twodim_table1(tswap=5, zfirst=True),
 }
+
+# models whose look-ahead pass forms the predicted observation
+PREDICT = {"lingauss", "lingauss_coupled", "twodim", "fourdim", "twodim_z", "twodim_swap", "twodim_z_swap"}
 
 
 def _gpu_filter(spec, N, M, seed, algo):
@@ -56,6 +63,8 @@ def _la_case(name, N, M, warm, steps, seed=4242, data_seed=3):
     for t in range(warm):
         st, _ = ladpf.step(model, st, ys[t], seed, 0)
     f = _gpu_filter(spec, N, M, seed, "lookahead")
+    if name in PREDICT:
+        f.set_prediction(True)
     reports = []
     for t in range(warm, warm + steps):
         st32 = to_state32(st)
@@ -70,6 +79,8 @@ def _la_case(name, N, M, warm, steps, seed=4242, data_seed=3):
         assert int(g["t"][0]) == st32["t"] + 1
         est = f.estimate()
         est["xhat_rb"] = f.estimate_rb()
+        if name in PREDICT:
+            est["yhat"] = f.predicted_observation()
         r, st, info = compare_la(model, st32, ys[t], seed, 0, gs, ell, logw, anc, sel)
         print("LA %s N=%d M=%d t=%d: %s" % (name, N, M, t + 1, r.line()), flush=True)
         reports.append((r, info, est, gs, logw))
@@ -131,12 +142,21 @@ def _check_self_estimates(est, gs, logw_g):
     ("twodim", 500, 19, 2, 2),
     ("fourdim", 120, 64, 3, 3),
     ("fourdim", 33, 200, 7, 2),
+    ("twodim_z", 130, 64, 3, 3),
+    ("twodim_z", 37, 300, 6, 2),
+    ("twodim_swap", 100, 50, 3, 4),
+    ("twodim_z_swap", 100, 50, 3, 4),
 ])
 def test_lookahead_step_parity(name, N, M, warm, steps):
     for r, info, est, gs, logw in _la_case(name, N, M, warm, steps):
         assert_clean(r, n=N)
         _check_evidence(est, info, logw, name)
         _check_self_estimates(est, gs, logw)
+        if name in PREDICT:
+            # the predicted observation depends on the look-ahead draws only
+            yg = float(est["yhat"][0])
+            yo = float(info["yhat"][0])
+            assert abs(yg - yo) <= 1e-4 * max(1.0, abs(yo)), (yg, yo)
         # the Rao-Blackwellised estimate involves no sampled index: compared
         # always; its weights come from FP32 ell (absolute error ~3e-5 at
         # |ell| ~ 100) applied to candidates up to ~20 apart

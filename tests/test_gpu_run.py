@@ -377,3 +377,30 @@ def test_cumulative_evidence_over_steps():
     ref = info1["dlogz"] + info2["dlogz"]
     print("cumulative evidence gpu %.9g oracle %.9g" % (ll, ref), flush=True)
     assert abs(ll - ref) <= 1e-4 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("zfirst", [False, True])
+def test_predicted_observation_run_equals_step_calls(zfirst):
+    """The predicted observation of a fused run (each step's look-ahead draws
+    formed in the previous step's new-cloud launch) equals step calls', bit
+    for bit, per step, across a chunk boundary and a change point."""
+    spec = S.twodim_table1(tswap=9, zfirst=zfirst)
+    N, M, T = [300, 77], [64, 20], 21
+    Y = np.stack([S.simulate(spec, T, 81 + q)[2] for q in range(2)], axis=1).astype(np.float32)
+    a = _filter(spec, N, M)
+    a.set_prediction(True)
+    ys = []
+    for t in range(T):
+        a.lookahead_step(torch.from_numpy(Y[t]))
+        ys.append(a.predicted_observation())
+    ref = torch.stack(ys)
+    b = _filter(spec, N, M)
+    tr = b.set_prediction(True, trace_T=T)
+    b.run(torch.from_numpy(Y), use_graph=True)
+    assert np.array_equal(a.export_state().cpu().numpy(), b.export_state().cpu().numpy())
+    assert torch.equal(ref, tr), (ref[:3], tr[:3])
+    assert torch.equal(b.predicted_observation(), ref[-1])
+    # switching the prediction off leaves the run's results unchanged
+    c = _filter(spec, N, M)
+    c.run(torch.from_numpy(Y), use_graph=True)
+    assert np.array_equal(b.export_state().cpu().numpy(), c.export_state().cpu().numpy())
