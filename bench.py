@@ -224,6 +224,8 @@ def main():
     ap.add_argument("--no-bandit", action="store_true",
                     help="skip the automatic decomposition experiment (Hedge / Exp3)")
     ap.add_argument("--only-bandit", action="store_true", help="only the automatic decomposition experiment")
+    ap.add_argument("--only-nested", action="store_true",
+                    help="only a nested look-ahead run (model 1 of Table 1, 256 x N=200 x M=20, K=8; profiling)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="after the timed steps, run one device-to-device copy of this many MB "
                          "(a kernel of known traffic for calibrating hardware byte counters)")
@@ -254,6 +256,9 @@ def main():
         return 0
     if args.only_bandit:
         print(json.dumps({"bandit": run_bandit(S, dpf, torch, np, dev)}))
+        return 0
+    if args.only_nested:
+        print(json.dumps({"nested": run_nested_point(S, dpf, torch, np, dev)}))
         return 0
     spec = S.nonlin_c2(PARAM_SEED)
     n_obs = max(T_TRAJ, K, W)
@@ -713,6 +718,28 @@ GRID_SEQS, GRID_N, GRID_M, GRID_SEED = 256, (20, 50, 100, 200), (10, 20), 20000
 GRID_K = (1, 4, 8)  # companions per look-ahead candidate (nested estimator)
 
 
+def run_nested_point(S, dpf, torch, np, dev, N=200, M=20, K=8):
+    """One point of the Table 1 grid with the nested look-ahead estimator:
+    model 1, GRID_SEQS sequences of TD_T steps as filters of one handle, run
+    twice (the second timed)."""
+    spec = S.twodim_table1()
+    sims = [S.simulate(spec, TD_T, GRID_SEED + q) for q in range(GRID_SEQS)]
+    Y = torch.tensor(np.stack([sm[2] for sm in sims], axis=1), dtype=torch.float32, device=dev).contiguous()
+    f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N] * GRID_SEQS, [M] * GRID_SEQS,
+                   seed=FILTER_SEED, device=dev)
+    f.set_companions(K)
+    f.run(Y, trace=False, use_graph=True)
+    f.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.run(Y, trace=False, use_graph=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    f.close()
+    return {"N": N, "M": M, "K": K, "filters": GRID_SEQS, "T": TD_T, "ms_per_step": round(dt * 1e3 / TD_T, 4),
+            "updates_per_s": N * M * GRID_SEQS * TD_T / dt}
+
+
 def run_table1_grid(S, dpf, torch, np, dev, ref):
     """Section 4.1's study on the models of Table 1: RMSE of x_hat and z_hat
     and the fraction of diverged runs against (N, M) for the look-ahead step
@@ -758,6 +785,13 @@ def run_table1_grid(S, dpf, torch, np, dev, ref):
                         zt = torch.stack(zs)
                         arms["lookahead"] = (torch.stack(xs), zt)
                         arms["lookahead_rb"] = (torch.stack(rs), zt)
+                    # the arm's own time: a second run of the handle, graph-replayed
+                    f.reset()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    f.run(Y, trace=False, use_graph=True)
+                    torch.cuda.synchronize()
+                    ms = (time.perf_counter() - t0) * 1e3 / TD_T
                     f.close()
                     for arm, (xt, zt) in arms.items():
                         xt, zt = xt.cpu().numpy(), zt.cpu().numpy()
@@ -767,12 +801,14 @@ def run_table1_grid(S, dpf, torch, np, dev, ref):
                         ok = ~div
                         row[arm] = {"rmse_x": round(float(np.sqrt(np.mean(ex[ok] ** 2))), 4) if ok.any() else None,
                                     "rmse_z": round(float(np.sqrt(np.mean(ez[ok] ** 2))), 4) if ok.any() else None,
-                                    "diverged": round(float(div.mean()), 4)}
+                                    "diverged": round(float(div.mean()), 4), "ms_per_step": round(ms, 4)}
                 rows.append(row)
         out[key] = {"divergence_limit_rmse_x": round(lim, 4), "points": rows}
     out["config"] = {"workload": "models 1 and 2 of Table 1, %d fresh sequences x T=%d per point as filters of "
                                  "one handle, N in %s, M in %s" % (GRID_SEQS, TD_T, list(GRID_N), list(GRID_M)),
                      "rmse": "over the sequences that did not diverge",
+                     "ms_per_step": "graph-replayed run of the %d filters (the Rao-Blackwellised arm is its "
+                                    "look-ahead arm's estimate, same run)" % GRID_SEQS,
                      "arms": "lookahead (one companion per candidate, paired), lookahead_rb (its "
                              "Rao-Blackwellised x estimate), lookahead_K<k> (nested estimator, k companions per "
                              "candidate), plain"}
