@@ -819,14 +819,24 @@ def run_highdim(S, dpf, torch, np, dev):
     """The high-dimensional inner block (dx=4, dz=64, dy=32; banded A,
     B sin(x), 32x64 projection, Gaussian / Student-t(3) outlier mixture
     likelihood), N=16384 x M=1024 (16.8M inner particles, 4.3 GB per state
-    copy), one look-ahead run of HD_T steps, graph-replayed, timed after one
-    untimed run."""
+    copy), one look-ahead run of HD_T steps, graph-replayed, timed after an
+    untimed run that records the estimates (RMSE against the simulated truth)
+    and an untimed run of the timed run's own graph."""
     spec = S.highdim_c4(PARAM_SEED)
-    _, _, ys = S.simulate(spec, HD_T, HD_SEED)
+    xs, zs, ys = S.simulate(spec, HD_T, HD_SEED)
     Y = torch.tensor(ys, dtype=torch.float32, device=dev).reshape(HD_T, 1, spec.dy).contiguous()
     f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [HD_N], [HD_M], seed=FILTER_SEED,
                    device=dev)
-    f.run(Y, trace=False, use_graph=True)
+    # untimed run with the estimates: RMSE of x and z against the simulated truth
+    xt, zt = f.run(Y, trace=True, use_graph=True)
+    torch.cuda.synchronize()
+    ex = xt[:, 0].cpu().numpy().astype(np.float64) - np.asarray(xs[1:HD_T + 1])
+    ez = zt[:, 0].cpu().numpy().astype(np.float64) - np.asarray(zs[1:HD_T + 1])
+    rmse = {"x": round(float(np.sqrt(np.mean(np.sum(ex ** 2, axis=1)))), 4),
+            "z": round(float(np.sqrt(np.mean(np.sum(ez ** 2, axis=1)))), 4),
+            "rule": "root of the mean over the %d steps of the squared Euclidean error of x_hat (z_hat)" % HD_T}
+    f.reset()
+    f.run(Y, trace=False, use_graph=True)  # the timed run's own graph, captured untimed
     f.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -839,7 +849,7 @@ def run_highdim(S, dpf, torch, np, dev):
     # each), lam, the parent's ell and the next ell (4 each)
     bytes_step = updates * (8 * spec.dz + 16)
     f.close()
-    return {"value": updates * HD_T / dt, "unit": UNIT, "ms_per_step": round(ms, 4), "steps": HD_T,
+    return {"value": updates * HD_T / dt, "unit": UNIT, "ms_per_step": round(ms, 4), "steps": HD_T, "rmse": rmse,
             "config": {"workload": "look-ahead DPF, high-dimensional inner block dx=4 dz=64 dy=32 "
                                    "(Student-t outlier mixture), N=16384 outer x M=1024 inner",
                        "execution": "dpf_run, graph replays"},

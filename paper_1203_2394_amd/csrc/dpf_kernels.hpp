@@ -51,6 +51,14 @@ constexpr bool has_moments() { return Mdl::DX + Mdl::DY + 2 * Mdl::DZ <= kFeatMa
 template <class Mdl>
 constexpr bool has_yhat() { return Mdl::DY == 1; }
 
+// Number of z-free terms of log p(x' | x, z) (px_pre); 1 for models whose
+// transition of x ignores z (unused there).
+template <class Mdl>
+constexpr int npx() {
+  if constexpr (Mdl::kXdepZ) return Mdl::NPX;
+  else return 1;
+}
+
 // Per-filter bookkeeping for the resampling groups.
 struct FilterInfo {
   int rg_base;  // first resampling group of the filter
@@ -170,7 +178,7 @@ __device__ __forceinline__ bool ident_slots(unsigned char c, int copy) { return 
 // wave, lane permutes when two segments share a wave) instead of every lane
 // evaluating all of them.
 template <class Mdl, int SEG>
-__device__ __forceinline__ void fz_pre_seg(const float* P, const float* xp, const float* xn, int ts, float* pre) {
+__device__ __forceinline__ void fz_pre_seg(Prm P, const float* xp, const float* xn, int ts, float* pre) {
   constexpr int DZ = Mdl::DZ;
   constexpr int W = SEG < 64 ? SEG : 64;
   if constexpr (DZ > W || Mdl::NPRE != DZ) {
@@ -340,17 +348,37 @@ __device__ __forceinline__ float la_logpy(const StepArgs& a, const Key& key, int
     asm volatile("" : "+v"(z[d]));
   }
 #pragma unroll
-  for (int d = 0; d < Mdl::DY; ++d) {
-    y[d] = yi[d];
-    asm volatile("" : "+v"(y[d]));
+  for (int d = 0; d < Mdl::DY; ++d) y[d] = yi[d];
+  if constexpr (Mdl::kStreamZ) {
+    // wide z: the candidate's z component by component, each folded into
+    // the residual at once (same arithmetic as fz_post then logpy_post)
+    static_assert(!H && Mdl::DZ % 4 == 0, "streamed look-ahead draw: DZ a multiple of 4, no predicted observation");
+    float nu_x[Mdl::DX], xl[Mdl::DX], c[Mdl::NPL], e[Mdl::DY];
+    normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
+    Mdl::fx(as_prm(a.prm), x, z, nu_x, t - 1, xl);
+    Mdl::fz_lite(as_prm(a.prm), x, xl, t - 1, c);
+    Mdl::obs_pre(as_prm(a.prm), y, xl, e);
+#pragma unroll
+    for (int g = 0; g < Mdl::DZ / 4; ++g) {
+      float nu4[4];
+      normals_k<4>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, g, nu4);
+      const Prm P = as_prm(a.prm);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = 4 * g + q;
+        const float zk = Mdl::fz_post_k(P, Mdl::fz_pre_lite(P, c, kk), z, nu4[q], kk);
+        Mdl::proj_add(P, e, zk, kk);
+      }
+    }
+    return Mdl::logpy_e(as_prm(a.prm), e);
   }
   float nu_x[Mdl::DX], nu_z[Mdl::DZ], xl[Mdl::DX], pre[Mdl::NPRE], zl[Mdl::DZ], r0[Mdl::DY];
   normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
   normals<Mdl::DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, nu_z);
-  Mdl::fx(a.prm, x, z, nu_x, t - 1, xl);
-  Mdl::fz_pre(a.prm, x, xl, t - 1, pre);
-  Mdl::fz_post(a.prm, pre, z, nu_z, zl);
-  Mdl::obs_pre(a.prm, y, xl, r0);
+  Mdl::fx(as_prm(a.prm), x, z, nu_x, t - 1, xl);
+  Mdl::fz_pre(as_prm(a.prm), x, xl, t - 1, pre);
+  Mdl::fz_post(as_prm(a.prm), pre, z, nu_z, zl);
+  Mdl::obs_pre(as_prm(a.prm), y, xl, r0);
   if constexpr (H) {
     // the noise-free observation of the draw, on opaque copies (no sharing
     // with the likelihood's arithmetic)
@@ -365,9 +393,9 @@ __device__ __forceinline__ float la_logpy(const StepArgs& a, const Key& key, int
       zh[d] = zl[d];
       asm volatile("" : "+v"(zh[d]));
     }
-    Mdl::obs_mean(a.prm, xh, zh, hout);
+    Mdl::obs_mean(as_prm(a.prm), xh, zh, hout);
   }
-  return Mdl::logpy_post(a.prm, r0, zl);
+  return Mdl::logpy_post(as_prm(a.prm), r0, zl);
 }
 
 // lam + g as a separate rounding: g is opaque to the compiler, so no
@@ -462,8 +490,8 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
   constexpr bool kCond = Mdl::kXdepZ;
   constexpr bool kHoldZ = kCond && JPT * DZ <= 64;  // the lane's cloud stays in registers
   __shared__ SegScratch sh;
-  __shared__ double cdf[NSEG][CAP];
-  __shared__ float xs[NSEG][kCond ? CAP : 1][DX];
+  __shared__ double cdf[NSEG][kCond ? 1 : CAP];
+  __shared__ float cz[NSEG][kCond ? CAP : 1][DZ];
   __shared__ float lms[NSEG][kCond ? CAP : 1];
   constexpr bool kH = has_yhat<Mdl>();
   const int4 tile = a.tiles[ti];
@@ -516,12 +544,8 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
       }
       lamv[r] = lrow[j];
       normals<DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu);
-      Mdl::fx(a.prm, x, z, nu, t - 1, xl[r]);
-      if constexpr (kCond) {
-#pragma unroll
-        for (int d = 0; d < DX; ++d) xs[s][kCond ? j : 0][d] = xl[r][d];
-        lms[s][kCond ? j : 0] = lamv[r];
-      }
+      Mdl::fx(as_prm(a.prm), x, z, nu, t - 1, xl[r]);
+      if constexpr (kCond) lms[s][kCond ? j : 0] = lamv[r];
     }
   }
   // predicted observation: sum over the lane's candidates of qbar times the
@@ -559,8 +583,8 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
       const int j = ls + r * SEG;
       if (vi && j < M) {
         float pre[Mdl::NPRE], r0[DY];
-        Mdl::fz_pre(a.prm, x, xl[r], t - 1, pre);
-        Mdl::obs_pre(a.prm, y, xl[r], r0);
+        Mdl::fz_pre(as_prm(a.prm), x, xl[r], t - 1, pre);
+        Mdl::obs_pre(as_prm(a.prm), y, xl[r], r0);
         const double u = uniform53_ab(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_B);
         Lse acck;
         float hk = 0.f;
@@ -570,12 +594,12 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
 #pragma unroll
           for (int d = 0; d < DZ; ++d) zg[d] = zrow[d * M + b];
           normals_k<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, k, nu);
-          Mdl::fz_post(a.prm, pre, zg, nu, zc);
-          acck.add(Mdl::logpy_post(a.prm, r0, zc));
+          Mdl::fz_post(as_prm(a.prm), pre, zg, nu, zc);
+          acck.add(Mdl::logpy_post(as_prm(a.prm), r0, zc));
           if constexpr (kH) {
             if (want_h) {
               float h[1];
-              Mdl::obs_mean(a.prm, xl[r], zc, h);
+              Mdl::obs_mean(as_prm(a.prm), xl[r], zc, h);
               hk += h[0];
             }
           }
@@ -586,71 +610,93 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
       }
     }
   } else {
-    // ---- candidates in order, each with its own conditioned weights
-    seg_lds_sync<SEG>();
-    for (int m = 0; m < M; ++m) {
-      float xm[DX];
+    // ---- each lane scores its own candidates.  Per candidate, three passes
+    // over the segment's cloud (staged in LDS, read by every lane at the same
+    // index): the largest conditioned log-weight, the FP64 total, then the
+    // cumulative sum in inner order up to each systematic point (companion k
+    // takes the first index whose cumulative weight exceeds point k; points
+    // at or past the total take the last index with positive weight).
 #pragma unroll
-      for (int d = 0; d < DX; ++d) xm[d] = xs[s][m][d];
-      float kv[JPT];
-      float mloc = -INFINITY;
+    for (int r = 0; r < JPT; ++r) {
+      const int j = ls + r * SEG;
+      if (j < M) {
+#pragma unroll
+        for (int d = 0; d < DZ; ++d)
+          cz[s][kCond ? j : 0][d] = vi ? (kHoldZ ? zh[kHoldZ ? r : 0][kHoldZ ? d : 0] : zrow[d * M + j]) : 0.f;
+      }
+    }
+    seg_lds_sync<SEG>();
+    if (vi) {
 #pragma unroll
       for (int r = 0; r < JPT; ++r) {
         const int j = ls + r * SEG;
-        kv[r] = -INFINITY;
-        if (vi && j < M && finitef(lamv[r])) {
+        if (j >= M) continue;
+        // conditioned log-weight of inner particle jj given this candidate
+        float cpx[Mdl::NPX];
+        Mdl::px_pre(as_prm(a.prm), xl[r], x, t - 1, cpx);
+        auto kappa = [&](int jj) {
           float zj[DZ];
 #pragma unroll
-          for (int d = 0; d < DZ; ++d) zj[d] = kHoldZ ? zh[kHoldZ ? r : 0][kHoldZ ? d : 0] : zrow[d * M + j];
-          kv[r] = lamv[r] + Mdl::logpx(a.prm, xm, x, zj, t - 1);
-          if (finitef(kv[r])) mloc = fmaxf(mloc, kv[r]);
+          for (int d = 0; d < DZ; ++d) zj[d] = cz[s][kCond ? jj : 0][d];
+          float kp = lms[s][kCond ? jj : 0] + Mdl::logpx_post(as_prm(a.prm), cpx, zj);
+          asm volatile("" : "+v"(kp));
+          return kp;
+        };
+        float mx = -INFINITY;
+        for (int jj = 0; jj < M; ++jj) {
+          const float kp = kappa(jj);
+          if (finitef(kp)) mx = fmaxf(mx, kp);
         }
-      }
-      const float m2 = seg_max<SEG>(mloc, sh);
-      const bool deg = !(m2 > -INFINITY);
-      double carry = 0.0;
-#pragma unroll
-      for (int r = 0; r < JPT; ++r) {
-        const int j = ls + r * SEG;
-        double w = 0.0;
-        if (j < M) w = deg ? 1.0 : (finitef(kv[r]) ? (double)fast_exp(kv[r] - m2) : 0.0);
-        double tot;
-        const double c = seg_scan_incl<SEG>(w, sh, tot);
-        cdf[s][r * SEG + ls] = carry + c;
-        carry += tot;
-      }
-      seg_lds_sync<SEG>();
-      Lse acck;
-      if (vi) {
-        const double total = cdf[s][M - 1];
-        const double u = uniform53_ab(key, (uint32_t)t, (uint32_t)i, (uint32_t)m, P_LA_B);
+        const bool deg = !(mx > -INFINITY);
+        auto weight = [&](int jj) -> double {
+          const float kp = kappa(jj);
+          return deg ? 1.0 : (finitef(kp) ? (double)fast_exp(kp - mx) : 0.0);
+        };
+        double total = 0.0;
+        int lastpos = 0;
+        for (int jj = 0; jj < M; ++jj) {
+          const double w = weight(jj);
+          total += w;
+          if (w > 0.0) lastpos = jj;
+        }
+        const double u = uniform53_ab(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_B);
         float pre[Mdl::NPRE], r0[DY];
-        Mdl::fz_pre(a.prm, x, xm, t - 1, pre);
-        Mdl::obs_pre(a.prm, y, xm, r0);
-        const float wm = want_h ? fast_exp(lms[s][kCond ? m : 0]) * invK : 0.f;
-        for (int k = ls; k < K; k += SEG) {
-          const int b = cdf_search(cdf[s], M, sys_point(k, u, total, K));
+        Mdl::fz_pre(as_prm(a.prm), x, xl[r], t - 1, pre);
+        Mdl::obs_pre(as_prm(a.prm), y, xl[r], r0);
+        Lse acck;
+        float hk = 0.f;
+        auto emit = [&](int b, int k) {
           float zg[DZ], nu[DZ], zc[DZ];
 #pragma unroll
-          for (int d = 0; d < DZ; ++d) zg[d] = zrow[d * M + b];
-          normals_k<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)m, P_LA_Z, k, nu);
-          Mdl::fz_post(a.prm, pre, zg, nu, zc);
-          acck.add(Mdl::logpy_post(a.prm, r0, zc));
+          for (int d = 0; d < DZ; ++d) zg[d] = cz[s][kCond ? b : 0][d];
+          normals_k<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, k, nu);
+          Mdl::fz_post(as_prm(a.prm), pre, zg, nu, zc);
+          acck.add(Mdl::logpy_post(as_prm(a.prm), r0, zc));
           if constexpr (kH) {
             if (want_h) {
               float h[1];
-              Mdl::obs_mean(a.prm, xm, zc, h);
-              hv += wm * h[0];
+              Mdl::obs_mean(as_prm(a.prm), xl[r], zc, h);
+              hk += h[0];
             }
           }
+        };
+        // companion k: a cursor over the cumulative sum advances to the
+        // first index whose sum exceeds point k (the points increase), then
+        // every lane propagates its companion k together
+        int jc = -1;
+        double c = 0.0;
+        for (int k = 0; k < K; ++k) {
+          const double P = sys_point(k, u, total, K);
+          while (!(c > P) && jc + 1 < M) {
+            ++jc;
+            c += weight(jc);
+          }
+          emit(c > P ? jc : lastpos, k);
         }
+        const float g = (acck.m == -INFINITY) ? -INFINITY : acck.m + fast_log(acck.s) - logK;
+        ev[r] = la_ell(lamv[r], g);
+        if (want_h) hv += fast_exp(lamv[r]) * (hk * invK);
       }
-      const float lse = seg_lse<SEG>(acck, sh);
-      // the lane holding candidate m keeps its score
-#pragma unroll
-      for (int r = 0; r < JPT; ++r)
-        if (vi && m == ls + r * SEG) ev[r] = la_ell(lamv[r], lse == -INFINITY ? -INFINITY : lse - logK);
-      seg_lds_sync<SEG>();
     }
   }
   Lse acc;
@@ -755,7 +801,7 @@ static __global__ __launch_bounds__(kBlock) void k_dpf_weights(StepArgs a) {
   load_y<Mdl>(a, f, t, y);
 #pragma unroll
   for (int d = 0; d < Mdl::DX; ++d) x[d] = vi ? a.x[src][(long long)d * a.NT + oo + i] : 0.f;
-  Mdl::obs_pre(a.prm, y, x, r0);
+  Mdl::obs_pre(as_prm(a.prm), y, x, r0);
   const float* zrow = a.z[src] + (io + (long long)(vi ? i : 0) * M) * Mdl::DZ;
   float* erow = a.ell + io + (long long)(vi ? i : 0) * M;
   float ev[JPT];
@@ -768,7 +814,7 @@ static __global__ __launch_bounds__(kBlock) void k_dpf_weights(StepArgs a) {
       float z[Mdl::DZ];
 #pragma unroll
       for (int d = 0; d < Mdl::DZ; ++d) z[d] = zrow[d * M + j];
-      ev[r] = Mdl::logpy_post(a.prm, r0, z);
+      ev[r] = Mdl::logpy_post(as_prm(a.prm), r0, z);
       erow[j] = ev[r];
       acc.add(ev[r]);
     }
@@ -1518,8 +1564,14 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
   constexpr int DX = Mdl::DX, DZ = Mdl::DZ, DY = Mdl::DY;
   constexpr int NSEG = kBlock / SEG;
   constexpr bool kKeepZ = JPT * DZ <= 64;  // new z stays in registers for the partial sums
+  // Wide z: the propagation takes one inner particle at a time (its gathered,
+  // noise and new z arrays alone fill most of the registers), passing each
+  // one's likelihoods to the later loops through LDS.
+  constexpr bool kRoll = DZ >= 32 && JPT > 1;
+  constexpr bool kStream = Mdl::kStreamZ;
   __shared__ SegScratch sh;
   __shared__ double cdf[NSEG][SEG * JPT];
+  __shared__ float roll_sh[kRoll ? 2 * JPT : 1][kRoll ? kBlock : 1];
   __shared__ float xs_sh[NSEG][DX];
   __shared__ int csel[NSEG];
   __shared__ float vred[kBlock / kWave][2 * DZ];
@@ -1566,12 +1618,15 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
   // the segment's other waves draw theirs meanwhile.
   constexpr bool kWaveDraw = SEG >= kWave;
   constexpr bool kEarly = SEG > kWave && JPT * DZ <= 16;
+  static_assert(!(kEarly && kStream), "a streamed model draws its noise in the propagation");
   float nue[kEarly ? JPT : 1][DZ];
   // One wave per outer particle: the parent's kappa inputs (lam, or ell in
   // plain mode, and z when p(x'|x, z) depends on z) are fetched together
   // with its ell row for the candidate draw, in the same memory round.
   constexpr bool kPre = SEG == kWave;
   constexpr bool kPreZ = kPre && Mdl::kXdepZ;
+  constexpr bool kXZ = Mdl::kXdepZ;
+  constexpr int NPX = npx<Mdl>();
   float kpre[kPre ? JPT : 1];
   float zpre[kPreZ ? JPT : 1][kPreZ ? DZ : 1];
 #pragma unroll
@@ -1657,7 +1712,7 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
         normals<DX>(key, (uint32_t)t, (uint32_t)k, 0u, P_DPF_X, nu);
       else
         normals<DX>(key, (uint32_t)t, (uint32_t)pw, (uint32_t)cw, P_LA_X, nu);
-      Mdl::fx(a.prm, xpw, zc, nu, PLAIN ? t : t - 1, xw);
+      Mdl::fx(as_prm(a.prm), xpw, zc, nu, PLAIN ? t : t - 1, xw);
       if (ls == 0) {
         if (!a.anc_ready) a.anc[oo + k] = pw;
         a.sel[oo + k] = cw;
@@ -1764,7 +1819,7 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
     else
       normals<DX>(key, (uint32_t)t, (uint32_t)p, (uint32_t)c, P_LA_X, nu);
     float xw[DX];
-    Mdl::fx(a.prm, xp, zc, nu, PLAIN ? t : t - 1, xw);
+    Mdl::fx(as_prm(a.prm), xp, zc, nu, PLAIN ? t : t - 1, xw);
 #pragma unroll
     for (int d = 0; d < DX; ++d) xs_sh[s][d] = xw[d];
     if (vk) {
@@ -1789,16 +1844,18 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
   const float* lp = a.lam[src] + io + (long long)pc * M;
   float ev[JPT];
   float mk = -INFINITY;
+  float cpx[kXZ ? NPX : 1];
+  if constexpr (kXZ) Mdl::px_pre(as_prm(a.prm), xn, xp, PLAIN ? t : t - 1, cpx);
 #pragma unroll
   for (int r = 0; r < JPT; ++r) {
     const int j = ls + r * SEG;
     if (vk && j < M) {
       float kap = kPre ? kpre[kPre ? r : 0] : (PLAIN ? ep[j] : lp[j]);
-      if (Mdl::kXdepZ) {
+      if constexpr (kXZ) {
         float zj[DZ];
 #pragma unroll
         for (int d = 0; d < DZ; ++d) zj[d] = kPreZ ? zpre[kPreZ ? r : 0][kPreZ ? d : 0] : zp[d * M + j];
-        kap += Mdl::logpx(a.prm, xn, xp, zj, PLAIN ? t : t - 1);
+        kap += Mdl::logpx_post(as_prm(a.prm), cpx, zj);
       }
       ev[r] = kap;
       if (finitef(kap)) mk = fmaxf(mk, kap);
@@ -1826,11 +1883,11 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
   // ---- 4. gather + propagate (+ measurement update in look-ahead mode) ---
   float pre[Mdl::NPRE];
   // (plain: t is the step just taken and the proposal is for t + 1)
-  fz_pre_seg<Mdl, SEG>(a.prm, xp, xn, PLAIN ? t : t - 1, pre);
+  fz_pre_seg<Mdl, SEG>(as_prm(a.prm), xp, xn, PLAIN ? t : t - 1, pre);
   float y[DY], r0[DY];
   if (!PLAIN) {
     load_y<Mdl>(a, f, t, y);
-    Mdl::obs_pre(a.prm, y, xn, r0);
+    Mdl::obs_pre(as_prm(a.prm), y, xn, r0);
   }
   float* zdst = a.z[dst] + (io + (long long)k * M) * DZ;
   float llv[JPT], gn[JPT];
@@ -1840,41 +1897,78 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
   const bool want_h = kH && fuse && a.yp_next != nullptr;
   float hn[kH ? JPT : 1];
   Lse acc;
-#pragma unroll
+#pragma unroll(kRoll ? 1 : JPT)
   for (int r = 0; r < JPT; ++r) {
     const int jj = ls + r * SEG;
-    llv[r] = -INFINITY;
+    float lv = -INFINITY, gv = 0.f;
     if (vk && jj < M) {
       const int b = cdf_search(cdf[s], M, sys_point(jj, u_in, tot2, M));
-      float zg[DZ], nu[DZ], zn[DZ];
+      float zg[DZ], zn[DZ];
 #pragma unroll
       for (int d = 0; d < DZ; ++d) zg[d] = zp[d * M + b];
-      if constexpr (kEarly) {
+      if constexpr (kStream) {
+        // component by component: new z, its store, its residual term
+        float e[DY];
 #pragma unroll
-        for (int d = 0; d < DZ; ++d) nu[d] = nue[kEarly ? r : 0][d];
+        for (int d = 0; d < DY; ++d) e[d] = PLAIN ? 0.f : r0[d];
+#pragma unroll
+        for (int g = 0; g < DZ / 4; ++g) {
+          float nu4[4];
+          normals_k<4>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, g, nu4);
+          const Prm P = as_prm(a.prm);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int d = 4 * g + q;
+            zn[d] = Mdl::fz_post_k(P, pre[d], zg, nu4[q], d);
+            zdst[d * M + jj] = zn[d];
+            if (!PLAIN) Mdl::proj_add(P, e, zn[d], d);
+          }
+        }
+        if (!PLAIN) lv = Mdl::logpy_e(as_prm(a.prm), e);
       } else {
-        normals<DZ>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, nu);
-      }
-      Mdl::fz_post(a.prm, pre, zg, nu, zn);
+        float nu[DZ];
+        if constexpr (kEarly) {
 #pragma unroll
-      for (int d = 0; d < DZ; ++d) zdst[d * M + jj] = zn[d];
+          for (int d = 0; d < DZ; ++d) nu[d] = nue[kEarly ? r : 0][d];
+        } else {
+          normals<DZ>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, nu);
+        }
+        Mdl::fz_post(as_prm(a.prm), pre, zg, nu, zn);
+#pragma unroll
+        for (int d = 0; d < DZ; ++d) zdst[d * M + jj] = zn[d];
+        if (!PLAIN) lv = Mdl::logpy_post(as_prm(a.prm), r0, zn);
+      }
       if constexpr (kKeepZ) {
 #pragma unroll
         for (int d = 0; d < DZ; ++d) zkeep[kKeepZ ? r : 0][d] = zn[d];
       }
       if (!PLAIN) {
-        llv[r] = Mdl::logpy_post(a.prm, r0, zn);
-        acc.add(llv[r]);
+        acc.add(lv);
         // the next step's look-ahead likelihood of this new inner particle
         // (ALU work that overlaps the gathers of the others)
         if (want_h) {
           float h[1];
-          gn[r] = la_logpy<Mdl, kH>(a, key, t + 1, k, jj, xn, zn, yn, h);
+          gv = la_logpy<Mdl, kH>(a, key, t + 1, k, jj, xn, zn, yn, h);
           hn[kH ? r : 0] = h[0];
         } else if (fuse) {
-          gn[r] = la_logpy<Mdl>(a, key, t + 1, k, jj, xn, zn, yn);
+          gv = la_logpy<Mdl>(a, key, t + 1, k, jj, xn, zn, yn);
         }
       }
+    }
+    if constexpr (kRoll) {
+      roll_sh[2 * r][threadIdx.x] = lv;
+      roll_sh[2 * r + 1][threadIdx.x] = gv;
+    } else {
+      llv[r] = lv;
+      gn[r] = gv;
+    }
+  }
+  if constexpr (kRoll) {
+    // (each thread reads back its own slots)
+#pragma unroll
+    for (int r = 0; r < JPT; ++r) {
+      llv[r] = roll_sh[2 * r][threadIdx.x];
+      gn[r] = roll_sh[2 * r + 1][threadIdx.x];
     }
   }
   uint32_t fl = (deg1 || deg2) ? (uint32_t)F_DEGENERATE_INNER : 0u;

@@ -236,7 +236,9 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
   float zd[DZ];
 #pragma unroll
   for (int d = 0; d < DZ; ++d) zd[d] = 0.f;
-  const float lpx0 = Mdl::kXdepZ ? 0.f : Mdl::logpx(a.prm, xn, xp, zd, t - 1);
+  const float lpx0 = Mdl::kXdepZ ? 0.f : Mdl::logpx(as_prm(a.prm), xn, xp, zd, t - 1);
+  float cpx[npx<Mdl>()];
+  if constexpr (Mdl::kXdepZ) Mdl::px_pre(as_prm(a.prm), xn, xp, t - 1, cpx);
   float ev[JPT];
   float mk = -INFINITY;
 #pragma unroll
@@ -245,11 +247,11 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
     ev[r] = -INFINITY;
     if (vi && j < M) {
       float kap = lp[j];
-      if (Mdl::kXdepZ) {
+      if constexpr (Mdl::kXdepZ) {
         float zj[DZ];
 #pragma unroll
         for (int d = 0; d < DZ; ++d) zj[d] = zp[d * M + j];
-        kap += Mdl::logpx(a.prm, xn, xp, zj, t - 1);
+        kap += Mdl::logpx_post(as_prm(a.prm), cpx, zj);
       } else {
         kap += lpx0;
       }
@@ -277,10 +279,10 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
 
   // ---- 3. local resampling, propagation, measurement update --------------
   float pre[Mdl::NPRE];
-  fz_pre_seg<Mdl, SEG>(a.prm, xp, xn, t - 1, pre);
+  fz_pre_seg<Mdl, SEG>(as_prm(a.prm), xp, xn, t - 1, pre);
   float y[DY], r0[DY];
   load_y<Mdl>(a, f, t, y);
-  Mdl::obs_pre(a.prm, y, xn, r0);
+  Mdl::obs_pre(as_prm(a.prm), y, xn, r0);
   float* zdst = a.z[dst] + (io + (long long)i * M) * DZ;
   float llv[JPT];
   float zkeep[kKeepZ ? JPT : 1][DZ];
@@ -295,14 +297,14 @@ __global__ __launch_bounds__(kBlock) void k_learned_inner(StepArgs a) {
 #pragma unroll
       for (int d = 0; d < DZ; ++d) zg[d] = zp[d * M + b];
       normals<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)jj, P_NEW_Z, nu);
-      Mdl::fz_post(a.prm, pre, zg, nu, zn);
+      Mdl::fz_post(as_prm(a.prm), pre, zg, nu, zn);
 #pragma unroll
       for (int d = 0; d < DZ; ++d) zdst[d * M + jj] = zn[d];
       if constexpr (kKeepZ) {
 #pragma unroll
         for (int d = 0; d < DZ; ++d) zkeep[kKeepZ ? r : 0][d] = zn[d];
       }
-      llv[r] = Mdl::logpy_post(a.prm, r0, zn);
+      llv[r] = Mdl::logpy_post(as_prm(a.prm), r0, zn);
       acc.add(llv[r]);
     }
   }

@@ -12,6 +12,10 @@
 //   obs_pre(P, y, x, r0)          the part of y - h(x, z) that depends only on x
 //   logpy_post(P, r0, z)          log p(y_t | x_t, z_t)
 //   logpx(P, xn, x, z, t)         log p(x_{t+1} | x_t, z_t)
+//   px_pre(P, xn, x, t, c)        models whose logpx depends on z (kXdepZ): the
+//                                 part that does not, NPX values, so that
+//   logpx_post(P, c, z)           gives logpx for many z at the cost of the
+//                                 z-dependent terms alone
 //   obs_mean(P, x, z, h)          the noise-free observation h(x, z) (models with
 //                                 a one-dimensional y: the predicted observation)
 //
@@ -22,7 +26,19 @@
 // not, the x-conditioning factor of eq:qnobar is constant over the inner
 // cloud and the kernels skip it.
 //
-// Parameters live in one float array in device memory: the raw parameter
+// kStreamZ models (a wide z) also give f^z and log p(y | x, z) one z
+// component at a time, so that a kernel can form z_{t+1} component by
+// component and fold each into the likelihood without holding the whole
+// new vector:
+//   fz_lite(P, x, xn, t, c)       a compact form of fz_pre (NPL values)
+//   fz_pre_lite(P, c, k)          pre[k] from it
+//   fz_post_k(P, prek, z, nuk, k) component k of fz_post
+//   proj_add(P, e, zk, k)         e -= (column k of the observation matrix) zk
+//   logpy_e(P, e)                 log p(y | z) from e = r0 - C z
+// fz_pre, fz_post and logpy_post are these composed, with the same
+// arithmetic in the same order.
+//
+// Parameters live in one float array in device memory (read through Prm): the raw parameter
 // values in the interface's blob order, followed by constants the host
 // derives from them in double precision (square roots, reciprocals, log
 // normalisers) at fixed offsets given by each model's `Layout`.
@@ -35,6 +51,12 @@ namespace dpf {
 constexpr float kLn2Pi = 1.8378770664093453f;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kInv2Pi = 0.15915494309189535f;
+
+// Model parameters are read-only for a whole launch.  Reading them through
+// the constant address space lets the compiler use scalar loads for them
+// (they are uniform) even after the kernel's own global stores.
+using Prm = const __attribute__((address_space(4))) float*;
+__device__ __forceinline__ Prm as_prm(const float* p) { return (Prm)p; }
 
 __device__ __forceinline__ float fast_exp(float v) { return __builtin_amdgcn_exp2f(v * kLog2e); }
 __device__ __forceinline__ float fast_log(float v) { return __builtin_amdgcn_logf(v) * 0.6931471805599453f; }
@@ -53,6 +75,7 @@ template <int DX_, int DZ_, int DY_>
 struct LinGauss {
   static constexpr int DX = DX_, DZ = DZ_, DY = DY_, NPRE = DZ_;
   static constexpr bool kXdepZ = true;
+  static constexpr bool kStreamZ = false;
   struct Layout {
     static constexpr int Ax = 0, Cxz = Ax + DX * DX, qx = Cxz + DX * DZ, Az = qx + 1,
                          Bzx = Az + DZ * DZ, qz = Bzx + DZ * DX, Hx = qz + 1, Hz = Hx + DY * DX,
@@ -63,7 +86,7 @@ struct LinGauss {
   };
   using L = Layout;
 
-  __device__ static void fx(const float* P, const float* x, const float* z, const float* nu, int,
+  __device__ static void fx(Prm P, const float* x, const float* z, const float* nu, int,
                             float* xn) {
 #pragma unroll
     for (int a = 0; a < DX; ++a) {
@@ -75,17 +98,17 @@ struct LinGauss {
       xn[a] = s + P[L::sx] * nu[a];
     }
   }
-  __device__ static void fz_pre(const float* P, const float* x, const float* xn, int t, float* pre) {
+  __device__ static void fz_pre(Prm P, const float* x, const float* xn, int t, float* pre) {
 #pragma unroll
     for (int a = 0; a < DZ; ++a) pre[a] = fz_pre_k(P, x, xn, t, a);
   }
-  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int, int a) {
+  __device__ static float fz_pre_k(Prm P, const float*, const float* xn, int, int a) {
     float s = 0.f;
 #pragma unroll
     for (int b = 0; b < DX; ++b) s += P[L::Bzx + a * DX + b] * xn[b];
     return s;
   }
-  __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu,
+  __device__ static void fz_post(Prm P, const float* pre, const float* z, const float* nu,
                                  float* zn) {
 #pragma unroll
     for (int a = 0; a < DZ; ++a) {
@@ -95,7 +118,7 @@ struct LinGauss {
       zn[a] = s + P[L::sz] * nu[a];
     }
   }
-  __device__ static void obs_pre(const float* P, const float* y, const float* x, float* r0) {
+  __device__ static void obs_pre(Prm P, const float* y, const float* x, float* r0) {
 #pragma unroll
     for (int a = 0; a < DY; ++a) {
       float s = y[a];
@@ -104,7 +127,7 @@ struct LinGauss {
       r0[a] = s;
     }
   }
-  __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
+  __device__ static float logpy_post(Prm P, const float* r0, const float* z) {
     float q = 0.f;
 #pragma unroll
     for (int a = 0; a < DY; ++a) {
@@ -116,7 +139,7 @@ struct LinGauss {
     return P[L::cy] - 0.5f * P[L::inv_r] * q;
   }
   // noise-free observation h(x, z) = Hx x + Hz z
-  __device__ static void obs_mean(const float* P, const float* x, const float* z, float* h) {
+  __device__ static void obs_mean(Prm P, const float* x, const float* z, float* h) {
 #pragma unroll
     for (int a = 0; a < DY; ++a) {
       float s = 0.f;
@@ -127,18 +150,32 @@ struct LinGauss {
       h[a] = s;
     }
   }
-  __device__ static float logpx(const float* P, const float* xn, const float* x, const float* z, int) {
-    float q = 0.f;
+  static constexpr int NPX = DX;
+  // x' - Ax x
+  __device__ static void px_pre(Prm P, const float* xn, const float* x, int, float* c) {
 #pragma unroll
     for (int a = 0; a < DX; ++a) {
       float s = xn[a];
 #pragma unroll
       for (int b = 0; b < DX; ++b) s -= P[L::Ax + a * DX + b] * x[b];
+      c[a] = s;
+    }
+  }
+  __device__ static float logpx_post(Prm P, const float* c, const float* z) {
+    float q = 0.f;
+#pragma unroll
+    for (int a = 0; a < DX; ++a) {
+      float s = c[a];
 #pragma unroll
       for (int b = 0; b < DZ; ++b) s -= P[L::Cxz + a * DZ + b] * z[b];
       q += s * s;
     }
     return P[L::cx] - 0.5f * P[L::inv_qx] * q;
+  }
+  __device__ static float logpx(Prm P, const float* xn, const float* x, const float* z, int t) {
+    float c[NPX];
+    px_pre(P, xn, x, t, c);
+    return logpx_post(P, c, z);
   }
 };
 
@@ -155,6 +192,7 @@ template <int DX_, int DZ_>
 struct NonLin {
   static constexpr int DX = DX_, DZ = DZ_, DY = DZ_, NPRE = DZ;
   static constexpr bool kXdepZ = false;
+  static constexpr bool kStreamZ = false;
   struct Layout {
     static constexpr int a = 0, b = 1, qx = 2, W = 3, rho = W + DZ * DX, qz = rho + 1, c = qz + 1,
                          r = c + 1, bmode = r + 1, n_raw = bmode + 1;
@@ -163,29 +201,29 @@ struct NonLin {
   };
   using L = Layout;
 
-  __device__ static void fx(const float* P, const float* x, const float*, const float* nu, int,
+  __device__ static void fx(Prm P, const float* x, const float*, const float* nu, int,
                             float* xn) {
     const float a = P[L::a], b = P[L::b], s = P[L::sx];
 #pragma unroll
     for (int d = 0; d < DX; ++d) xn[d] = growth(a, b, x[d]) + s * nu[d];
   }
-  __device__ static void fz_pre(const float* P, const float* x, const float* xn, int t, float* pre) {
+  __device__ static void fz_pre(Prm P, const float* x, const float* xn, int t, float* pre) {
 #pragma unroll
     for (int k = 0; k < DZ; ++k) pre[k] = fz_pre_k(P, x, xn, t, k);
   }
-  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int, int k) {
+  __device__ static float fz_pre_k(Prm P, const float*, const float* xn, int, int k) {
     float s = 0.f;
 #pragma unroll
     for (int d = 0; d < DX; ++d) s += P[L::W + k * DX + d] * xn[d];
     return tanh_f(s);
   }
-  __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu,
+  __device__ static void fz_post(Prm P, const float* pre, const float* z, const float* nu,
                                  float* zn) {
     const float rho = P[L::rho], s = P[L::sz];
 #pragma unroll
     for (int k = 0; k < DZ; ++k) zn[k] = pre[k] + rho * z[k] + s * nu[k];
   }
-  __device__ static void obs_pre(const float* P, const float* y, const float* x, float* r0) {
+  __device__ static void obs_pre(Prm P, const float* y, const float* x, float* r0) {
     const float c = P[L::c];
     if (P[L::bmode] == 0.0f) {
 #pragma unroll
@@ -198,7 +236,7 @@ struct NonLin {
       for (int k = 0; k < DY; ++k) r0[k] = y[k] - c * q;
     }
   }
-  __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
+  __device__ static float logpy_post(Prm P, const float* r0, const float* z) {
     float q = 0.f;
 #pragma unroll
     for (int k = 0; k < DY; ++k) {
@@ -207,7 +245,7 @@ struct NonLin {
     }
     return P[L::cy] - 0.5f * P[L::inv_r] * q;
   }
-  __device__ static float logpx(const float* P, const float* xn, const float* x, const float*, int) {
+  __device__ static float logpx(Prm P, const float* xn, const float* x, const float*, int) {
     const float a = P[L::a], b = P[L::b];
     float q = 0.f;
 #pragma unroll
@@ -226,6 +264,8 @@ template <int DX_, int DZ_, int DY_>
 struct HighDim {
   static constexpr int DX = DX_, DZ = DZ_, DY = DY_, NPRE = DZ;
   static constexpr bool kXdepZ = false;
+  static constexpr bool kStreamZ = true;
+  static constexpr int NPL = DX;
   struct Layout {
     static constexpr int a = 0, b = 1, qx = 2, Alo = 3, Adg = Alo + DZ - 1, Aup = Adg + DZ,
                          B = Aup + DZ - 1, qz = B + DZ * DX, C = qz + 1, r = C + DY * DZ,
@@ -234,60 +274,69 @@ struct HighDim {
     // mixture: half_inv_r, lg0 = log(1-eps) - 0.5 log(2 pi r),
     //          lt0 = log eps + lgamma((nu+1)/2) - lgamma(nu/2) - 0.5 log(nu pi r),
     //          tnu = (nu+1)/2, inv_nur = 1/(nu r)
+    // Ct: the observation matrix transposed ([DZ][DY]), for proj_add
     static constexpr int sx = n_raw, sz = sx + 1, inv_qx = sz + 1, cx = inv_qx + 1,
                          inv_r = cx + 1, cy = inv_r + 1, lg0 = cy + 1, lt0 = lg0 + 1,
-                         tnu = lt0 + 1, inv_nur = tnu + 1, n_total = inv_nur + 1;
+                         tnu = lt0 + 1, inv_nur = tnu + 1, Ct = inv_nur + 1, n_total = Ct + DZ * DY;
   };
   using L = Layout;
 
-  __device__ static void fx(const float* P, const float* x, const float*, const float* nu, int,
+  __device__ static void fx(Prm P, const float* x, const float*, const float* nu, int,
                             float* xn) {
     const float a = P[L::a], b = P[L::b], s = P[L::sx];
 #pragma unroll
     for (int d = 0; d < DX; ++d) xn[d] = growth(a, b, x[d]) + s * nu[d];
   }
-  __device__ static void fz_pre(const float* P, const float*, const float* xn, int, float* pre) {
-    float sn[DX];
+  // c = sin(x'); pre[k] = (B sin(x'))_k
+  __device__ static void fz_lite(Prm, const float*, const float* xn, int, float* c) {
 #pragma unroll
-    for (int d = 0; d < DX; ++d) sn[d] = __builtin_amdgcn_sinf(xn[d] * kInv2Pi);
-#pragma unroll
-    for (int k = 0; k < DZ; ++k) {
-      float s = 0.f;
-#pragma unroll
-      for (int d = 0; d < DX; ++d) s += P[L::B + k * DX + d] * sn[d];
-      pre[k] = s;
-    }
+    for (int d = 0; d < DX; ++d) c[d] = __builtin_amdgcn_sinf(xn[d] * kInv2Pi);
   }
-  __device__ static float fz_pre_k(const float* P, const float*, const float* xn, int, int k) {
+  __device__ static float fz_pre_lite(Prm P, const float* c, int k) {
     float s = 0.f;
 #pragma unroll
-    for (int d = 0; d < DX; ++d) s += P[L::B + k * DX + d] * __builtin_amdgcn_sinf(xn[d] * kInv2Pi);
+    for (int d = 0; d < DX; ++d) s += P[L::B + k * DX + d] * c[d];
     return s;
   }
-  __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu,
-                                 float* zn) {
-    const float s = P[L::sz];
+  __device__ static void fz_pre(Prm P, const float* x, const float* xn, int t, float* pre) {
+    float c[NPL];
+    fz_lite(P, x, xn, t, c);
 #pragma unroll
-    for (int k = 0; k < DZ; ++k) {
-      float v = pre[k] + P[L::Adg + k] * z[k] + s * nu[k];
-      if (k > 0) v += P[L::Alo + k - 1] * z[k - 1];
-      if (k + 1 < DZ) v += P[L::Aup + k] * z[k + 1];
-      zn[k] = v;
-    }
+    for (int k = 0; k < DZ; ++k) pre[k] = fz_pre_lite(P, c, k);
   }
-  __device__ static void obs_pre(const float*, const float* y, const float*, float* r0) {
+  __device__ static float fz_pre_k(Prm P, const float* x, const float* xn, int t, int k) {
+    float c[NPL];
+    fz_lite(P, x, xn, t, c);
+    return fz_pre_lite(P, c, k);
+  }
+  // component k of A z + pre + sqrt(qz) nu, A tridiagonal
+  __device__ static float fz_post_k(Prm P, float prek, const float* z, float nuk, int k) {
+    float v = prek + P[L::Adg + k] * z[k] + P[L::sz] * nuk;
+    if (k > 0) v += P[L::Alo + k - 1] * z[k - 1];
+    if (k + 1 < DZ) v += P[L::Aup + k] * z[k + 1];
+    return v;
+  }
+  __device__ static void fz_post(Prm P, const float* pre, const float* z, const float* nu,
+                                 float* zn) {
+#pragma unroll
+    for (int k = 0; k < DZ; ++k) zn[k] = fz_post_k(P, pre[k], z, nu[k], k);
+  }
+  __device__ static void obs_pre(Prm, const float* y, const float*, float* r0) {
 #pragma unroll
     for (int k = 0; k < DY; ++k) r0[k] = y[k];
   }
-  __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
+  __device__ static void proj_add(Prm P, float* e, float zk, int k) {
+#pragma unroll
+    for (int a = 0; a < DY; ++a) e[a] -= P[L::Ct + k * DY + a] * zk;
+  }
+  // Gaussian: cy - q / (2 r); mixture: per component log((1 - eps) N(e; 0, r)
+  // + eps t_nu(e; 0, r)) as max + log(1 + exp(-|difference|))
+  __device__ static float logpy_e(Prm P, const float* e) {
     const bool gonly = P[L::gonly] != 0.0f;
     float acc = 0.f, q = 0.f;
-#pragma unroll 4
-    for (int k = 0; k < DY; ++k) {
-      float e = r0[k];
 #pragma unroll
-      for (int d = 0; d < DZ; ++d) e -= P[L::C + k * DZ + d] * z[d];
-      const float e2 = e * e;
+    for (int k = 0; k < DY; ++k) {
+      const float e2 = e[k] * e[k];
       q += e2;
       if (!gonly) {
         const float lg = P[L::lg0] - 0.5f * P[L::inv_r] * e2;
@@ -298,7 +347,20 @@ struct HighDim {
     }
     return gonly ? P[L::cy] - 0.5f * P[L::inv_r] * q : acc;
   }
-  __device__ static float logpx(const float* P, const float* xn, const float* x, const float*, int) {
+  // row by row: e_k = r0_k - sum_d C_kd z_d in order d (the same rounding
+  // sequence as proj_add over d)
+  __device__ static float logpy_post(Prm P, const float* r0, const float* z) {
+    float e[DY];
+#pragma unroll 4
+    for (int k = 0; k < DY; ++k) {
+      float v = r0[k];
+#pragma unroll
+      for (int d = 0; d < DZ; ++d) v -= P[L::C + k * DZ + d] * z[d];
+      e[k] = v;
+    }
+    return logpy_e(P, e);
+  }
+  __device__ static float logpx(Prm P, const float* xn, const float* x, const float*, int) {
     const float a = P[L::a], b = P[L::b];
     float q = 0.f;
 #pragma unroll
@@ -335,6 +397,7 @@ template <bool ZF>
 struct Table1M1 {
   static constexpr int DX = 1, DZ = 1, DY = 1, NPRE = 3;
   static constexpr bool kXdepZ = true;
+  static constexpr bool kStreamZ = false;
   struct Layout {
     static constexpr int qx = 0, qz = 1, cxz = 2, rho = 3, b = 4, amp = 5, freq = 6, r = 7, tswap = 8,
                          n_raw = 9;
@@ -346,18 +409,18 @@ struct Table1M1 {
 
   __device__ static float sat(float v) { return v / (1.0f + v * v); }
   // the angle in double (t runs to thousands of radians)
-  __device__ static float cyc(const float* P, int t) {
+  __device__ static float cyc(Prm P, int t) {
     return (float)((double)P[L::amp] * cos((double)P[L::freq] * (double)t));
   }
   // whether the outer variable follows the slow law at t
-  __device__ static bool outer_slow(const float* P, int t) { return ((float)t >= P[L::tswap]) == ZF; }
-  __device__ static float mean_o(const float* P, float o, float i, int t) {
+  __device__ static bool outer_slow(Prm P, int t) { return ((float)t >= P[L::tswap]) == ZF; }
+  __device__ static float mean_o(Prm P, float o, float i, int t) {
     return outer_slow(P, t) ? o + sat(i) : i + P[L::rho] * o + P[L::b] * sat(o) + cyc(P, t);
   }
-  __device__ static void fx(const float* P, const float* x, const float* z, const float* nu, int t, float* xn) {
+  __device__ static void fx(Prm P, const float* x, const float* z, const float* nu, int t, float* xn) {
     xn[0] = mean_o(P, x[0], z[0], t) + P[L::so] * nu[0];
   }
-  __device__ static void fz_pre(const float* P, const float* x, const float* xn, int t, float* pre) {
+  __device__ static void fz_pre(Prm P, const float* x, const float* xn, int t, float* pre) {
     const float o = x[0], on = xn[0], k = P[L::k];
     if (outer_slow(P, t)) {
       // inner growth: o + A + k (o' - o) + rho i + (b - k) sat(i)
@@ -371,22 +434,41 @@ struct Table1M1 {
       pre[2] = 0.0f;
     }
   }
-  __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu, float* zn) {
+  __device__ static void fz_post(Prm P, const float* pre, const float* z, const float* nu, float* zn) {
     zn[0] = pre[1] * z[0] + pre[2] * sat(z[0]) + pre[0] + P[L::sic] * nu[0];
   }
-  __device__ static void obs_pre(const float*, const float* y, const float* x, float* r0) {
+  __device__ static void obs_pre(Prm, const float* y, const float* x, float* r0) {
     r0[0] = ZF ? y[0] - 0.05f * x[0] * x[0] : y[0] - atanf(x[0]);
   }
-  __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
+  __device__ static float logpy_post(Prm P, const float* r0, const float* z) {
     const float e = ZF ? r0[0] - atanf(z[0]) : r0[0] - 0.05f * z[0] * z[0];
     return P[L::cy] - 0.5f * P[L::inv_r] * e * e;
   }
-  __device__ static float logpx(const float* P, const float* xn, const float* x, const float* z, int t) {
-    const float e = xn[0] - mean_o(P, x[0], z[0], t);
+  // x' - mean_o = c0 - c1 i - c2 sat(i)
+  static constexpr int NPX = 3;
+  __device__ static void px_pre(Prm P, const float* xn, const float* x, int t, float* c) {
+    const float o = x[0];
+    if (outer_slow(P, t)) {
+      c[0] = xn[0] - o;
+      c[1] = 0.0f;
+      c[2] = 1.0f;
+    } else {
+      c[0] = xn[0] - (P[L::rho] * o + P[L::b] * sat(o) + cyc(P, t));
+      c[1] = 1.0f;
+      c[2] = 0.0f;
+    }
+  }
+  __device__ static float logpx_post(Prm P, const float* c, const float* z) {
+    const float e = c[0] - c[1] * z[0] - c[2] * sat(z[0]);
     return P[L::co] - 0.5f * P[L::inv_qo] * e * e;
   }
+  __device__ static float logpx(Prm P, const float* xn, const float* x, const float* z, int t) {
+    float c[NPX];
+    px_pre(P, xn, x, t, c);
+    return logpx_post(P, c, z);
+  }
   // noise-free observation h(x, z) = atan(x) + z^2 / 20
-  __device__ static void obs_mean(const float*, const float* x, const float* z, float* h) {
+  __device__ static void obs_mean(Prm, const float* x, const float* z, float* h) {
     h[0] = ZF ? atanf(z[0]) + 0.05f * x[0] * x[0] : atanf(x[0]) + 0.05f * z[0] * z[0];
   }
 };
@@ -406,6 +488,7 @@ using TwoDimZ = Table1M1<true>;
 struct FourDim {
   static constexpr int DX = 2, DZ = 2, DY = 1, NPRE = 2;
   static constexpr bool kXdepZ = false;
+  static constexpr bool kStreamZ = false;
   struct Layout {
     static constexpr int a1 = 0, bs = 1, c21 = 2, a2 = 3, qx1 = 4, qx2 = 5, qz1 = 6, qz2 = 7, cz = 8, rho = 9,
                          b = 10, amp = 11, freq = 12, r = 13, n_raw = 14;
@@ -416,37 +499,37 @@ struct FourDim {
   using L = Layout;
 
   // the time-dependent drift in double (t runs to thousands of radians)
-  __device__ static float drift_x(const float* P, int t) { return (float)((double)P[L::bs] * sin((double)t)); }
-  __device__ static void fx(const float* P, const float* x, const float*, const float* nu, int t, float* xn) {
+  __device__ static float drift_x(Prm P, int t) { return (float)((double)P[L::bs] * sin((double)t)); }
+  __device__ static void fx(Prm P, const float* x, const float*, const float* nu, int t, float* xn) {
     xn[0] = P[L::a1] * x[0] + drift_x(P, t) + P[L::sx1] * nu[0];
     xn[1] = P[L::c21] * x[0] + P[L::a2] * x[1] + P[L::sx2] * nu[1];
   }
-  __device__ static float fz_pre_k(const float* P, const float*, const float*, int t, int k) {
+  __device__ static float fz_pre_k(Prm P, const float*, const float*, int t, int k) {
     return k == 1 ? (float)((double)P[L::amp] * cos((double)P[L::freq] * (double)t)) : 0.0f;
   }
-  __device__ static void fz_pre(const float* P, const float* x, const float* xn, int t, float* pre) {
+  __device__ static void fz_pre(Prm P, const float* x, const float* xn, int t, float* pre) {
     pre[0] = 0.0f;
     pre[1] = fz_pre_k(P, x, xn, t, 1);
   }
-  __device__ static void fz_post(const float* P, const float* pre, const float* z, const float* nu, float* zn) {
+  __device__ static void fz_post(Prm P, const float* pre, const float* z, const float* nu, float* zn) {
     const float g = z[1] / (1.0f + z[1] * z[1]);
     const float w1 = P[L::sz1] * nu[0];
     const float z1 = z[0] + g + w1;
     zn[0] = z1;
     zn[1] = z1 + P[L::rho] * z[1] + P[L::b] * g + pre[1] + P[L::kz] * w1 + P[L::szc] * nu[1];
   }
-  __device__ static void obs_pre(const float*, const float* y, const float* x, float* r0) {
+  __device__ static void obs_pre(Prm, const float* y, const float* x, float* r0) {
     r0[0] = y[0] - (x[0] + x[1]) / (1.0f + x[0] * x[0]);
   }
-  __device__ static float logpy_post(const float* P, const float* r0, const float* z) {
+  __device__ static float logpy_post(Prm P, const float* r0, const float* z) {
     const float e = r0[0] - atanf(z[0]) - 0.05f * z[1] * z[1];
     return P[L::cy] - 0.5f * P[L::inv_r] * e * e;
   }
   // noise-free observation h(x, z) = (x1 + x2) / (1 + x1^2) + atan(z1) + z2^2 / 20
-  __device__ static void obs_mean(const float*, const float* x, const float* z, float* h) {
+  __device__ static void obs_mean(Prm, const float* x, const float* z, float* h) {
     h[0] = (x[0] + x[1]) / (1.0f + x[0] * x[0]) + atanf(z[0]) + 0.05f * z[1] * z[1];
   }
-  __device__ static float logpx(const float* P, const float* xn, const float* x, const float*, int t) {
+  __device__ static float logpx(Prm P, const float* xn, const float* x, const float*, int t) {
     const float e0 = xn[0] - (P[L::a1] * x[0] + drift_x(P, t));
     const float e1 = xn[1] - (P[L::c21] * x[0] + P[L::a2] * x[1]);
     return P[L::cx] - 0.5f * (P[L::inv_qx1] * e0 * e0 + P[L::inv_qx2] * e1 * e1);

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_rb_outer(StepArgs a, double* xrb) {
 #pragma unroll
     for (int d = 0; d < DZ; ++d) z[d] = zrow[d * M + j];
     normals<DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu);
-    Mdl::fx(a.prm, x, z, nu, t - 1, xl);
+    Mdl::fx(as_prm(a.prm), x, z, nu, t - 1, xl);
 #pragma unroll
     for (int d = 0; d < DX; ++d) acc[d] += w * (double)xl[d];
   }
