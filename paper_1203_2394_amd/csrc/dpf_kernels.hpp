@@ -504,6 +504,7 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
   if (tile.z == 0 && threadIdx.x == 0) a.act[f] = act ? 1 : 0;
   if (!act) return;
   const int N = fv.N, M = fv.M, K = a.n_comp;
+  constexpr int CPB = comp_per_block<DZ>();  // companions per block of normals
   const int s = threadIdx.x / SEG;
   const int i = tile.y + s;
   const int ls = threadIdx.x % SEG;
@@ -588,19 +589,25 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
         const double u = uniform53_ab(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_B);
         Lse acck;
         float hk = 0.f;
-        for (int k = 0; k < K; ++k) {
-          const int b = cdf_search(cdf[s], M, sys_point(k, u, total, K));
-          float zg[DZ], nu[DZ], zc[DZ];
+        for (int k0 = 0; k0 < K; k0 += CPB) {
+          float nb[CPB * DZ];
+          normals_kb<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, k0, nb);
 #pragma unroll
-          for (int d = 0; d < DZ; ++d) zg[d] = zrow[d * M + b];
-          normals_k<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, k, nu);
-          Mdl::fz_post(as_prm(a.prm), pre, zg, nu, zc);
-          acck.add(Mdl::logpy_post(as_prm(a.prm), r0, zc));
-          if constexpr (kH) {
-            if (want_h) {
-              float h[1];
-              Mdl::obs_mean(as_prm(a.prm), xl[r], zc, h);
-              hk += h[0];
+          for (int q = 0; q < CPB; ++q) {
+            const int k = k0 + q;
+            if (k >= K) break;
+            const int b = cdf_search(cdf[s], M, sys_point(k, u, total, K));
+            float zg[DZ], zc[DZ];
+#pragma unroll
+            for (int d = 0; d < DZ; ++d) zg[d] = zrow[d * M + b];
+            Mdl::fz_post(as_prm(a.prm), pre, zg, nb + q * DZ, zc);
+            acck.add(Mdl::logpy_post(as_prm(a.prm), r0, zc));
+            if constexpr (kH) {
+              if (want_h) {
+                float h[1];
+                Mdl::obs_mean(as_prm(a.prm), xl[r], zc, h);
+                hk += h[0];
+              }
             }
           }
         }
@@ -665,11 +672,10 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
         Mdl::obs_pre(as_prm(a.prm), y, xl[r], r0);
         Lse acck;
         float hk = 0.f;
-        auto emit = [&](int b, int k) {
-          float zg[DZ], nu[DZ], zc[DZ];
+        auto emit = [&](int b, const float* nu) {
+          float zg[DZ], zc[DZ];
 #pragma unroll
           for (int d = 0; d < DZ; ++d) zg[d] = cz[s][kCond ? b : 0][d];
-          normals_k<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, k, nu);
           Mdl::fz_post(as_prm(a.prm), pre, zg, nu, zc);
           acck.add(Mdl::logpy_post(as_prm(a.prm), r0, zc));
           if constexpr (kH) {
@@ -685,13 +691,20 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
         // every lane propagates its companion k together
         int jc = -1;
         double c = 0.0;
-        for (int k = 0; k < K; ++k) {
-          const double P = sys_point(k, u, total, K);
-          while (!(c > P) && jc + 1 < M) {
-            ++jc;
-            c += weight(jc);
+        for (int k0 = 0; k0 < K; k0 += CPB) {
+          float nb[CPB * DZ];
+          normals_kb<DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, k0, nb);
+#pragma unroll
+          for (int q = 0; q < CPB; ++q) {
+            const int k = k0 + q;
+            if (k >= K) break;
+            const double P = sys_point(k, u, total, K);
+            while (!(c > P) && jc + 1 < M) {
+              ++jc;
+              c += weight(jc);
+            }
+            emit(c > P ? jc : lastpos, nb + q * DZ);
           }
-          emit(c > P ? jc : lastpos, k);
         }
         const float g = (acck.m == -INFINITY) ? -INFINITY : acck.m + fast_log(acck.s) - logK;
         ev[r] = la_ell(lamv[r], g);

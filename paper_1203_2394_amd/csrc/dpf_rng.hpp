@@ -160,4 +160,26 @@ __device__ __forceinline__ void normals_k(Key key, uint32_t t, uint32_t a, uint3
   }
 }
 
+// Companions served by one Philox block of normals_k<D>: four for D = 1, two
+// for D = 2, one (D / 4 blocks each) for D a multiple of 4.
+template <int D>
+constexpr int comp_per_block() {
+  return D == 1 ? 4 : (D == 2 ? 2 : 1);
+}
+
+// normals_k<D> for k = k0 .. k0 + comp_per_block<D>() - 1 at once (k0 a
+// multiple of that count), companion q's D normals at out[q D]: for D = 1
+// and 2 the block's four normals in slot order, so one block serves them all.
+template <int D>
+__device__ __forceinline__ void normals_kb(Key key, uint32_t t, uint32_t a, uint32_t b, uint32_t purpose, int k0,
+                                           float* out) {
+  if constexpr (D == 1 || D == 2) {
+    const Words w = draw(key, t, a, b, purpose, (uint32_t)(k0 / comp_per_block<D>()));
+    box_muller(w.w[0], w.w[1], out[0], out[1]);
+    box_muller(w.w[2], w.w[3], out[2], out[3]);
+  } else {
+    normals_k<D>(key, t, a, b, purpose, k0, out);
+  }
+}
+
 }  // namespace dpf
