@@ -23,9 +23,6 @@ static void derive_highdim(int dx, int dz, int dy, const double* p, std::vector<
                       0.5 * log(nu * M_PI * r)));                // lt0
   o.push_back((float)(0.5 * (nu + 1.0)));                        // tnu
   o.push_back((float)(1.0 / (nu * r)));                          // inv_nur
-  const size_t ic = iqz + 1;                                     // C [dy][dz]
-  for (int d = 0; d < dz; ++d)
-    for (int k = 0; k < dy; ++k) o.push_back((float)p[ic + (size_t)k * dz + d]);  // Ct [dz][dy]
 }
 
 const Engine kEngHighDim = make_engine<HighDim<4, 64, 32>>([](const double* p, std::vector<float>& o) { derive_highdim(4, 64, 32, p, o); });

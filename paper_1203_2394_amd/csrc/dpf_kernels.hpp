@@ -26,6 +26,7 @@
 #include <stdint.h>
 
 #include "dpf_models.hpp"
+#include "dpf_proj.hpp"
 #include "dpf_rng.hpp"
 #include "dpf_seg.hpp"
 
@@ -214,6 +215,11 @@ __device__ __forceinline__ void load_y(const StepArgs& a, int f, int t, float* y
   for (int k = 0; k < Mdl::DY; ++k) y[k] = yp[k];
 }
 
+template <class Mdl>
+__device__ __forceinline__ const float* y_row(const StepArgs& a, int f, int t) {
+  return a.Y + (long long)(t - 1) * a.y_tstride + (long long)f * Mdl::DY;
+}
+
 // Online log-sum-exp accumulator (non-finite values are skipped).
 struct Lse {
   float m = -INFINITY, s = 0.f;
@@ -349,29 +355,6 @@ __device__ __forceinline__ float la_logpy(const StepArgs& a, const Key& key, int
   }
 #pragma unroll
   for (int d = 0; d < Mdl::DY; ++d) y[d] = yi[d];
-  if constexpr (Mdl::kStreamZ) {
-    // wide z: the candidate's z component by component, each folded into
-    // the residual at once (same arithmetic as fz_post then logpy_post)
-    static_assert(!H && Mdl::DZ % 4 == 0, "streamed look-ahead draw: DZ a multiple of 4, no predicted observation");
-    float nu_x[Mdl::DX], xl[Mdl::DX], c[Mdl::NPL], e[Mdl::DY];
-    normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
-    Mdl::fx(as_prm(a.prm), x, z, nu_x, t - 1, xl);
-    Mdl::fz_lite(as_prm(a.prm), x, xl, t - 1, c);
-    Mdl::obs_pre(as_prm(a.prm), y, xl, e);
-#pragma unroll
-    for (int g = 0; g < Mdl::DZ / 4; ++g) {
-      float nu4[4];
-      normals_k<4>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, g, nu4);
-      const Prm P = as_prm(a.prm);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int kk = 4 * g + q;
-        const float zk = Mdl::fz_post_k(P, Mdl::fz_pre_lite(P, c, kk), z, nu4[q], kk);
-        Mdl::proj_add(P, e, zk, kk);
-      }
-    }
-    return Mdl::logpy_e(as_prm(a.prm), e);
-  }
   float nu_x[Mdl::DX], nu_z[Mdl::DZ], xl[Mdl::DX], pre[Mdl::NPRE], zl[Mdl::DZ], r0[Mdl::DY];
   normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
   normals<Mdl::DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, nu_z);
@@ -396,6 +379,48 @@ __device__ __forceinline__ float la_logpy(const StepArgs& a, const Key& key, int
     Mdl::obs_mean(as_prm(a.prm), xh, zh, hout);
   }
   return Mdl::logpy_post(as_prm(a.prm), r0, zl);
+}
+
+// The same for a wide-z model, for the 64 inner particles of a wave at once
+// (converged code; lane l's particle j): the candidate's z component by
+// component, each pair of components into the matrix-core residual
+// (WaveProj; ca its A values, yrow the observation y_t).
+template <class Mdl>
+__device__ __forceinline__ float la_logpy_wave(const StepArgs& a, const Key& key, int t, int i, int j,
+                                               const float* xi, const float* zi, const float* yrow,
+                                               const float* ca) {
+  static_assert(Mdl::kStreamZ && Mdl::DZ % 4 == 0, "la_logpy_wave: wide-z models, DZ a multiple of 4");
+  const Prm P = as_prm(a.prm);
+  float x[Mdl::DX], z[Mdl::DZ];
+#pragma unroll
+  for (int d = 0; d < Mdl::DX; ++d) {
+    x[d] = xi[d];
+    asm volatile("" : "+v"(x[d]));
+  }
+#pragma unroll
+  for (int d = 0; d < Mdl::DZ; ++d) {
+    z[d] = zi[d];
+    asm volatile("" : "+v"(z[d]));
+  }
+  float nu_x[Mdl::DX], xl[Mdl::DX], c[Mdl::NPL];
+  normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
+  Mdl::fx(P, x, z, nu_x, t - 1, xl);
+  Mdl::fz_lite(P, x, xl, t - 1, c);
+  WaveProj<Mdl> pj;
+  pj.start();
+#pragma unroll
+  for (int g = 0; g < Mdl::DZ / 4; ++g) {
+    float nu4[4], z4[4];
+    normals_k<4>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, g, nu4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kk = 4 * g + q;
+      z4[q] = Mdl::fz_post_k(P, Mdl::fz_pre_lite(P, c, kk), z, nu4[q], kk);
+    }
+    pj.add(ca[2 * g], z4[0], z4[1]);
+    pj.add(ca[2 * g + 1], z4[2], z4[3]);
+  }
+  return pj.logpy(P, yrow);
 }
 
 // lam + g as a separate rounding: g is opaque to the compiler, so no
@@ -441,6 +466,26 @@ __device__ __forceinline__ void la_weights_tile(const StepArgs& a, int ti, bool 
   constexpr bool kH = has_yhat<Mdl>();
   const bool want_h = kH && a.yp != nullptr && !fallback;
   float hv = 0.f;  // sum over the lane's draws of qbar h(xla, zla)
+  if constexpr (Mdl::kStreamZ) {
+    // wide z: every lane of the wave takes part in the matrix-core residual
+    float ca[WaveProj<Mdl>::NA];
+    WaveProj<Mdl>::load_a(as_prm(a.prm), ca);
+    const float* yrow = y_row<Mdl>(a, f, t);
+    for (int r = 0; r < JPT; ++r) {
+      const int j = ls + r * SEG;
+      const bool on = vi && j < M;
+      float z[Mdl::DZ];
+#pragma unroll
+      for (int d = 0; d < Mdl::DZ; ++d) z[d] = on ? zrow[d * M + j] : 0.f;
+      const float lj = on ? lrow[j] : 0.f;
+      const float g = la_logpy_wave<Mdl>(a, key, t, i, on ? j : 0, x, z, yrow, ca);
+      if (on) {
+        const float e = la_ell(lj, g);
+        erow[j] = e;
+        acc.add(e);
+      }
+    }
+  } else {
 #pragma unroll
   for (int r = 0; r < JPT; ++r) {
     const int j = ls + r * SEG;
@@ -461,6 +506,7 @@ __device__ __forceinline__ void la_weights_tile(const StepArgs& a, int ti, bool 
       erow[j] = e;
       acc.add(e);
     }
+  }
   }
   const float lw = seg_lse<SEG>(acc, sh);
   if (vi && ls == 0) a.logw[oo + i] = lw;
@@ -1910,47 +1956,69 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
   const bool want_h = kH && fuse && a.yp_next != nullptr;
   float hn[kH ? JPT : 1];
   Lse acc;
-#pragma unroll(kRoll ? 1 : JPT)
+  // wide z: the new z of every lane of the wave goes through the matrix-core
+  // residual together (lanes without a particle carry zeros)
+  float ca[kStream ? Mdl::DZ / 2 : 1];
+  if constexpr (kStream) WaveProj<Mdl>::load_a(as_prm(a.prm), ca);
+#pragma unroll kRoll ? 1 : JPT
   for (int r = 0; r < JPT; ++r) {
     const int jj = ls + r * SEG;
     float lv = -INFINITY, gv = 0.f;
-    if (vk && jj < M) {
-      const int b = cdf_search(cdf[s], M, sys_point(jj, u_in, tot2, M));
+    if constexpr (kStream) {
+      const bool on = vk && jj < M;
+      const int b = on ? cdf_search(cdf[s], M, sys_point(jj, u_in, tot2, M)) : 0;
       float zg[DZ], zn[DZ];
 #pragma unroll
-      for (int d = 0; d < DZ; ++d) zg[d] = zp[d * M + b];
-      if constexpr (kStream) {
-        // component by component: new z, its store, its residual term
-        float e[DY];
+      for (int d = 0; d < DZ; ++d) zg[d] = on ? zp[d * M + b] : 0.f;
+      const Prm P = as_prm(a.prm);
+      WaveProj<Mdl> pj;
+      pj.start();
 #pragma unroll
-        for (int d = 0; d < DY; ++d) e[d] = PLAIN ? 0.f : r0[d];
+      for (int g = 0; g < DZ / 4; ++g) {
+        float nu4[4];
+        normals_k<4>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, g, nu4);
 #pragma unroll
-        for (int g = 0; g < DZ / 4; ++g) {
-          float nu4[4];
-          normals_k<4>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, g, nu4);
-          const Prm P = as_prm(a.prm);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int d = 4 * g + q;
-            zn[d] = Mdl::fz_post_k(P, pre[d], zg, nu4[q], d);
-            zdst[d * M + jj] = zn[d];
-            if (!PLAIN) Mdl::proj_add(P, e, zn[d], d);
-          }
+        for (int q = 0; q < 4; ++q) {
+          const int d = 4 * g + q;
+          zn[d] = Mdl::fz_post_k(P, pre[d], zg, nu4[q], d);
+          if (on) zdst[d * M + jj] = zn[d];
         }
-        if (!PLAIN) lv = Mdl::logpy_e(as_prm(a.prm), e);
-      } else {
-        float nu[DZ];
-        if constexpr (kEarly) {
-#pragma unroll
-          for (int d = 0; d < DZ; ++d) nu[d] = nue[kEarly ? r : 0][d];
-        } else {
-          normals<DZ>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, nu);
+        if (!PLAIN) {
+          pj.add(ca[2 * g], zn[4 * g], zn[4 * g + 1]);
+          pj.add(ca[2 * g + 1], zn[4 * g + 2], zn[4 * g + 3]);
         }
-        Mdl::fz_post(as_prm(a.prm), pre, zg, nu, zn);
-#pragma unroll
-        for (int d = 0; d < DZ; ++d) zdst[d * M + jj] = zn[d];
-        if (!PLAIN) lv = Mdl::logpy_post(as_prm(a.prm), r0, zn);
       }
+      if constexpr (kKeepZ) {
+#pragma unroll
+        for (int d = 0; d < DZ; ++d) zkeep[kKeepZ ? r : 0][d] = zn[d];
+      }
+      if (!PLAIN) {
+        const float l0 = pj.logpy(P, y_row<Mdl>(a, f, t));
+        // the next step's look-ahead likelihood of these new inner particles
+        const float g0 = fuse ? la_logpy_wave<Mdl>(a, key, t + 1, k, jj, xn, zn,
+                                                   y_row<Mdl>(a, f, min(fv.t, a.run_T - 1) + 1), ca)
+                              : 0.f;
+        if (on) {
+          lv = l0;
+          gv = g0;
+          acc.add(lv);
+        }
+      }
+    } else if (vk && jj < M) {
+      const int b = cdf_search(cdf[s], M, sys_point(jj, u_in, tot2, M));
+      float zg[DZ], zn[DZ], nu[DZ];
+#pragma unroll
+      for (int d = 0; d < DZ; ++d) zg[d] = zp[d * M + b];
+      if constexpr (kEarly) {
+#pragma unroll
+        for (int d = 0; d < DZ; ++d) nu[d] = nue[kEarly ? r : 0][d];
+      } else {
+        normals<DZ>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, nu);
+      }
+      Mdl::fz_post(as_prm(a.prm), pre, zg, nu, zn);
+#pragma unroll
+      for (int d = 0; d < DZ; ++d) zdst[d * M + jj] = zn[d];
+      if (!PLAIN) lv = Mdl::logpy_post(as_prm(a.prm), r0, zn);
       if constexpr (kKeepZ) {
 #pragma unroll
         for (int d = 0; d < DZ; ++d) zkeep[kKeepZ ? r : 0][d] = zn[d];

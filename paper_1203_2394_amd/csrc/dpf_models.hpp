@@ -26,17 +26,19 @@
 // not, the x-conditioning factor of eq:qnobar is constant over the inner
 // cloud and the kernels skip it.
 //
-// kStreamZ models (a wide z) also give f^z and log p(y | x, z) one z
-// component at a time, so that a kernel can form z_{t+1} component by
-// component and fold each into the likelihood without holding the whole
-// new vector:
+// kStreamZ models (a wide z, y = C z + e with 32 components) give f^z one
+// z component at a time, so that a kernel forms z_{t+1} component by
+// component and hands each pair to the matrix cores for the residual
+// y - C z of a wave's particles at once, and the likelihood as a sum of
+// per-component terms:
 //   fz_lite(P, x, xn, t, c)       a compact form of fz_pre (NPL values)
 //   fz_pre_lite(P, c, k)          pre[k] from it
 //   fz_post_k(P, prek, z, nuk, k) component k of fz_post
-//   proj_add(P, e, zk, k)         e -= (column k of the observation matrix) zk
-//   logpy_e(P, e)                 log p(y | z) from e = r0 - C z
-// fz_pre, fz_post and logpy_post are these composed, with the same
-// arithmetic in the same order.
+//   Layout::C                     C, [DY][DZ] row-major
+//   row_term(P, e)                the likelihood's term of one residual component
+//   logpy_sum(P, s)               log p(y | z) from the sum of the terms
+// fz_pre and fz_post are the first three composed, with the same arithmetic
+// in the same order; logpy_post(P, y, z) = logpy_sum(sum_k row_term(e_k)).
 //
 // Parameters live in one float array in device memory (read through Prm): the raw parameter
 // values in the interface's blob order, followed by constants the host
@@ -274,10 +276,9 @@ struct HighDim {
     // mixture: half_inv_r, lg0 = log(1-eps) - 0.5 log(2 pi r),
     //          lt0 = log eps + lgamma((nu+1)/2) - lgamma(nu/2) - 0.5 log(nu pi r),
     //          tnu = (nu+1)/2, inv_nur = 1/(nu r)
-    // Ct: the observation matrix transposed ([DZ][DY]), for proj_add
     static constexpr int sx = n_raw, sz = sx + 1, inv_qx = sz + 1, cx = inv_qx + 1,
                          inv_r = cx + 1, cy = inv_r + 1, lg0 = cy + 1, lt0 = lg0 + 1,
-                         tnu = lt0 + 1, inv_nur = tnu + 1, Ct = inv_nur + 1, n_total = Ct + DZ * DY;
+                         tnu = lt0 + 1, inv_nur = tnu + 1, n_total = inv_nur + 1;
   };
   using L = Layout;
 
@@ -325,40 +326,31 @@ struct HighDim {
 #pragma unroll
     for (int k = 0; k < DY; ++k) r0[k] = y[k];
   }
-  __device__ static void proj_add(Prm P, float* e, float zk, int k) {
-#pragma unroll
-    for (int a = 0; a < DY; ++a) e[a] -= P[L::Ct + k * DY + a] * zk;
+  // Gaussian: cy - q / (2 r), q the sum of e_k^2; mixture: the sum over the
+  // components of log((1 - eps) N(e_k; 0, r) + eps t_nu(e_k; 0, r)), each as
+  // max + log(1 + exp(-|difference|))
+  __device__ static float row_term(Prm P, float e) {
+    const float e2 = e * e;
+    if (P[L::gonly] != 0.0f) return e2;
+    const float lg = P[L::lg0] - 0.5f * P[L::inv_r] * e2;
+    const float lt = P[L::lt0] - P[L::tnu] * fast_log(1.0f + e2 * P[L::inv_nur]);
+    const float mx = fmaxf(lg, lt);
+    return mx + fast_log(1.0f + fast_exp(-fabsf(lg - lt)));
   }
-  // Gaussian: cy - q / (2 r); mixture: per component log((1 - eps) N(e; 0, r)
-  // + eps t_nu(e; 0, r)) as max + log(1 + exp(-|difference|))
-  __device__ static float logpy_e(Prm P, const float* e) {
-    const bool gonly = P[L::gonly] != 0.0f;
-    float acc = 0.f, q = 0.f;
-#pragma unroll
-    for (int k = 0; k < DY; ++k) {
-      const float e2 = e[k] * e[k];
-      q += e2;
-      if (!gonly) {
-        const float lg = P[L::lg0] - 0.5f * P[L::inv_r] * e2;
-        const float lt = P[L::lt0] - P[L::tnu] * fast_log(1.0f + e2 * P[L::inv_nur]);
-        const float mx = fmaxf(lg, lt);
-        acc += mx + fast_log(1.0f + fast_exp(-fabsf(lg - lt)));
-      }
-    }
-    return gonly ? P[L::cy] - 0.5f * P[L::inv_r] * q : acc;
+  __device__ static float logpy_sum(Prm P, float s) {
+    return P[L::gonly] != 0.0f ? P[L::cy] - 0.5f * P[L::inv_r] * s : s;
   }
-  // row by row: e_k = r0_k - sum_d C_kd z_d in order d (the same rounding
-  // sequence as proj_add over d)
+  // one particle on the vector ALU, row by row
   __device__ static float logpy_post(Prm P, const float* r0, const float* z) {
-    float e[DY];
+    float s = 0.f;
 #pragma unroll 4
     for (int k = 0; k < DY; ++k) {
       float v = r0[k];
 #pragma unroll
       for (int d = 0; d < DZ; ++d) v -= P[L::C + k * DZ + d] * z[d];
-      e[k] = v;
+      s += row_term(P, v);
     }
-    return logpy_e(P, e);
+    return logpy_sum(P, s);
   }
   __device__ static float logpx(Prm P, const float* xn, const float* x, const float*, int) {
     const float a = P[L::a], b = P[L::b];

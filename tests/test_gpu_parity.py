@@ -137,6 +137,10 @@ def _check_self_estimates(est, gs, logw_g):
     ("nonlin_bmode1", 64, 128, 1, 1),
     ("highdim", 8, 1024, 1, 1),
     ("highdim_gauss", 12, 100, 1, 1),
+    # segments of 32 lanes (two outer particles per wave, an odd N) and
+    # lanes without an inner particle in the matrix-core residual
+    ("highdim", 9, 24, 1, 2),
+    ("highdim_gauss", 5, 40, 1, 1),
     ("twodim", 130, 64, 3, 3),
     ("twodim", 37, 300, 6, 2),
     ("twodim", 500, 19, 2, 2),

@@ -168,6 +168,33 @@ def test_time_varying_model_run_equals_step_calls(algo, model):
     assert np.all(np.isfinite(xt.cpu().numpy()))
 
 
+@pytest.mark.parametrize("algo", ["lookahead", "plain"])
+def test_wide_z_run_equals_step_calls(algo):
+    """The high-dimensional model forms its residuals on the matrix cores with
+    every lane of a wave taking part (zeros where a lane holds no inner
+    particle), in the weights kernel and in the new-cloud kernel that computes
+    the next step's weights in a run: run and step calls agree bit for bit,
+    with 32-lane segments (two outer particles per wave, an odd N), inner
+    sizes that leave lanes empty and a 256-lane class."""
+    spec = S.highdim_c4(1)
+    N, M, T = [33, 10, 3], [24, 100, 512], 4
+    Y = np.stack([S.simulate(spec, T, 81 + f)[2] for f in range(3)], axis=1).astype(np.float32)
+    a = _filter(spec, N, M, algo=algo)
+    step = a.lookahead_step if algo == "lookahead" else a.step
+    for t in range(T):
+        step(torch.from_numpy(Y[t]))
+    b = _filter(spec, N, M, algo=algo)
+    xt, _ = b.run(torch.from_numpy(Y), use_graph=True)
+    sa, sb = a.unpack_state(a.export_state()), b.unpack_state(b.export_state())
+    keys = ("t", "x", "z", "lam") if algo == "lookahead" else ("t", "x", "z")
+    for k in keys:
+        for u, v in zip(sa[k], sb[k]):
+            assert np.array_equal(u, v), k
+    ea, eb = a.estimate(), b.estimate()
+    assert torch.equal(ea["xhat"], eb["xhat"]) and torch.equal(ea["loglik"], eb["loglik"])
+    assert np.all(np.isfinite(xt.cpu().numpy()))
+
+
 @pytest.mark.parametrize("use_run", [False, True])
 def test_step_end_kernels_agree(use_run):
     """Filter 0 alone (one step-end launch) and next to a filter of 66
