@@ -399,6 +399,34 @@ dpf_status dpf_mlp_train_step(float* d_state, void* d_blob, const float* d_X, co
                               float lr, int32_t adam_t, void* d_train_ws, size_t ws_bytes, float* d_loss,
                               float* d_grad, void* hip_stream);
 
+/* ---- the training set of the learned proposal (pairs the look-ahead DPF
+ * generates; training-loop plumbing, not the filter's arithmetic) ---- */
+
+/* Mean and sample standard deviation (divisor n - 1, floored at std_floor
+ * >= 0) of each of the first `cols` columns of d_X [n][ld] float, row-major:
+ * d_mean, d_std [cols].  FP64 sums in a fixed order (the same bits on every
+ * call).  n >= 2, 1 <= cols <= ld. */
+dpf_status dpf_feature_stats(const float* d_X, int64_t n, int32_t cols, int32_t ld, float* d_mean,
+                             float* d_std, float std_floor, void* hip_stream);
+
+/* d_out [n][ld_out] = (X - mean) / std in the first `cols` columns (FP32,
+ * IEEE division), 0 in the others (the network's zero-padded inputs). */
+dpf_status dpf_standardize(const float* d_X, int64_t n, int32_t cols, int32_t ld, const float* d_mean,
+                           const float* d_std, float* d_out, int32_t ld_out, void* hip_stream);
+
+/* d_perm [n] int32: a pseudo-random permutation of 0..n-1 keyed by (seed,
+ * epoch) -- a four-round Feistel network on the smallest even number of
+ * bits that covers n, walked until the value falls below n.  The same
+ * (seed, epoch, n) always gives the same permutation.  0 <= n < 2^31. */
+dpf_status dpf_permutation(uint64_t seed, uint32_t epoch, int64_t n, int32_t* d_perm, void* hip_stream);
+
+/* d_dst [count][ld_dst] = rows d_idx[0..count) of d_src [n_src][ld_src]
+ * (first `cols` columns).  An index outside 0..n_src-1 gives a row of NaN
+ * (no read outside d_src). */
+dpf_status dpf_gather_rows(const float* d_src, int64_t n_src, int32_t cols, int32_t ld_src,
+                           const int32_t* d_idx, int32_t count, float* d_dst, int32_t ld_dst,
+                           void* hip_stream);
+
 /* ---- kernel-level primitives (same device code as the step kernels) ---- */
 
 /* Philox4x32-10 words: d_ctr [n][4] uint32 counters -> d_out [n][4] words

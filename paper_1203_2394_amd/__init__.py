@@ -34,7 +34,8 @@ EXPORTS = [
     "dpf_mlp_blob_bytes", "dpf_mlp_param_count", "dpf_mlp_forward", "dpf_mlp_train_workspace_bytes",
     "dpf_mlp_pack", "dpf_mlp_train_step", "dpf_learned_run", "dpf_tile_classes", "dpf_set_tiling",
     "dpf_estimate_rb", "dpf_systematic_noalloc", "dpf_set_lookahead_companions", "dpf_set_prediction",
-    "dpf_predicted_observation",
+    "dpf_predicted_observation", "dpf_feature_stats", "dpf_standardize", "dpf_permutation",
+    "dpf_gather_rows",
 ]
 
 
@@ -113,6 +114,10 @@ def lib():
         "dpf_mlp_pack": (_i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
         "dpf_mlp_train_step": (_i32, [_vp, _vp, _vp, _vp, _i32, ctypes.c_float, _i32, _vp, _sz, _vp, _vp,
                                       _vp]),
+        "dpf_feature_stats": (_i32, [_vp, ctypes.c_int64, _i32, _i32, _vp, _vp, ctypes.c_float, _vp]),
+        "dpf_standardize": (_i32, [_vp, ctypes.c_int64, _i32, _i32, _vp, _vp, _vp, _i32, _vp]),
+        "dpf_permutation": (_i32, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, _vp, _vp]),
+        "dpf_gather_rows": (_i32, [_vp, ctypes.c_int64, _i32, _i32, _vp, _i32, _vp, _i32, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -543,13 +548,14 @@ class MLP:
         self._keep = X
         return out
 
-    def _step(self, X, xt, lr, adam_t, want_grad):
+    def _step(self, X, xt, lr, adam_t, want_grad, loss=None):
         torch = _torch()
         X = torch.as_tensor(X, dtype=torch.float32, device=self.device).contiguous()
         xt = torch.as_tensor(xt, dtype=torch.float32, device=self.device).contiguous()
         if X.shape[0] != self.batch:
             raise DPFError("batch of %d rows, network built for %d" % (X.shape[0], self.batch))
-        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
         grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=self.device) if want_grad else None
         _check(lib().dpf_mlp_train_step(_ptr(self.state), _ptr(self.blob), _ptr(X), _ptr(xt), self.batch,
                                         float(lr), int(adam_t), _ptr(self._ws), self._ws.numel(), _ptr(loss),
@@ -557,10 +563,12 @@ class MLP:
         self._keep = (X, xt)
         return loss, grad
 
-    def train_step(self, X, xt, lr=1e-3, want_grad=False):
-        """One Adam step on a batch (standardised features, targets [B][2])."""
+    def train_step(self, X, xt, lr=1e-3, want_grad=False, loss=None):
+        """One Adam step on a batch (standardised features, targets [B][2]);
+        loss: an optional one-element device tensor (view) for the batch's
+        mean NLL."""
         self.adam_t += 1
-        return self._step(X, xt, lr, self.adam_t, want_grad)
+        return self._step(X, xt, lr, self.adam_t, want_grad, loss)
 
     def loss_and_grad(self, X, xt):
         """Mean NLL and its gradient at the current parameters (no update)."""

@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libdpf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["dpf_lib.hip", "dpf_eng_lingauss.hip", "dpf_eng_nonlin.hip", "dpf_eng_highdim.hip",
-           "dpf_eng_twodim.hip", "dpf_eng_fourdim.hip", "dpf_eng_twodimz.hip"]
+           "dpf_eng_twodim.hip", "dpf_eng_fourdim.hip", "dpf_eng_twodimz.hip", "dpf_data.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed-FP32 instructions (v_pk_*_f32) in generated code

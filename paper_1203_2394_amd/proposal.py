@@ -6,8 +6,10 @@ outer ancestors A_k and the new particles x_t^(k) (the SIR draws from the
 Monte Carlo optimal proposal eq:approx3).  The pairs (features of A_k,
 x_t^(k)) teach the mixture density network q(x_t | features) to stand in
 for that proposal.  Training minimises the mixture negative log-likelihood
-with Adam, all on the library's BF16 matrix-core kernels; PyTorch only
-holds the device buffers, shuffles and standardises the data set.
+with Adam, all on the library's BF16 matrix-core kernels; the feature
+statistics, the standardisation, the per-epoch shuffle and the batch gather
+are library calls too (dpf_feature_stats, dpf_standardize, dpf_permutation,
+dpf_gather_rows), PyTorch only holding the device buffers.
 
 The evaluation runs the look-ahead DPF and the learned step (with its ESS
 fallback) on the same fresh observation sequence and reports the RMSE of the
@@ -18,7 +20,7 @@ import time
 
 import numpy as np
 
-from . import BUF_ANC, BUF_FALLBACK, BUF_X, MLP_IN, DPFError, Filter, MLP, init_params
+from . import BUF_ANC, BUF_FALLBACK, BUF_X, MLP_IN, DPFError, Filter, MLP, _check, _ptr, _stream_ptr, init_params, lib
 
 N_FEAT = 26  # x (2), y (8), cloud mean (8), cloud variance (8)
 
@@ -63,34 +65,51 @@ def generate_pairs(spec, n_pairs, N=256, M=256, T=200, n_filters=20, data_seed=1
 
 
 def feature_stats(X):
-    """Mean and standard deviation of each raw feature (floor 1e-3)."""
-    mean = X.mean(dim=0)
-    std = X.std(dim=0).clamp_min(1e-3)
+    """Mean and sample standard deviation of each raw feature (floor 1e-3),
+    computed on the device (dpf_feature_stats)."""
+    torch = _torch()
+    X = X.contiguous()
+    n, cols = X.shape
+    mean = torch.empty(cols, dtype=torch.float32, device=X.device)
+    std = torch.empty(cols, dtype=torch.float32, device=X.device)
+    _check(lib().dpf_feature_stats(_ptr(X), int(n), int(cols), int(cols), _ptr(mean), _ptr(std), 1e-3,
+                                   _stream_ptr(X.device)))
     return mean.cpu().numpy(), std.cpu().numpy()
 
 
 def train(X, xt, epochs=10, batch=4096, lr=1e-3, seed=0, verbose=False):
-    """Fit the network to (raw features X, targets xt).  Returns (MLP, losses
-    per epoch)."""
+    """Fit the network to (raw features X [n][26], targets xt [n][2]).  Each
+    epoch takes a fresh permutation of the pairs (dpf_permutation keyed by
+    (seed, epoch)) and its first floor(n / batch) batches.  Returns (MLP,
+    mean NLL per epoch)."""
     torch = _torch()
     device = X.device
+    X = X.contiguous()
+    xt = xt.contiguous()
+    n = X.shape[0]
     fmean, fstd = feature_stats(X)
     mlp = MLP(init_params(seed, N_FEAT), fmean, fstd, batch=batch, device=device)
-    Xs = torch.zeros(X.shape[0], MLP_IN, dtype=torch.float32, device=device)
-    Xs[:, :N_FEAT] = (X - mlp.fmean[:N_FEAT]) / mlp.fstd[:N_FEAT]
-    gen = torch.Generator(device=device)
-    gen.manual_seed(seed)
-    n = (X.shape[0] // batch) * batch
-    if n == 0:
+    L = lib()
+    st = _stream_ptr(device)
+    Xs = torch.empty(n, MLP_IN, dtype=torch.float32, device=device)
+    _check(L.dpf_standardize(_ptr(X), int(n), N_FEAT, N_FEAT, _ptr(mlp.fmean), _ptr(mlp.fstd), _ptr(Xs), MLP_IN,
+                             st))
+    nb = n // batch
+    if nb == 0:
         raise DPFError("need at least one batch of %d pairs" % batch)
+    perm = torch.empty(n, dtype=torch.int32, device=device)
+    xb = torch.empty(batch, MLP_IN, dtype=torch.float32, device=device)
+    tb = torch.empty(batch, 2, dtype=torch.float32, device=device)
+    lossv = torch.empty(max(nb, 1), dtype=torch.float32, device=device)
     losses = []
     for ep in range(epochs):
-        perm = torch.randperm(X.shape[0], generator=gen, device=device)[:n].reshape(-1, batch)
-        acc = torch.zeros(1, dtype=torch.float32, device=device)
-        for idx in perm:
-            loss, _ = mlp.train_step(Xs[idx], xt[idx], lr=lr)
-            acc += loss
-        losses.append(float(acc) / perm.shape[0])
+        _check(L.dpf_permutation(int(seed), int(ep), int(n), _ptr(perm), st))
+        for b in range(nb):
+            idx = perm[b * batch:(b + 1) * batch]
+            _check(L.dpf_gather_rows(_ptr(Xs), int(n), MLP_IN, MLP_IN, _ptr(idx), batch, _ptr(xb), MLP_IN, st))
+            _check(L.dpf_gather_rows(_ptr(xt), int(n), 2, 2, _ptr(idx), batch, _ptr(tb), 2, st))
+            mlp.train_step(xb, tb, lr=lr, loss=lossv[b:b + 1])
+        losses.append(float(np.mean(lossv[:nb].cpu().numpy().astype(np.float64))))
         if verbose:
             print("epoch %d: mean NLL %.4f" % (ep, losses[-1]), flush=True)
     return mlp, losses

@@ -157,6 +157,27 @@ def test_model_ids_agree_across_header_binding_and_inputs():
         assert getattr(S, name) == v
 
 
+def test_training_set_calls_validate_on_the_host():
+    """The training-set calls reject bad sizes and null buffers before any
+    launch (no device needed); empty requests succeed."""
+    L = _lib()
+    c_f = ctypes.c_float
+    EINVAL = 1
+    buf = ctypes.c_void_p(16)  # never dereferenced: the arguments are rejected first
+    assert L.dpf_feature_stats(None, 100, 3, 3, None, None, c_f(1e-3), None) == EINVAL
+    assert L.dpf_feature_stats(buf, 1, 3, 3, buf, buf, c_f(1e-3), None) == EINVAL       # n < 2
+    assert L.dpf_feature_stats(buf, 10, 4, 3, buf, buf, c_f(1e-3), None) == EINVAL      # cols > ld
+    assert L.dpf_feature_stats(buf, 10, 3, 3, buf, buf, c_f(-1.0), None) == EINVAL      # negative floor
+    assert L.dpf_standardize(buf, 10, 5, 4, buf, buf, buf, 8, None) == EINVAL           # cols > ld
+    assert L.dpf_standardize(buf, 0, 3, 3, buf, buf, buf, 8, None) == 0                 # nothing to do
+    assert L.dpf_permutation(1, 0, -1, buf, None) == EINVAL
+    assert L.dpf_permutation(1, 0, 1 << 31, buf, None) == EINVAL
+    assert L.dpf_permutation(1, 0, 0, None, None) == 0
+    assert L.dpf_permutation(1, 0, 5, None, None) == EINVAL
+    assert L.dpf_gather_rows(buf, 10, 3, 2, buf, 4, buf, 3, None) == EINVAL             # cols > ld_src
+    assert L.dpf_gather_rows(None, 10, 3, 3, None, 0, None, 3, None) == 0               # count 0
+
+
 def test_run_calls_reject_null_handles():
     # both runs check their handle before touching it
     L = _lib()
