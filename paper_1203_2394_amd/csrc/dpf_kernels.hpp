@@ -539,6 +539,11 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
   __shared__ double cdf[NSEG][kCond ? 1 : CAP];
   __shared__ float cz[NSEG][kCond ? CAP : 1][DZ];
   __shared__ float lms[NSEG][kCond ? CAP : 1];
+  // each lane's conditioned weights of its current candidate, kept between
+  // the total and the cumulative pass when the cloud is small (row padded
+  // by one word: lanes at the same index fall in different banks)
+  constexpr bool kWCache = kCond && CAP <= 32;
+  __shared__ float wc[kWCache ? kBlock : 1][kWCache ? CAP + 1 : 1];
   constexpr bool kH = has_yhat<Mdl>();
   const int4 tile = a.tiles[ti];
   const int f = tile.x;
@@ -701,17 +706,24 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
           if (finitef(kp)) mx = fmaxf(mx, kp);
         }
         const bool deg = !(mx > -INFINITY);
-        auto weight = [&](int jj) -> double {
+        auto weight = [&](int jj) -> float {
           const float kp = kappa(jj);
-          return deg ? 1.0 : (finitef(kp) ? (double)fast_exp(kp - mx) : 0.0);
+          return deg ? 1.0f : (finitef(kp) ? fast_exp(kp - mx) : 0.0f);
         };
         double total = 0.0;
         int lastpos = 0;
         for (int jj = 0; jj < M; ++jj) {
-          const double w = weight(jj);
-          total += w;
-          if (w > 0.0) lastpos = jj;
+          const float w = weight(jj);
+          if constexpr (kWCache) wc[kWCache ? threadIdx.x : 0][kWCache ? jj : 0] = w;
+          total += (double)w;
+          if (w > 0.0f) lastpos = jj;
         }
+        // the third pass takes these weights back (small clouds) or forms
+        // them again, the same values either way
+        auto weight3 = [&](int jj) -> double {
+          if constexpr (kWCache) return (double)wc[kWCache ? threadIdx.x : 0][kWCache ? jj : 0];
+          else return (double)weight(jj);
+        };
         const double u = uniform53_ab(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_B);
         float pre[Mdl::NPRE], r0[DY];
         Mdl::fz_pre(as_prm(a.prm), x, xl[r], t - 1, pre);
@@ -747,7 +759,7 @@ __device__ __forceinline__ void la_weights_nested_tile(const StepArgs& a, int ti
             const double P = sys_point(k, u, total, K);
             while (!(c > P) && jc + 1 < M) {
               ++jc;
-              c += weight(jc);
+              c += weight3(jc);
             }
             emit(c > P ? jc : lastpos, nb + q * DZ);
           }
