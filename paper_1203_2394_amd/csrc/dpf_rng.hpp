@@ -43,9 +43,9 @@ struct Words {
   uint32_t w[4];
 };
 
-// Ten Philox4x32 rounds.  Each 32x32->64 product is one v_mad_u64_u32.
-// (gfx950's three-input v_bitop3_b32 would take each round's two exclusive
-// ors in one instruction, but measured slower in the step kernels.)
+// Ten Philox4x32 rounds.  Each 32x32->64 product is one v_mad_u64_u32; each
+// three-way exclusive or (hi(p) ^ c ^ k) one gfx950 v_bitop3_b32 (truth
+// table 0x96, odd parity of its three inputs).
 __device__ __forceinline__ Words philox(Key key, uint32_t c0, uint32_t c1, uint32_t c2,
                                         uint32_t c3) {
   constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
@@ -59,8 +59,8 @@ __device__ __forceinline__ Words philox(Key key, uint32_t c0, uint32_t c1, uint3
     }
     const uint64_t p0 = (uint64_t)M0 * c0;
     const uint64_t p1 = (uint64_t)M1 * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
