@@ -199,6 +199,14 @@ __device__ __forceinline__ void fz_pre_seg(Prm P, const float* xp, const float* 
   }
 }
 
+// Minimum waves per SIMD the compiler must leave room for: two for the
+// wide-z models (their per-particle arrays would otherwise take the whole
+// register file for one wave), no constraint otherwise.
+template <class Mdl>
+constexpr int min_waves() {
+  return Mdl::kStreamZ ? 2 : 1;
+}
+
 // Whether filter f takes this step: the caller's mask and the run limits,
 // evaluated by the weights kernel (before the time advances) and recorded in
 // act[f] for the later kernels of the step.
@@ -798,7 +806,7 @@ static __device__ bool learned_rejected(const StepArgs& a, int f, int N, float* 
 // markedly slower code for the single-tile case, so the learned step's
 // fallback has kernels of its own.)
 template <class Mdl, int SEG, int JPT>
-static __global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
+static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_waves<Mdl>()))) void k_la_weights(StepArgs a) {
   la_weights_tile<Mdl, SEG, JPT>(a, blockIdx.x, false);
 }
 
@@ -808,7 +816,7 @@ static __global__ __launch_bounds__(kBlock) void k_la_weights(StepArgs a) {
 // tile records the decision and the fallback flag), and runs the look-ahead
 // weights only for the tiles of rejecting filters.
 template <class Mdl, int SEG, int JPT>
-static __global__ __launch_bounds__(kBlock) void k_la_weights_fallback(StepArgs a) {
+static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_waves<Mdl>()))) void k_la_weights_fallback(StepArgs a) {
   __shared__ int tfl[kBlock], runs[kBlock], todo[kBlock], wcnt[kBlock / kWave];
   __shared__ unsigned char rejr[kBlock];
   __shared__ float fred4[kBlock / kWave];
@@ -2148,14 +2156,14 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
 }
 
 template <class Mdl, int SEG, int JPT, bool PLAIN>
-static __global__ __launch_bounds__(kBlock) void k_newcloud(StepArgs a) {
+static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_waves<Mdl>()))) void k_newcloud(StepArgs a) {
   newcloud_tile<Mdl, SEG, JPT, PLAIN>(a, blockIdx.x);
 }
 
 // Learned step: the new clouds of the filters that fell back only (smaller
 // grid looping over the tiles, tiles checked at once).
 template <class Mdl, int SEG, int JPT>
-static __global__ __launch_bounds__(kBlock) void k_newcloud_fallback(StepArgs a) {
+static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_waves<Mdl>()))) void k_newcloud_fallback(StepArgs a) {
   constexpr bool PLAIN = false;
   // the first n_commit workgroups commit the filters that kept their
   // learned proposals

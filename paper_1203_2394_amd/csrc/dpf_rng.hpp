@@ -80,9 +80,11 @@ __device__ __forceinline__ Words draw(Key key, uint32_t t, uint32_t a, uint32_t 
 }
 
 // (2 floor(w / 2^9) + 1) / 2^24, the centre of one of 2^23 equal cells: the
-// top 23 bits scaled, plus half a cell, in one exact FMA.
+// top 23 bits placed under the exponent of 1.0 (one v_alignbit_b32 forms
+// 1 + floor(w / 2^9) 2^-23), minus 1 - 2^-24; the subtraction is exact (its
+// operands lie within a factor of two of each other).
 __device__ __forceinline__ float u24f(uint32_t w) {
-  return __builtin_fmaf((float)(w >> 9), 0x1p-23f, 0x1p-24f);
+  return __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, w, 9u)) - 0x1.fffffep-1f;
 }
 
 __device__ __forceinline__ double u53(uint32_t w0, uint32_t w1) {
