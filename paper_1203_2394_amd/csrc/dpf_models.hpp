@@ -63,6 +63,19 @@ __device__ __forceinline__ Prm as_prm(const float* p) { return (Prm)p; }
 __device__ __forceinline__ float fast_exp(float v) { return __builtin_amdgcn_exp2f(v * kLog2e); }
 __device__ __forceinline__ float fast_log(float v) { return __builtin_amdgcn_logf(v) * 0.6931471805599453f; }
 
+// cos a and sin a for an angle in radians that runs to thousands (a drift
+// in t): a / 2 pi reduced to [-1/2, 1/2] revolutions in double, then the
+// hardware cosine / sine of that many revolutions in FP32 (absolute error of
+// order 1e-6; the FP64 library functions cost tens of FP64 instructions).
+__device__ __forceinline__ float cos_rad(double a) {
+  const double r = a * 0.15915494309189535;
+  return __builtin_amdgcn_cosf((float)(r - rint(r)));
+}
+__device__ __forceinline__ float sin_rad(double a) {
+  const double r = a * 0.15915494309189535;
+  return __builtin_amdgcn_sinf((float)(r - rint(r)));
+}
+
 // tanh(a) = sign(a) (1 - 2 / (exp(2|a|) + 1)); absolute error ~1e-7.
 __device__ __forceinline__ float tanh_f(float a) {
   const float e = fast_exp(2.0f * fabsf(a));
@@ -400,10 +413,7 @@ struct Table1M1 {
   using L = Layout;
 
   __device__ static float sat(float v) { return v / (1.0f + v * v); }
-  // the angle in double (t runs to thousands of radians)
-  __device__ static float cyc(Prm P, int t) {
-    return (float)((double)P[L::amp] * cos((double)P[L::freq] * (double)t));
-  }
+  __device__ static float cyc(Prm P, int t) { return P[L::amp] * cos_rad((double)P[L::freq] * (double)t); }
   // whether the outer variable follows the slow law at t
   __device__ static bool outer_slow(Prm P, int t) { return ((float)t >= P[L::tswap]) == ZF; }
   __device__ static float mean_o(Prm P, float o, float i, int t) {
@@ -451,7 +461,10 @@ struct Table1M1 {
     }
   }
   __device__ static float logpx_post(Prm P, const float* c, const float* z) {
-    const float e = c[0] - c[1] * z[0] - c[2] * sat(z[0]);
+    // (c[2] is 0 under the growth law of the outer variable: sat(i) is
+    // skipped, the same value as multiplying it by 0 for finite i)
+    const float si = c[2] != 0.0f ? c[2] * sat(z[0]) : 0.0f;
+    const float e = c[0] - c[1] * z[0] - si;
     return P[L::co] - 0.5f * P[L::inv_qo] * e * e;
   }
   __device__ static float logpx(Prm P, const float* xn, const float* x, const float* z, int t) {
@@ -490,14 +503,13 @@ struct FourDim {
   };
   using L = Layout;
 
-  // the time-dependent drift in double (t runs to thousands of radians)
-  __device__ static float drift_x(Prm P, int t) { return (float)((double)P[L::bs] * sin((double)t)); }
+  __device__ static float drift_x(Prm P, int t) { return P[L::bs] * sin_rad((double)t); }
   __device__ static void fx(Prm P, const float* x, const float*, const float* nu, int t, float* xn) {
     xn[0] = P[L::a1] * x[0] + drift_x(P, t) + P[L::sx1] * nu[0];
     xn[1] = P[L::c21] * x[0] + P[L::a2] * x[1] + P[L::sx2] * nu[1];
   }
   __device__ static float fz_pre_k(Prm P, const float*, const float*, int t, int k) {
-    return k == 1 ? (float)((double)P[L::amp] * cos((double)P[L::freq] * (double)t)) : 0.0f;
+    return k == 1 ? P[L::amp] * cos_rad((double)P[L::freq] * (double)t) : 0.0f;
   }
   __device__ static void fz_pre(Prm P, const float* x, const float* xn, int t, float* pre) {
     pre[0] = 0.0f;
