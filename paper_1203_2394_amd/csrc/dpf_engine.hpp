@@ -37,8 +37,9 @@ struct ClassShape {
 // the default is one wave per outer particle with four inner particles per
 // lane, which measured faster than a 256-lane workgroup per particle.
 static constexpr ClassShape kClasses[] = {{32, 1}, {64, 1}, {128, 1}, {64, 4},  {256, 4}, {256, 16},
-                                          {32, 2}, {32, 4}, {64, 2},  {256, 1}, {128, 2}};
-constexpr int kNumClasses = 11;
+                                          {32, 2}, {32, 4}, {64, 2},  {256, 1}, {128, 2},
+                                          {16, 2}, {16, 4}, {16, 8}};
+constexpr int kNumClasses = 14;
 constexpr int kNumDefaultClasses = 6;
 
 struct TileClass {

@@ -99,6 +99,9 @@ static dpf_status engine_launch(int op, const StepArgs& a, const TileClass& tc, 
     case 8: launch_op<Mdl, 64, 2>(op, a, n, s); break;
     case 9: launch_op<Mdl, 256, 1>(op, a, n, s); break;
     case 10: launch_op<Mdl, 128, 2>(op, a, n, s); break;
+    case 11: launch_op<Mdl, 16, 2>(op, a, n, s); break;
+    case 12: launch_op<Mdl, 16, 4>(op, a, n, s); break;
+    case 13: launch_op<Mdl, 16, 8>(op, a, n, s); break;
     default: return fail(DPF_EUNSUPPORTED, "no kernel class %d", tc.cls);
   }
   LAUNCH_CHECK("step kernel");

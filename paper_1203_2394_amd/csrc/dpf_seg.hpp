@@ -1,7 +1,7 @@
 // Segment primitives for 256-thread workgroups on wave64 hardware.
 //
 // A workgroup is split into 256/SEG segments of SEG lanes (SEG in
-// {32, 64, 128, 256}); one segment serves one outer particle's inner cloud
+// {16, 32, 64, 128, 256}); one segment serves one outer particle's inner cloud
 // of M <= SEG*JPT inner particles, lane l handling inner indices
 // l, l+SEG, ... (coalesced in the [N][dz][M] layout).  Segments of up to 64
 // lanes live inside one wavefront and reduce / scan with cross-lane
@@ -195,10 +195,15 @@ __device__ __forceinline__ double seg_scan_incl(double v, SegScratch& sh, double
   constexpr int W = wave_width<SEG>();
   v = seg_scan_wave<W>(v);
   if constexpr (SEG <= kWave) {
-    if constexpr (W == 32)
+    if constexpr (W == 16) {
+      const int row = (threadIdx.x & 63) >> 4;
+      const double t0 = readlane_d(v, 15), t1 = readlane_d(v, 31), t2 = readlane_d(v, 47), t3 = readlane_d(v, 63);
+      total = row == 0 ? t0 : (row == 1 ? t1 : (row == 2 ? t2 : t3));
+    } else if constexpr (W == 32) {
       total = (threadIdx.x & 63) < 32 ? readlane_d(v, 31) : readlane_d(v, 63);
-    else
+    } else {
       total = readlane_d(v, 63);
+    }
   } else {
     const int w = threadIdx.x / kWave;
     if ((threadIdx.x & (kWave - 1)) == kWave - 1) sh.d[0][w] = v;

@@ -9,8 +9,9 @@
 //               and max are commutative, so all lanes hold identical bits);
 //   row scan:   row_shr 1, 2, 4, 8 with zero fill (Hillis-Steele);
 //   rows:       row totals read with readlane and combined in a fixed order.
-// FP64 values move as two 32-bit halves.  Segments of 32 lanes are two
-// rows; 64 lanes are the whole wave.  Every lane of the wave must be active.
+// FP64 values move as two 32-bit halves.  Segments of 16 lanes are rows, of
+// 32 lanes two rows; 64 lanes are the whole wave.  Every lane of the wave
+// must be active.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -98,12 +99,12 @@ __device__ __forceinline__ T seg_reduce_wave(T v) {
   }
 }
 
-// Inclusive sum scan over segments of W lanes (W = 32 or 64).  Lanes of a
-// row combine in Hillis-Steele order, so neighbouring prefixes may differ in
-// association (at the rounding level) from a serial sum.
+// Inclusive sum scan over segments of W lanes (W = 16, 32 or 64).  Lanes of
+// a row combine in Hillis-Steele order, so neighbouring prefixes may differ
+// in association (at the rounding level) from a serial sum.
 template <int W, class T>
 __device__ __forceinline__ T seg_scan_wave(T v) {
-  static_assert(W == 32 || W == 64, "segment width");
+  static_assert(W == 16 || W == 32 || W == 64, "segment width");
   const T z = T(0);
   if constexpr (sizeof(T) == 8) {
     v += dpp_d<kDppRowShr1>(v, z);
@@ -116,6 +117,7 @@ __device__ __forceinline__ T seg_scan_wave(T v) {
     v += dpp_f<kDppRowShr4>(v, z);
     v += dpp_f<kDppRowShr8>(v, z);
   }
+  if constexpr (W == 16) return v;
   const T t0 = readlane_of(v, 15), t1 = readlane_of(v, 31), t2 = readlane_of(v, 47);
   const int row = (threadIdx.x & 63) >> 4;
   if constexpr (W == 32) {

@@ -126,7 +126,7 @@ def test_learned_calls_reject_null_handles():
 def test_tile_class_table():
     classes = dpf.tile_classes()
     assert classes[:6] == [(32, 1), (64, 1), (128, 1), (64, 4), (256, 4), (256, 16)]
-    assert set(classes[6:]) == {(32, 2), (32, 4), (64, 2), (256, 1), (128, 2)}
+    assert set(classes[6:]) == {(32, 2), (32, 4), (64, 2), (256, 1), (128, 2), (16, 2), (16, 4), (16, 8)}
     assert all(256 % seg == 0 for seg, _ in classes)
     assert _lib().dpf_set_tiling(None, None) == 1
 

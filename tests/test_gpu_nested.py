@@ -36,20 +36,24 @@ SPECS = {
 }
 
 
-@pytest.mark.parametrize("name,N,M,K,warm,steps", [
-    ("lingauss", 103, 50, 3, 2, 2),
-    ("lingauss_coupled", 64, 37, 4, 2, 2),
-    ("lingauss_coupled", 9, 300, 3, 1, 1),     # a 256-lane segment per particle
-    ("nonlin", 150, 64, 2, 1, 2),
-    ("nonlin", 20, 300, 5, 1, 1),
-    ("highdim", 6, 256, 2, 1, 1),
-    ("twodim", 100, 10, 8, 3, 2),
-    ("twodim", 60, 20, 4, 5, 2),
-    ("twodim", 7, 300, 2, 2, 1),
-    ("fourdim", 90, 20, 8, 3, 2),
-    ("fourdim", 40, 128, 1, 2, 1),
+@pytest.mark.parametrize("name,N,M,K,warm,steps,cls", [
+    ("lingauss", 103, 50, 3, 2, 2, None),
+    ("lingauss_coupled", 64, 37, 4, 2, 2, None),
+    ("lingauss_coupled", 9, 300, 3, 1, 1, None),     # a 256-lane segment per particle
+    ("nonlin", 150, 64, 2, 1, 2, None),
+    ("nonlin", 20, 300, 5, 1, 1, None),
+    ("highdim", 6, 256, 2, 1, 1, None),
+    ("twodim", 100, 10, 8, 3, 2, None),
+    ("twodim", 60, 20, 4, 5, 2, None),
+    ("twodim", 7, 300, 2, 2, 1, None),
+    ("fourdim", 90, 20, 8, 3, 2, None),
+    ("fourdim", 40, 128, 1, 2, 1, None),
+    # 16-lane segments: (16, 2), (16, 4), (16, 8)
+    ("twodim", 61, 20, 8, 3, 2, 11),
+    ("lingauss_coupled", 42, 50, 3, 2, 1, 12),
+    ("nonlin", 50, 100, 2, 1, 1, 13),
 ])
-def test_nested_step_parity(name, N, M, K, warm, steps):
+def test_nested_step_parity(name, N, M, K, warm, steps, cls):
     spec = SPECS[name]()
     model = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
     seed = 6161
@@ -59,6 +63,8 @@ def test_nested_step_parity(name, N, M, K, warm, steps):
     for t in range(warm):
         st, _ = ladpf.step(model, st, ys[t], seed, 0, n_comp=K)
     f = dpf.Filter(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob, [N], [M], seed=seed)
+    if cls is not None:
+        f.set_tiling([cls])
     f.set_companions(K)
     predict = spec.dy == 1
     if predict:

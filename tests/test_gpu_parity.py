@@ -278,7 +278,11 @@ def _tiling_start_cached(name, algo, N, M, seed):
     ("nonlin", 10, 200, 150), ("nonlin", 10, 256, 150),
     ("lingauss_coupled", 9, 200, 90), ("lingauss_coupled", 10, 150, 90), ("lingauss_coupled", 3, 100, 90),
     ("nonlin", 9, 8, 16700), ("nonlin", 3, 8, 16700), ("nonlin", 0, 8, 16700),
-    ("twodim", 9, 200, 90), ("twodim", 7, 100, 90), ("fourdim", 8, 100, 90), ("fourdim", 10, 256, 90)])
+    ("twodim", 9, 200, 90), ("twodim", 7, 100, 90), ("fourdim", 8, 100, 90), ("fourdim", 10, 256, 90),
+    # 16-lane segments (four outer particles per wave)
+    ("nonlin", 11, 32, 150), ("nonlin", 12, 50, 151), ("nonlin", 13, 128, 150), ("nonlin", 13, 100, 16700),
+    ("lingauss_coupled", 11, 20, 90), ("lingauss_coupled", 12, 64, 91), ("lingauss_coupled", 13, 77, 90),
+    ("twodim", 12, 40, 90), ("fourdim", 13, 128, 90)])
 @pytest.mark.parametrize("algo", ["lookahead", "plain"])
 def test_step_parity_under_every_tiling(name, cls, M, N, algo):
     """The same step under a non-default tile class (SEG, JPT) matches the
