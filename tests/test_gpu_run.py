@@ -306,22 +306,25 @@ def test_autotuner_picks_a_measured_class_and_round_trips(tmp_path):
     assert np.all(np.isfinite(xt.cpu().numpy()))
 
 
-def _lingauss_tuned_handle(seed):
-    """Three linear-Gaussian filters under the batched run's tuned classes:
-    (32, 1), (32, 2) and (32, 4) for M = 32, 64 and 128."""
+def _lingauss_tuned_handle(seed, cls):
+    """Three linear-Gaussian filters (M = 32, 64, 128) under tile classes the
+    autotuner picks for the batched run: the 16-lane (16, 2), (16, 4), (16, 8)
+    or the 32-lane (32, 1), (32, 2), (32, 4)."""
     spec = S.lingauss_c1(False)
-    N, M, cls = [300, 200, 150], [32, 64, 128], [0, 6, 7]
+    N, M = [300, 200, 150], [32, 64, 128]
     f = _filter(spec, N, M, seed=seed)
     f.set_tiling(cls)
     return spec, N, M, f
 
 
-def test_tuned_batched_classes_match_oracle():
+@pytest.mark.parametrize("cls", [[11, 12, 13], [0, 6, 7]])
+def test_tuned_batched_classes_match_oracle(cls):
     """The tile classes the autotuner picks for the batched linear-Gaussian
     run, in one ragged handle, two consecutive steps each compared with the
     oracle per filter (every step starts from the oracle's state, rounded)."""
     seed = 4040
-    spec, N, M, g = _lingauss_tuned_handle(seed)
+    assert [dpf.tile_classes()[c][0] for c in cls] in ([16, 16, 16], [32, 32, 32])
+    spec, N, M, g = _lingauss_tuned_handle(seed, cls)
     model = make_model(spec.kind, spec.dx, spec.dz, spec.dy, spec.blob)
     F = len(N)
     ys = np.stack([S.simulate(spec, 4, 90 + f)[2] for f in range(F)], axis=1)  # [T][F][1]
@@ -359,18 +362,19 @@ def test_tuned_batched_classes_match_oracle():
         states = nxt
 
 
-def test_tuned_batched_classes_run_equals_step_calls():
+@pytest.mark.parametrize("cls", [[11, 12, 13], [0, 6, 7]])
+def test_tuned_batched_classes_run_equals_step_calls(cls):
     """Under the same classes, a graph-replayed run (fused steps: each step's
     look-ahead weights inside the previous new-cloud launch) equals step
     calls bit for bit, with per-filter horizons across a chunk boundary."""
     T = 21
-    spec, N, M, a = _lingauss_tuned_handle(77)
+    spec, N, M, a = _lingauss_tuned_handle(77, cls)
     Y = np.stack([S.simulate(spec, T, 130 + f)[2] for f in range(len(N))], axis=1).astype(np.float32)
     Tf = [21, 18, 9]
     for t in range(T):
         act = np.array([t < Tf[f] for f in range(len(N))], dtype=np.uint8)
         a.lookahead_step(torch.from_numpy(Y[t]), active=act)
-    _, _, _, b = _lingauss_tuned_handle(77)
+    _, _, _, b = _lingauss_tuned_handle(77, cls)
     b.run(torch.from_numpy(Y), Tf=Tf, use_graph=True)
     assert np.array_equal(a.export_state().cpu().numpy(), b.export_state().cpu().numpy())
     ea, eb = a.estimate(), b.estimate()
