@@ -2155,9 +2155,22 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
   if (vk && ls == 0 && fl) atomicOr(&a.flags[f], fl);
 }
 
+// Workgroups are dealt to the eight XCDs in turn (workgroup b to XCD b % 8).
+// The tile of workgroup b when each XCD instead takes one contiguous run of
+// the n tiles: a bijection of [0, n).
+__device__ __forceinline__ int xcd_contiguous_tile(int b, int n) {
+  constexpr int kXcd = 8;
+  const int q = n / kXcd, r = n % kXcd, x = b % kXcd;
+  return x * q + min(x, r) + b / kXcd;
+}
+
+// With the wide inner state the children of one parent (neighbouring tiles
+// after the ordered resampling) run on one XCD and read the parent's cloud
+// through one L2.
 template <class Mdl, int SEG, int JPT, bool PLAIN>
 static __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(min_waves<Mdl>()))) void k_newcloud(StepArgs a) {
-  newcloud_tile<Mdl, SEG, JPT, PLAIN>(a, blockIdx.x);
+  const int ti = Mdl::kStreamZ ? xcd_contiguous_tile((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  newcloud_tile<Mdl, SEG, JPT, PLAIN>(a, ti);
 }
 
 // Learned step: the new clouds of the filters that fell back only (smaller
