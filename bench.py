@@ -68,14 +68,20 @@ BYTES_PER_OUTER = 4 + 8 * DX + 8 + 4 * DZ + 4
 # slot: one 32-bit lane operation; 32x32->64 products and transcendentals
 # issue at quarter rate on CDNA and count 4).  A Philox4x32-10 block is ten
 # rounds of two products and four exclusive ors; a U24 uniform is shift,
-# convert, FMA; a Box-Muller pair is log, sqrt, cos, sin and three products.
+# convert, FMA; a remnant uniform four more to gather its bits; a Box-Muller
+# pair is log, sqrt, cos, sin and three products.
 PHILOX_BLOCK = 10 * (2 * 4 + 4)
 BM_PAIR = 4 * 4 + 3
 
 
 def normals_slots(n):
-    """Issue slots for n standard normals (Philox blocks of four words)."""
-    return ((n + 3) // 4) * PHILOX_BLOCK + n * 3 + (n // 2) * BM_PAIR
+    """Issue slots for the first n standard normals of a draw in the packed
+    layout (ten per two Philox blocks, the last two of each ten from the
+    blocks' remnant uniforms)."""
+    q, r = divmod(n, 10)
+    blocks = 2 * q + (r > 0) + (r > 4)
+    remnant = 2 * q + max(0, r - 8)
+    return blocks * PHILOX_BLOCK + n * 3 + remnant * 4 + ((n + 1) // 2) * BM_PAIR
 
 
 ISSUE_PER_UPDATE = {
@@ -84,11 +90,12 @@ ISSUE_PER_UPDATE = {
     # FP64 compare-and-select steps), eq:qbar and the weighted moments
     "new_z": normals_slots(DZ),
     "propagate_and_weigh": 2 * DZ + 2 * DY + 2 + 8 * 3 + 4 + 2 + 3 * DZ,
-    # the next step's look-ahead weight: LA_X and LA_Z normals, f^x (growth
+    # the next step's look-ahead weight: the candidate's draw (x's normals,
+    # then z's), f^x (growth
     # term: two products, add, reciprocal, FMAs), f^z's tanh(W x) (two FMAs,
     # exp and reciprocal, three more), f^z, the observation residual and
     # log p(y|x, z), ell = lam + that, and the running log-sum-exp
-    "la_normals": normals_slots(DX) + normals_slots(DZ),
+    "la_normals": normals_slots(DX + DZ),
     "la_model": DX * 10 + DZ * (2 * DX + 2 * 4 + 4) + 2 * DZ + DY + 2 * DY + 2 + 1 + 4 + 4,
 }
 VALU_SLOTS_PER_UPDATE = sum(ISSUE_PER_UPDATE.values())

@@ -203,10 +203,12 @@ dpf_status dpf_run(dpf_handle* h, const float* d_Y, int32_t T, const int32_t* d_
  * companions z drawn from the inner predictive given the candidate -- their
  * ancestors by systematic resampling (U53 of purpose LA_B = 13 at (t, i, m))
  * of the inner weights conditioned on the candidate as in eq:qnobar, their
- * propagation with LA_Z normals k dz .. k dz + dz - 1 at (t, i, m):
+ * propagation with LA_Z normals k dz .. k dz + dz - 1 at (t, i, m) (block-
+ * aligned layout: normal n from Philox block n / 4):
  *   ell^{(i,m)} = log qbar^{(i,m)} + log (1/K) sum_k p(y_t | x^{(i,m)}, z^{(i,m,k)}).
  * n_comp = 0 (the default): one companion drawn together with the candidate
- * from the same inner component.  1 <= K <= 1024; DPF_ESTATE for a plain
+ * from the same inner component (normals dx .. dx + dz - 1 of the candidate's
+ * LA_X draw).  1 <= K <= 1024; DPF_ESTATE for a plain
  * handle.  Takes effect from the next dpf_lookahead_step / dpf_run (a run
  * with K >= 1 takes each step whole instead of computing the next step's
  * weights inside the new-cloud launch; results still equal step calls).  Cost
@@ -435,7 +437,11 @@ dpf_status dpf_philox_words(uint64_t seed, uint32_t filter_id, const uint32_t* d
                             uint32_t* d_out, void* hip_stream);
 
 /* FP32 standard normals of the random-number contract: d_out [n_a][n_b][D]
- * = normal d of counter (t, a, b, purpose) for a < n_a, b < n_b. */
+ * = normal d of counter (t, a, b, purpose) for a < n_a, b < n_b, in the
+ * packed layout (ten normals per two Philox blocks: normals 10q .. 10q+7
+ * from the words of blocks 2q and 2q+1, normals 10q+8 and 10q+9 from the two
+ * blocks' remnant uniforms).  D in {1, 2, 4, 8, 10, 64, 68}, else
+ * DPF_EUNSUPPORTED. */
 dpf_status dpf_normals(uint64_t seed, uint32_t filter_id, uint32_t t, uint32_t purpose, int32_t n_a,
                        int32_t n_b, int32_t D, float* d_out, void* hip_stream);
 

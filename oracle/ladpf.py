@@ -15,7 +15,8 @@ Step t, given y_t, in the order of Fig. 4:
    Drawing x from every inner component once, weighted by qbar, is the
    mixture eq:approx1; each candidate carries one companion z
    (N_x' = M candidates with N_z' = 1 companion each, the O(N M) cost stated
-   after eq:weightsMC).
+   after eq:weightsMC).  Both come from one draw at (t, i, j) of purpose
+   LA_X: normals 0 .. dx-1 for x, dx .. dx+dz-1 for z (packed layout).
 2. Weights (eq:weightsMC): ell^{(i,j)} = lam^{(i,j)} + log p(y_t | xla, zla)
    and log w^{(i)} = logsumexp_j ell^{(i,j)}, an estimate of the predictive
    likelihood p(y_t | y_{0:t-1}, x_{0:t-1}^{(i)}) that eq:weightsopt makes the
@@ -43,7 +44,7 @@ weights conditioned on the candidate as in eq:qnobar,
 kappa_j = lam^{(i,j)} + log p(xla^{(i,m)} | x_{t-1}^{(i)}, z_{t-1}^{(i,j)}),
 and are propagated with the inner prior, zla^{(i,m,k)} ~
 p(z_t | x_{t-1}^{(i)}, xla^{(i,m)}, z_{t-1}^{(i,b_k)}) (LA_Z normals k dz ..
-k dz + dz - 1 of the draw at (t, i, m)); then
+k dz + dz - 1 of the draw at (t, i, m), block-aligned layout); then
 ell^{(i,m)} = lam^{(i,m)} + log (1/K) sum_k p(y_t | xla^{(i,m)}, zla^{(i,m,k)})
 and log w^{(i)} = logsumexp_m ell^{(i,m)} as before.  Steps 3-4 are
 unchanged (the SIR of step 4 uses these ell).  Cost K M^2 model
@@ -96,8 +97,9 @@ def lookahead(model, state, y, seed, fid):
     N, M = lam.shape
     i = np.arange(N)[:, None]
     j = np.arange(M)[None, :]
-    nu_x = P.normals(seed, fid, t, i, j, P.LA_X, model.dx)
-    nu_z = P.normals(seed, fid, t, i, j, P.LA_Z, model.dz)
+    # one draw per candidate: x first, then z
+    nu = P.normals(seed, fid, t, i, j, P.LA_X, model.dx + model.dz)
+    nu_x, nu_z = nu[..., :model.dx], nu[..., model.dx:]
     xp = x[:, None, :]
     xla = model.fx(xp, z, nu_x, t - 1)
     zla = model.fz(xp, xla, z, nu_z, t - 1)
@@ -119,7 +121,7 @@ def lookahead_nested(model, state, y, seed, fid, K, u_comp=None):
     j_ = np.arange(M)[None, :]
     nu_x = P.normals(seed, fid, t, i_, j_, P.LA_X, model.dx)
     xla = model.fx(x[:, None, :], z, nu_x, t - 1)
-    nu_z = P.normals(seed, fid, t, i_, j_, P.LA_Z, K * dz).reshape(N, M, K, dz)
+    nu_z = P.normals_blocked(seed, fid, t, i_, j_, P.LA_Z, K * dz).reshape(N, M, K, dz)
     if u_comp is None:
         u_comp = P.uniform53_ab(seed, fid, t, i_, j_, P.LA_B)
     ell = np.empty((N, M))

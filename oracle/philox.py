@@ -18,10 +18,20 @@ index of the 4-word block within one draw.
 Transforms (exact in FP32 and FP64):
     U24(w)      = (2 * (w >> 9) + 1) * 2**-24          in (0, 1)
     U53(w0, w1) = ((w0 << 21) | (w1 >> 11)) * 2**-53    in [0, 1)
-Normals: Box-Muller on word pairs; normal ``d`` of a draw comes from block
-``d // 4``; slots (w0, w1) give normals 4b, 4b+1 = r cos, r sin and
-(w2, w3) give 4b+2, 4b+3, with r = sqrt(-2 ln U24(w_even)) and the angle
-2 pi U24(w_odd).
+    R24(block)  = (2 * v + 1) * 2**-24,                  in (0, 1)
+                  v = (w0 & 0x1ff) | (w1 & 0x1ff) << 9 | (w2 & 0x1f) << 18
+R24 is the block's remnant uniform: 23 of the low bits that U24 leaves unused.
+Normals come from Box-Muller pairs: r = sqrt(-2 ln a), (r cos 2 pi b,
+r sin 2 pi b) for two uniforms (a, b).  Within a block, slots (w0, w1) and
+(w2, w3) form the pairs (U24(w0), U24(w1)) and (U24(w2), U24(w3)).
+
+Layout of a draw's normals (packed): ten per two blocks.  Normal d = 10 q + r
+comes, for r < 8, from block 2q + r // 4 (normals 4 per block in slot order,
+cosine first), and for r = 8, 9 from the pair (R24(block 2q), R24(block 2q+1)).
+The first eight normals of a draw are therefore those of blocks 0 and 1 in
+slot order.  The nested look-ahead estimator's companion draws use the
+block-aligned layout instead (normal d from block d // 4, no remnant pairs),
+so that one block serves several companions (``normals_blocked``).
 """
 import numpy as np
 
@@ -114,8 +124,53 @@ def uniform53_ab(seed, filter_id, t, a, b, purpose):
     return u53(w[..., 0], w[..., 1])
 
 
+def r24(w):
+    """The remnant uniform of a block (words on the last axis): 23 of the
+    low bits U24 leaves unused, (2 v + 1) 2^-24."""
+    w = np.asarray(w, dtype=np.uint64)
+    v = ((w[..., 0] & np.uint64(0x1FF)) | ((w[..., 1] & np.uint64(0x1FF)) << np.uint64(9))
+         | ((w[..., 2] & np.uint64(0x1F)) << np.uint64(18)))
+    return (v * np.uint64(2) + np.uint64(1)).astype(np.float64) * 2.0 ** -24
+
+
+def _box_muller(ua, ub):
+    r = np.sqrt(-2.0 * np.log(ua))
+    ang = 2.0 * np.pi * ub
+    return r * np.cos(ang), r * np.sin(ang)
+
+
 def normals(seed, filter_id, t, a, b, purpose, D):
-    """D standard normals per counter (t, a, b), shape broadcast(a, b) + (D,)."""
+    """D standard normals per counter (t, a, b) in the packed layout (ten per
+    two blocks, see the module text), shape broadcast(a, b) + (D,)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    shape = np.broadcast(a, b).shape
+    out = np.empty(shape + (D,), dtype=np.float64)
+    for q in range((D + 9) // 10):
+        base = 10 * q
+        blocks = [words(seed, filter_id, t, a, b, purpose, 2 * q + h) if base + 4 * h < D or base + 8 < D
+                  else None for h in range(2)]
+        for h in range(2):
+            w = blocks[h]
+            for pair in range(2):
+                d0 = base + 4 * h + 2 * pair
+                if d0 >= D:
+                    continue
+                n0, n1 = _box_muller(u24(w[..., 2 * pair]), u24(w[..., 2 * pair + 1]))
+                out[..., d0] = n0
+                if d0 + 1 < D:
+                    out[..., d0 + 1] = n1
+        if base + 8 < D:
+            n0, n1 = _box_muller(r24(blocks[0]), r24(blocks[1]))
+            out[..., base + 8] = n0
+            if base + 9 < D:
+                out[..., base + 9] = n1
+    return out
+
+
+def normals_blocked(seed, filter_id, t, a, b, purpose, D):
+    """D standard normals per counter (t, a, b) in the block-aligned layout:
+    normal d from block d // 4, slot pairs as in the packed layout."""
     a = np.asarray(a)
     b = np.asarray(b)
     shape = np.broadcast(a, b).shape
@@ -126,9 +181,8 @@ def normals(seed, filter_id, t, a, b, purpose, D):
             d0 = 4 * blk + 2 * pair
             if d0 >= D:
                 break
-            r = np.sqrt(-2.0 * np.log(u24(w[..., 2 * pair])))
-            ang = 2.0 * np.pi * u24(w[..., 2 * pair + 1])
-            out[..., d0] = r * np.cos(ang)
+            n0, n1 = _box_muller(u24(w[..., 2 * pair]), u24(w[..., 2 * pair + 1]))
+            out[..., d0] = n0
             if d0 + 1 < D:
-                out[..., d0 + 1] = r * np.sin(ang)
+                out[..., d0 + 1] = n1
     return out

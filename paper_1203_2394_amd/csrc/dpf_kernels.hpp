@@ -363,12 +363,12 @@ __device__ __forceinline__ float la_logpy(const StepArgs& a, const Key& key, int
   }
 #pragma unroll
   for (int d = 0; d < Mdl::DY; ++d) y[d] = yi[d];
-  float nu_x[Mdl::DX], nu_z[Mdl::DZ], xl[Mdl::DX], pre[Mdl::NPRE], zl[Mdl::DZ], r0[Mdl::DY];
-  normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
-  normals<Mdl::DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, nu_z);
-  Mdl::fx(as_prm(a.prm), x, z, nu_x, t - 1, xl);
+  // one draw per candidate: x's normals first, then z's
+  float nu[Mdl::DX + Mdl::DZ], xl[Mdl::DX], pre[Mdl::NPRE], zl[Mdl::DZ], r0[Mdl::DY];
+  normals<Mdl::DX + Mdl::DZ>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu);
+  Mdl::fx(as_prm(a.prm), x, z, nu, t - 1, xl);
   Mdl::fz_pre(as_prm(a.prm), x, xl, t - 1, pre);
-  Mdl::fz_post(as_prm(a.prm), pre, z, nu_z, zl);
+  Mdl::fz_post(as_prm(a.prm), pre, z, nu + Mdl::DX, zl);
   Mdl::obs_pre(as_prm(a.prm), y, xl, r0);
   if constexpr (H) {
     // the noise-free observation of the draw, on opaque copies (no sharing
@@ -397,7 +397,8 @@ template <class Mdl>
 __device__ __forceinline__ float la_logpy_wave(const StepArgs& a, const Key& key, int t, int i, int j,
                                                const float* xi, const float* zi, const float* yrow,
                                                const float* ca) {
-  static_assert(Mdl::kStreamZ && Mdl::DZ % 4 == 0, "la_logpy_wave: wide-z models, DZ a multiple of 4");
+  static_assert(Mdl::kStreamZ && Mdl::DZ % 2 == 0 && Mdl::DX == 4,
+                "la_logpy_wave: wide-z models, DX = 4, DZ even");
   const Prm P = as_prm(a.prm);
   float x[Mdl::DX], z[Mdl::DZ];
 #pragma unroll
@@ -410,24 +411,23 @@ __device__ __forceinline__ float la_logpy_wave(const StepArgs& a, const Key& key
     z[d] = zi[d];
     asm volatile("" : "+v"(z[d]));
   }
+  // the candidate's draw: block 0 gives x's four normals (and its remnant
+  // uniform), z's normals 4 .. 4 + DZ - 1 follow in pairs
   float nu_x[Mdl::DX], xl[Mdl::DX], c[Mdl::NPL];
-  normals<Mdl::DX>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, nu_x);
+  const Words w0 = draw(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, 0u);
+  box_muller(w0.w[0], w0.w[1], nu_x[0], nu_x[1]);
+  box_muller(w0.w[2], w0.w[3], nu_x[2], nu_x[3]);
   Mdl::fx(P, x, z, nu_x, t - 1, xl);
   Mdl::fz_lite(P, x, xl, t - 1, c);
   WaveProj<Mdl> pj;
   pj.start();
-#pragma unroll
-  for (int g = 0; g < Mdl::DZ / 4; ++g) {
-    float nu4[4], z4[4];
-    normals_k<4>(key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_Z, g, nu4);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = 4 * g + q;
-      z4[q] = Mdl::fz_post_k(P, Mdl::fz_pre_lite(P, c, kk), z, nu4[q], kk);
-    }
-    pj.add(ca[2 * g], z4[0], z4[1]);
-    pj.add(ca[2 * g + 1], z4[2], z4[3]);
-  }
+  normal_pairs<Mdl::DX, Mdl::DX + Mdl::DZ, true>(
+      key, (uint32_t)t, (uint32_t)i, (uint32_t)j, P_LA_X, r24f(w0), [&](int d, float n0, float n1) {
+        const int kk = d - Mdl::DX;
+        const float z0 = Mdl::fz_post_k(P, Mdl::fz_pre_lite(P, c, kk), z, n0, kk);
+        const float z1 = Mdl::fz_post_k(P, Mdl::fz_pre_lite(P, c, kk + 1), z, n1, kk + 1);
+        pj.add(ca[kk / 2], z0, z1);
+      });
   return pj.logpy(P, yrow);
 }
 
@@ -1993,21 +1993,16 @@ __device__ __forceinline__ void newcloud_tile(const StepArgs& a, int ti) {
       const Prm P = as_prm(a.prm);
       WaveProj<Mdl> pj;
       pj.start();
-#pragma unroll
-      for (int g = 0; g < DZ / 4; ++g) {
-        float nu4[4];
-        normals_k<4>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, g, nu4);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int d = 4 * g + q;
-          zn[d] = Mdl::fz_post_k(P, pre[d], zg, nu4[q], d);
-          if (on) zdst[d * M + jj] = zn[d];
-        }
-        if (!PLAIN) {
-          pj.add(ca[2 * g], zn[4 * g], zn[4 * g + 1]);
-          pj.add(ca[2 * g + 1], zn[4 * g + 2], zn[4 * g + 3]);
-        }
-      }
+      normal_pairs<0, DZ, false>(key, (uint32_t)t, (uint32_t)k, (uint32_t)jj, PLAIN ? P_DPF_Z : P_NEW_Z, 0.f,
+                                 [&](int d, float n0, float n1) {
+                                   zn[d] = Mdl::fz_post_k(P, pre[d], zg, n0, d);
+                                   zn[d + 1] = Mdl::fz_post_k(P, pre[d + 1], zg, n1, d + 1);
+                                   if (on) {
+                                     zdst[d * M + jj] = zn[d];
+                                     zdst[(d + 1) * M + jj] = zn[d + 1];
+                                   }
+                                   if (!PLAIN) pj.add(ca[d / 2], zn[d], zn[d + 1]);
+                                 });
       if constexpr (kKeepZ) {
 #pragma unroll
         for (int d = 0; d < DZ; ++d) zkeep[kKeepZ ? r : 0][d] = zn[d];

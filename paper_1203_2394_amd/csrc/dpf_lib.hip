@@ -984,8 +984,10 @@ extern "C" dpf_status dpf_normals(uint64_t seed, uint32_t filter_id, uint32_t t,
     case 2: hipLaunchKernelGGL(k_normals_grid<2>, g, dim3(256), 0, s, key, t, purpose, n_a, n_b, d_out); break;
     case 4: hipLaunchKernelGGL(k_normals_grid<4>, g, dim3(256), 0, s, key, t, purpose, n_a, n_b, d_out); break;
     case 8: hipLaunchKernelGGL(k_normals_grid<8>, g, dim3(256), 0, s, key, t, purpose, n_a, n_b, d_out); break;
+    case 10: hipLaunchKernelGGL(k_normals_grid<10>, g, dim3(256), 0, s, key, t, purpose, n_a, n_b, d_out); break;
     case 64: hipLaunchKernelGGL(k_normals_grid<64>, g, dim3(256), 0, s, key, t, purpose, n_a, n_b, d_out); break;
-    default: return fail(DPF_EUNSUPPORTED, "D = %d (built: 1, 2, 4, 8, 64)", D);
+    case 68: hipLaunchKernelGGL(k_normals_grid<68>, g, dim3(256), 0, s, key, t, purpose, n_a, n_b, d_out); break;
+    default: return fail(DPF_EUNSUPPORTED, "D = %d (built: 1, 2, 4, 8, 10, 64, 68)", D);
   }
   LAUNCH_CHECK("k_normals_grid");
   return DPF_OK;

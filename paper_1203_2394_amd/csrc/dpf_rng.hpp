@@ -11,11 +11,21 @@
 // Transforms (exact in FP32 / FP64):
 //   U24(w)      = (2 (w >> 9) + 1) 2^-24          in (0, 1)
 //   U53(w0, w1) = ((w0 << 21) | (w1 >> 11)) 2^-53  in [0, 1)
-// Normals: Box-Muller on word pairs (w0,w1) -> normals 4b, 4b+1 and
-// (w2,w3) -> 4b+2, 4b+3 of block b: r = sqrt(-2 ln U24(w_even)),
-// (r cos 2 pi U24(w_odd), r sin 2 pi U24(w_odd)).  The FP32 transform uses
-// the hardware log2 / sqrt / sin / cos (the sin and cos units take their
-// argument in revolutions, so 2 pi u is never formed).
+//   R24(block)  = (2 v + 1) 2^-24                   in (0, 1),
+//                 v = (w0 & 0x1ff) | (w1 & 0x1ff) << 9 | (w2 & 0x1f) << 18
+// R24 is a block's remnant uniform, from 23 of the low bits U24 leaves
+// unused.  Normals come from Box-Muller pairs on two uniforms (a, b):
+// r = sqrt(-2 ln a), (r cos 2 pi b, r sin 2 pi b); within a block the slot
+// pairs (w0, w1) and (w2, w3) give (U24, U24) pairs.  The FP32 transform
+// uses the hardware log2 / sqrt / sin / cos (the sin and cos units take
+// their argument in revolutions, so 2 pi b is never formed).
+//
+// Packed layout of a draw's normals, ten per two blocks: normal d = 10 q + r
+// comes, for r < 8, from block 2q + r / 4 (slot pairs in order, cosine
+// first), and for r = 8, 9 from the pair (R24(block 2q), R24(block 2q + 1)).
+// A shorter draw is a prefix of a longer one.  The nested estimator's
+// companion draws use the block-aligned layout (normal d from block d / 4),
+// so that one block serves several companions (normals_k, normals_kb).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -104,39 +114,107 @@ __device__ __forceinline__ double uniform53_ab(Key key, uint32_t t, uint32_t a, 
   return u53(w.w[0], w.w[1]);
 }
 
-// Box-Muller pair in FP32 from two words.
-__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& n0, float& n1) {
+// The block's remnant uniform R24: the three fields joined under the
+// exponent of 1.0 (1 + v 2^-23), minus 1 - 2^-24 (exact, as in u24f).
+__device__ __forceinline__ float r24f(const Words& w) {
+  const uint32_t v = (w.w[0] & 0x1ffu) | ((w.w[1] & 0x1ffu) << 9) | ((w.w[2] & 0x1fu) << 18);
+  return __uint_as_float(0x3f800000u | v) - 0x1.fffffep-1f;
+}
+
+// Box-Muller pair in FP32 from two uniforms.
+__device__ __forceinline__ void box_muller_u(float a, float b, float& n0, float& n1) {
   constexpr float kMinus2Ln2 = -1.3862943611198906f;  // -2 ln 2
-  const float a = u24f(wa);
-  const float b = u24f(wb);
   const float r = __builtin_amdgcn_sqrtf(kMinus2Ln2 * __builtin_amdgcn_logf(a));
   n0 = r * __builtin_amdgcn_cosf(b);
   n1 = r * __builtin_amdgcn_sinf(b);
 }
 
-// D standard normals of the draw at counter (t, a, b) for one purpose.
+// Box-Muller pair in FP32 from two words.
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& n0, float& n1) {
+  box_muller_u(u24f(wa), u24f(wb), n0, n1);
+}
+
+// D standard normals of the draw at counter (t, a, b) for one purpose
+// (packed layout; blocks generated once, only those the D normals need).
 template <int D>
 __device__ __forceinline__ void normals(Key key, uint32_t t, uint32_t a, uint32_t b,
                                         uint32_t purpose, float* out) {
 #pragma unroll
-  for (int blk = 0; blk < (D + 3) / 4; ++blk) {
-    const Words w = draw(key, t, a, b, purpose, (uint32_t)blk);
+  for (int q = 0; q < (D + 9) / 10; ++q) {
+    const int base = 10 * q;
+    float rem[2] = {0.f, 0.f};
 #pragma unroll
-    for (int pr = 0; pr < 2; ++pr) {
-      const int d0 = 4 * blk + 2 * pr;
-      if (d0 < D) {
-        float n0, n1;
-        box_muller(w.w[2 * pr], w.w[2 * pr + 1], n0, n1);
-        out[d0] = n0;
-        if (d0 + 1 < D) out[d0 + 1] = n1;
+    for (int h = 0; h < 2; ++h) {
+      if (base + 4 * h < D || base + 8 < D) {
+        const Words w = draw(key, t, a, b, purpose, (uint32_t)(2 * q + h));
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) {
+          const int d0 = base + 4 * h + 2 * pr;
+          if (d0 < D) {
+            float n0, n1;
+            box_muller(w.w[2 * pr], w.w[2 * pr + 1], n0, n1);
+            out[d0] = n0;
+            if (d0 + 1 < D) out[d0 + 1] = n1;
+          }
+        }
+        if (base + 8 < D) rem[h] = r24f(w);
+      }
+    }
+    if (base + 8 < D) {
+      float n0, n1;
+      box_muller_u(rem[0], rem[1], n0, n1);
+      out[base + 8] = n0;
+      if (base + 9 < D) out[base + 9] = n1;
+    }
+  }
+}
+
+// Normals D0 .. D1 - 1 of the draw at counter (t, a, b), packed layout,
+// streamed in order as pairs: f(d, n_d, n_d+1) for even d.  Each block is
+// generated once.  With kRem0 the caller has drawn block 0 itself (D0 >= 4,
+// so none of its words are wanted here) and passes its remnant rem_b0.
+template <int D0, int D1, bool kRem0, class F>
+__device__ __forceinline__ void normal_pairs(Key key, uint32_t t, uint32_t a, uint32_t b, uint32_t purpose,
+                                             float rem_b0, F&& f) {
+  static_assert(D0 % 2 == 0 && D1 % 2 == 0 && D0 < D1, "normal_pairs: even, ordered bounds");
+  static_assert(!kRem0 || (D0 >= 4 && D0 < 10), "normal_pairs: block 0 given, its words not wanted");
+  float rem0 = rem_b0;
+#pragma unroll
+  for (int q = D0 / 10; q < (D1 + 9) / 10; ++q) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int lo = 10 * q + 4 * h;
+      const bool want_words = lo + 4 > D0 && lo < D1;
+      const bool want_rem = 10 * q + 8 >= D0 && 10 * q + 8 < D1;
+      if (kRem0 && q == 0 && h == 0) continue;
+      if (want_words || want_rem) {
+        const Words w = draw(key, t, a, b, purpose, (uint32_t)(2 * q + h));
+#pragma unroll
+        for (int pr = 0; pr < 2; ++pr) {
+          const int d = lo + 2 * pr;
+          if (d >= D0 && d < D1) {
+            float n0, n1;
+            box_muller(w.w[2 * pr], w.w[2 * pr + 1], n0, n1);
+            f(d, n0, n1);
+          }
+        }
+        if (want_rem) {
+          if (h == 0) {
+            rem0 = r24f(w);
+          } else {
+            float n0, n1;
+            box_muller_u(rem0, r24f(w), n0, n1);
+            f(10 * q + 8, n0, n1);
+          }
+        }
       }
     }
   }
 }
 
-// Normals k D .. k D + D - 1 of the draw at counter (t, a, b): the k-th
-// group of D (normal n from block n / 4, slots as above), so that k = 0 is
-// normals<D>.
+// Block-aligned layout (the nested estimator's companion draws): normals
+// k D .. k D + D - 1 of the draw at counter (t, a, b), normal n from block
+// n / 4, slot pairs as above.
 template <int D>
 __device__ __forceinline__ void normals_k(Key key, uint32_t t, uint32_t a, uint32_t b, uint32_t purpose, int k,
                                           float* out) {

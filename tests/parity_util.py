@@ -90,7 +90,7 @@ def compare_la(model, st32, y32, seed, fid, g_state, g_ell, g_logw, g_anc, g_sel
     unexpl = 0
     for k, j in zip(*np.nonzero(zflip)):
         p = A_o[k]
-        kap = st32["lam"][p] + model.logpx(new_o["x"][k], st32["x"][p], st32["z"][p])
+        kap = st32["lam"][p] + model.logpx(new_o["x"][k], st32["x"][p], st32["z"][p], st32["t"])
         wk, _, _ = weights_from_log(kap)
         b = info["binner"][k, j]
         C = np.cumsum(wk)
@@ -140,7 +140,7 @@ def compare_plain(model, st32, y32, seed, fid, g_state, g_ell, g_logw, g_anc, g_
     unexpl = 0
     for k, j in zip(*np.nonzero(zflip)):
         p = A_o[k]
-        kap = lq[p] + model.logpx(new_o["xt"][k], st32["xt"][p], st32["zt"][p])
+        kap = lq[p] + model.logpx(new_o["xt"][k], st32["xt"][p], st32["zt"][p], st32["t"] + 1)
         wk, _, _ = weights_from_log(kap)
         b = info["binner"][k, j]
         C = np.cumsum(wk)
@@ -169,7 +169,7 @@ def assert_clean(r, max_flip_frac=0.02, n=None):
 def _inner_tie(model, st32, i, xt_i, u_in, b, j, M):
     """Whether inner point j of particle i lies within DELTA of the boundary
     of its chosen index b in the x-conditioned inner weights (FP64)."""
-    kap = st32["lam"][i] + model.logpx(xt_i, st32["x"][i], st32["z"][i])
+    kap = st32["lam"][i] + model.logpx(xt_i, st32["x"][i], st32["z"][i], st32["t"])
     wk, _, _ = weights_from_log(kap)
     C = np.cumsum(wk)
     Pj = ((j + u_in) * C[-1]) / M
@@ -177,7 +177,7 @@ def _inner_tie(model, st32, i, xt_i, u_in, b, j, M):
 
 
 def _inner_any_tie(model, st32, i, xt_i, u_in, M):
-    kap = st32["lam"][i] + model.logpx(xt_i, st32["x"][i], st32["z"][i])
+    kap = st32["lam"][i] + model.logpx(xt_i, st32["x"][i], st32["z"][i], st32["t"])
     wk, _, _ = weights_from_log(kap)
     C = np.cumsum(wk)
     Pj = ((np.arange(M) + u_in) * C[-1]) / M

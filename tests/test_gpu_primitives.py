@@ -43,7 +43,8 @@ def test_philox_bit_identical_to_oracle():
     assert np.array_equal(got, expect)
 
 
-@pytest.mark.parametrize("D,purpose", [(1, P.LA_X), (2, P.INIT_X), (8, P.LA_Z), (64, P.NEW_Z)])
+@pytest.mark.parametrize("D,purpose", [(1, P.LA_X), (2, P.INIT_X), (8, P.LA_Z), (10, P.LA_X), (64, P.NEW_Z),
+                                       (68, P.LA_X)])
 def test_normals_match_oracle(D, purpose):
     na, nb = 300, 257
     got = dpf.normals(99, 3, 17, purpose, na, nb, D).cpu().numpy().astype(np.float64)

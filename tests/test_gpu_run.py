@@ -57,7 +57,7 @@ def test_ragged_batch_matches_oracle_per_filter():
         r, _, info = compare_la(model, states[f], ys[1, f], seed, f, gs, ell[io:io + n * m].reshape(n, m),
                                 logw[oo:oo + n], anc[oo:oo + n], sel[oo:oo + n])
         print("filter %d N=%d M=%d: %s" % (f, n, m, r.line()), flush=True)
-        assert_clean(r, max_flip_frac=0.05)
+        assert_clean(r, max_flip_frac=0.05, n=n)
         # the Rao-Blackwellised estimate of each filter of the ragged handle
         assert np.allclose(rb[f], info["xhat_rb"], rtol=1e-4, atol=1e-3), (f, rb[f], info["xhat_rb"])
         oo += n

@@ -162,7 +162,8 @@ def test_twodim_time_convention_in_the_filters():
     st = ladpf.init_state(m, 3, 4, 9, 0)
     st["t"] = 4                                   # the step consumes y_5
     xla, zla, _, _ = ladpf.lookahead(m, st, np.array([0.2]), 9, 0)
-    nu_z = P.normals(9, 0, 5, np.arange(3)[:, None], np.arange(4)[None, :], P.LA_Z, 1)
+    # the candidate's z normal follows its x normal in the one look-ahead draw
+    nu_z = P.normals(9, 0, 5, np.arange(3)[:, None], np.arange(4)[None, :], P.LA_X, 2)[..., 1:]
     x, z = st["x"][:, None, :], st["z"]
     vx = xla - x - z / (1 + z * z)
     want = x + 0.5 * z + 25 * z / (1 + z * z) + 8 * math.cos(f12 * 4) + 0.1 * vx + math.sqrt(0.99) * nu_z

@@ -5,6 +5,7 @@ known-answer vectors pin the round function, multipliers and key schedule;
 the transforms are pinned by exact end points, by Python-integer evaluation
 of the bit formulas and by distribution tests against SciPy.
 """
+import math
 import os
 
 import numpy as np
@@ -97,6 +98,50 @@ def test_normals_distribution_and_independence():
     r = np.sqrt(-2 * np.log(P.u24(w1[0])))
     assert np.isclose(n[5, 2, 4], r * np.cos(2 * np.pi * P.u24(w1[1])), rtol=0, atol=1e-15)
     assert np.isclose(n[5, 2, 5], r * np.sin(2 * np.pi * P.u24(w1[1])), rtol=0, atol=1e-15)
+
+
+def test_packed_normals_distribution_and_independence():
+    """Ten normals per two blocks: the remnant pairs (normals 8, 9, 18, 19)
+    are standard normal and uncorrelated with the word normals of the same
+    blocks and with each other."""
+    n = P.normals(11, 2, 5, np.arange(30000)[:, None], np.arange(2)[None, :], P.NEW_Z, 20)
+    flat = n.reshape(-1, 20)
+    for d in range(20):
+        assert stats.kstest(flat[:, d], "norm").pvalue > 1e-3, d
+    c = np.corrcoef(flat.T)
+    assert np.max(np.abs(c - np.eye(20))) < 0.02
+    # squares too: a remnant built from bits shared with U24 would couple radii
+    c2 = np.corrcoef((flat ** 2).T)
+    assert np.max(np.abs(c2 - np.eye(20))) < 0.03
+
+
+def test_packed_layout_from_raw_words():
+    """Normals 0-7 of a packed draw are blocks 0 and 1 in slot order (the
+    block-aligned layout); normals 8, 9 come from the two blocks' remnant
+    uniforms, here rebuilt bit by bit with Python integers; normals 10-13
+    come from block 2."""
+    D = 14
+    n = P.normals(5, 1, 9, 3, 7, P.LA_X, D)
+    nb = P.normals_blocked(5, 1, 9, 3, 7, P.LA_X, 8)
+    assert np.array_equal(n[:8], nb)
+    w0 = [int(v) for v in P.words(5, 1, 9, 3, 7, P.LA_X, 0)]
+    w1 = [int(v) for v in P.words(5, 1, 9, 3, 7, P.LA_X, 1)]
+    w2 = [int(v) for v in P.words(5, 1, 9, 3, 7, P.LA_X, 2)]
+
+    def rem(w):
+        bits = [(w[0] >> k) & 1 for k in range(9)] + [(w[1] >> k) & 1 for k in range(9)] + \
+            [(w[2] >> k) & 1 for k in range(5)]
+        v = sum(b << k for k, b in enumerate(bits))
+        return (2 * v + 1) / 2.0 ** 24
+
+    a, b = rem(w0), rem(w1)
+    r = math.sqrt(-2 * math.log(a))
+    assert math.isclose(n[8], r * math.cos(2 * math.pi * b), rel_tol=0, abs_tol=1e-14)
+    assert math.isclose(n[9], r * math.sin(2 * math.pi * b), rel_tol=0, abs_tol=1e-14)
+    r2 = math.sqrt(-2 * math.log((2 * (w2[0] >> 9) + 1) / 2.0 ** 24))
+    assert math.isclose(n[10], r2 * math.cos(2 * math.pi * (2 * (w2[1] >> 9) + 1) / 2.0 ** 24), abs_tol=1e-14)
+    # a shorter draw is a prefix of a longer one
+    assert np.array_equal(P.normals(5, 1, 9, 3, 7, P.LA_X, 9), n[:9])
 
 
 def test_streams_differ_by_every_key_field():
