@@ -37,11 +37,18 @@ def test_issue_slot_count():
     # (4 slots each) and four exclusive ors; a Box-Muller pair: four
     # quarter-rate transcendentals and three full-rate operations
     assert bench.PHILOX_BLOCK == 120 and bench.BM_PAIR == 19
-    # n normals: ceil(n/4) Philox blocks, one U24 conversion of three slots
-    # per word, n/2 Box-Muller pairs
+    # n normals in the packed layout: two blocks per ten normals (one for a
+    # remainder of up to four, two above), three slots per uniform, four more
+    # per remnant uniform, one Box-Muller pair per two normals
     assert bench.normals_slots(8) == 2 * 120 + 24 + 4 * 19
     assert bench.normals_slots(2) == 120 + 6 + 19
-    assert bench.VALU_SLOTS_PER_UPDATE == sum(bench.ISSUE_PER_UPDATE.values()) == 1112
+    assert bench.normals_slots(10) == 2 * 120 + 30 + 2 * 4 + 5 * 19
+    assert bench.normals_slots(3) == 120 + 9 + 2 * 19
+    assert bench.normals_slots(64) == 13 * 120 + 192 + 12 * 4 + 32 * 19
+    # nonlinear model: the new z (8 normals) and the candidate's x and z (10)
+    assert bench.ISSUE_PER_UPDATE["new_z"] == bench.normals_slots(8)
+    assert bench.ISSUE_PER_UPDATE["la_normals"] == bench.normals_slots(10)
+    assert bench.VALU_SLOTS_PER_UPDATE == sum(bench.ISSUE_PER_UPDATE.values()) == 1000
     assert abs(bench.VALU_PEAK_TOPS - 39.3216) < 1e-9
 
 
