@@ -185,3 +185,17 @@ def test_run_calls_reject_null_handles():
         assert fn(None, ctypes.c_void_p(256), 4, None, None, None, 1) == 1
         assert len(L.dpf_last_error()) > 0
         assert fn(None, None, 4, None, None, None, 0) == 1
+
+
+def test_normals_call_validates_on_the_host():
+    """dpf_normals serves the built draw lengths only (the packed layout's
+    ten per two blocks included) and rejects the rest before any launch."""
+    L = _lib()
+    EINVAL, EUNSUPPORTED = 1, 5
+    buf = ctypes.c_void_p(16)  # never dereferenced: rejected or empty first
+    assert L.dpf_normals(1, 0, 1, 3, 4, 4, 3, buf, None) == EUNSUPPORTED
+    assert "built: 1, 2, 4, 8, 10, 64, 68" in L.dpf_last_error().decode()
+    assert L.dpf_normals(1, 0, 1, 3, -1, 4, 10, buf, None) == EINVAL
+    assert L.dpf_normals(1, 0, 1, 3, 4, 4, 10, None, None) == EINVAL
+    for D in (1, 2, 4, 8, 10, 64, 68):
+        assert L.dpf_normals(1, 0, 1, 3, 0, 4, D, buf, None) == 0  # nothing to draw
