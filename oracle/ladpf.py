@@ -90,12 +90,15 @@ def cloud_moments(z, lam):
     return m, v
 
 
-def lookahead(model, state, y, seed, fid):
-    """Fig. 4 steps 1-2 for all outer particles; returns (xla, zla, ell, logw)."""
+def lookahead(model, state, y, seed, fid, rows=None):
+    """Fig. 4 steps 1-2 for all outer particles; returns (xla, zla, ell, logw).
+    rows: the outer indices of the state's rows (their random-number
+    counters), by default 0 .. N-1; a subset of a filter's particles gives
+    exactly those particles' values."""
     x, z, lam = state["x"], state["z"], state["lam"]
     t = state["t"] + 1
     N, M = lam.shape
-    i = np.arange(N)[:, None]
+    i = (np.arange(N) if rows is None else np.asarray(rows))[:, None]
     j = np.arange(M)[None, :]
     # one draw per candidate: x first, then z
     nu = P.normals(seed, fid, t, i, j, P.LA_X, model.dx + model.dz)
@@ -207,24 +210,11 @@ def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None, n_
     lamnew = np.empty_like(lam)
     cand = np.empty(N, dtype=np.int64)
     binner = np.empty((N, M), dtype=np.int64)
-    j = np.arange(M)
     for k in range(N):
         p = A[k]
-        c, deg_c, _ = systematic_log(ell[p], 1, float(u_cand[k]))
-        cand[k] = c[0]
-        xnew[k] = xla[p, cand[k]]
-        kappa = lam[p] + model.logpx(xnew[k], x[p], z[p], t - 1)
-        b, deg_i, nonf_i = systematic_log(kappa, M, float(u_inner[k]))
-        if deg_i:
-            flags |= FLAG_DEGENERATE_INNER
-        if nonf_i:
-            flags |= FLAG_NONFINITE
-        binner[k] = b
-        nu = P.normals(seed, fid, t, k, j, P.NEW_Z, model.dz)
-        znew[k] = model.fz(x[p], xnew[k], z[p, b], nu, t - 1)
-        lamnew[k], deg_l = normalise_log(model.logpy(y, xnew[k], znew[k]))
-        if deg_l:
-            flags |= FLAG_DEGENERATE_INNER
+        xnew[k], znew[k], lamnew[k], cand[k], binner[k], fl = new_particle(
+            model, x[p], z[p], lam[p], ell[p], xla[p], y, seed, fid, t, k, float(u_cand[k]), float(u_inner[k]))
+        flags |= fl
 
     xhat = xnew.mean(axis=0)
     zhat = np.einsum("nm,nmd->d", np.exp(lamnew), znew) / N
@@ -237,6 +227,32 @@ def step(model, state, y, seed, fid, u_outer=None, u_cand=None, u_inner=None, n_
         "yhat": yhat, "flags": flags,
     }
     return new_state, info
+
+
+def new_particle(model, xp, zp, lamp, ellp, xlap, y, seed, fid, t, k, u_cand_k, u_inner_k):
+    """Fig. 4 step 4 for new particle k whose parent p has x xp (dx,), cloud
+    zp (M, dz), inner log-weights lamp (M,), look-ahead log-weights ellp
+    (M,) and candidates xlap (M, dx): the candidate by SIR over ellp (U53
+    u_cand_k), the cloud conditioned on it (eq:qnobar) and resampled
+    systematically (u_inner_k), propagated (NEW_Z at (t, k, j)) and updated
+    (eq:qbar).  Returns (x_t, z_t (M, dz), lam_t (M,), candidate, inner
+    ancestors (M,), flags)."""
+    M = lamp.shape[0]
+    flags = 0
+    c, _, _ = systematic_log(ellp, 1, u_cand_k)
+    xk = xlap[c[0]]
+    kappa = lamp + model.logpx(xk, xp, zp, t - 1)
+    b, deg_i, nonf_i = systematic_log(kappa, M, u_inner_k)
+    if deg_i:
+        flags |= FLAG_DEGENERATE_INNER
+    if nonf_i:
+        flags |= FLAG_NONFINITE
+    nu = P.normals(seed, fid, t, k, np.arange(M), P.NEW_Z, model.dz)
+    zk = model.fz(xp, xk, zp[b], nu, t - 1)
+    lamk, deg_l = normalise_log(model.logpy(y, xk, zk))
+    if deg_l:
+        flags |= FLAG_DEGENERATE_INNER
+    return xk, zk, lamk, int(c[0]), b, flags
 
 
 def training_pairs(state, y, info):
