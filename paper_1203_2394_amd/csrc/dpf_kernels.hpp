@@ -111,6 +111,7 @@ struct StepArgs {
   int n_tiles;  // tiles of the class being launched (tile-looping kernels)
   int anc_ready;  // outer ancestors already in anc
   const int2* rgroups;  // (filter, group) of each resampling workgroup
+  const int4* ginfo;    // per resampling group: its filter's (first outer index, N, first group, groups)
   int n_commit;         // learned-step commit workgroups at the head of the launch
   int n_comp;           // companions per look-ahead candidate (nested estimator; 0: paired)
   // predicted observation (models with a one-dimensional y), or null: per
@@ -1520,29 +1521,36 @@ static __global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* 
   __shared__ double part[kBlock / kWave][NV];
   __shared__ int last;
   const int2 rg = rgroups[blockIdx.x];
+  const int4 gi = a.ginfo[blockIdx.x];  // static: the filter's offsets and groups
   const int f = rg.x, g = rg.y;
-  const int tf = (next && a.run_Tf != nullptr) ? a.run_Tf[f] : 0x7fffffff;
-  const int rb = a.finfo[f].rg_base;
-  asm volatile("" ::"v"(tf), "v"(rb));
-  const FilterView fv = load_filter(a, f);
-  if (!fv.act) return;
-  const int N = fv.N, oo = fv.oo;
-  const int t = fv.t;  // the step just taken
-  const unsigned char cb = (unsigned char)fv.cur;
-  const float* xs = a.x[copy_of(cb)];
+  const int oo = gi.x, N = gi.y, rb = gi.z, G = gi.w;
   const int i = g * kResGroup + threadIdx.x;
-  const double w = 1.0 / N;
   // loads at a clamped index, masked afterwards (a load guarded by i < N
-  // would wait inside its own branch: one memory round per value)
+  // would wait inside its own branch: one memory round per value); the
+  // particles' values do not depend on the filter's time, so they are
+  // fetched in the same memory round as it (x from both state copies)
   const int ic = min(i, N - 1);
-  const bool act_next = next && t < min(tf, a.run_T);
-  float raw[NV];
+  float raw[NV], xo[DX];
 #pragma unroll
-  for (int d = 0; d < DX; ++d) raw[d] = xs[(long long)d * a.NT + oo + ic];
+  for (int d = 0; d < DX; ++d) {
+    raw[d] = a.x[0][(long long)d * a.NT + oo + ic];
+    xo[d] = a.x[1][(long long)d * a.NT + oo + ic];
+  }
 #pragma unroll
   for (int d = 0; d < DZ; ++d) raw[DX + d] = a.kpart[(long long)(oo + ic) * DZ + d];
   if constexpr (YH) raw[NV - 1] = a.yp[oo + ic];
-  const float lwn = act_next ? a.logw_next[oo + ic] : 0.f;
+  const float lwn = (next && a.logw_next != nullptr) ? a.logw_next[oo + ic] : 0.f;
+  const int tf = (next && a.run_Tf != nullptr) ? a.run_Tf[f] : 0x7fffffff;
+  const int act = a.act[f], t = a.tcur[f], cu = a.cur[f];  // t: the step just taken
+  asm volatile("" ::"v"(tf), "v"(act), "v"(t), "v"(cu));
+  if (!act) return;
+  const unsigned char cb = (unsigned char)cu;
+  if (copy_of(cb)) {
+#pragma unroll
+    for (int d = 0; d < DX; ++d) raw[d] = xo[d];
+  }
+  const double w = 1.0 / N;
+  const bool act_next = next && t < min(tf, a.run_T);
   double v[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) v[q] = i < N ? w * (double)raw[q] : 0.0;
@@ -1570,12 +1578,12 @@ static __global__ __launch_bounds__(kBlock) void k_post(StepArgs a, const int2* 
   }
   if (split) return;  // k_post_end finishes the filters
   __threadfence();
-  if (threadIdx.x == 0) last = atomicAdd(&a.fcount[f], 1) == fv.ngroup - 1;
+  if (threadIdx.x == 0) last = atomicAdd(&a.fcount[f], 1) == G - 1;
   __syncthreads();
   if (!last) return;
   __threadfence();
   if (threadIdx.x == 0) a.fcount[f] = 0;
-  post_finish<DX, DZ, YH>(a, f, rb, fv.ngroup, t, cb, next, act_next, kBlock);
+  post_finish<DX, DZ, YH>(a, f, rb, G, t, cb, next, act_next, kBlock);
 }
 
 // Filter-level end of k_post: the estimates from the group partials (in

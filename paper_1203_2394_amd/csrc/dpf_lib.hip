@@ -62,7 +62,7 @@ static const Engine* find_engine(int model, int dx, int dz, int dy) {
 // ---------------------------------------------------------------- layout
 struct Layout {
   size_t total = 0;
-  size_t prm, fN, fM, ooff, ooff64, ioff, finfo, tcur, cur, act, tiles, rgroups, x0, x1, z0, z1, l0, l1, ell,
+  size_t prm, fN, fM, ooff, ooff64, ioff, finfo, tcur, cur, act, tiles, rgroups, ginfo, x0, x1, z0, z1, l0, l1, ell,
       logw, anc, sel, kpart, gstat, fstat, ess, dlogz, loglik, flags, est_x, est_z;
   // slot indirection and learned-proposal buffers
   size_t ind0, ind1, mom, mlp, mdn, xtmp, logq, kpart_tmp, mom_tmp, fb, lflags;
@@ -140,6 +140,7 @@ static dpf_status plan(const dpf_config* c, const Engine*& eng, Layout& L) {
   L.act = carve(cur, F);
   L.tiles = carve(cur, (size_t)L.n_tiles * sizeof(int4));
   L.rgroups = carve(cur, (size_t)L.n_rgroups * sizeof(int2));
+  L.ginfo = carve(cur, (size_t)L.n_rgroups * sizeof(int4));
   L.x0 = carve(cur, NT * dx * 4);
   L.x1 = carve(cur, NT * dx * 4);
   L.z0 = carve(cur, NMT * dz * 4);
@@ -199,6 +200,7 @@ struct dpf_handle {
   std::vector<long long> ioff, ooff64;
   std::vector<int4> tiles_h;
   std::vector<int2> rgroups_h;
+  std::vector<int4> ginfo_h;  // per group: the filter's (first outer index, N, first group, groups)
   std::vector<FilterInfo> finfo_h;
   std::vector<float> prm_h;
   std::vector<TileClass> classes;
@@ -255,6 +257,7 @@ static StepArgs make_args(dpf_handle* h) {
   a.ooff = at<int>(h, h->L.ooff);
   a.ioff = at<long long>(h, h->L.ioff);
   a.finfo = at<FilterInfo>(h, h->L.finfo);
+  a.ginfo = at<int4>(h, h->L.ginfo);
   a.NT = h->L.NT;
   a.advance = 1;
   a.seed = h->seed;
@@ -411,7 +414,10 @@ extern "C" dpf_status dpf_create(const dpf_config* cfg, void* d_workspace, size_
   int rg = 0;
   for (int f = 0; f < F; ++f) {
     const int G = (h->N[f] + kResGroup - 1) / kResGroup;
-    for (int g = 0; g < G; ++g) h->rgroups_h.push_back(make_int2(f, g));
+    for (int g = 0; g < G; ++g) {
+      h->rgroups_h.push_back(make_int2(f, g));
+      h->ginfo_h.push_back(make_int4(h->ooff[f], h->N[f], rg, G));
+    }
     h->finfo_h[f] = FilterInfo{rg, G, 0, 0};
     rg += G;
   }
@@ -429,6 +435,7 @@ extern "C" dpf_status dpf_create(const dpf_config* cfg, void* d_workspace, size_
   UP(L.ooff64, h->ooff64)
   UP(L.ioff, h->ioff)
   UP(L.rgroups, h->rgroups_h)
+  UP(L.ginfo, h->ginfo_h)
   UP(L.finfo, h->finfo_h)
 #undef UP
   if (e != hipSuccess) {
