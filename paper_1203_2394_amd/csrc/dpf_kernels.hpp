@@ -1335,13 +1335,17 @@ static __device__ void res_finish(const StepArgs& a, int f, int t, int N, const 
 static __global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const int2* rgroups, int advance_time) {
   __shared__ ResScratch sh;
   const int2 rg = rgroups[blockIdx.x];
+  const int4 gi = a.ginfo[blockIdx.x];  // static: the filter's offsets and groups
   const int f = rg.x;
-  // the filter's values in one memory round (a load under a branch would
-  // wait inside it)
+  const int oo = gi.x, N = gi.y, rb = gi.z;
+  const int i = rg.y * kResGroup + threadIdx.x;
+  // the group's log-weight (clamped index, masked below) and the filter's
+  // values in one memory round (a load under a branch would wait inside it)
+  const float lw = a.logw[oo + min(i, N - 1)];
   const int ac = a.act[f];
   const int fbv = a.fb != nullptr ? a.fb[f] : 1;
-  const int tc = a.tcur[f], cu = a.cur[f], N = a.fN[f], oo = a.ooff[f], rb = a.finfo[f].rg_base;
-  asm volatile("" ::"v"(ac), "v"(fbv), "v"(tc), "v"(cu), "v"(N), "v"(oo), "v"(rb));
+  const int tc = a.tcur[f], cu = a.cur[f];
+  asm volatile("" ::"v"(ac), "v"(fbv), "v"(tc), "v"(cu));
   if (!ac) return;
   if (fbv == 0) {
     if (advance_time && rg.y == 0 && threadIdx.x == 0) {
@@ -1352,9 +1356,8 @@ static __global__ __launch_bounds__(kBlock) void k_res_stats(StepArgs a, const i
   }
   float mg;
   double sg, qg;
-  res_group_stat(LogSrc{a.logw + oo}, N, rg.y, mg, sg, qg, sh);
-  const int i = rg.y * kResGroup + threadIdx.x;
-  const float v = i < N ? a.logw[oo + i] : 0.f;
+  res_group_stat_lw(lw, i < N, mg, sg, qg, sh);
+  const float v = i < N ? lw : 0.f;
   const int nonf = __syncthreads_or((!finitef(v) && !(v == -INFINITY)) ? 1 : 0);
   if (threadIdx.x == 0) {
     double* gs = a.gstat + 4LL * (rb + rg.y);
