@@ -620,7 +620,7 @@ def run_bandit(S, dpf, torch, np, dev):
                                     "chooses which filter's estimate is reported"}}
 
 
-HD_N, HD_M, HD_T, HD_SEED = 16384, 1024, 12, 4
+HD_N, HD_M, HD_T, HD_SEED = 16384, 1024, 100, 4
 
 # fixed-RMSE comparison: sequences, their length, the outer-particle grid and
 # the tolerance on the reference RMSE (the look-ahead step at N = 4096)
