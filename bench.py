@@ -8,7 +8,7 @@ M=256 inner particles per outer particle, synthetic seeded observations.
 A step is one look-ahead DPF step (Fig. 4: look-ahead weights, outer
 resampling, new particles, inner resampling, propagation, inner measurement
 update, estimates) with the observations already resident in HBM; the K
-timed steps run as replays of a captured 16-step HIP graph (dpf_run).
+timed steps run as a captured HIP graph of the run's steps after the first (dpf_run).
 
 In a run the new-cloud kernel of each step also computes the next step's
 look-ahead weights, and a step-end kernel takes the estimates and prepares
@@ -392,7 +392,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "look-ahead DPF step, nonlinear model dx=2 dz=8 dy=8, N=4096 outer x M=256 inner",
                    "algo": "lookahead", "N": N_OUT, "M": M_IN, "dx": DX, "dz": DZ, "dy": DY,
-                   "execution": "HIP graph replays of a captured 16-step chunk (dpf_run); each step's "
+                   "execution": "one captured HIP graph of the steps after the first (dpf_run); each step's "
                                 "new-cloud kernel also computes the next step's look-ahead weights",
                    "rmse_x_T200": rmse_x},
         "eager_value": updates * K / edt if edt else None,

@@ -185,9 +185,11 @@ dpf_status dpf_estimate(dpf_handle* h, float* d_xmean, float* d_zmean, float* d_
  * (absolute time).  d_Tf: [F] int32 or NULL (all T).  d_xtrace [T][F][dx]
  * and d_ztrace [T][F][dz] (or NULL) receive the per-step estimates at row
  * t-1.  use_graph != 0 runs the first step directly, then captures a chunk
- * of 16 steps into a HIP graph once and replays it (the step's launches read
- * every per-filter time and buffer choice from device memory, so replays
- * need no host work); the steps the chunks do not cover are queued directly.
+ * of min(T - 1, 256) steps into a HIP graph once and replays it (the step's
+ * launches read every per-filter time and buffer choice from device memory,
+ * so replays need no host work), and the steps the chunks do not cover as a
+ * second captured graph; both are cached for the next run of the same
+ * length and buffers.
  * A look-ahead run takes Fig. 4 steps 1-2 of step t+1 (the look-ahead
  * weights, eq:weightsMC) inside step t's new-cloud launch, from the clouds
  * it has just built, and the outer-weight statistics of step t+1 inside step

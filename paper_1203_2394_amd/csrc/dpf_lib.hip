@@ -208,6 +208,7 @@ struct dpf_handle {
   // multi-step graph cache
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipGraphExec_t gexec_tail = nullptr;  // the run's last (T - 1) mod S steps
   const void* g_key[11] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                            nullptr, nullptr, nullptr, nullptr, nullptr};
   int g_T = -1;
@@ -233,6 +234,14 @@ struct dpf_handle {
 
 constexpr int kPhaseEvents = 5;
 constexpr int kMaxCompanions = 1024;
+
+// Drop the cached run graphs (their captured arguments are out of date).
+static void drop_graphs(dpf_handle* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->gexec_tail) (void)hipGraphExecDestroy(h->gexec_tail);
+  h->gexec = nullptr;
+  h->gexec_tail = nullptr;
+}
 
 static dpf_status phase_mark(dpf_handle* h, int phase) {
   if (h->prof_next + (size_t)(kPhaseEvents - phase) > h->prof_events.size()) return DPF_OK;
@@ -481,10 +490,7 @@ static dpf_status build_tiles(dpf_handle* h) {
   if ((int)h->tiles_h.size() > h->L.n_tiles) return fail(DPF_EINVAL, "internal: tile room exceeded");
   HIP_TRY(hipMemcpyAsync(h->ws + h->L.tiles, h->tiles_h.data(), h->tiles_h.size() * sizeof(int4),
                          hipMemcpyHostToDevice, h->stream));
-  if (h->gexec) {
-    (void)hipGraphExecDestroy(h->gexec);
-    h->gexec = nullptr;
-  }
+  drop_graphs(h);
   return DPF_OK;
 }
 
@@ -518,7 +524,7 @@ extern "C" dpf_status dpf_reset(dpf_handle* h) {
 
 extern "C" dpf_status dpf_destroy(dpf_handle* h) {
   if (!h) return DPF_OK;
-  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  drop_graphs(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
   return DPF_OK;
@@ -775,13 +781,15 @@ static dpf_status queue_run_step(dpf_handle* h, int mode, const float* d_Y, int 
 }
 
 // T steps of mode 0 (the handle's algorithm) or 1 (learned), eagerly or as
-// replays of a captured chunk of kGraphChunk steps (every step reads the
-// per-filter time and state copy from device memory, so one capture serves
-// every chunk); the steps the chunks do not cover run eagerly.  The first
-// step always runs eagerly (in a look-ahead run it is the only one with a
-// weights kernel); kGraphChunk is even, so the chunks see the same
-// alternation of weight buffers.
-constexpr int kGraphChunk = 16;
+// replays of a captured chunk of S = min(T - 1, kGraphChunk) steps (every
+// step reads the per-filter time and state copy from device memory, so one
+// capture serves every chunk), the last (T - 1) mod S steps as a second
+// captured graph.  The first step always runs eagerly (in a look-ahead run it
+// is the only one with a weights kernel); kGraphChunk is even, so repeated
+// chunks and the tail see the same alternation of weight buffers.  Each graph
+// launch costs a gap of several microseconds between the kernels of
+// successive steps, hence long chunks.
+constexpr int kGraphChunk = 256;
 
 static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T, const int32_t* d_Tf,
                             float* d_xtrace, float* d_ztrace, int32_t use_graph) {
@@ -806,6 +814,7 @@ static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T
     if (st != DPF_OK || T == 1) return st;
   }
   const int S = T - 1 < kGraphChunk ? T - 1 : kGraphChunk;
+  const int R = (T - 1) % S;  // tail steps T - R .. T - 1
   // every value make_args copies into the captured kernel arguments that can
   // change between runs is part of the key: the buffers, the stream, the
   // mode, whether cloud moments are maintained, and the fallback threshold
@@ -817,41 +826,44 @@ static dpf_status run_steps(dpf_handle* h, int mode, const float* d_Y, int32_t T
                          (const void*)h->ytrace};
   const bool cached = h->gexec && h->g_T == T && memcmp(key, h->g_key, sizeof(key)) == 0;
   if (!cached) {
-    if (h->gexec) {
-      (void)hipGraphExecDestroy(h->gexec);
-      h->gexec = nullptr;
-    }
+    drop_graphs(h);
     if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    hipStream_t user = h->stream;
-    h->stream = h->cap_stream;
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
-    dpf_status st = DPF_OK;
-    for (int q = 1; e == hipSuccess && st == DPF_OK && q <= S; ++q)
-      st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace, q);
-    hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
-    h->stream = user;
-    if (e != hipSuccess) return fail(DPF_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    // steps q0 .. q0 + n - 1 captured into *out
+    auto capture = [&](int q0, int n, hipGraphExec_t* out) -> dpf_status {
+      hipStream_t user = h->stream;
+      h->stream = h->cap_stream;
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+      dpf_status st = DPF_OK;
+      for (int q = q0; e == hipSuccess && st == DPF_OK && q < q0 + n; ++q)
+        st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace, q);
+      hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+      h->stream = user;
+      if (e != hipSuccess) return fail(DPF_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+      if (st != DPF_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+      }
+      if (e2 != hipSuccess) return fail(DPF_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+      e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        *out = nullptr;
+        return fail(DPF_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+      }
+      return DPF_OK;
+    };
+    dpf_status st = capture(1, S, &h->gexec);
+    if (st == DPF_OK && R > 0) st = capture(T - R, R, &h->gexec_tail);
     if (st != DPF_OK) {
-      if (g) (void)hipGraphDestroy(g);
+      drop_graphs(h);
       return st;
-    }
-    if (e2 != hipSuccess) return fail(DPF_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
-    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-      h->gexec = nullptr;
-      return fail(DPF_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     memcpy(h->g_key, key, sizeof(key));
     h->g_T = T;
   }
-  int q = 1;
-  for (; q + S <= T; q += S) HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
-  for (; q < T; ++q) {
-    dpf_status st = queue_run_step(h, mode, d_Y, T, d_Tf, d_xtrace, d_ztrace, q);
-    if (st != DPF_OK) return st;
-  }
+  for (int q = 1; q + S <= T; q += S) HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
+  if (R > 0) HIP_TRY(hipGraphLaunch(h->gexec_tail, h->stream));
   // (the captured steps do not update the host's record of the buffers)
   if (mode == 0 && h->algo == DPF_ALGO_LOOKAHEAD && h->n_comp == 0) h->ell_sel = (T - 1) & 1;
   return DPF_OK;

@@ -100,12 +100,14 @@ def test_graph_run_equals_step_calls_bit_for_bit(N, M):
     assert torch.equal(a.copy_buffer(dpf.BUF_ELL), b.copy_buffer(dpf.BUF_ELL))
 
 
-@pytest.mark.parametrize("T", [17, 20, 35])
+@pytest.mark.parametrize("T", [17, 20, 300, 514])
 def test_run_chunks_and_remainder_equal_step_calls(T):
-    """Look-ahead runs longer than one 16-step graph chunk: the first step
-    eager, then chunk replays, then the remainder eagerly -- the alternating
-    weight buffers must line up across every boundary.  A second run of the
-    same length replays the cached graph."""
+    """Look-ahead runs as graphs: the first step eager, then one captured
+    graph of the other T - 1 steps (T - 1 <= 256), or replays of a 256-step
+    chunk and a captured tail of the remaining steps (T = 300: one chunk and
+    43 steps; T = 514: two chunks and one step) -- the alternating weight
+    buffers must line up across every boundary.  A second run of the same
+    length replays the cached graphs."""
     spec = S.nonlin_c2(1)
     N, M = [200, 90], [64, 40]
     Y = np.stack([S.simulate(spec, T, 41 + f)[2] for f in range(2)], axis=1).astype(np.float32)
