@@ -257,6 +257,9 @@ __device__ __forceinline__ int cdf_search(const double* C, int n, double P) {
 __device__ __forceinline__ double sys_point(int k, double u, double total, int n_out) {
   const double a = (double)k + u;
   const double b = a * total;
+  // a power-of-two count: b scaled by 2^-e is the correctly rounded b / n_out
+  // as well (the same exact value, one rounding), in one instruction
+  if ((n_out & (n_out - 1)) == 0) return __builtin_amdgcn_ldexp(b, -__builtin_ctz((unsigned)n_out));
   return b / (double)n_out;
 }
 
